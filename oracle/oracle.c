@@ -1,0 +1,955 @@
+/*
+ * oracle.c -- FP64 CPU oracle of the second-order explicit ("A3") photoionisation
+ * source-term step of Mackey, "Accuracy and efficiency of raytracing
+ * photoionisation algorithms" (A&A 2012).
+ *
+ * TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the bench's
+ * CPU-baseline leg are its only callers.  It shares no code with the HIP
+ * library and is written to be read against the paper, not to be fast: plain
+ * loops, IEEE double, one thread, no blocking or fusion.
+ *
+ * What it computes, section by section of the paper:
+ *   - short-characteristics point-source raytrace (Sect. 2, "short
+ *     characteristics ray-tracing module"; Sect. 5, source on a cell vertex,
+ *     octants traced independently)  -> orc_raytrace_sc
+ *   - exact long-characteristics columns, used only as an accuracy bound on the
+ *     short-characteristics columns                                -> orc_raytrace_lc
+ *   - photon-conserving per-cell photoionisation and photoheating rates, with
+ *     rates tabulated against optical depth for a blackbody source (Sect. 2,
+ *     multi-frequency rates tabulated as a function of optical depth)
+ *   - integration of the neutral fraction 1-y and the internal energy (eq. 2,
+ *     Sect. 2.1: the neutral fraction is the integrated variable)  -> micro()
+ *   - the timestep criterion (eq. 4, Table 1)                      -> orc_timestep
+ *   - algorithm 3 (Sect. 2.2): raytrace at t_n sets dt; microphysics over dt/2
+ *     on the instantaneous columns; raytrace of the half-step state; microphysics
+ *     over dt from the initial state on the time-centred columns   -> orc_step
+ *   - algorithm 2 (Sect. 2.2), the first-order variant, for order tests only
+ *   - 1D spherical and plane-parallel modes of Sect. 3 (tests only)
+ *   - front locator (eq. 5)
+ *
+ * Readings where the paper is silent are listed in the design notes; the ones
+ * that shape code here are repeated beside the code they shape.
+ *
+ * Parity unpinned (no closed form, printed value or brute force fixes them;
+ * they are documented choices that only GPU <-> oracle parity checks): the
+ * cooling and collisional-ionisation coefficients (Cen 1992 fits), the power
+ * law of the recombination coefficient, the 0.6 floor of the Mellema weights,
+ * and the placement of the 64 table nodes.  Everything else is pinned by the
+ * tests in tests/test_oracle_pins.py.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- constants */
+static const double KB = 1.380649e-16;        /* Boltzmann constant [erg/K]         */
+static const double EV = 1.602176634e-12;     /* [erg]                              */
+static const double HNU0_EV = 13.6;           /* threshold energy, Sect. 2.1        */
+static const double TAU0_MELLEMA = 0.6;       /* reading: weight 1/max(0.6, tau)    */
+static const double T_FLOOR = 10.0;           /* [K], reading                       */
+static const double THIN_CELL = 1e-2;         /* table mode: midpoint rule below    */
+static const double NEWTON_RTOL = 1e-13;
+static const double NEWTON_STALL = 1e-9;
+static const int    NEWTON_2D_MAXIT = 20;
+static const int    FALLBACK_MAXIT = 200;
+static const int    NEWTON_MAXIT = 60;
+/* (2/pi) * integral over the unit cube of dV/|r|^2: mean chord that makes the
+ * corner cell absorb exactly its octant's Q/8 in both the thin and the thick
+ * limit (reading of the source-cell normalisation). */
+static const double MEAN_CHORD_SOURCE_CELL = 1.2213748039031678;
+
+static int64_t g_newton_fail = 0;
+
+int64_t orc_newton_failures(void) { return g_newton_fail; }
+void orc_reset_newton_failures(void) { g_newton_fail = 0; }
+double orc_mean_chord_source_cell(void) { return MEAN_CHORD_SOURCE_CELL; }
+
+/* ------------------------------------------------------------- rate tables */
+/* Gauss-Legendre nodes on [-1,1] by Newton iteration on P_n. */
+static void gauss_legendre(int n, double* xg, double* wg)
+{
+    for (int i = 0; i < n; ++i) {
+        double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = 0.0;
+            for (int k = 1; k <= n; ++k) {
+                double p2 = p1;
+                p1 = p0;
+                p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+            }
+            dp = n * (z * p0 - p1) / (z * z - 1.0);
+            double dz = p0 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        {   /* derivative at the converged node, for the weight */
+            double p0 = 1.0, p1 = 0.0;
+            for (int k = 1; k <= n; ++k) {
+                double p2 = p1;
+                p1 = p0;
+                p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+            }
+            dp = n * (z * p0 - p1) / (z * z - 1.0);
+        }
+        xg[i] = z;
+        wg[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+/* Table of a blackbody source of temperature T_bb normalised to Q ionising
+ * photons/s, with cross-section sigma_nu = sigma0 (nu0/nu)^3 (reading), against
+ * the threshold optical depth tau (Sect. 2, multi-frequency rates tabulated as
+ * a function of optical depth):
+ *   P(tau)  = photons/s surviving a threshold column tau
+ *   P1(tau) = -dP/dtau
+ *   H(tau)  = excess energy (h nu - h nu0) carried by those photons [erg/s]
+ *   H1(tau) = -dH/dtau
+ * Nodes: tau=0, then 63 log-spaced nodes on [1e-4, 1e4]. */
+int orc_table_build(double T_bb, double Q, double* out)
+{
+    if (!(T_bb > 0) || !(Q >= 0) || !out) return -1;
+    double* tau = out;
+    double* P = out + ORC_NTAB;
+    double* P1 = out + 2 * ORC_NTAB;
+    double* H = out + 3 * ORC_NTAB;
+    double* H1 = out + 4 * ORC_NTAB;
+    tau[0] = 0.0;
+    for (int j = 1; j < ORC_NTAB; ++j) tau[j] = 1e-4 * pow(10.0, 8.0 * (j - 1) / 62.0);
+
+    enum { NG = 10 };
+    double xg[NG], wg[NG];
+    gauss_legendre(NG, xg, wg);
+    const double kT = KB * T_bb;
+    const double u0 = HNU0_EV * EV / kT;
+    const double width = 0.25;
+    const int npanel = 800; /* u in [u0, u0 + 200] */
+
+    double norm = 0.0;
+    for (int p = 0; p < npanel; ++p) {
+        double a = u0 + p * width, b = a + width;
+        for (int q = 0; q < NG; ++q) {
+            double u = 0.5 * (a + b) + 0.5 * (b - a) * xg[q];
+            norm += 0.5 * (b - a) * wg[q] * u * u / expm1(u);
+        }
+    }
+    for (int j = 0; j < ORC_NTAB; ++j) {
+        double sp = 0, sp1 = 0, sh = 0, sh1 = 0;
+        for (int p = 0; p < npanel; ++p) {
+            double a = u0 + p * width, b = a + width;
+            for (int q = 0; q < NG; ++q) {
+                double u = 0.5 * (a + b) + 0.5 * (b - a) * xg[q];
+                double w = 0.5 * (b - a) * wg[q] * u * u / expm1(u);
+                double s = (u0 / u) * (u0 / u) * (u0 / u);
+                double att = exp(-tau[j] * s);
+                sp += w * att;
+                sp1 += w * s * att;
+                sh += w * (u - u0) * att;
+                sh1 += w * (u - u0) * s * att;
+            }
+        }
+        P[j] = Q * sp / norm;
+        P1[j] = Q * sp1 / norm;
+        H[j] = Q * kT * sh / norm;
+        H1[j] = Q * kT * sh1 / norm;
+    }
+    return 0;
+}
+
+/* Interpolate the table (which = 0: P, 1: H) at optical depth tau >= 0.
+ * Reading: cubic Hermite in (ln tau, ln V/V(0)) between log-spaced nodes, with the
+ * node slopes dlnV/dlntau = -tau V1/V from the tabulated derivative; first-order
+ * Taylor from tau=0 below the first log node; zero at and beyond the last node.
+ * Returns V and sets *dvdtau = dV/dtau of the same interpolant. */
+double orc_table_eval(const double* table, int which, double tau, double* dvdtau)
+{
+    const double* tn = table;
+    const double* V = table + (which == 0 ? 1 : 3) * ORC_NTAB;
+    const double* V1 = table + (which == 0 ? 2 : 4) * ORC_NTAB;
+    if (tau < tn[1]) {
+        if (dvdtau) *dvdtau = -V1[0];
+        return V[0] - V1[0] * tau;
+    }
+    if (tau >= tn[ORC_NTAB - 1]) {
+        if (dvdtau) *dvdtau = 0.0;
+        return 0.0;
+    }
+    const double s1 = log(tn[1]);
+    const double delta = log(tn[2]) - log(tn[1]);
+    const double s = log(tau);
+    int j = 1 + (int)floor((s - s1) / delta);
+    if (j < 1) j = 1;
+    if (j > ORC_NTAB - 2) j = ORC_NTAB - 2;
+    const double sj = log(tn[j]);
+    const double sk = log(tn[j + 1]);
+    const double h = sk - sj;
+    const double t = (s - sj) / h;
+    const double Lj = log(V[j] / V[0]), Lk = log(V[j + 1] / V[0]);
+    const double mj = -tn[j] * V1[j] / V[j];
+    const double mk = -tn[j + 1] * V1[j + 1] / V[j + 1];
+    const double t2 = t * t, t3 = t2 * t;
+    const double h00 = 2 * t3 - 3 * t2 + 1, h10 = t3 - 2 * t2 + t;
+    const double h01 = -2 * t3 + 3 * t2, h11 = t3 - t2;
+    const double L = h00 * Lj + h10 * h * mj + h01 * Lk + h11 * h * mk;
+    const double dL = ((6 * t2 - 6 * t) * Lj + (3 * t2 - 4 * t + 1) * h * mj +
+                       (-6 * t2 + 6 * t) * Lk + (3 * t2 - 2 * t) * h * mk) / h;
+    const double val = V[0] * exp(L);
+    if (dvdtau) *dvdtau = val * dL / tau;
+    return val;
+}
+
+/* ------------------------------------------------------------- cell geometry */
+/* Octant-local description of cell (i,j,k) for a source on vertex src
+ * (Sect. 5: the source is moved to the nearest cell vertex and octants are
+ * traced independently).  ad[] = |cell centre - source| / dx per axis (half
+ * integers), l[] = octant-local indices, a = dominant axis (ties: z > y > x,
+ * reading), o[] = octant signs. */
+typedef struct {
+    double ad[3];
+    int l[3];
+    int o[3];
+    int a;
+} cellpos;
+
+static void cell_pos(const orc_desc* g, int i, int j, int k, cellpos* c)
+{
+    int idx[3] = { i, j, k };
+    for (int d = 0; d < 3; ++d) {
+        double dd = idx[d] + 0.5 - g->src[d];
+        c->o[d] = dd > 0 ? 1 : -1;
+        c->ad[d] = fabs(dd);
+        c->l[d] = (int)(c->ad[d] - 0.5);
+    }
+    if (c->ad[2] >= c->ad[0] && c->ad[2] >= c->ad[1]) c->a = 2;
+    else if (c->ad[1] >= c->ad[0]) c->a = 1;
+    else c->a = 0;
+}
+
+/* geometry factors of the photon-conserving rate: photons absorbed per unit
+ * volume = geo * [P(tau_in) - P(tau_in + n_H sigma0 ell x)].  Reading: the ray
+ * through the cell centre sets r (source to centre) and the chord ell = Delta s;
+ * the photons entering are spread over the shell volume 4 pi r^2 Delta s.  The
+ * octant-corner cell instead takes its octant's Q/8 over its own volume with
+ * the mean chord of the corner cube. */
+static void env_3d(const orc_desc* g, const cellpos* c, double* geo, double* ell)
+{
+    const double dx = g->dx;
+    double rr = c->ad[0] * c->ad[0] + c->ad[1] * c->ad[1] + c->ad[2] * c->ad[2];
+    double norm = sqrt(rr);
+    double ds = dx * norm / c->ad[c->a];
+    if (g->source_cell_rule && c->l[0] == 0 && c->l[1] == 0 && c->l[2] == 0) {
+        *geo = 1.0 / (8.0 * dx * dx * dx);
+        *ell = MEAN_CHORD_SOURCE_CELL * dx;
+    } else {
+        double r2 = rr * dx * dx;
+        *geo = 1.0 / (4.0 * M_PI * r2 * ds);
+        *ell = ds;
+    }
+}
+
+static void env_1d(const orc_desc* g, int i, double* geo, double* ell)
+{
+    const double dr = g->dx;
+    if (g->geometry == ORC_GEOM_SPHERICAL_1D) {
+        double a = (double)i, b = (double)(i + 1);
+        double vol = 4.0 / 3.0 * M_PI * dr * dr * dr * (b * b * b - a * a * a);
+        *geo = 1.0 / vol;
+    } else {
+        *geo = 1.0 / dr; /* per unit area; Q is then the photon flux */
+    }
+    *ell = dr;
+}
+
+static int64_t ncells(const orc_desc* g)
+{
+    if (g->geometry == ORC_GEOM_3D) return (int64_t)g->n[0] * g->n[1] * g->n[2];
+    return g->n[0];
+}
+
+int orc_cell_env(const orc_desc* g, int64_t cell, double* geo, double* ell)
+{
+    if (cell < 0 || cell >= ncells(g)) return -1;
+    if (g->geometry != ORC_GEOM_3D) {
+        env_1d(g, (int)cell, geo, ell);
+        return 0;
+    }
+    int i = (int)(cell % g->n[0]);
+    int j = (int)((cell / g->n[0]) % g->n[1]);
+    int k = (int)(cell / ((int64_t)g->n[0] * g->n[1]));
+    cellpos c;
+    cell_pos(g, i, j, k, &c);
+    env_3d(g, &c, geo, ell);
+    return 0;
+}
+
+/* ----------------------------------------------------------------- raytrace */
+/* Short characteristics from a vertex source (Sect. 2; Sect. 5).  Per octant,
+ * cells are visited in increasing octant-local (z, y, x); every upstream
+ * neighbour has no larger local index on any axis and a smaller one on the
+ * dominant axis, so it is already done.  Reading of the interpolation: each
+ * cell carries N_c, the neutral column from the source to its centre.  For a
+ * cell C with dominant axis a:
+ *   - the ray from the source to C's centre crosses the plane through the
+ *     centres of the upstream layer (one cell back along a) at offset
+ *     delta_b = |d_b| / |d_a| in (0, 1] from C's own column on each other axis b;
+ *   - the four upstream centres around that point each contribute
+ *     T_m = N_c(m) + (Delta s / 2) n_H x (m), the column carried on to C's entry
+ *     face, with bilinear weights, each divided by max(0.6, sigma0 T_m) in the
+ *     Mellema et al. weighting (reading of the weighting the paper cites);
+ *   - neighbours across a source plane (octant-local index -1) are dropped and
+ *     the weights renormalised, so octants stay independent;
+ *   - N_in = sum w T / sum w is the column to C's entry face and
+ *     N_c(C) = N_in + (Delta s / 2) n_H x (C); the output is tau_in = sigma0 N_in.
+ * Delta s = dx |d| / |d_a| is the length of the ray between two successive
+ * planes of the dominant axis. */
+static int raytrace_sc_3d(const orc_desc* g, const double* nH, const double* x, double* tau_in)
+{
+    const int nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const int64_t N = (int64_t)nx * ny * nz;
+    double* Nc = (double*)malloc(sizeof(double) * (size_t)N);
+    if (!Nc) return -2;
+    for (int oz = -1; oz <= 1; oz += 2)
+    for (int oy = -1; oy <= 1; oy += 2)
+    for (int ox = -1; ox <= 1; ox += 2) {
+        int o[3] = { ox, oy, oz };
+        int ext[3];
+        for (int d = 0; d < 3; ++d) ext[d] = o[d] > 0 ? g->n[d] - g->src[d] : g->src[d];
+        if (ext[0] <= 0 || ext[1] <= 0 || ext[2] <= 0) continue;
+        for (int lz = 0; lz < ext[2]; ++lz)
+        for (int ly = 0; ly < ext[1]; ++ly)
+        for (int lx = 0; lx < ext[0]; ++lx) {
+            int l[3] = { lx, ly, lz };
+            int gi[3];
+            for (int d = 0; d < 3; ++d) gi[d] = o[d] > 0 ? g->src[d] + l[d] : g->src[d] - 1 - l[d];
+            int64_t idx = gi[0] + (int64_t)nx * (gi[1] + (int64_t)ny * gi[2]);
+            cellpos c;
+            cell_pos(g, gi[0], gi[1], gi[2], &c);
+            const int a = c.a;
+            const double norm = sqrt(c.ad[0] * c.ad[0] + c.ad[1] * c.ad[1] + c.ad[2] * c.ad[2]);
+            const double ds = g->dx * norm / c.ad[a];
+            double Nin = 0.0;
+            if (l[a] > 0) {
+                int b = (a + 1) % 3, cc = (a + 2) % 3;
+                double db = c.ad[b] / c.ad[a];
+                double dc = c.ad[cc] / c.ad[a];
+                double sw = 0.0, s = 0.0;
+                for (int mb = 0; mb <= 1; ++mb)
+                for (int mc = 0; mc <= 1; ++mc) {
+                    int ln[3];
+                    ln[a] = l[a] - 1;
+                    ln[b] = l[b] - mb;
+                    ln[cc] = l[cc] - mc;
+                    if (ln[b] < 0 || ln[cc] < 0) continue; /* across a source plane */
+                    int gn[3];
+                    for (int d = 0; d < 3; ++d) gn[d] = o[d] > 0 ? g->src[d] + ln[d] : g->src[d] - 1 - ln[d];
+                    int64_t nidx = gn[0] + (int64_t)nx * (gn[1] + (int64_t)ny * gn[2]);
+                    double w = (mb ? db : 1.0 - db) * (mc ? dc : 1.0 - dc);
+                    double T = Nc[nidx] + 0.5 * ds * nH[nidx] * x[nidx];
+                    if (g->weights == ORC_W_MELLEMA) w = w / fmax(TAU0_MELLEMA, g->sigma0 * T);
+                    s += w * T;
+                    sw += w;
+                }
+                Nin = s / sw;
+            }
+            Nc[idx] = Nin + 0.5 * ds * nH[idx] * x[idx];
+            tau_in[idx] = g->sigma0 * Nin;
+        }
+    }
+    free(Nc);
+    return 0;
+}
+
+static int raytrace_1d(const orc_desc* g, const double* nH, const double* x, double* tau_in)
+{
+    double N = 0.0;
+    for (int i = 0; i < g->n[0]; ++i) {
+        tau_in[i] = g->sigma0 * N;
+        N += nH[i] * x[i] * g->dx;
+    }
+    return 0;
+}
+
+int orc_raytrace_sc(const orc_desc* g, const double* nH, const double* x, double* tau_in)
+{
+    if (!g || !nH || !x || !tau_in) return -1;
+    if (g->geometry == ORC_GEOM_3D) return raytrace_sc_3d(g, nH, x, tau_in);
+    return raytrace_1d(g, nH, x, tau_in);
+}
+
+static int cmp_double(const void* a, const void* b)
+{
+    double da = *(const double*)a, db = *(const double*)b;
+    return (da > db) - (da < db);
+}
+
+/* Exact columns along straight rays from the source to the same entry points
+ * the short-characteristics tracer uses (the ray through the cell centre,
+ * stopped on the upstream face along the dominant axis): the segment is cut at
+ * every grid plane it crosses and each piece is charged n_H x of the cell that
+ * holds its midpoint.  Accuracy reference for the short characteristics only. */
+int orc_raytrace_lc(const orc_desc* g, const double* nH, const double* x, double* tau_in)
+{
+    if (!g || g->geometry != ORC_GEOM_3D) return -1;
+    const int nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+        int64_t idx = i + (int64_t)nx * (j + (int64_t)ny * k);
+        cellpos c;
+        cell_pos(g, i, j, k, &c);
+        if (c.l[c.a] == 0) { tau_in[idx] = 0.0; continue; }
+        /* entry point, octant-local, in cell units from the source */
+        double f = (c.ad[c.a] - 0.5) / c.ad[c.a];
+        double P[3] = { c.ad[0] * f, c.ad[1] * f, c.ad[2] * f };
+        int cap = 3 + (int)(P[0] + P[1] + P[2]) + 8;
+        double* ts = (double*)malloc(sizeof(double) * (size_t)cap);
+        int nt = 0;
+        ts[nt++] = 0.0;
+        for (int d = 0; d < 3; ++d)
+            for (int m = 1; m < P[d]; ++m) ts[nt++] = m / P[d];
+        ts[nt++] = 1.0;
+        qsort(ts, (size_t)nt, sizeof(double), cmp_double);
+        double len = g->dx * sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
+        double col = 0.0;
+        for (int q = 0; q + 1 < nt; ++q) {
+            double t0 = ts[q], t1 = ts[q + 1];
+            if (t1 <= t0) continue;
+            double tm = 0.5 * (t0 + t1);
+            int gn[3];
+            for (int d = 0; d < 3; ++d) {
+                int ld = (int)floor(tm * P[d]);
+                gn[d] = c.o[d] > 0 ? g->src[d] + ld : g->src[d] - 1 - ld;
+            }
+            int64_t nidx = gn[0] + (int64_t)nx * (gn[1] + (int64_t)ny * gn[2]);
+            col += nH[nidx] * x[nidx] * (t1 - t0) * len;
+        }
+        free(ts);
+        tau_in[idx] = g->sigma0 * col;
+    }
+    return 0;
+}
+
+/* -------------------------------------------------------------- microphysics */
+/* Rate coefficients (reading: pure hydrogen; the paper's heating/cooling
+ * models are in the papers it cites).  Each returns the value and its
+ * logarithmic derivative d ln f / dT. */
+static double alpha_rr(const orc_desc* g, double T, double* dlndT)
+{
+    if (g->recomb == ORC_ALPHA_CONST) { *dlndT = 0.0; return g->alpha_B; }
+    *dlndT = -0.7 / T;
+    return g->alpha_B * pow(T / 1e4, -0.7);
+}
+
+/* collisional ionisation of H (Cen 1992) */
+static double coll_ion(double T, double* dlndT)
+{
+    double q = 1.0 + sqrt(T / 1e5);
+    double dq = 0.5 / sqrt(T * 1e5);
+    *dlndT = 0.5 / T - dq / q + 157809.1 / (T * T);
+    return 5.85e-11 * sqrt(T) / q * exp(-157809.1 / T);
+}
+
+/* cooling coefficients [erg cm^3 / s] (Cen 1992): recombination, free-free
+ * (g_ff = 1.3), collisional excitation, collisional ionisation */
+static void cooling_coeffs(const orc_desc* g, double T, double* cii, double* dcii,
+                           double* cin, double* dcin)
+{
+    double q = 1.0 + sqrt(T / 1e5);
+    double dq = 0.5 / sqrt(T * 1e5);
+    double t6 = pow(T / 1e6, 0.7);
+    double crec = 8.70e-27 * sqrt(T) * pow(T / 1e3, -0.2) / (1.0 + t6);
+    double dlrec = 0.5 / T - 0.2 / T - 0.7 * t6 / (T * (1.0 + t6));
+    double cff = 1.42e-27 * 1.3 * sqrt(T);
+    double dlff = 0.5 / T;
+    double cce = 7.50e-19 / q * exp(-118348.0 / T);
+    double dlce = -dq / q + 118348.0 / (T * T);
+    double cci = 0.0, dlci = 0.0;
+    if (g->collisional) {
+        cci = 1.27e-21 * sqrt(T) / q * exp(-157809.1 / T);
+        dlci = 0.5 / T - dq / q + 157809.1 / (T * T);
+    }
+    *cii = crec + cff;                       /* multiplies n_e n_HII */
+    *dcii = crec * dlrec + cff * dlff;
+    *cin = cce + cci;                        /* multiplies n_e n_HI  */
+    *dcin = cce * dlce + cci * dlci;
+}
+
+typedef struct {
+    double nH, geo, ell, tau_in;
+    double Pin, Hin; /* table values at tau_in */
+} cellenv;
+
+/* photon absorption per unit volume A(x) and heating per unit volume G(x) in a
+ * cell whose neutral fraction is x, with the entering column tau_in frozen
+ * (photon-conserving form: what enters minus what leaves). */
+static void photo(const orc_desc* g, const cellenv* c, double x, double* A, double* dA,
+                  double* G, double* dG)
+{
+    const double k = c->nH * g->sigma0 * c->ell;
+    const double u = k * x;
+    if (g->spectrum == ORC_SPEC_MONO) {
+        const double Fin = g->Q * exp(-c->tau_in);
+        *A = c->geo * Fin * (-expm1(-u));
+        *dA = c->geo * Fin * exp(-u) * k;
+        *G = *A * g->e_excess;
+        *dG = *dA * g->e_excess;
+        return;
+    }
+    if (u < THIN_CELL) {
+        double dP, dH;
+        orc_table_eval(g->table, 0, c->tau_in + 0.5 * u, &dP);
+        orc_table_eval(g->table, 1, c->tau_in + 0.5 * u, &dH);
+        *A = c->geo * (-dP) * u;
+        *dA = c->geo * (-dP) * k;
+        *G = c->geo * (-dH) * u;
+        *dG = c->geo * (-dH) * k;
+    } else {
+        double dP, dH;
+        double Pout = orc_table_eval(g->table, 0, c->tau_in + u, &dP);
+        double Hout = orc_table_eval(g->table, 1, c->tau_in + u, &dH);
+        *A = c->geo * (c->Pin - Pout);
+        *dA = c->geo * (-dP) * k;
+        *G = c->geo * (c->Hin - Hout);
+        *dG = c->geo * (-dH) * k;
+    }
+}
+
+/* Right-hand side of eq.(2) written for the neutral fraction x = 1 - y and the
+ * internal energy E, with its Jacobian.  T = 2E / (3 k_B n_H (2 - x)) for pure H
+ * with gamma = 5/3 (Sect. 2: E_int = p/(gamma-1)); floor T_FLOOR. */
+typedef struct {
+    double fx, fE;
+    double jxx, jxE, jEx, jEE;
+    double A, rec, T;
+} rhsval;
+
+static void rhs(const orc_desc* g, const cellenv* c, double x, double E, rhsval* r)
+{
+    const double n = c->nH;
+    double T, dTdx = 0.0, dTdE = 0.0;
+    if (g->thermal == ORC_T_FIXED) {
+        T = g->T_fixed;
+    } else {
+        T = 2.0 * E / (3.0 * KB * n * (2.0 - x));
+        if (T > T_FLOOR) {
+            dTdx = T / (2.0 - x);
+            dTdE = T / E;
+        } else {
+            T = T_FLOOR;
+        }
+    }
+    double A, dA, G, dG;
+    photo(g, c, x, &A, &dA, &G, &dG);
+    double dla, alpha = alpha_rr(g, T, &dla);
+    double aci = 0.0, dlci = 0.0;
+    if (g->collisional) aci = coll_ion(T, &dlci);
+    const double y = 1.0 - x;
+    r->A = A;
+    r->rec = alpha * n * n * y * y;
+    r->T = T;
+    /* x-equation: photoionisation, collisional ionisation, recombination */
+    r->fx = -A / n - aci * n * x * y + alpha * n * y * y;
+    double dfx_dT = -aci * dlci * n * x * y + alpha * dla * n * y * y;
+    r->jxx = -dA / n - aci * n * (1.0 - 2.0 * x) - 2.0 * alpha * n * y + dfx_dT * dTdx;
+    r->jxE = dfx_dT * dTdE;
+    if (g->thermal == ORC_T_FIXED) {
+        r->fE = 0.0;
+        r->jEx = r->jEE = 0.0;
+        return;
+    }
+    double cii = 0.0, dcii = 0.0, cin = 0.0, dcin = 0.0;
+    if (g->cooling) cooling_coeffs(g, T, &cii, &dcii, &cin, &dcin);
+    double lam = n * n * (y * y * cii + x * y * cin);
+    double dlam_dx = n * n * (-2.0 * y * cii + (1.0 - 2.0 * x) * cin);
+    double dlam_dT = n * n * (y * y * dcii + x * y * dcin);
+    r->fE = G - lam;
+    r->jEx = dG - dlam_dx - dlam_dT * dTdx;
+    r->jEE = -dlam_dT * dTdE;
+}
+
+static double e_floor(const orc_desc* g, double n, double x)
+{
+    (void)g;
+    return 1.5 * n * (2.0 - x) * KB * T_FLOOR;
+}
+
+static void stage_solve(const orc_desc* g, const cellenv* c, double xb, double Eb, double hg,
+                        double* xio, double* Eio);
+
+/* Scalar x-solve of the stage equation at a fixed temperature T (the fallback
+ * path of the T-evolving stage solve): bracketed Newton on [0, 1], as in the
+ * T-fixed case. */
+static double x_at_fixed_T(const orc_desc* g, const cellenv* c, double xb, double hg, double T)
+{
+    orc_desc gf = *g;
+    gf.thermal = ORC_T_FIXED;
+    gf.T_fixed = T;
+    double x = fmin(fmax(xb, 0.0), 1.0), E = 0.0;
+    stage_solve(&gf, c, xb, 0.0, hg, &x, &E);
+    return x;
+}
+
+/* energy residual of the stage equation with T held: E(x*(T), T) - Eb - hg fE */
+static double t_residual(const orc_desc* g, const cellenv* c, double xb, double Eb, double hg,
+                         double T, double* xs)
+{
+    double x = x_at_fixed_T(g, c, xb, hg, T);
+    double E = 1.5 * c->nH * (2.0 - x) * KB * T;
+    rhsval r;
+    rhs(g, c, x, E, &r);
+    *xs = x;
+    return E - Eb - hg * r.fE;
+}
+
+/* Solve the implicit stage equation Y = base + hg f(Y) by Newton's method.
+ * T fixed: scalar in x, safeguarded by the bracket [0,1] (the residual is
+ * increasing in x); a root outside [0,1] is returned clamped.  T evolving:
+ * 2x2 Newton with x clamped to [0,1] and E to the temperature floor. */
+static void stage_solve(const orc_desc* g, const cellenv* c, double xb, double Eb, double hg,
+                        double* xio, double* Eio)
+{
+    double x = *xio, E = *Eio;
+    if (x < 0.0) x = 0.0;
+    if (x > 1.0) x = 1.0;
+    rhsval r;
+    if (g->thermal == ORC_T_FIXED) {
+        double lo = 0.0, hi = 1.0, eprev = INFINITY;
+        for (int it = 0; it < NEWTON_MAXIT; ++it) {
+            rhs(g, c, x, E, &r);
+            double G = x - xb - hg * r.fx;
+            double dG = 1.0 - hg * r.jxx;
+            if (G > 0) hi = x; else lo = x;
+            double xn = x - G / dG;
+            if (xn <= 0.0 && lo == 0.0) {
+                rhs(g, c, 0.0, E, &r);
+                if (0.0 - xb - hg * r.fx >= 0.0) { x = 0.0; break; }
+            }
+            if (xn >= 1.0 && hi == 1.0) {
+                rhs(g, c, 1.0, E, &r);
+                if (1.0 - xb - hg * r.fx <= 0.0) { x = 1.0; break; }
+            }
+            if (!(xn >= lo && xn <= hi)) xn = 0.5 * (lo + hi);
+            double dx = xn - x;
+            x = xn;
+            /* converged; or stalled at the rounding floor of the residual (the
+             * correction stopped shrinking while already small) */
+            double e = fabs(dx) / fmax(x, 1e-12);
+            if (e <= NEWTON_RTOL || (e >= eprev && e <= NEWTON_STALL)) break;
+            eprev = e;
+            if (it == NEWTON_MAXIT - 1) ++g_newton_fail;
+        }
+        *xio = x;
+        return;
+    }
+    /* T evolving, first: Newton on (x, E) with x projected onto [0, 1] and E
+     * onto the temperature floor, at most NEWTON_2D_MAXIT iterations. */
+    double Emin = e_floor(g, c->nH, x);
+    if (E < Emin) E = Emin;
+    double eprev = INFINITY;
+    for (int it = 0; it < NEWTON_2D_MAXIT; ++it) {
+        rhs(g, c, x, E, &r);
+        double Rx = x - xb - hg * r.fx;
+        double RE = E - Eb - hg * r.fE;
+        double a11 = 1.0 - hg * r.jxx, a12 = -hg * r.jxE;
+        double a21 = -hg * r.jEx, a22 = 1.0 - hg * r.jEE;
+        double det = a11 * a22 - a12 * a21;
+        double xn = x - (a22 * Rx - a12 * RE) / det;
+        double En = E - (a11 * RE - a21 * Rx) / det;
+        if (!(xn >= 0.0)) xn = 0.0;   /* also catches NaN */
+        if (xn > 1.0) xn = 1.0;
+        double Emn = e_floor(g, c->nH, xn);
+        if (!(En >= Emn)) En = Emn;
+        double e = fmax(fabs(xn - x) / fmax(xn, 1e-12), fabs(En - E) / En);
+        x = xn;
+        E = En;
+        /* converged; or stalled at the rounding floor of the residual */
+        if (e <= NEWTON_RTOL || (e >= eprev && e <= NEWTON_STALL)) {
+            *xio = x;
+            *Eio = E;
+            return;
+        }
+        eprev = e;
+    }
+    /* Fallback (Newton did not settle): nested bracketed solve in (x, T).
+     * For a fixed T the x-equation is the scalar, bracketed problem of the
+     * T-fixed case; the energy residual g(T) = E(x*(T), T) - Eb - hg fE is then
+     * bracketed in ln T from the floor upwards and solved by the Illinois
+     * variant of regula falsi. */
+    {
+        double xs;
+        double la = log(T_FLOOR);
+        double ga = t_residual(g, c, xb, Eb, hg, T_FLOOR, &xs);
+        if (ga >= 0.0) {
+            *xio = xs;
+            *Eio = 1.5 * c->nH * (2.0 - xs) * KB * T_FLOOR;
+            return;
+        }
+        double Tg = fmax(2.0 * E / (3.0 * KB * c->nH * (2.0 - x)), 2.0 * T_FLOOR);
+        double lb = log(Tg), gb = t_residual(g, c, xb, Eb, hg, Tg, &xs);
+        for (int k = 0; k < 60 && gb < 0.0; ++k) {
+            la = lb;
+            ga = gb;
+            lb += 1.0;
+            gb = t_residual(g, c, xb, Eb, hg, exp(lb), &xs);
+        }
+        double lc = lb;
+        int side = 0;
+        for (int it = 0; it < FALLBACK_MAXIT; ++it) {
+            lc = (la * gb - lb * ga) / (gb - ga);
+            double gc = t_residual(g, c, xb, Eb, hg, exp(lc), &xs);
+            if (gc == 0.0 || fabs(lb - la) <= NEWTON_RTOL * fabs(lc)) break;
+            if ((gc > 0.0) == (gb > 0.0)) {
+                lb = lc;
+                gb = gc;
+                if (side == -1) ga *= 0.5;
+                side = -1;
+            } else {
+                la = lc;
+                ga = gc;
+                if (side == 1) gb *= 0.5;
+                side = 1;
+            }
+            if (it == FALLBACK_MAXIT - 1) ++g_newton_fail;
+        }
+        double T = exp(lc);
+        t_residual(g, c, xb, Eb, hg, T, &xs);
+        *xio = xs;
+        *Eio = 1.5 * c->nH * (2.0 - xs) * KB * T;
+    }
+}
+
+static void make_env(const orc_desc* g, double nH, double geo, double ell, double tau_in, cellenv* c)
+{
+    c->nH = nH;
+    c->geo = geo;
+    c->ell = ell;
+    c->tau_in = tau_in;
+    c->Pin = c->Hin = 0.0;
+    if (g->spectrum == ORC_SPEC_TABLE) {
+        c->Pin = orc_table_eval(g->table, 0, tau_in, NULL);
+        c->Hin = orc_table_eval(g->table, 1, tau_in, NULL);
+    }
+}
+
+/* Micro-integration M(x0, E0; tau_in, h): eq.(2) over h with the entering
+ * column frozen and the cell's own optical depth following x (reading).  The
+ * paper integrates with CVODE (backward differences, Newton); this oracle uses
+ * a fixed structure instead (reading): n_sub equal substeps of the two-stage,
+ * L-stable, stiffly accurate SDIRK method with gamma = 1 - 1/sqrt(2). */
+static void micro(const orc_desc* g, const cellenv* c, double x0, double E0, double h,
+                  double* x1, double* E1)
+{
+    double x = x0, E = E0;
+    if (h > 0.0) {
+        const double gam = 1.0 - sqrt(0.5);
+        const double cst = (1.0 - gam) / gam;
+        const int ns = g->n_sub > 0 ? g->n_sub : 1;
+        const double hs = h / ns;
+        for (int s = 0; s < ns; ++s) {
+            double X1 = x, F1 = E;
+            stage_solve(g, c, x, E, gam * hs, &X1, &F1);
+            double xb = x + cst * (X1 - x);
+            double Eb = E + cst * (F1 - E);
+            double X2 = X1, F2 = F1;
+            stage_solve(g, c, xb, Eb, gam * hs, &X2, &F2);
+            x = X2;
+            E = F2;
+        }
+    }
+    *x1 = x;
+    *E1 = E;
+}
+
+int orc_micro_cell(const orc_desc* g, double nH, double geo, double ell, double tau_in,
+                   double x0, double E0, double h, double* x1, double* E1)
+{
+    cellenv c;
+    make_env(g, nH, geo, ell, tau_in, &c);
+    double e;
+    micro(g, &c, x0, E0, h, x1, E1 ? E1 : &e);
+    return 0;
+}
+
+int orc_rhs_cell(const orc_desc* g, double nH, double geo, double ell, double tau_in,
+                 double x, double E, double* fx, double* fE)
+{
+    cellenv c;
+    make_env(g, nH, geo, ell, tau_in, &c);
+    rhsval r;
+    rhs(g, &c, x, E, &r);
+    *fx = r.fx;
+    if (fE) *fE = r.fE;
+    return 0;
+}
+
+/* Per-cell timestep limit of eq.(4) with the factors of Table 1, evaluated at
+ * the state and columns of t_n: K1 t_rec, K2 E/|dE/dt|, K3 max(0.05, 1-y)/|dy/dt|,
+ * K4/|dy/dt|.  A criterion with K = inf, or a zero rate, does not limit. */
+static double cell_dt(const orc_desc* g, const cellenv* c, double x, double E)
+{
+    rhsval r;
+    rhs(g, c, x, E, &r);
+    double dt = INFINITY;
+    const double ydot = fabs(r.fx);
+    if (isfinite(g->K[0])) {
+        double dla;
+        double alpha = alpha_rr(g, r.T, &dla);
+        dt = fmin(dt, g->K[0] / (alpha * c->nH));
+    }
+    if (isfinite(g->K[1]) && g->thermal == ORC_T_EVOLVE && r.fE != 0.0)
+        dt = fmin(dt, g->K[1] * E / fabs(r.fE));
+    if (isfinite(g->K[2]) && ydot > 0.0) dt = fmin(dt, g->K[2] * fmax(0.05, x) / ydot);
+    if (isfinite(g->K[3]) && ydot > 0.0) dt = fmin(dt, g->K[3] / ydot);
+    return dt;
+}
+
+double orc_cell_dt(const orc_desc* g, double nH, double geo, double ell, double tau_in,
+                   double x, double E)
+{
+    cellenv c;
+    make_env(g, nH, geo, ell, tau_in, &c);
+    return cell_dt(g, &c, x, E);
+}
+
+static void env_of(const orc_desc* g, int64_t i, double* geo, double* ell)
+{
+    orc_cell_env(g, i, geo, ell);
+}
+
+int orc_timestep(const orc_desc* g, const double* nH, const double* x, const double* E,
+                 const double* tau, double* dt_out)
+{
+    const int64_t N = ncells(g);
+    double dt = INFINITY;
+    for (int64_t i = 0; i < N; ++i) {
+        double geo, ell;
+        env_of(g, i, &geo, &ell);
+        cellenv c;
+        make_env(g, nH[i], geo, ell, tau[i], &c);
+        dt = fmin(dt, cell_dt(g, &c, x[i], E ? E[i] : 0.0));
+    }
+    *dt_out = dt;
+    return 0;
+}
+
+int orc_chem(const orc_desc* g, const double* nH, const double* x0, const double* E0,
+             const double* tau, double h, double* x1, double* E1)
+{
+    const int64_t N = ncells(g);
+    for (int64_t i = 0; i < N; ++i) {
+        double geo, ell;
+        env_of(g, i, &geo, &ell);
+        cellenv c;
+        make_env(g, nH[i], geo, ell, tau[i], &c);
+        double xe, Ee;
+        micro(g, &c, x0[i], E0 ? E0[i] : 0.0, h, &xe, &Ee);
+        x1[i] = xe;
+        if (E1) E1[i] = Ee;
+    }
+    return 0;
+}
+
+/* One step of algorithm 3 (algo = 3) or algorithm 2 (algo = 2), Sect. 2.2.
+ * On entry tau holds the columns of the current state (from the raytrace that
+ * ended the previous step, or the initial raytrace); on exit it holds the
+ * columns of the new state, ready for the next step.
+ *   1. dt = min over cells of eq.(4), capped at t_end - t; a remainder below
+ *      1e-12 t_end is absorbed into this step (reading).
+ *   2. A3: micro-integrate over dt/2 on the columns of t_n ("half step");
+ *      raytrace the half-step neutral fractions; micro-integrate over dt from
+ *      the state at t_n on those time-centred columns.
+ *      A2: micro-integrate over dt on the columns of t_n.
+ *   3. raytrace the new state. */
+int orc_step(const orc_desc* g, const double* nH, double* x, double* E, double* tau,
+             double* t, double t_end, int algo, double* dt_out)
+{
+    const int64_t N = ncells(g);
+    double dt;
+    orc_timestep(g, nH, x, E, tau, &dt);
+    double rem = t_end - *t;
+    if (!(rem > 0.0)) { if (dt_out) *dt_out = 0.0; return 1; }
+    if (dt > rem) dt = rem;
+    if (rem - dt <= 1e-12 * t_end) dt = rem;
+    if (algo == 3) {
+        double* xs = (double*)malloc(sizeof(double) * (size_t)N);
+        double* Es = E ? (double*)malloc(sizeof(double) * (size_t)N) : NULL;
+        double* ts = (double*)malloc(sizeof(double) * (size_t)N);
+        orc_chem(g, nH, x, E, tau, 0.5 * dt, xs, Es);
+        orc_raytrace_sc(g, nH, xs, ts);
+        orc_chem(g, nH, x, E, ts, dt, x, E);
+        free(xs);
+        free(Es);
+        free(ts);
+    } else {
+        orc_chem(g, nH, x, E, tau, dt, x, E);
+    }
+    orc_raytrace_sc(g, nH, x, tau);
+    *t = (rem - dt <= 0.0) ? t_end : *t + dt;
+    if (dt_out) *dt_out = dt;
+    return 0;
+}
+
+/* Ionised volume, ion count and volume-equivalent front radius (the Stromgren
+ * test of Sect. 3.2 compares it with R_S [1 - exp(-t/t_rec)]^{1/3}), plus the
+ * instantaneous photoionisation and recombination rates summed over the grid. */
+int orc_diagnostics(const orc_desc* g, const double* nH, const double* x, const double* E,
+                    const double* tau, orc_diag* out)
+{
+    const int64_t N = ncells(g);
+    double nion = 0, vion = 0, pr = 0, rr = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        double geo, ell, vol;
+        env_of(g, i, &geo, &ell);
+        if (g->geometry == ORC_GEOM_3D) vol = g->dx * g->dx * g->dx;
+        else if (g->geometry == ORC_GEOM_SPHERICAL_1D) vol = 1.0 / geo;
+        else vol = g->dx;
+        cellenv c;
+        make_env(g, nH[i], geo, ell, tau ? tau[i] : 0.0, &c);
+        rhsval r;
+        rhs(g, &c, x[i], E ? E[i] : 0.0, &r);
+        nion += nH[i] * (1.0 - x[i]) * vol;
+        vion += (1.0 - x[i]) * vol;
+        pr += r.A * vol;
+        rr += r.rec * vol;
+    }
+    out->n_ion = nion;
+    out->v_ion = vion;
+    out->photo_rate = pr;
+    out->recomb_rate = rr;
+    out->newton_fail = g_newton_fail;
+    if (g->geometry == ORC_GEOM_3D) {
+        int noct = 0;
+        for (int o = 0; o < 8; ++o) {
+            int ok = 1;
+            for (int d = 0; d < 3; ++d) {
+                int ext = ((o >> d) & 1) ? g->n[d] - g->src[d] : g->src[d];
+                if (ext <= 0) ok = 0;
+            }
+            noct += ok;
+        }
+        out->r_ion = cbrt(3.0 * vion * 8.0 / (4.0 * M_PI * noct));
+    } else if (g->geometry == ORC_GEOM_SPHERICAL_1D) {
+        out->r_ion = cbrt(3.0 * vion / (4.0 * M_PI));
+    } else {
+        out->r_ion = vion;
+    }
+    return 0;
+}
+
+/* Front locator of eq.(5): the zero-offset index i in [1, n-2] with the largest
+ * centred difference of the ion fraction y = 1 - x (uniform cells). */
+int orc_front_index_1d(int n, const double* x)
+{
+    int best = -1;
+    double bv = -INFINITY;
+    for (int i = 1; i <= n - 2; ++i) {
+        double grad = ((1.0 - x[i + 1]) - (1.0 - x[i - 1])) / 2.0;
+        /* y decreases outwards; the steepest front has the most negative
+         * gradient, i.e. the largest |dy/dr| */
+        double v = -grad;
+        if (v > bv) { bv = v; best = i; }
+    }
+    return best;
+}
