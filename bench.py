@@ -1,0 +1,211 @@
+#!/usr/bin/env python
+"""Throughput of the A3 photoionisation source-term step on one MI355X.
+
+Workload: the 256^3 clumpy medium -- lognormal density (sigma_ln = 1, power
+spectrum k^-11/3, seed 1201), mean n_H = 5 cm^-3, central 1e5 K blackbody
+source of 5e48 photons/s with rates tabulated against optical depth, evolving
+temperature, timestep criterion dt02 -- advanced from a neutral start to
+0.1 t_rec before timing.  One "step" is one full second-order step
+(algorithm 3): timestep reduction, predictor micro-physics, raytrace of the
+half-step state, corrector micro-physics, raytrace of the new state.
+
+Prints ONE JSON line: cell-updates/s (whole job), ms per step, the roofline
+object of the dominant kernel (measured live with HIP events on the stream the
+kernels run on) and the FP64 oracle's rate on a bounded CPU sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def word_bytes(precision: str) -> int:
+    return 8 if precision == "fp64" else 4
+
+
+def dtype_name(precision: str) -> str:
+    return {"fp64": "f64", "fp32": "f32", "mixed": "f32+f64"}[precision]
+
+
+def cpu_baseline(n: int, budget_s: float):
+    """The FP64 oracle, single thread, on a coarse copy of the same workload
+    (same recipe at n^3), advanced to 0.1 t_rec untimed, then timed for at
+    least budget_s seconds of whole steps."""
+    import numpy as np
+
+    import oracle
+    from paper_1201_5651_amd import synth
+
+    oracle.build()
+    spec = synth.cfg3(n=n)
+    pb = oracle.Problem.from_spec(spec)
+    nH = synth.density(spec)
+    st = pb.initial_state(nH, T0=spec.T0)
+    t_pre = 0.1 * spec.t_rec
+    pre = 0
+    while st["t"] < t_pre and pre < 400:
+        pb.step(st, t_pre)
+        pre += 1
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        pb.step(st, 1e30)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 200:
+            break
+    return {
+        "value": spec.ncells * steps / el,
+        "unit": "cell-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"FP64 oracle, 1 thread, {steps} A3 steps of the same workload recipe at {n}^3 "
+                  f"(box 2.4 R_S, lognormal seed 1201) after {pre} untimed steps to 0.1 t_rec; "
+                  f"{el:.1f} s",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "mixed"])
+    ap.add_argument("--pre-trec", type=float, default=0.1,
+                    help="untimed evolution before timing, in units of t_rec")
+    ap.add_argument("--pre-steps-max", type=int, default=400)
+    ap.add_argument("--phase-steps", type=int, default=3,
+                    help="extra steps timed phase by phase after the timed region")
+    ap.add_argument("--cpu-sample-n", type=int, default=32)
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1201_5651_amd import binding, synth
+
+    torch.cuda.set_device(0)
+    spec = synth.cfg3(n=args.n)
+    nH = synth.density(spec)
+    g = binding.Grid(spec, precision=args.precision)
+    g.load(nH, 1.0, T0=spec.T0)
+    t_end = 1e30   # open-ended: every step is a full step
+
+    # untimed pre-evolution to the benchmark state
+    t_pre = args.pre_trec * spec.t_rec
+    pre = 0
+    tick = time.time()
+    while pre < args.pre_steps_max:
+        burst = min(25, args.pre_steps_max - pre)
+        for _ in range(burst):
+            g.step_o2(t_pre)
+        t, n, _ = g.state()
+        pre = n
+        if time.time() - tick > 20:
+            print(f"# pre-evolution: {pre} steps, t = {t / spec.t_rec:.4f} t_rec", file=sys.stderr,
+                  flush=True)
+            tick = time.time()
+        if t >= t_pre:
+            break
+    t_start, n_start, _ = g.state()
+
+    for _ in range(args.warmup):
+        g.step_o2(t_end)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        g.step_o2(t_end)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ms_step = ms / args.steps
+    value = spec.ncells * args.steps / (ms * 1e-3)
+
+    # phase-by-phase timing of the same kernels (same stream, HIP events)
+    phases = {"timestep": 0.0, "chem_predictor": 0.0, "raytrace_half": 0.0,
+              "chem_corrector": 0.0, "raytrace": 0.0}
+    for _ in range(args.phase_steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        ev[0].record(stream)
+        g.timestep(t_end)
+        ev[1].record(stream)
+        g.chem_step(0.5, binding.PI_BUF_N, binding.PI_BUF_N, binding.PI_BUF_HALF, use_device_dt=True)
+        ev[2].record(stream)
+        g.raytrace(binding.PI_BUF_HALF, binding.PI_BUF_HALF)
+        ev[3].record(stream)
+        g.chem_step(1.0, binding.PI_BUF_HALF, binding.PI_BUF_N, binding.PI_BUF_N, use_device_dt=True)
+        ev[4].record(stream)
+        g.raytrace(binding.PI_BUF_N, binding.PI_BUF_N)
+        ev[5].record(stream)
+        torch.cuda.synchronize()
+        for i, k in enumerate(phases):
+            phases[k] += ev[i].elapsed_time(ev[i + 1]) / args.phase_steps
+    diag = g.diagnostics()
+    t_now, n_now, _ = g.state()
+
+    W = word_bytes(args.precision)
+    N = spec.ncells
+    # algorithmic bytes per launch: chemistry reads n_H, x, E, tau and writes
+    # x, E (6 words per cell); a raytrace reads n_H, x and writes tau (3 words);
+    # the timestep reads n_H, x, E, tau (4 words)
+    alg = {"chem_predictor": 6 * W * N, "chem_corrector": 6 * W * N,
+           "raytrace_half": 3 * W * N, "raytrace": 3 * W * N, "timestep": 4 * W * N}
+    dom = max(phases, key=phases.get)
+    achieved = alg[dom] / (phases[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": None,
+                "phase_ms": {k: round(v, 4) for k, v in phases.items()}}
+
+    out = {
+        "metric": "cell-updates/s per raytrace+chemistry step at 256^3",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype_name(args.precision),
+        "data": "synthetic",
+        "config": {
+            "workload": f"cfg3 clumpy medium {args.n}^3: lognormal n_H (sigma_ln 1, k^-11/3, seed "
+                        f"1201), mean 5 cm^-3, central 1e5 K blackbody Q=5e48/s, 64-node rate "
+                        f"table, T evolving, A3-dt02, pre-evolved to {args.pre_trec} t_rec",
+            "n": args.n, "precision": args.precision, "pre_steps": int(n_start),
+            "t_start_trec": t_start / spec.t_rec, "t_end_trec": t_now / spec.t_rec,
+            "r_ion_cells": diag["r_ion"] / spec.dx, "n_sub": spec.n_sub,
+        },
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, args.cpu_budget)
+    g.close()
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

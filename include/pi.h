@@ -1,0 +1,179 @@
+/*
+ * pi.h -- C ABI of the MI355X photoionisation source-term library.
+ *
+ * The library advances non-equilibrium hydrogen photoionisation on a uniform
+ * 3D Cartesian grid around a point source by the second-order explicit,
+ * operator-split step of Mackey, "Accuracy and efficiency of raytracing
+ * photoionisation algorithms" (A&A 2012), algorithm 3 of Sect. 2.2:
+ * raytrace at t_n (which also sets the timestep, eq. 4 and Table 1),
+ * micro-physics over dt/2 on those columns, raytrace of the half-step state,
+ * micro-physics over dt from t_n on the time-centred columns.  The paper's
+ * statement of the problem gives the module two interfaces, one for the
+ * timestep and one for the micro-physical update (Sect. 2.1); pi_timestep and
+ * pi_chem_step are those two, pi_raytrace is the short-characteristics tracer
+ * they depend on (Sect. 2, Sect. 5), and pi_step_o2 composes them.
+ *
+ * Conventions
+ *  - Units are CGS.  Fields are structure-of-arrays of nx*ny*nz cells with x
+ *    varying fastest: cell (i,j,k) is element i + nx*(j + ny*k).
+ *  - Field pointers are DEVICE pointers owned by the caller (e.g. torch
+ *    tensors); they must stay valid until pi_grid_destroy.  Element type is
+ *    double for PI_FP64 and float for PI_FP32 / PI_MIXED.
+ *  - Every call that takes a stream enqueues asynchronous work on that HIP
+ *    stream (hipStream_t passed as void*; NULL = the null stream) and returns
+ *    without waiting, except the calls documented as synchronising.
+ *  - Every call returns a pi_status; nothing throws across the ABI.  On error
+ *    pi_last_error() returns a message (thread-local, valid until the next call
+ *    on the same thread).
+ */
+#ifndef PI_H
+#define PI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PI_OK = 0,
+    PI_EINVAL = -1,      /* invalid argument or descriptor                    */
+    PI_ENOMEM = -2,      /* device allocation failed                          */
+    PI_EDEVICE = -3,     /* HIP runtime error                                 */
+    PI_ENAN = -5         /* a non-finite value was found in the grid's state  */
+} pi_status;
+
+typedef enum { PI_FP64 = 0, PI_FP32 = 1, PI_MIXED = 2 } pi_precision;
+enum { PI_SPEC_MONO = 0, PI_SPEC_TABLE = 1 };
+enum { PI_T_FIXED = 0, PI_T_EVOLVE = 1 };
+enum { PI_ALPHA_CONST = 0, PI_ALPHA_POWER = 1 };
+enum { PI_W_GEOMETRIC = 0, PI_W_MELLEMA = 1 };
+/* which state / column buffer an operation reads or writes */
+enum { PI_BUF_N = 0, PI_BUF_HALF = 1 };
+/* number of FP64 diagnostics returned by pi_diagnostics */
+#define PI_NDIAG 8
+#define PI_NTAB 64
+
+/* Problem description (copied by pi_grid_create). */
+typedef struct {
+    int32_t n[3];             /* cells per axis, each >= 1                            */
+    int32_t src[3];           /* source vertex, 0 <= src[d] <= n[d] (Sect. 5: the     */
+                              /* source sits on the nearest cell vertex)              */
+    double  dx;               /* cell size [cm], > 0                                  */
+    double  Q;                /* ionising photons per second, >= 0                    */
+    double  sigma0;           /* photoionisation cross-section at 13.6 eV [cm^2] > 0  */
+    int32_t spectrum;         /* PI_SPEC_MONO, or PI_SPEC_TABLE: blackbody of T_bb    */
+                              /* with rates tabulated against optical depth (Sect. 2) */
+    double  e_excess;         /* MONO: heating per photoionisation [erg], >= 0        */
+    double  T_bb;             /* TABLE: blackbody temperature [K], > 0                */
+    int32_t thermal;          /* PI_T_FIXED (T = T_fixed) or PI_T_EVOLVE (eq. 2 for E)*/
+    double  T_fixed;          /* [K]                                                  */
+    int32_t recomb;           /* PI_ALPHA_CONST: alpha_B; PI_ALPHA_POWER:             */
+                              /* alpha_B (T / 1e4 K)^-0.7                             */
+    double  alpha_B;          /* case-B coefficient [cm^3/s], >= 0                    */
+    int32_t collisional;      /* 1: collisional ionisation rate and its cooling       */
+    int32_t cooling;          /* 1: radiative cooling (PI_T_EVOLVE only)              */
+    int32_t weights;          /* PI_W_MELLEMA (default) or PI_W_GEOMETRIC             */
+    int32_t source_cell_rule; /* 1: each octant's corner cell takes Q/8 (default)     */
+    int32_t n_sub;            /* micro-integration substeps, 1..64                    */
+    double  K[4];             /* eq. (4) factors K1..K4; +inf disables a criterion    */
+                              /* (dt02 of Table 1: {inf, inf, inf, 0.25})             */
+    int32_t precision;        /* pi_precision                                         */
+} pi_grid_desc;
+
+/* Caller-owned device fields (see Conventions).  E and E_half may be NULL when
+ * thermal == PI_T_FIXED.  x_half / E_half / tau_half hold the half-step state
+ * and its columns. */
+typedef struct {
+    void* nH;        /* hydrogen number density [cm^-3], > 0                  */
+    void* x;         /* neutral fraction 1 - y in [0, 1] (Sect. 2.1)          */
+    void* E;         /* internal energy density [erg cm^-3]                   */
+    void* tau;       /* threshold optical depth from the source to each       */
+                     /* cell's entry face, for (x, E)                         */
+    void* x_half;
+    void* E_half;
+    void* tau_half;
+} pi_fields;
+
+typedef struct pi_grid pi_grid;
+
+/* Validate the descriptor (n >= 1, 0 <= src <= n, dx > 0, Q >= 0, sigma0 > 0,
+ * n_sub in 1..64, K >= 0, known enums), build the rate table (TABLE mode), upload
+ * the constants and bind the fields.  Allocates the grid's small private device
+ * buffers (reduction partials, timestep scalars, tile schedule, table).
+ * Returns PI_EINVAL, PI_ENOMEM or PI_EDEVICE on failure (nothing is leaked). */
+pi_status pi_grid_create(const pi_grid_desc* desc, const pi_fields* fields, pi_grid** out);
+
+/* Free the grid's private buffers (synchronises the device first).  The
+ * caller's fields are not touched.  NULL is accepted. */
+pi_status pi_grid_destroy(pi_grid* grid);
+
+/* Short-characteristics raytrace (Sect. 2; Sect. 5): columns tau of the
+ * neutral fractions of state `state` (PI_BUF_N: x, PI_BUF_HALF: x_half) into
+ * `tau_buf` (PI_BUF_N: tau, PI_BUF_HALF: tau_half).  Octants around the
+ * source vertex are traced independently in tile-wavefront order. */
+pi_status pi_raytrace(pi_grid* grid, int state, int tau_buf, void* stream);
+
+/* Micro-physics update (eq. 2 for the neutral fraction and, with PI_T_EVOLVE,
+ * the internal energy) of every cell from state `from_state` over an interval
+ * h with the entering columns `tau_buf` frozen, written to `to_state`
+ * (from == to updates in place).  h = h_value seconds when use_device_dt == 0,
+ * else h = h_value * (the timestep last computed by pi_timestep/pi_step_o2,
+ * held on the device). */
+pi_status pi_chem_step(pi_grid* grid, int use_device_dt, double h_value, int tau_buf,
+                       int from_state, int to_state, void* stream);
+
+/* Timestep (eq. 4 with the grid's K1..K4): min over cells of the limit
+ * evaluated at state PI_BUF_N with columns tau, reduced in FP64, capped at
+ * t_end - t (a remainder below 1e-12 t_end is absorbed).  The result stays on
+ * the device for pi_chem_step / pi_step_o2; pi_grid_state reads it. */
+pi_status pi_timestep(pi_grid* grid, double t_end, void* stream);
+
+/* One step of algorithm 3 (Sect. 2.2): pi_timestep; predictor over dt/2 on
+ * tau into the half state; raytrace of the half state into tau_half; corrector
+ * over dt from (x, E) on tau_half in place; raytrace of the new state into
+ * tau; t += dt.  Requires tau to hold the columns of (x, E) on entry (call
+ * pi_raytrace(grid, PI_BUF_N, PI_BUF_N, s) once after loading a state).  Does
+ * nothing useful once t >= t_end (dt = 0). */
+pi_status pi_step_o2(pi_grid* grid, double t_end, void* stream);
+
+/* One step of algorithm 2 (Sect. 2.2), the first-order variant: timestep,
+ * micro-physics over dt on tau, raytrace of the new state. */
+pi_status pi_step_o1(pi_grid* grid, double t_end, void* stream);
+
+/* Energy density of state `state` from a uniform temperature T0 [K] for pure
+ * hydrogen with gamma = 5/3 (Sect. 2): E = 3/2 n_H (2 - x) k_B T0. */
+pi_status pi_init_energy(pi_grid* grid, double T0, int state, void* stream);
+
+/* Set the grid clock (t, step count, last dt) on the device. */
+pi_status pi_set_time(pi_grid* grid, double t, int64_t nsteps, void* stream);
+
+/* Read the grid clock.  SYNCHRONISES the stream. */
+pi_status pi_grid_state(pi_grid* grid, double* t, int64_t* nsteps, double* last_dt,
+                        void* stream);
+
+/* FP64 diagnostics of state PI_BUF_N with columns tau (SYNCHRONISES):
+ * out[0] ions sum n_H (1-x) V, out[1] ionised volume sum (1-x) V,
+ * out[2] volume-equivalent ionised radius (3 V_ion 8 / (4 pi n_octants))^1/3,
+ * out[3] photoionisations per second, out[4] recombinations per second,
+ * out[5] number of non-finite cells, out[6] number of octants, out[7] time t. */
+pi_status pi_diagnostics(pi_grid* grid, double* out, void* stream);
+
+/* Host-only: blackbody rate table of the TABLE spectrum (Sect. 2, rates
+ * tabulated against optical depth): out[5*PI_NTAB] = node optical depths, P
+ * (photons/s surviving a threshold column tau), -dP/dtau, H (excess energy
+ * carried, erg/s), -dH/dtau, for a T_bb blackbody of Q photons/s with
+ * cross-section sigma0 (nu0/nu)^3.  Nodes: 0, then 63 log-spaced in [1e-4, 1e4]. */
+pi_status pi_table_build(double T_bb, double Q, double* out);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* pi_last_error(void);
+
+/* ABI version of this header (major * 100 + minor). */
+int pi_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

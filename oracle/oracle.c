@@ -49,10 +49,16 @@ static const double EV = 1.602176634e-12;     /* [erg]                          
 static const double HNU0_EV = 13.6;           /* threshold energy, Sect. 2.1        */
 static const double TAU0_MELLEMA = 0.6;       /* reading: weight 1/max(0.6, tau)    */
 static const double T_FLOOR = 10.0;           /* [K], reading                       */
-static const double THIN_CELL = 1e-2;         /* table mode: midpoint rule below    */
+static const double THIN_CELL = 2e-2;         /* table mode: quadrature when the cell
+                                                 absorbs less than this fraction  */
 static const double NEWTON_RTOL = 1e-13;
-static const double NEWTON_STALL = 1e-9;
+static const double NEWTON_STALL = 1e-11;
 static const int    NEWTON_2D_MAXIT = 20;
+static const double SUB_DX = 0.2;             /* initial substeps: max x change  */
+static const int    SUB_MAX = 128;
+static const int    SUB_LEVELS = 6;           /* substep halvings allowed        */
+static const double REJ_DX = 0.3;             /* reject a substep moving x more  */
+static const double REJ_E = 3.0;              /* ... or changing E by this factor */
 static const int    FALLBACK_MAXIT = 200;
 static const int    NEWTON_MAXIT = 60;
 /* (2/pi) * integral over the unit cube of dV/|r|^2: mean chord that makes the
@@ -67,6 +73,14 @@ void orc_reset_newton_failures(void) { g_newton_fail = 0; }
 double orc_mean_chord_source_cell(void) { return MEAN_CHORD_SOURCE_CELL; }
 
 /* ------------------------------------------------------------- rate tables */
+static void kahan_add(double* sum, double* comp, double v)
+{
+    double y = v - *comp;
+    double t = *sum + y;
+    *comp = (t - *sum) - y;
+    *sum = t;
+}
+
 /* Gauss-Legendre nodes on [-1,1] by Newton iteration on P_n. */
 static void gauss_legendre(int n, double* xg, double* wg)
 {
@@ -127,16 +141,17 @@ int orc_table_build(double T_bb, double Q, double* out)
     const double width = 0.25;
     const int npanel = 800; /* u in [u0, u0 + 200] */
 
-    double norm = 0.0;
+    /* sums are compensated (Kahan) so that rounding stays at the 1e-16 level */
+    double norm = 0.0, cn = 0.0;
     for (int p = 0; p < npanel; ++p) {
         double a = u0 + p * width, b = a + width;
         for (int q = 0; q < NG; ++q) {
             double u = 0.5 * (a + b) + 0.5 * (b - a) * xg[q];
-            norm += 0.5 * (b - a) * wg[q] * u * u / expm1(u);
+            kahan_add(&norm, &cn, 0.5 * (b - a) * wg[q] * u * u / expm1(u));
         }
     }
     for (int j = 0; j < ORC_NTAB; ++j) {
-        double sp = 0, sp1 = 0, sh = 0, sh1 = 0;
+        double sp = 0, sp1 = 0, sh = 0, sh1 = 0, c0 = 0, c1 = 0, c2 = 0, c3 = 0;
         for (int p = 0; p < npanel; ++p) {
             double a = u0 + p * width, b = a + width;
             for (int q = 0; q < NG; ++q) {
@@ -144,10 +159,10 @@ int orc_table_build(double T_bb, double Q, double* out)
                 double w = 0.5 * (b - a) * wg[q] * u * u / expm1(u);
                 double s = (u0 / u) * (u0 / u) * (u0 / u);
                 double att = exp(-tau[j] * s);
-                sp += w * att;
-                sp1 += w * s * att;
-                sh += w * (u - u0) * att;
-                sh1 += w * (u - u0) * s * att;
+                kahan_add(&sp, &c0, w * att);
+                kahan_add(&sp1, &c1, w * s * att);
+                kahan_add(&sh, &c2, w * (u - u0) * att);
+                kahan_add(&sh1, &c3, w * (u - u0) * s * att);
             }
         }
         P[j] = Q * sp / norm;
@@ -479,6 +494,7 @@ static void cooling_coeffs(const orc_desc* g, double T, double* cii, double* dci
 typedef struct {
     double nH, geo, ell, tau_in;
     double Pin, Hin; /* table values at tau_in */
+    double lin;      /* -d ln P / d tau at tau_in: fraction absorbed per unit depth */
 } cellenv;
 
 /* photon absorption per unit volume A(x) and heating per unit volume G(x) in a
@@ -497,14 +513,22 @@ static void photo(const orc_desc* g, const cellenv* c, double x, double* A, doub
         *dG = *dA * g->e_excess;
         return;
     }
-    if (u < THIN_CELL) {
-        double dP, dH;
-        orc_table_eval(g->table, 0, c->tau_in + 0.5 * u, &dP);
-        orc_table_eval(g->table, 1, c->tau_in + 0.5 * u, &dH);
-        *A = c->geo * (-dP) * u;
-        *dA = c->geo * (-dP) * k;
-        *G = c->geo * (-dH) * u;
-        *dG = c->geo * (-dH) * k;
+    if (u * c->lin < THIN_CELL) {
+        /* the cell absorbs a small fraction of what enters: P(tau) - P(tau + u)
+         * as the integral of -dP/dtau over the cell, by two-point
+         * Gauss-Legendre (no cancellation); the x-derivative keeps only the
+         * leading term k * mean(-dP/dtau) */
+        const double c2 = 0.5 / sqrt(3.0);
+        double dP1, dP2, dH1, dH2;
+        orc_table_eval(g->table, 0, c->tau_in + (0.5 - c2) * u, &dP1);
+        orc_table_eval(g->table, 0, c->tau_in + (0.5 + c2) * u, &dP2);
+        orc_table_eval(g->table, 1, c->tau_in + (0.5 - c2) * u, &dH1);
+        orc_table_eval(g->table, 1, c->tau_in + (0.5 + c2) * u, &dH2);
+        const double mP = -0.5 * (dP1 + dP2), mH = -0.5 * (dH1 + dH2);
+        *A = c->geo * mP * u;
+        *dA = c->geo * mP * k;
+        *G = c->geo * mH * u;
+        *dG = c->geo * mH * k;
     } else {
         double dP, dH;
         double Pout = orc_table_eval(g->table, 0, c->tau_in + u, &dP);
@@ -518,7 +542,10 @@ static void photo(const orc_desc* g, const cellenv* c, double x, double* A, doub
 
 /* Right-hand side of eq.(2) written for the neutral fraction x = 1 - y and the
  * internal energy E, with its Jacobian.  T = 2E / (3 k_B n_H (2 - x)) for pure H
- * with gamma = 5/3 (Sect. 2: E_int = p/(gamma-1)); floor T_FLOOR. */
+ * with gamma = 5/3 (Sect. 2: E_int = p/(gamma-1)).  Temperature floor (reading):
+ * the rate coefficients see max(T, T_FLOOR) and the cooling is tapered by
+ * max(0, 1 - T_FLOOR/T), so the floor is approached smoothly and never crossed
+ * by cooling. */
 typedef struct {
     double fx, fE;
     double jxx, jxE, jEx, jEE;
@@ -528,27 +555,27 @@ typedef struct {
 static void rhs(const orc_desc* g, const cellenv* c, double x, double E, rhsval* r)
 {
     const double n = c->nH;
-    double T, dTdx = 0.0, dTdE = 0.0;
+    double T, Tc, dTdx = 0.0, dTdE = 0.0, above = 1.0;
     if (g->thermal == ORC_T_FIXED) {
-        T = g->T_fixed;
+        T = Tc = g->T_fixed;
     } else {
         T = 2.0 * E / (3.0 * KB * n * (2.0 - x));
-        if (T > T_FLOOR) {
-            dTdx = T / (2.0 - x);
-            dTdE = T / E;
-        } else {
-            T = T_FLOOR;
-        }
+        dTdx = T / (2.0 - x);
+        dTdE = T / E;
+        above = T > T_FLOOR ? 1.0 : 0.0;
+        Tc = T > T_FLOOR ? T : T_FLOOR;
     }
     double A, dA, G, dG;
     photo(g, c, x, &A, &dA, &G, &dG);
-    double dla, alpha = alpha_rr(g, T, &dla);
+    double dla, alpha = alpha_rr(g, Tc, &dla);
     double aci = 0.0, dlci = 0.0;
-    if (g->collisional) aci = coll_ion(T, &dlci);
+    if (g->collisional) aci = coll_ion(Tc, &dlci);
+    dla *= above;
+    dlci *= above;
     const double y = 1.0 - x;
     r->A = A;
     r->rec = alpha * n * n * y * y;
-    r->T = T;
+    r->T = Tc;
     /* x-equation: photoionisation, collisional ionisation, recombination */
     r->fx = -A / n - aci * n * x * y + alpha * n * y * y;
     double dfx_dT = -aci * dlci * n * x * y + alpha * dla * n * y * y;
@@ -560,10 +587,15 @@ static void rhs(const orc_desc* g, const cellenv* c, double x, double E, rhsval*
         return;
     }
     double cii = 0.0, dcii = 0.0, cin = 0.0, dcin = 0.0;
-    if (g->cooling) cooling_coeffs(g, T, &cii, &dcii, &cin, &dcin);
-    double lam = n * n * (y * y * cii + x * y * cin);
-    double dlam_dx = n * n * (-2.0 * y * cii + (1.0 - 2.0 * x) * cin);
-    double dlam_dT = n * n * (y * y * dcii + x * y * dcin);
+    if (g->cooling) cooling_coeffs(g, Tc, &cii, &dcii, &cin, &dcin);
+    const double w = T > T_FLOOR ? 1.0 - T_FLOOR / T : 0.0;
+    const double dw = T > T_FLOOR ? T_FLOOR / (T * T) : 0.0;
+    double lam0 = n * n * (y * y * cii + x * y * cin);
+    double dlam0_dx = n * n * (-2.0 * y * cii + (1.0 - 2.0 * x) * cin);
+    double dlam0_dT = above * n * n * (y * y * dcii + x * y * dcin);
+    double lam = lam0 * w;
+    double dlam_dx = dlam0_dx * w;
+    double dlam_dT = dlam0_dT * w + lam0 * dw;
     r->fE = G - lam;
     r->jEx = dG - dlam_dx - dlam_dT * dTdx;
     r->jEE = -dlam_dT * dTdE;
@@ -575,8 +607,8 @@ static double e_floor(const orc_desc* g, double n, double x)
     return 1.5 * n * (2.0 - x) * KB * T_FLOOR;
 }
 
-static void stage_solve(const orc_desc* g, const cellenv* c, double xb, double Eb, double hg,
-                        double* xio, double* Eio);
+static int stage_solve(const orc_desc* g, const cellenv* c, double xb, double Eb, double hg,
+                       double* xio, double* Eio);
 
 /* Scalar x-solve of the stage equation at a fixed temperature T (the fallback
  * path of the T-evolving stage solve): bracketed Newton on [0, 1], as in the
@@ -607,8 +639,8 @@ static double t_residual(const orc_desc* g, const cellenv* c, double xb, double 
  * T fixed: scalar in x, safeguarded by the bracket [0,1] (the residual is
  * increasing in x); a root outside [0,1] is returned clamped.  T evolving:
  * 2x2 Newton with x clamped to [0,1] and E to the temperature floor. */
-static void stage_solve(const orc_desc* g, const cellenv* c, double xb, double Eb, double hg,
-                        double* xio, double* Eio)
+static int stage_solve(const orc_desc* g, const cellenv* c, double xb, double Eb, double hg,
+                       double* xio, double* Eio)
 {
     double x = *xio, E = *Eio;
     if (x < 0.0) x = 0.0;
@@ -641,12 +673,11 @@ static void stage_solve(const orc_desc* g, const cellenv* c, double xb, double E
             if (it == NEWTON_MAXIT - 1) ++g_newton_fail;
         }
         *xio = x;
-        return;
+        return 0;
     }
     /* T evolving, first: Newton on (x, E) with x projected onto [0, 1] and E
-     * onto the temperature floor, at most NEWTON_2D_MAXIT iterations. */
-    double Emin = e_floor(g, c->nH, x);
-    if (E < Emin) E = Emin;
+     * kept positive, at most NEWTON_2D_MAXIT iterations. */
+    if (!(E > 0.0)) E = e_floor(g, c->nH, x);
     double eprev = INFINITY;
     for (int it = 0; it < NEWTON_2D_MAXIT; ++it) {
         rhs(g, c, x, E, &r);
@@ -659,16 +690,18 @@ static void stage_solve(const orc_desc* g, const cellenv* c, double xb, double E
         double En = E - (a11 * RE - a21 * Rx) / det;
         if (!(xn >= 0.0)) xn = 0.0;   /* also catches NaN */
         if (xn > 1.0) xn = 1.0;
-        double Emn = e_floor(g, c->nH, xn);
-        if (!(En >= Emn)) En = Emn;
-        double e = fmax(fabs(xn - x) / fmax(xn, 1e-12), fabs(En - E) / En);
+        if (!(En > 0.0)) En = 0.5 * E;
+        double e = fmax(fabs(xn - x) / fmax(xn, 1e-12), fabs(E - En) / En);
+        /* x held on a bound while the residual puts the root inside [0, 1]
+         * (a negative slope of the x-residual): not a solution */
+        const int stuck = (xn >= 1.0 && Rx > 0.0) || (xn <= 0.0 && Rx < 0.0);
         x = xn;
         E = En;
         /* converged; or stalled at the rounding floor of the residual */
-        if (e <= NEWTON_RTOL || (e >= eprev && e <= NEWTON_STALL)) {
+        if (!stuck && (e <= NEWTON_RTOL || (e >= eprev && e <= NEWTON_STALL))) {
             *xio = x;
             *Eio = E;
-            return;
+            return 0;
         }
         eprev = e;
     }
@@ -684,7 +717,7 @@ static void stage_solve(const orc_desc* g, const cellenv* c, double xb, double E
         if (ga >= 0.0) {
             *xio = xs;
             *Eio = 1.5 * c->nH * (2.0 - xs) * KB * T_FLOOR;
-            return;
+            return 1;
         }
         double Tg = fmax(2.0 * E / (3.0 * KB * c->nH * (2.0 - x)), 2.0 * T_FLOOR);
         double lb = log(Tg), gb = t_residual(g, c, xb, Eb, hg, Tg, &xs);
@@ -718,6 +751,7 @@ static void stage_solve(const orc_desc* g, const cellenv* c, double xb, double E
         *xio = xs;
         *Eio = 1.5 * c->nH * (2.0 - xs) * KB * T;
     }
+    return 1;
 }
 
 static void make_env(const orc_desc* g, double nH, double geo, double ell, double tau_in, cellenv* c)
@@ -726,36 +760,81 @@ static void make_env(const orc_desc* g, double nH, double geo, double ell, doubl
     c->geo = geo;
     c->ell = ell;
     c->tau_in = tau_in;
-    c->Pin = c->Hin = 0.0;
+    c->Pin = c->Hin = c->lin = 0.0;
     if (g->spectrum == ORC_SPEC_TABLE) {
-        c->Pin = orc_table_eval(g->table, 0, tau_in, NULL);
+        double dP;
+        c->Pin = orc_table_eval(g->table, 0, tau_in, &dP);
         c->Hin = orc_table_eval(g->table, 1, tau_in, NULL);
+        c->lin = c->Pin > 0.0 ? -dP / c->Pin : 0.0;
     }
+}
+
+/* Initial substep count of one micro-integration (reading, a fixed-structure
+ * stand-in for an integrator's own step control): at least n_sub, and enough
+ * that at the initial rate no substep moves x by more than SUB_DX; at most
+ * SUB_MAX. */
+static int substeps(const orc_desc* g, const cellenv* c, double x0, double E0, double h)
+{
+    rhsval r;
+    rhs(g, c, x0, E0, &r);
+    double s = h * fabs(r.fx) / SUB_DX;
+    int ns = g->n_sub > 0 ? g->n_sub : 1;
+    if (s > ns) ns = s >= SUB_MAX ? SUB_MAX : (int)ceil(s);
+    return ns;
+}
+
+/* One step of the two-stage, L-stable, stiffly accurate SDIRK method
+ * (gamma = 1 - 1/sqrt 2) of size hs; the second stage starts from
+ * y + ((1-gamma)/gamma)(Y1 - y).  Returns 1 if a stage needed the fallback. */
+static int sdirk_step(const orc_desc* g, const cellenv* c, double hs, double* x, double* E)
+{
+    const double gam = 1.0 - sqrt(0.5);
+    const double cst = (1.0 - gam) / gam;
+    double X1 = *x, F1 = *E;
+    int fb = stage_solve(g, c, *x, *E, gam * hs, &X1, &F1);
+    double xb = *x + cst * (X1 - *x);
+    double Eb = *E + cst * (F1 - *E);
+    double X2 = X1, F2 = F1;
+    fb |= stage_solve(g, c, xb, Eb, gam * hs, &X2, &F2);
+    *x = X2;
+    *E = F2;
+    return fb;
 }
 
 /* Micro-integration M(x0, E0; tau_in, h): eq.(2) over h with the entering
  * column frozen and the cell's own optical depth following x (reading).  The
  * paper integrates with CVODE (backward differences, Newton); this oracle uses
- * a fixed structure instead (reading): n_sub equal substeps of the two-stage,
- * L-stable, stiffly accurate SDIRK method with gamma = 1 - 1/sqrt(2). */
+ * a deterministic substep control instead (reading): the interval is cut into
+ * U = ns 2^SUB_LEVELS units (ns from substeps()); a substep of s units is
+ * rejected and halved if a stage needed the fallback solve, x moved by more
+ * than REJ_DX or E changed by more than a factor REJ_E (while s > 1), and an
+ * accepted substep is doubled again when the position allows.  E is held at
+ * or above the temperature floor between substeps. */
 static void micro(const orc_desc* g, const cellenv* c, double x0, double E0, double h,
                   double* x1, double* E1)
 {
     double x = x0, E = E0;
     if (h > 0.0) {
-        const double gam = 1.0 - sqrt(0.5);
-        const double cst = (1.0 - gam) / gam;
-        const int ns = g->n_sub > 0 ? g->n_sub : 1;
-        const double hs = h / ns;
-        for (int s = 0; s < ns; ++s) {
-            double X1 = x, F1 = E;
-            stage_solve(g, c, x, E, gam * hs, &X1, &F1);
-            double xb = x + cst * (X1 - x);
-            double Eb = E + cst * (F1 - E);
-            double X2 = X1, F2 = F1;
-            stage_solve(g, c, xb, Eb, gam * hs, &X2, &F2);
-            x = X2;
-            E = F2;
+        if (g->thermal == ORC_T_EVOLVE && E < e_floor(g, c->nH, x)) E = e_floor(g, c->nH, x);
+        const int ns = substeps(g, c, x, E, h);
+        const long top = 1L << SUB_LEVELS;
+        const long U = (long)ns * top;
+        long p = 0, s = top;
+        while (p < U) {
+            const double hs = h * (double)s / (double)U;
+            double xn = x, En = E;
+            int fb = sdirk_step(g, c, hs, &xn, &En);
+            int bad = fb || fabs(xn - x) > REJ_DX ||
+                      (g->thermal == ORC_T_EVOLVE && (En > REJ_E * E || En * REJ_E < E));
+            if (bad && s > 1) {
+                s >>= 1;
+                continue;
+            }
+            x = xn;
+            E = En;
+            if (g->thermal == ORC_T_EVOLVE && E < e_floor(g, c->nH, x)) E = e_floor(g, c->nH, x);
+            p += s;
+            if (s < top && p % (2 * s) == 0) s <<= 1;
         }
     }
     *x1 = x;

@@ -1,0 +1,250 @@
+"""Python binding of the C ABI in include/pi.h (ctypes).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+libpi.so.  PyTorch provides the device memory (caller-owned field tensors) and
+the stream handed to every call.  There is no CPU fallback: without a built
+libpi.so, or without a GPU, the calls fail loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpi.so")
+
+PI_OK, PI_EINVAL, PI_ENOMEM, PI_EDEVICE, PI_ENAN = 0, -1, -2, -3, -5
+PI_FP64, PI_FP32, PI_MIXED = 0, 1, 2
+PI_SPEC_MONO, PI_SPEC_TABLE = 0, 1
+PI_T_FIXED, PI_T_EVOLVE = 0, 1
+PI_ALPHA_CONST, PI_ALPHA_POWER = 0, 1
+PI_W_GEOMETRIC, PI_W_MELLEMA = 0, 1
+PI_BUF_N, PI_BUF_HALF = 0, 1
+PI_NDIAG = 8
+PI_NTAB = 64
+
+# every symbol include/pi.h declares
+ABI_SYMBOLS = (
+    "pi_grid_create", "pi_grid_destroy", "pi_raytrace", "pi_chem_step", "pi_timestep",
+    "pi_step_o2", "pi_step_o1", "pi_init_energy", "pi_set_time", "pi_grid_state",
+    "pi_diagnostics", "pi_table_build", "pi_last_error", "pi_abi_version",
+)
+
+
+class PiError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"pi status {status}: {msg}")
+        self.status = status
+
+
+class GridDesc(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32 * 3),
+        ("src", C.c_int32 * 3),
+        ("dx", C.c_double),
+        ("Q", C.c_double),
+        ("sigma0", C.c_double),
+        ("spectrum", C.c_int32),
+        ("e_excess", C.c_double),
+        ("T_bb", C.c_double),
+        ("thermal", C.c_int32),
+        ("T_fixed", C.c_double),
+        ("recomb", C.c_int32),
+        ("alpha_B", C.c_double),
+        ("collisional", C.c_int32),
+        ("cooling", C.c_int32),
+        ("weights", C.c_int32),
+        ("source_cell_rule", C.c_int32),
+        ("n_sub", C.c_int32),
+        ("K", C.c_double * 4),
+        ("precision", C.c_int32),
+    ]
+
+
+class Fields(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("nH", "x", "E", "tau", "x_half", "E_half", "tau_half")]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libpi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, d = C.c_void_p, C.c_int, C.c_int64, C.c_double
+        dp = C.POINTER(C.c_double)
+        L.pi_grid_create.argtypes = [C.POINTER(GridDesc), C.POINTER(Fields), C.POINTER(vp)]
+        L.pi_grid_destroy.argtypes = [vp]
+        L.pi_raytrace.argtypes = [vp, i32, i32, vp]
+        L.pi_chem_step.argtypes = [vp, i32, d, i32, i32, i32, vp]
+        L.pi_timestep.argtypes = [vp, d, vp]
+        L.pi_step_o2.argtypes = [vp, d, vp]
+        L.pi_step_o1.argtypes = [vp, d, vp]
+        L.pi_init_energy.argtypes = [vp, d, i32, vp]
+        L.pi_set_time.argtypes = [vp, d, i64, vp]
+        L.pi_grid_state.argtypes = [vp, dp, C.POINTER(C.c_int64), dp, vp]
+        L.pi_diagnostics.argtypes = [vp, dp, vp]
+        L.pi_table_build.argtypes = [d, d, dp]
+        L.pi_last_error.restype = C.c_char_p
+        L.pi_abi_version.restype = C.c_int
+        for name in ABI_SYMBOLS:
+            if name not in ("pi_last_error", "pi_abi_version"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != PI_OK:
+        raise PiError(status, lib().pi_last_error().decode())
+
+
+def table_build(T_bb: float, Q: float):
+    """pi_table_build: rows tau, P, -dP/dtau, H, -dH/dtau (host-only)."""
+    import numpy as np
+    out = np.zeros(5 * PI_NTAB)
+    check(lib().pi_table_build(T_bb, Q, out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out.reshape(5, PI_NTAB)
+
+
+def desc_from_spec(spec, precision: Optional[str] = None, sigma0: float = 6.3e-18) -> GridDesc:
+    """pi_grid_desc for a synth.GridSpec."""
+    d = GridDesc()
+    d.n[:] = tuple(int(v) for v in spec.n)
+    d.src[:] = tuple(int(v) for v in spec.src)
+    d.dx = spec.dx
+    d.Q = spec.Q
+    d.sigma0 = sigma0
+    d.spectrum = PI_SPEC_TABLE if spec.spectrum == "table" else PI_SPEC_MONO
+    d.e_excess = spec.e_excess
+    d.T_bb = spec.T_bb
+    d.thermal = PI_T_EVOLVE if spec.thermal == "evolve" else PI_T_FIXED
+    d.T_fixed = spec.T_fixed
+    d.recomb = PI_ALPHA_POWER if spec.recomb == "power" else PI_ALPHA_CONST
+    d.alpha_B = spec.alpha_B
+    d.collisional = int(spec.collisional)
+    d.cooling = int(spec.cooling)
+    d.weights = PI_W_MELLEMA if spec.weights == "mellema" else PI_W_GEOMETRIC
+    d.source_cell_rule = int(spec.source_cell_rule)
+    d.n_sub = int(spec.n_sub)
+    d.K[:] = tuple(float(k) for k in spec.K)
+    prec = precision or spec.precision
+    d.precision = {"fp64": PI_FP64, "fp32": PI_FP32, "mixed": PI_MIXED}[prec]
+    return d
+
+
+class Grid:
+    """One photoionisation problem resident on the GPU.
+
+    Owns its field tensors (torch, on ``device``) and the library handle.
+    Methods map one-to-one onto the ABI calls, on torch's current stream.
+    """
+
+    def __init__(self, spec, device: str = "cuda:0", precision: Optional[str] = None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the photoionisation library needs a GPU (no CPU fallback)")
+        self.spec = spec
+        self.precision = precision or spec.precision
+        self.dtype = torch.float64 if self.precision == "fp64" else torch.float32
+        self.device = torch.device(device)
+        shape = spec.shape
+        z = lambda: torch.zeros(shape, dtype=self.dtype, device=self.device)
+        self.nH, self.x, self.tau = z(), z(), z()
+        self.x_half, self.tau_half = z(), z()
+        evolve = spec.thermal == "evolve"
+        self.E = z() if evolve else None
+        self.E_half = z() if evolve else None
+        f = Fields()
+        for k in ("nH", "x", "E", "tau", "x_half", "E_half", "tau_half"):
+            t = getattr(self, k)
+            setattr(f, k, t.data_ptr() if t is not None else None)
+        self._fields = f
+        self._desc = desc_from_spec(spec, self.precision)
+        h = C.c_void_p()
+        check(lib().pi_grid_create(C.byref(self._desc), C.byref(f), C.byref(h)))
+        self._h = h
+
+    # -- stream
+    @staticmethod
+    def _stream():
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    # -- state
+    def load(self, nH, x=1.0, T0: Optional[float] = None, t: float = 0.0, nsteps: int = 0):
+        """Copy density and neutral fraction in, set E from T0 (T-evolving
+        grids), raytrace the initial columns and set the clock."""
+        import torch
+        self.nH.copy_(torch.as_tensor(nH, dtype=self.dtype).reshape(self.spec.shape))
+        if isinstance(x, (int, float)):
+            self.x.fill_(float(x))
+        else:
+            self.x.copy_(torch.as_tensor(x, dtype=self.dtype).reshape(self.spec.shape))
+        s = self._stream()
+        if self.E is not None:
+            check(lib().pi_init_energy(self._h, float(T0 if T0 is not None else self.spec.T0),
+                                       PI_BUF_N, s))
+        check(lib().pi_raytrace(self._h, PI_BUF_N, PI_BUF_N, s))
+        check(lib().pi_set_time(self._h, float(t), int(nsteps), s))
+
+    def raytrace(self, state=PI_BUF_N, tau_buf=PI_BUF_N):
+        check(lib().pi_raytrace(self._h, state, tau_buf, self._stream()))
+
+    def chem_step(self, h: float, tau_buf=PI_BUF_N, from_state=PI_BUF_N, to_state=PI_BUF_N,
+                  use_device_dt: bool = False):
+        check(lib().pi_chem_step(self._h, int(use_device_dt), float(h), tau_buf, from_state,
+                                 to_state, self._stream()))
+
+    def timestep(self, t_end: float):
+        check(lib().pi_timestep(self._h, float(t_end), self._stream()))
+
+    def step_o2(self, t_end: float):
+        check(lib().pi_step_o2(self._h, float(t_end), self._stream()))
+
+    def step_o1(self, t_end: float):
+        check(lib().pi_step_o1(self._h, float(t_end), self._stream()))
+
+    def state(self):
+        t, dt = C.c_double(), C.c_double()
+        n = C.c_int64()
+        check(lib().pi_grid_state(self._h, C.byref(t), C.byref(n), C.byref(dt), self._stream()))
+        return t.value, n.value, dt.value
+
+    def diagnostics(self):
+        out = (C.c_double * PI_NDIAG)()
+        check(lib().pi_diagnostics(self._h, out, self._stream()))
+        keys = ("n_ion", "v_ion", "r_ion", "photo_rate", "recomb_rate", "nonfinite", "octants", "t")
+        return dict(zip(keys, list(out)))
+
+    def run(self, t_end: float, order: int = 2, max_steps: int = 10**8, check_every: int = 64):
+        """Step until t_end (order 2: algorithm 3; order 1: algorithm 2).
+        Returns the number of steps taken."""
+        t0, n0, _ = self.state()
+        taken = 0
+        while taken < max_steps:
+            burst = min(check_every, max_steps - taken)
+            for _ in range(burst):
+                (self.step_o2 if order == 2 else self.step_o1)(t_end)
+            t, n, _ = self.state()
+            taken = n - n0
+            if t >= t_end:
+                break
+        return taken
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(lib().pi_grid_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

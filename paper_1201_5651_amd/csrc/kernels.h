@@ -1,0 +1,42 @@
+// kernels.h -- launch interface between the C-ABI runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "physics.h"
+
+namespace pi {
+
+// Tile of the raytrace wavefront (octant-local cells per workgroup).
+constexpr int SWEEP_TX = 8, SWEEP_TY = 8, SWEEP_TZ = 8;
+// Per-block partials of the timestep/diagnostics reduction:
+// [0] min dt limit, [1] sum n(1-x), [2] sum (1-x), [3] sum A, [4] sum recomb, [5] non-finite cells
+constexpr int NPART = 6;
+
+// Grid clock and last reduction results, resident in device memory.
+struct DevState {
+    double t;
+    double dt;        // timestep of the step in flight (0 once t >= t_end)
+    double t_end;
+    double last_dt;
+    long long nsteps;
+    long long pad;
+    double diag[8];   // see pi_diagnostics
+};
+
+template <typename R>
+hipError_t launch_sweep_stage(const Params<R>& p, const R* nH, const R* x, R* tau,
+                              const int4* tiles, int first, int count, hipStream_t s);
+template <typename R>
+hipError_t launch_chem(const Params<R>& p, const R* nH, const R* x0, const R* E0, const R* tau,
+                       R* x1, R* E1, const DevState* st, double hscale, hipStream_t s);
+template <typename R>
+hipError_t launch_dtdiag(const Params<R>& p, const R* nH, const R* x, const R* E, const R* tau,
+                         double* part, int nblk, DevState* st, double t_end, double cell_vol,
+                         int noct, hipStream_t s);
+hipError_t launch_advance(DevState* st, hipStream_t s);
+template <typename R>
+hipError_t launch_energy(int64_t n, const R* nH, const R* x, R* E, double T0, hipStream_t s);
+
+}  // namespace pi

@@ -1,0 +1,317 @@
+// kernels.hip -- gfx950 kernels of the photoionisation source-term step and
+// their launchers.
+//
+//  k_sweep     short-characteristics raytrace of one tile-wavefront stage
+//              (all octants at once), Sect. 2 and Sect. 5 of Mackey (A&A 2012)
+//  k_chem      micro-physics of every cell over h on frozen columns (eq. 2)
+//  k_dtdiag    per-cell timestep limit (eq. 4) and FP64 diagnostics,
+//              reduced to per-block partials
+//  k_finalize  fixed-order reduction of the partials; dt capped at t_end
+//  k_advance   clock update at the end of a step
+//  k_energy    internal energy from a uniform temperature
+#include "kernels.h"
+
+#include <hip/hip_runtime.h>
+
+namespace pi {
+
+// ------------------------------------------------------------------ raytrace
+// One tile-diagonal stage of the octant sweeps.  Each workgroup owns one
+// TX*TY*TZ tile of one octant (one thread per cell) and needs only the tiles
+// of earlier stages, so a stage is one launch.  The tile's cells and its
+// upstream halo (octant-local index -1 on any axis) are staged in LDS as
+//   s_kap: sigma0 n_H x dx (optical depth per cell length),
+//   s_tc : optical depth from the source to the cell centre (halo only, from
+//          the stored entering depth of the earlier stage);
+// the tile is then swept diagonal plane by diagonal plane, lx+ly+lz = s.
+//
+// A cell C with dominant axis a interpolates, on the plane through the centres
+// of the layer one step back along a, the four upstream centres around the
+// point where the ray to C crosses that plane (offsets ad_b/ad_a in (0, 1]);
+// each carries T = tau_centre + (ds_C/2) kap, its depth at C's entry face, with
+// bilinear weights divided by max(0.6, T) (Mellema weighting).  Neighbours
+// across a source plane (octant-local index -1) get weight 0.
+template <typename R, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(TX * TY * TZ)
+k_sweep(Params<R> p, const R* __restrict__ nH, const R* __restrict__ xs, R* __restrict__ tau,
+        const int4* __restrict__ tiles, int first)
+{
+    constexpr int HX = TX + 1, HY = TY + 1, HZ = TZ + 1, NHALO = HX * HY * HZ;
+    __shared__ R s_tc[NHALO];
+    __shared__ R s_kap[NHALO];
+
+    const int4 tl = tiles[first + blockIdx.x];
+    const int oct = tl.x;
+    const bool px = oct & 1, py = oct & 2, pz = oct & 4;
+    const int ex = px ? p.nx - p.sx : p.sx;
+    const int ey = py ? p.ny - p.sy : p.sy;
+    const int ez = pz ? p.nz - p.sz : p.sz;
+    const int X0 = tl.y * TX, Y0 = tl.z * TY, Z0 = tl.w * TZ;
+
+    for (int q = threadIdx.x; q < NHALO; q += TX * TY * TZ) {
+        const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
+        const int Lx = X0 + hx - 1, Ly = Y0 + hy - 1, Lz = Z0 + hz - 1;
+        R kap = R(0), tc = R(0);
+        if (Lx >= 0 && Ly >= 0 && Lz >= 0 && Lx < ex && Ly < ey && Lz < ez) {
+            const int gi = px ? p.sx + Lx : p.sx - 1 - Lx;
+            const int gj = py ? p.sy + Ly : p.sy - 1 - Ly;
+            const int gk = pz ? p.sz + Lz : p.sz - 1 - Lz;
+            const int64_t g = gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk);
+            kap = p.sdx * nH[g] * xs[g];
+            if (hx == 0 || hy == 0 || hz == 0) {
+                const R ax = R(Lx) + R(0.5), ay = R(Ly) + R(0.5), az = R(Lz) + R(0.5);
+                const R da = (az >= ax && az >= ay) ? az : (ay >= ax ? ay : ax);
+                const R ds = r_sqrt(ax * ax + ay * ay + az * az) / da;
+                tc = tau[g] + R(0.5) * ds * kap;
+            }
+        }
+        s_kap[q] = kap;
+        s_tc[q] = tc;
+    }
+    __syncthreads();
+
+    const int t = threadIdx.x;
+    const int lx = t % TX, ly = (t / TX) % TY, lz = t / (TX * TY);
+    const int L[3] = { X0 + lx, Y0 + ly, Z0 + lz };
+    const bool active = L[0] < ex && L[1] < ey && L[2] < ez;
+    const R ad[3] = { R(L[0]) + R(0.5), R(L[1]) + R(0.5), R(L[2]) + R(0.5) };
+    const int a = (ad[2] >= ad[0] && ad[2] >= ad[1]) ? 2 : (ad[1] >= ad[0] ? 1 : 0);
+    const int b = a == 2 ? 0 : a + 1;
+    const int c = a == 0 ? 2 : a - 1;
+    const int st[3] = { 1, HX, HX * HY };
+    const int self = (lz + 1) * HX * HY + (ly + 1) * HX + (lx + 1);
+    const int n00 = self - st[a];
+    const int n10 = n00 - st[b];
+    const int n01 = n00 - st[c];
+    const int n11 = n10 - st[c];
+    const R fb = ad[b] / ad[a], fc = ad[c] / ad[a];
+    const bool vb = L[b] >= 1, vc = L[c] >= 1;
+    const R g00 = (R(1) - fb) * (R(1) - fc);
+    const R g10 = vb ? fb * (R(1) - fc) : R(0);
+    const R g01 = vc ? (R(1) - fb) * fc : R(0);
+    const R g11 = (vb && vc) ? fb * fc : R(0);
+    const R hds = R(0.5) * r_sqrt(ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2]) / ad[a];
+    const bool corner = L[a] == 0;
+    const bool mellema = p.weights == 1;
+    const int diag = lx + ly + lz;
+
+    R tin = R(0);
+    for (int s = 0; s < TX + TY + TZ - 2; ++s) {
+        if (active && diag == s) {
+            if (!corner) {
+                const R T00 = s_tc[n00] + hds * s_kap[n00];
+                const R T10 = s_tc[n10] + hds * s_kap[n10];
+                const R T01 = s_tc[n01] + hds * s_kap[n01];
+                const R T11 = s_tc[n11] + hds * s_kap[n11];
+                R w00 = g00, w10 = g10, w01 = g01, w11 = g11;
+                if (mellema) {
+                    w00 /= r_max(R(W_FLOOR), T00);
+                    w10 /= r_max(R(W_FLOOR), T10);
+                    w01 /= r_max(R(W_FLOOR), T01);
+                    w11 /= r_max(R(W_FLOOR), T11);
+                }
+                tin = (w00 * T00 + w10 * T10 + w01 * T01 + w11 * T11) / (w00 + w10 + w01 + w11);
+            }
+            s_tc[self] = tin + hds * s_kap[self];
+        }
+        __syncthreads();
+    }
+    if (active) {
+        const int gi = px ? p.sx + L[0] : p.sx - 1 - L[0];
+        const int gj = py ? p.sy + L[1] : p.sy - 1 - L[1];
+        const int gk = pz ? p.sz + L[2] : p.sz - 1 - L[2];
+        tau[gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk)] = tin;
+    }
+}
+
+// ---------------------------------------------------------------- chemistry
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_chem(Params<R> p, const R* __restrict__ nH, const R* x0, const R* E0, const R* __restrict__ tau,
+       R* x1, R* E1, const DevState* __restrict__ st, double hscale)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= p.ncell) return;
+    const double hd = st ? hscale * st->dt : hscale;
+    const int i = q % p.nx, j = (q / p.nx) % p.ny, k = q / (p.nx * p.ny);
+    const CellGeom<R> cg = cell_geom(p, i, j, k);
+    const Env<R> e = make_env(p, nH[q], cg, tau[q]);
+    R x = x0[q];
+    R E = E0 ? E0[q] : R(0);
+    micro(p, e, R(hd), x, E);
+    x1[q] = x;
+    if (E1) E1[q] = E;
+}
+
+// ------------------------------------------------------ timestep + diagnostics
+template <typename T> __device__ __forceinline__ T wave_sum(T v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <typename T> __device__ __forceinline__ T wave_min(T v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_dtdiag(Params<R> p, const R* __restrict__ nH, const R* __restrict__ x, const R* __restrict__ E,
+         const R* __restrict__ tau, double* __restrict__ part)
+{
+    double v[NPART] = { __builtin_huge_val(), 0.0, 0.0, 0.0, 0.0, 0.0 };
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < p.ncell; q += gridDim.x * blockDim.x) {
+        const int i = q % p.nx, j = (q / p.nx) % p.ny, k = q / (p.nx * p.ny);
+        const CellGeom<R> cg = cell_geom(p, i, j, k);
+        const R n = nH[q], xq = x[q], tq = tau[q];
+        const R Eq = E ? E[q] : R(0);
+        const Env<R> e = make_env(p, n, cg, tq);
+        Rhs<R> r;
+        rhs_full(p, e, xq, Eq, r);
+        v[0] = fmin(v[0], cell_dt(p, r, n, xq, Eq));
+        v[1] += (double)n * (1.0 - (double)xq);
+        v[2] += 1.0 - (double)xq;
+        v[3] += (double)r.A;
+        v[4] += (double)r.rec;
+        const bool bad = !isfinite((double)xq) || !isfinite((double)tq) ||
+                         (E && !isfinite((double)Eq));
+        v[5] += bad ? 1.0 : 0.0;
+    }
+    __shared__ double sm[NPART][4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    v[0] = wave_min(v[0]);
+    for (int m = 1; m < NPART; ++m) v[m] = wave_sum(v[m]);
+    if (lane == 0)
+        for (int m = 0; m < NPART; ++m) sm[m][w] = v[m];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double o[NPART];
+        o[0] = fmin(fmin(sm[0][0], sm[0][1]), fmin(sm[0][2], sm[0][3]));
+        for (int m = 1; m < NPART; ++m) o[m] = ((sm[m][0] + sm[m][1]) + sm[m][2]) + sm[m][3];
+        for (int m = 0; m < NPART; ++m) part[blockIdx.x * NPART + m] = o[m];
+    }
+}
+
+// Fixed-order reduction of the per-block partials (deterministic for a given
+// grid), then dt = min(limit, t_end - t) with a remainder below 1e-12 t_end
+// absorbed into the step.
+__global__ void __launch_bounds__(256)
+k_finalize(const double* __restrict__ part, int nblk, DevState* st, double t_end, double cell_vol,
+           int noct)
+{
+    __shared__ double sm[NPART][256];
+    double v[NPART] = { __builtin_huge_val(), 0.0, 0.0, 0.0, 0.0, 0.0 };
+    for (int b = threadIdx.x; b < nblk; b += 256) {
+        v[0] = fmin(v[0], part[b * NPART]);
+        for (int m = 1; m < NPART; ++m) v[m] += part[b * NPART + m];
+    }
+    for (int m = 0; m < NPART; ++m) sm[m][threadIdx.x] = v[m];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sm[0][threadIdx.x] = fmin(sm[0][threadIdx.x], sm[0][threadIdx.x + w]);
+            for (int m = 1; m < NPART; ++m) sm[m][threadIdx.x] += sm[m][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double dt = sm[0][0];
+        const double rem = t_end - st->t;
+        if (!(rem > 0.0)) {
+            dt = 0.0;
+        } else {
+            if (dt > rem) dt = rem;
+            if (rem - dt <= 1e-12 * t_end) dt = rem;
+        }
+        st->dt = dt;
+        st->t_end = t_end;
+        st->diag[0] = sm[1][0] * cell_vol;
+        st->diag[1] = sm[2][0] * cell_vol;
+        st->diag[2] = cbrt(3.0 * sm[2][0] * cell_vol * 8.0 / (4.0 * 3.14159265358979323846 * noct));
+        st->diag[3] = sm[3][0] * cell_vol;
+        st->diag[4] = sm[4][0] * cell_vol;
+        st->diag[5] = sm[5][0];
+        st->diag[6] = noct;
+        st->diag[7] = st->t;
+    }
+}
+
+__global__ void k_advance(DevState* st)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double dt = st->dt;
+        if (dt > 0.0) {
+            st->t = (st->t_end - st->t - dt <= 0.0) ? st->t_end : st->t + dt;
+            st->nsteps += 1;
+            st->last_dt = dt;
+        }
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_energy(int64_t n, const R* __restrict__ nH, const R* __restrict__ x, R* __restrict__ E, double T0)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) E[q] = R(1.5 * KB * T0) * nH[q] * (R(2) - x[q]);
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename R>
+hipError_t launch_sweep_stage(const Params<R>& p, const R* nH, const R* x, R* tau,
+                              const int4* tiles, int first, int count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_sweep<R, SWEEP_TX, SWEEP_TY, SWEEP_TZ>), dim3(count),
+                       dim3(SWEEP_TX * SWEEP_TY * SWEEP_TZ), 0, s, p, nH, x, tau, tiles, first);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_chem(const Params<R>& p, const R* nH, const R* x0, const R* E0, const R* tau,
+                       R* x1, R* E1, const DevState* st, double hscale, hipStream_t s)
+{
+    const int nb = (int)((p.ncell + 255) / 256);
+    hipLaunchKernelGGL((k_chem<R>), dim3(nb), dim3(256), 0, s, p, nH, x0, E0, tau, x1, E1, st,
+                       hscale);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_dtdiag(const Params<R>& p, const R* nH, const R* x, const R* E, const R* tau,
+                         double* part, int nblk, DevState* st, double t_end, double cell_vol,
+                         int noct, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_dtdiag<R>), dim3(nblk), dim3(256), 0, s, p, nH, x, E, tau, part);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, part, nblk, st, t_end, cell_vol, noct);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(DevState* st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_energy(int64_t n, const R* nH, const R* x, R* E, double T0, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_energy<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, nH, x,
+                       E, T0);
+    return hipGetLastError();
+}
+
+#define PI_INSTANTIATE(R)                                                                          \
+    template hipError_t launch_sweep_stage<R>(const Params<R>&, const R*, const R*, R*,           \
+                                              const int4*, int, int, hipStream_t);                 \
+    template hipError_t launch_chem<R>(const Params<R>&, const R*, const R*, const R*, const R*,  \
+                                       R*, R*, const DevState*, double, hipStream_t);              \
+    template hipError_t launch_dtdiag<R>(const Params<R>&, const R*, const R*, const R*,          \
+                                         const R*, double*, int, DevState*, double, double, int,   \
+                                         hipStream_t);                                             \
+    template hipError_t launch_energy<R>(int64_t, const R*, const R*, R*, double, hipStream_t);
+PI_INSTANTIATE(double)
+PI_INSTANTIATE(float)
+
+}  // namespace pi

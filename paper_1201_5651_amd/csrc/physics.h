@@ -1,0 +1,598 @@
+// physics.h -- device-side physics of the photoionisation source-term step.
+//
+// Per-cell geometry of a vertex source, photon-conserving photoionisation and
+// photoheating rates, hydrogen rate coefficients and cooling, and the
+// micro-integrator of eq. (2) (neutral fraction x = 1 - y and internal energy
+// E) of Mackey (A&A 2012).  Everything is templated on the arithmetic type R
+// (double for PI_FP64, float for PI_FP32/PI_MIXED bulk work).
+//
+// Dimensionless geometry: distances are in cell units and the host folds the
+// large dimensional constants into Q/dx^3 and sigma0*dx, so every quantity a
+// kernel touches stays inside the float range (Q ~ 1e48 and r^2 ~ 1e40 do not).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// Host and device: the same code also builds into host-side unit harnesses.
+#define PI_HD __host__ __device__
+
+namespace pi {
+
+constexpr double KB = 1.380649e-16;           // Boltzmann constant [erg/K]
+constexpr double T_FLOOR = 10.0;              // temperature floor [K]
+constexpr double THIN_CELL = 2e-2;            // table rates: quadrature below this absorbed fraction
+constexpr double W_FLOOR = 0.6;               // Mellema weights: 1 / max(0.6, tau)
+// (2/pi) * integral of dV/r^2 over a unit cube seen from one corner: the chord
+// that lets the source-corner cell absorb its octant's Q/8 exactly in both the
+// optically thin and the optically thick limit.
+constexpr double CORNER_CHORD = 1.2213748039031678;
+constexpr int NTAB = 64;
+constexpr int NEWTON_MAXIT = 60;
+constexpr int NEWTON_2D_MAXIT = 20;
+constexpr int FALLBACK_MAXIT = 200;
+constexpr double SUB_DX = 0.2;    // initial substeps: max x change at the initial rate
+constexpr int SUB_MAX = 128;
+constexpr int SUB_LEVELS = 6;     // substep halvings allowed
+constexpr double REJ_DX = 0.3;    // reject a substep that moves x by more
+constexpr double REJ_E = 3.0;     // ... or changes E by more than this factor
+
+template <typename R> struct Tol;
+template <> struct Tol<double> {
+    static constexpr double rtol = 1e-13;   // Newton converged
+    static constexpr double stall = 1e-11;  // correction stopped shrinking: rounding floor
+};
+template <> struct Tol<float> {
+    static constexpr float rtol = 4e-7f;
+    static constexpr float stall = 1e-4f;
+};
+
+// Rate table as the kernels use it: values normalised by Q, and the log-Hermite
+// form (ln V_j/V_0 and d ln V / d ln tau at the log-spaced nodes) so that the
+// interpolation is accurate in float too.
+template <typename R> struct DevTable {
+    R p0, p1_0, h0, h1_0;    // P(0)/Q, -P'(0)/Q, H(0)/Q [erg], -H'(0)/Q [erg]
+    R s1, inv_delta, delta;  // ln tau_1, 1/Delta, Delta (node spacing in ln tau)
+    R tau1, tau_last;
+    R lp[NTAB], mp[NTAB], lh[NTAB], mh[NTAB];
+};
+
+// Per-grid constants, passed by value to every kernel.
+template <typename R> struct Params {
+    int nx, ny, nz;
+    int sx, sy, sz;
+    int64_t ncell;
+    R QV;        // Q / dx^3                  [photons s^-1 cm^-3]
+    R sdx;       // sigma0 * dx               [cm^3] (times n_H x: optical depth per cell length)
+    R eps;       // mono: heating per photoionisation [erg]
+    R T_fixed, alpha_B;
+    R K[4];
+    int spectrum, thermal, recomb, collisional, cooling, weights, src_rule, n_sub;
+    const DevTable<R>* tab;
+};
+
+template <typename R> PI_HD __forceinline__ R r_exp(R v);
+template <> PI_HD __forceinline__ double r_exp<double>(double v) { return exp(v); }
+template <> PI_HD __forceinline__ float r_exp<float>(float v) { return expf(v); }
+template <typename R> PI_HD __forceinline__ R r_expm1(R v);
+template <> PI_HD __forceinline__ double r_expm1<double>(double v) { return expm1(v); }
+template <> PI_HD __forceinline__ float r_expm1<float>(float v) { return expm1f(v); }
+template <typename R> PI_HD __forceinline__ R r_log(R v);
+template <> PI_HD __forceinline__ double r_log<double>(double v) { return log(v); }
+template <> PI_HD __forceinline__ float r_log<float>(float v) { return logf(v); }
+template <typename R> PI_HD __forceinline__ R r_sqrt(R v);
+template <> PI_HD __forceinline__ double r_sqrt<double>(double v) { return sqrt(v); }
+template <> PI_HD __forceinline__ float r_sqrt<float>(float v) { return sqrtf(v); }
+template <typename R> PI_HD __forceinline__ R r_pow(R a, R b);
+template <> PI_HD __forceinline__ double r_pow<double>(double a, double b) { return pow(a, b); }
+template <> PI_HD __forceinline__ float r_pow<float>(float a, float b) { return powf(a, b); }
+template <typename R> PI_HD __forceinline__ R r_abs(R v) { return v < R(0) ? -v : v; }
+template <typename R> PI_HD __forceinline__ R r_max(R a, R b) { return a > b ? a : b; }
+template <typename R> PI_HD __forceinline__ R r_min(R a, R b) { return a < b ? a : b; }
+
+// ------------------------------------------------------------------ geometry
+// Cell (i,j,k) seen from the source vertex (Sect. 5): ad[d] = |centre - src|
+// in cell units (half integers), dominant axis a (ties z > y > x), and the
+// two factors of the photon-conserving rate: g = 1 / (4 pi r^2 ds) in cell
+// units (the shell volume the entering photons spread over), ell = ds, the
+// chord between successive planes of the dominant axis; the octant's corner
+// cell instead takes g = 1/8 of the source over its own volume with the
+// corner-cube mean chord.
+template <typename R> struct CellGeom {
+    R g, ell;
+};
+
+template <typename R>
+PI_HD __forceinline__ CellGeom<R> cell_geom(const Params<R>& p, int i, int j, int k)
+{
+    // exact half-integers: (2i + 1 - 2s) / 2
+    const R ax = r_abs(R(2 * (i - p.sx) + 1)) * R(0.5);
+    const R ay = r_abs(R(2 * (j - p.sy) + 1)) * R(0.5);
+    const R az = r_abs(R(2 * (k - p.sz) + 1)) * R(0.5);
+    const R rr = ax * ax + ay * ay + az * az;
+    const R da = (az >= ax && az >= ay) ? az : (ay >= ax ? ay : ax);
+    CellGeom<R> c;
+    if (p.src_rule && da == R(0.5)) {
+        c.g = R(0.125);
+        c.ell = R(CORNER_CHORD);
+    } else {
+        const R ds = r_sqrt(rr) / da;
+        c.g = R(1) / (R(4.0 * 3.14159265358979323846) * rr * ds);
+        c.ell = ds;
+    }
+    return c;
+}
+
+// -------------------------------------------------------------------- table
+// Normalised table value and d/dtau at optical depth tau >= 0 for P (which=0)
+// and H (which=1) together: first-order Taylor from tau = 0 below the first
+// log node, cubic Hermite in (ln tau, ln V/V0) between nodes, zero beyond.
+template <typename R>
+PI_HD __forceinline__ void table_pair(const DevTable<R>* __restrict__ T, R tau, R& P, R& dP,
+                                           R& H, R& dH)
+{
+    if (tau < T->tau1) {
+        P = T->p0 - T->p1_0 * tau;
+        dP = -T->p1_0;
+        H = T->h0 - T->h1_0 * tau;
+        dH = -T->h1_0;
+        return;
+    }
+    if (tau >= T->tau_last) {
+        P = dP = H = dH = R(0);
+        return;
+    }
+    const R s = r_log(tau);
+    const R f = (s - T->s1) * T->inv_delta;
+    int j = (int)f;                     // f >= 0 here
+    j = j < 0 ? 0 : (j > NTAB - 3 ? NTAB - 3 : j);
+    const R t = f - R(j);
+    const int n0 = j + 1, n1 = j + 2;   // node indices (node 0 is tau = 0)
+    const R t2 = t * t, t3 = t2 * t;
+    const R h00 = R(2) * t3 - R(3) * t2 + R(1), h10 = t3 - R(2) * t2 + t;
+    const R h01 = R(-2) * t3 + R(3) * t2, h11 = t3 - t2;
+    const R d00 = R(6) * t2 - R(6) * t, d10 = R(3) * t2 - R(4) * t + R(1);
+    const R d01 = R(-6) * t2 + R(6) * t, d11 = R(3) * t2 - R(2) * t;
+    const R dl = T->delta;
+    {
+        const R L0 = T->lp[n0], L1 = T->lp[n1], m0 = T->mp[n0] * dl, m1 = T->mp[n1] * dl;
+        const R L = h00 * L0 + h10 * m0 + h01 * L1 + h11 * m1;
+        const R dL = (d00 * L0 + d10 * m0 + d01 * L1 + d11 * m1) * T->inv_delta;
+        P = T->p0 * r_exp(L);
+        dP = P * dL / tau;
+    }
+    {
+        const R L0 = T->lh[n0], L1 = T->lh[n1], m0 = T->mh[n0] * dl, m1 = T->mh[n1] * dl;
+        const R L = h00 * L0 + h10 * m0 + h01 * L1 + h11 * m1;
+        const R dL = (d00 * L0 + d10 * m0 + d01 * L1 + d11 * m1) * T->inv_delta;
+        H = T->h0 * r_exp(L);
+        dH = H * dL / tau;
+    }
+}
+
+// ------------------------------------------------------ rates of one cell
+// Environment of one cell for a micro-integration: density, geometry and the
+// entering column, fixed over the interval.
+template <typename R> struct Env {
+    R n;        // n_H
+    R Qg;       // Q/dx^3 * g: photons entering per unit volume and time, unattenuated
+    R k;        // cell optical depth per unit neutral fraction = n sigma0 dx ell
+    R tau;      // entering column
+    R att;      // mono: exp(-tau)
+    R Pin, Hin; // table: normalised P, H at tau
+    R lin;      // table: -d ln P / d tau at tau (fraction absorbed per unit depth)
+};
+
+template <typename R>
+PI_HD __forceinline__ Env<R> make_env(const Params<R>& p, R n, CellGeom<R> c, R tau)
+{
+    Env<R> e;
+    e.n = n;
+    e.Qg = p.QV * c.g;
+    e.k = n * p.sdx * c.ell;
+    e.tau = tau;
+    e.att = R(0);
+    e.Pin = e.Hin = e.lin = R(0);
+    if (p.spectrum == 0) {
+        e.att = r_exp(-tau);
+    } else {
+        R dP, dH;
+        table_pair(p.tab, tau, e.Pin, dP, e.Hin, dH);
+        e.lin = e.Pin > R(0) ? -dP / e.Pin : R(0);
+    }
+    return e;
+}
+
+// Photoionisations A and photoheating G per unit volume and time, and their
+// x-derivatives: what enters the cell minus what leaves it (photon-conserving
+// form), with the entering column frozen and the cell's own depth k x.
+template <typename R>
+PI_HD __forceinline__ void photo(const Params<R>& p, const Env<R>& e, R x, R& A, R& dA, R& G,
+                                      R& dG)
+{
+    const R u = e.k * x;
+    if (p.spectrum == 0) {
+        const R f = e.Qg * e.att;
+        A = f * (-r_expm1(-u));
+        dA = f * r_exp(-u) * e.k;
+        G = A * p.eps;
+        dG = dA * p.eps;
+        return;
+    }
+    if (u * e.lin < R(THIN_CELL)) {
+        // the cell absorbs a small fraction of what enters: P(tau) - P(tau + u)
+        // as the integral of -dP/dtau over the cell by two-point Gauss-Legendre
+        // (no cancellation); the x-derivative keeps only the leading term
+        // k * mean(-dP/dtau)
+        const R c2 = R(0.28867513459481288225);   // 1 / (2 sqrt 3)
+        R P1, dP1, H1, dH1, P2, dP2, H2, dH2;
+        table_pair(p.tab, e.tau + (R(0.5) - c2) * u, P1, dP1, H1, dH1);
+        table_pair(p.tab, e.tau + (R(0.5) + c2) * u, P2, dP2, H2, dH2);
+        const R mP = R(-0.5) * (dP1 + dP2), mH = R(-0.5) * (dH1 + dH2);
+        A = e.Qg * mP * u;
+        dA = e.Qg * mP * e.k;
+        G = e.Qg * mH * u;
+        dG = e.Qg * mH * e.k;
+    } else {
+        R P, dP, H, dH;
+        table_pair(p.tab, e.tau + u, P, dP, H, dH);
+        A = e.Qg * (e.Pin - P);
+        dA = -e.Qg * dP * e.k;
+        G = e.Qg * (e.Hin - H);
+        dG = -e.Qg * dH * e.k;
+    }
+}
+
+// Temperature-dependent coefficients and their logarithmic T-derivatives:
+// case-B recombination (constant or alpha_B (T/1e4)^-0.7), collisional
+// ionisation and the cooling coefficients of Cen (1992): recombination and
+// free-free (times n_e n_HII), collisional excitation and ionisation (times
+// n_e n_HI).
+template <typename R> struct Coef {
+    R alpha, dla;
+    R aci, dlci;
+    R cii, dcii;   // value and dT-derivative (not logarithmic)
+    R cin, dcin;
+};
+
+template <typename R>
+PI_HD __forceinline__ Coef<R> coefs(const Params<R>& p, R T)
+{
+    Coef<R> c;
+    if (p.recomb == 0) {
+        c.alpha = p.alpha_B;
+        c.dla = R(0);
+    } else {
+        c.alpha = p.alpha_B * r_pow(T * R(1e-4), R(-0.7));
+        c.dla = R(-0.7) / T;
+    }
+    const R sT = r_sqrt(T);
+    const R s5 = sT * R(0.0031622776601683794);   // sqrt(T/1e5)
+    const R q = R(1) + s5;
+    const R dlq = s5 * R(0.5) / (T * q);           // d ln q / dT
+    const R invT = R(1) / T;
+    const R eci = (p.collisional || p.cooling) ? r_exp(R(-157809.1) * invT) : R(0);
+    c.aci = R(0);
+    c.dlci = R(0);
+    if (p.collisional) {
+        c.aci = R(5.85e-11) * sT / q * eci;
+        c.dlci = R(0.5) * invT - dlq + R(157809.1) * invT * invT;
+    }
+    c.cii = c.dcii = c.cin = c.dcin = R(0);
+    if (p.thermal == 1 && p.cooling) {
+        const R t6 = r_pow(T * R(1e-6), R(0.7));
+        const R crec = R(8.70e-27) * sT * r_pow(T * R(1e-3), R(-0.2)) / (R(1) + t6);
+        const R dlrec = R(0.3) * invT - R(0.7) * t6 * invT / (R(1) + t6);
+        const R cff = R(1.42e-27 * 1.3) * sT;
+        const R cce = R(7.50e-19) / q * r_exp(R(-118348.0) * invT);
+        const R dlce = -dlq + R(118348.0) * invT * invT;
+        R cci = R(0), dlci2 = R(0);
+        if (p.collisional) {
+            cci = R(1.27e-21) * sT / q * eci;
+            dlci2 = R(0.5) * invT - dlq + R(157809.1) * invT * invT;
+        }
+        c.cii = crec + cff;
+        c.dcii = crec * dlrec + cff * R(0.5) * invT;
+        c.cin = cce + cci;
+        c.dcin = cce * dlce + cci * dlci2;
+    }
+    return c;
+}
+
+// Right-hand side of eq. (2) in (x, E) and its Jacobian.
+template <typename R> struct Rhs {
+    R fx, fE, jxx, jxE, jEx, jEE;
+    R A, rec, T;
+};
+
+template <typename R>
+PI_HD __forceinline__ void rhs_xT(const Params<R>& p, const Env<R>& e, const Coef<R>& c, R x,
+                                       R& fx, R& dfx)
+{
+    R A, dA, G, dG;
+    photo(p, e, x, A, dA, G, dG);
+    const R n = e.n, y = R(1) - x;
+    fx = -A / n - c.aci * n * x * y + c.alpha * n * y * y;
+    dfx = -dA / n - c.aci * n * (R(1) - R(2) * x) - R(2) * c.alpha * n * y;
+}
+
+// Temperature floor: the coefficients see max(T, T_FLOOR) and the cooling is
+// tapered by max(0, 1 - T_FLOOR/T), so the floor is approached smoothly and
+// never crossed by cooling.
+template <typename R>
+PI_HD __forceinline__ void rhs_full(const Params<R>& p, const Env<R>& e, R x, R E, Rhs<R>& r)
+{
+    const R n = e.n;
+    R T, Tc, dTdx = R(0), dTdE = R(0), above = R(1);
+    if (p.thermal == 0) {
+        T = Tc = p.T_fixed;
+    } else {
+        T = R(2) * E / (R(3.0 * KB) * n * (R(2) - x));
+        dTdx = T / (R(2) - x);
+        dTdE = T / E;
+        above = T > R(T_FLOOR) ? R(1) : R(0);
+        Tc = T > R(T_FLOOR) ? T : R(T_FLOOR);
+    }
+    Coef<R> c = coefs(p, Tc);
+    c.dla *= above;
+    c.dlci *= above;
+    R A, dA, G, dG;
+    photo(p, e, x, A, dA, G, dG);
+    const R y = R(1) - x;
+    r.A = A;
+    r.rec = c.alpha * n * n * y * y;
+    r.T = Tc;
+    r.fx = -A / n - c.aci * n * x * y + c.alpha * n * y * y;
+    const R dfx_dT = -c.aci * c.dlci * n * x * y + c.alpha * c.dla * n * y * y;
+    r.jxx = -dA / n - c.aci * n * (R(1) - R(2) * x) - R(2) * c.alpha * n * y + dfx_dT * dTdx;
+    r.jxE = dfx_dT * dTdE;
+    if (p.thermal == 0) {
+        r.fE = r.jEx = r.jEE = R(0);
+        return;
+    }
+    const R w = T > R(T_FLOOR) ? R(1) - R(T_FLOOR) / T : R(0);
+    const R dw = T > R(T_FLOOR) ? R(T_FLOOR) / (T * T) : R(0);
+    const R n2 = n * n;
+    const R lam0 = n2 * (y * y * c.cii + x * y * c.cin);
+    const R dlam0_dx = n2 * (R(-2) * y * c.cii + (R(1) - R(2) * x) * c.cin);
+    const R dlam0_dT = above * n2 * (y * y * c.dcii + x * y * c.dcin);
+    const R dlam_dT = dlam0_dT * w + lam0 * dw;
+    r.fE = G - lam0 * w;
+    r.jEx = dG - dlam0_dx * w - dlam_dT * dTdx;
+    r.jEE = -dlam_dT * dTdE;
+}
+
+template <typename R> PI_HD __forceinline__ R e_floor(R n, R x)
+{
+    return R(1.5 * KB * T_FLOOR) * n * (R(2) - x);
+}
+
+// Scalar stage solve x = xb + hg fx(x) at fixed temperature (coefficients c):
+// Newton safeguarded by the bracket [0, 1] (the residual increases with x); a
+// root outside [0, 1] is returned clamped.
+template <typename R>
+PI_HD R solve_x(const Params<R>& p, const Env<R>& e, const Coef<R>& c, R xb, R hg, R x)
+{
+    x = r_min(r_max(x, R(0)), R(1));
+    R lo = R(0), hi = R(1);
+    R eprev = R(1e30);
+    for (int it = 0; it < NEWTON_MAXIT; ++it) {
+        R fx, dfx;
+        rhs_xT(p, e, c, x, fx, dfx);
+        const R G = x - xb - hg * fx;
+        const R dG = R(1) - hg * dfx;
+        if (G > R(0)) hi = x; else lo = x;
+        R xn = x - G / dG;
+        if (xn <= R(0) && lo == R(0)) {
+            R f0, d0;
+            rhs_xT(p, e, c, R(0), f0, d0);
+            if (-xb - hg * f0 >= R(0)) return R(0);
+        }
+        if (xn >= R(1) && hi == R(1)) {
+            R f1, d1;
+            rhs_xT(p, e, c, R(1), f1, d1);
+            if (R(1) - xb - hg * f1 <= R(0)) return R(1);
+        }
+        if (!(xn >= lo && xn <= hi)) xn = R(0.5) * (lo + hi);
+        const R err = r_abs(xn - x) / r_max(xn, R(1e-12));
+        x = xn;
+        if (err <= Tol<R>::rtol || (err >= eprev && err <= Tol<R>::stall)) break;
+        eprev = err;
+    }
+    return x;
+}
+
+// Energy residual of the stage equation with T held, after solving x at that T.
+template <typename R>
+PI_HD R t_residual(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg, R T, R& xs)
+{
+    const Coef<R> c = coefs(p, T);
+    const R x = solve_x(p, e, c, xb, hg, r_min(r_max(xb, R(0)), R(1)));
+    const R E = R(1.5 * KB) * e.n * (R(2) - x) * T;
+    Rhs<R> r;
+    rhs_full(p, e, x, E, r);
+    xs = x;
+    return E - Eb - hg * r.fE;
+}
+
+// Fallback of the T-evolving stage solve (rarely taken): nested bracketed
+// solve in (x, T) -- x at fixed T by the scalar solve, and the energy residual
+// bracketed in ln T from the floor upwards and solved by the Illinois variant
+// of regula falsi.
+template <typename R>
+PI_HD void fallback_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg,
+                                            R& x, R& E)
+{
+    R xs;
+    R la = r_log(R(T_FLOOR));
+    R ga = t_residual(p, e, xb, Eb, hg, R(T_FLOOR), xs);
+    if (ga >= R(0)) {
+        x = xs;
+        E = R(1.5 * KB) * e.n * (R(2) - xs) * R(T_FLOOR);
+        return;
+    }
+    const R Tg = r_max(R(2) * E / (R(3.0 * KB) * e.n * (R(2) - x)), R(2.0 * T_FLOOR));
+    R lb = r_log(Tg);
+    R gb = t_residual(p, e, xb, Eb, hg, Tg, xs);
+    for (int k = 0; k < 60 && gb < R(0); ++k) {
+        la = lb;
+        ga = gb;
+        lb += R(1);
+        gb = t_residual(p, e, xb, Eb, hg, r_exp(lb), xs);
+    }
+    R lc = lb;
+    int side = 0;
+    for (int it = 0; it < FALLBACK_MAXIT; ++it) {
+        lc = (la * gb - lb * ga) / (gb - ga);
+        const R gc = t_residual(p, e, xb, Eb, hg, r_exp(lc), xs);
+        if (gc == R(0) || r_abs(lb - la) <= Tol<R>::rtol * r_abs(lc)) break;
+        if ((gc > R(0)) == (gb > R(0))) {
+            lb = lc;
+            gb = gc;
+            if (side == -1) ga *= R(0.5);
+            side = -1;
+        } else {
+            la = lc;
+            ga = gc;
+            if (side == 1) gb *= R(0.5);
+            side = 1;
+        }
+    }
+    const R T = r_exp(lc);
+    t_residual(p, e, xb, Eb, hg, T, xs);
+    x = xs;
+    E = R(1.5 * KB) * e.n * (R(2) - xs) * T;
+}
+
+
+// Stage solve Y = base + hg f(Y); returns true when the fallback was needed.
+// T fixed: the scalar bracketed Newton.  T evolving: Newton on (x, E) with x
+// projected onto [0,1] and E kept positive, at most NEWTON_2D_MAXIT iterations;
+// if it has not settled, a nested bracketed solve in (x, T): x at fixed T by the
+// scalar solve, and the energy residual bracketed in ln T from the floor
+// upwards and solved by the Illinois variant of regula falsi.
+template <typename R>
+PI_HD bool stage_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg, R& x, R& E)
+{
+    if (p.thermal == 0) {
+        const Coef<R> c = coefs(p, p.T_fixed);
+        x = solve_x(p, e, c, xb, hg, x);
+        return false;
+    }
+    x = r_min(r_max(x, R(0)), R(1));
+    if (!(E > R(0))) E = e_floor(e.n, x);
+    R eprev = R(1e30);
+    for (int it = 0; it < NEWTON_2D_MAXIT; ++it) {
+        Rhs<R> r;
+        rhs_full(p, e, x, E, r);
+        const R Rx = x - xb - hg * r.fx;
+        const R RE = E - Eb - hg * r.fE;
+        const R a11 = R(1) - hg * r.jxx, a12 = -hg * r.jxE;
+        const R a21 = -hg * r.jEx, a22 = R(1) - hg * r.jEE;
+        const R det = a11 * a22 - a12 * a21;
+        R xn = x - (a22 * Rx - a12 * RE) / det;
+        R En = E - (a11 * RE - a21 * Rx) / det;
+        if (!(xn >= R(0))) xn = R(0);
+        if (xn > R(1)) xn = R(1);
+        if (!(En > R(0))) En = R(0.5) * E;
+        const R err = r_max(r_abs(xn - x) / r_max(xn, R(1e-12)), r_abs(En - E) / En);
+        // x held on a bound while the residual puts the root inside [0, 1]
+        // (a negative slope of the x-residual): not a solution
+        const bool stuck = (xn >= R(1) && Rx > R(0)) || (xn <= R(0) && Rx < R(0));
+        x = xn;
+        E = En;
+        if (!stuck && (err <= Tol<R>::rtol || (err >= eprev && err <= Tol<R>::stall))) return false;
+        eprev = err;
+    }
+    fallback_solve(p, e, xb, Eb, hg, x, E);
+    return true;
+}
+
+// Initial substep count of one micro-integration: at least n_sub, and enough
+// that at the initial rate no substep moves x by more than SUB_DX; at most
+// SUB_MAX.
+template <typename R>
+PI_HD __forceinline__ int substeps(const Params<R>& p, const Env<R>& e, R x0, R E0, R h)
+{
+    Rhs<R> r;
+    rhs_full(p, e, x0, E0, r);
+    const double s = (double)h * (double)r_abs(r.fx) / SUB_DX;
+    int ns = p.n_sub > 0 ? p.n_sub : 1;
+    if (s > (double)ns) ns = s >= (double)SUB_MAX ? SUB_MAX : (int)ceil(s);
+    return ns;
+}
+
+// One step of the two-stage, L-stable, stiffly accurate SDIRK method
+// (gamma = 1 - 1/sqrt 2); the second stage starts from y + ((1-gamma)/gamma)(Y1 - y).
+template <typename R>
+PI_HD __forceinline__ bool sdirk_step(const Params<R>& p, const Env<R>& e, R hs, R& x, R& E)
+{
+    const R gam = R(0.29289321881345247560);          // 1 - 1/sqrt(2)
+    const R cst = R(2.41421356237309504880);          // (1 - gamma)/gamma
+    R X1 = x, F1 = E;
+    bool fb = stage_solve(p, e, x, E, gam * hs, X1, F1);
+    const R xb = x + cst * (X1 - x);
+    const R Eb = E + cst * (F1 - E);
+    R X2 = X1, F2 = F1;
+    fb |= stage_solve(p, e, xb, Eb, gam * hs, X2, F2);
+    x = X2;
+    E = F2;
+    return fb;
+}
+
+// Micro-integration M(x0, E0; tau, h) with deterministic substep control: the
+// interval is cut into U = ns 2^SUB_LEVELS units; a substep of s units is
+// rejected and halved (while s > 1) if a stage needed the fallback, x moved by
+// more than REJ_DX or E changed by more than a factor REJ_E, and doubled again
+// after an accepted substep when the position allows.  E is held at or above
+// the temperature floor between substeps.
+template <typename R>
+PI_HD void micro(const Params<R>& p, const Env<R>& e, R h, R& x, R& E)
+{
+    if (!(h > R(0))) return;
+    const bool evolve = p.thermal == 1;
+    if (evolve && E < e_floor(e.n, x)) E = e_floor(e.n, x);
+    const int ns = substeps(p, e, x, E, h);
+    const int top = 1 << SUB_LEVELS;
+    const int U = ns * top;
+    int pos = 0, s = top;
+    while (pos < U) {
+        const R hs = R((double)h * (double)s / (double)U);
+        R xn = x, En = E;
+        const bool fb = sdirk_step(p, e, hs, xn, En);
+        const bool bad = fb || r_abs(xn - x) > R(REJ_DX) ||
+                         (evolve && (En > R(REJ_E) * E || En * R(REJ_E) < E));
+        if (bad && s > 1) {
+            s >>= 1;
+            continue;
+        }
+        x = xn;
+        E = En;
+        if (evolve && E < e_floor(e.n, x)) E = e_floor(e.n, x);
+        pos += s;
+        if (s < top && pos % (2 * s) == 0) s <<= 1;
+    }
+}
+
+// Per-cell limit of eq. (4) at (x, E) with the entering column of t_n:
+// min(K1 t_rec, K2 E/|dE/dt|, K3 max(0.05, x)/|dy/dt|, K4/|dy/dt|); a factor
+// of +inf (or any value above 1e30) disables its criterion, and a zero rate
+// does not limit.
+template <typename R>
+PI_HD __forceinline__ double cell_dt(const Params<R>& p, const Rhs<R>& r, R n, R x, R E)
+{
+    const R KOFF = R(1e30);
+    double dt = __builtin_huge_val();
+    const double ydot = (double)r_abs(r.fx);
+    if (p.K[0] < KOFF) {
+        const Coef<R> c = coefs(p, r.T);
+        dt = fmin(dt, (double)p.K[0] / ((double)c.alpha * (double)n));
+    }
+    if (p.K[1] < KOFF && p.thermal == 1 && r.fE != R(0))
+        dt = fmin(dt, (double)p.K[1] * (double)E / fabs((double)r.fE));
+    if (p.K[2] < KOFF && ydot > 0.0) dt = fmin(dt, (double)p.K[2] * fmax(0.05, (double)x) / ydot);
+    if (p.K[3] < KOFF && ydot > 0.0) dt = fmin(dt, (double)p.K[3] / ydot);
+    return dt;
+}
+
+}  // namespace pi

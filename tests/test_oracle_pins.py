@@ -160,7 +160,7 @@ def test_micro_recombination_only_closed_form(oracle_lib, y0):
     """No source: dy/dt = -alpha n y^2 gives y(t) = y0 / (1 + alpha n y0 t).
     The integrator is second order: the error falls ~4x per halving of h."""
     n, a = 100.0, 2.59e-13
-    h = 0.3 / (a * n)
+    h = 0.15 / (a * n)   # below the per-cell substep threshold: n_sub sets the count
     errs = []
     for nsub in (1, 2, 4, 8):
         pb = _cell_problem(n_sub=nsub)
@@ -169,8 +169,9 @@ def test_micro_recombination_only_closed_form(oracle_lib, y0):
         errs.append(abs((1.0 - x1) - exact) / exact)
     assert errs[1] < 2e-3
     for e0, e1 in zip(errs, errs[1:]):
-        # second order until the rounding floor of 1 - x (x ~ 1 - 1e-6) is hit
-        assert e1 < e0 / 3.0 or e1 < 1e-9
+        # second order until the rounding floor of y = 1 - x is hit (with
+        # y ~ 1e-6 each stage carries ~1e-10 relative rounding of y)
+        assert e1 < e0 / 3.0 or e1 < 1e-8
 
 
 @pytest.mark.parametrize("u0", [0.05, 2.0, 30.0])
