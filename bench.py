@@ -118,10 +118,8 @@ def main() -> int:
             g.step_o2(t_pre)
         t, n, _ = g.state()
         pre = n
-        if time.time() - tick > 20:
-            print(f"# pre-evolution: {pre} steps, t = {t / spec.t_rec:.4f} t_rec", file=sys.stderr,
-                  flush=True)
-            tick = time.time()
+        print(f"# pre-evolution: {pre} steps, t = {t / spec.t_rec:.4f} t_rec, "
+              f"{time.time() - tick:.1f} s", file=sys.stderr, flush=True)
         if t >= t_pre:
             break
     t_start, n_start, _ = g.state()

@@ -806,9 +806,9 @@ static int sdirk_step(const orc_desc* g, const cellenv* c, double hs, double* x,
  * paper integrates with CVODE (backward differences, Newton); this oracle uses
  * a deterministic substep control instead (reading): the interval is cut into
  * U = ns 2^SUB_LEVELS units (ns from substeps()); a substep of s units is
- * rejected and halved if a stage needed the fallback solve, x moved by more
- * than REJ_DX or E changed by more than a factor REJ_E (while s > 1), and an
- * accepted substep is doubled again when the position allows.  E is held at
+ * rejected and halved if x moved by more than REJ_DX or E changed by more than
+ * a factor REJ_E (while s > 1), and an accepted substep is doubled again when
+ * the position allows.  E is held at
  * or above the temperature floor between substeps. */
 static void micro(const orc_desc* g, const cellenv* c, double x0, double E0, double h,
                   double* x1, double* E1)
@@ -823,8 +823,8 @@ static void micro(const orc_desc* g, const cellenv* c, double x0, double E0, dou
         while (p < U) {
             const double hs = h * (double)s / (double)U;
             double xn = x, En = E;
-            int fb = sdirk_step(g, c, hs, &xn, &En);
-            int bad = fb || fabs(xn - x) > REJ_DX ||
+            sdirk_step(g, c, hs, &xn, &En);
+            int bad = fabs(xn - x) > REJ_DX ||
                       (g->thermal == ORC_T_EVOLVE && (En > REJ_E * E || En * REJ_E < E));
             if (bad && s > 1) {
                 s >>= 1;

@@ -542,9 +542,9 @@ PI_HD __forceinline__ bool sdirk_step(const Params<R>& p, const Env<R>& e, R hs,
 
 // Micro-integration M(x0, E0; tau, h) with deterministic substep control: the
 // interval is cut into U = ns 2^SUB_LEVELS units; a substep of s units is
-// rejected and halved (while s > 1) if a stage needed the fallback, x moved by
-// more than REJ_DX or E changed by more than a factor REJ_E, and doubled again
-// after an accepted substep when the position allows.  E is held at or above
+// rejected and halved (while s > 1) if x moved by more than REJ_DX or E changed
+// by more than a factor REJ_E, and doubled again after an accepted substep
+// when the position allows.  E is held at or above
 // the temperature floor between substeps.
 template <typename R>
 PI_HD void micro(const Params<R>& p, const Env<R>& e, R h, R& x, R& E)
@@ -559,8 +559,8 @@ PI_HD void micro(const Params<R>& p, const Env<R>& e, R h, R& x, R& E)
     while (pos < U) {
         const R hs = R((double)h * (double)s / (double)U);
         R xn = x, En = E;
-        const bool fb = sdirk_step(p, e, hs, xn, En);
-        const bool bad = fb || r_abs(xn - x) > R(REJ_DX) ||
+        sdirk_step(p, e, hs, xn, En);
+        const bool bad = r_abs(xn - x) > R(REJ_DX) ||
                          (evolve && (En > R(REJ_E) * E || En * R(REJ_E) < E));
         if (bad && s > 1) {
             s >>= 1;
