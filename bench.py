@@ -139,6 +139,8 @@ def main() -> int:
     ms_step = ms / args.steps
     value = spec.ncells * args.steps / (ms * 1e-3)
 
+    work = g.work_counters(reset=True)   # over pre-evolution + warm-up + timed steps
+
     # phase-by-phase timing of the same kernels (same stream, HIP events)
     phases = {"timestep": 0.0, "chem_predictor": 0.0, "raytrace_half": 0.0,
               "chem_corrector": 0.0, "raytrace": 0.0}
@@ -160,6 +162,7 @@ def main() -> int:
             phases[k] += ev[i].elapsed_time(ev[i + 1]) / args.phase_steps
     diag = g.diagnostics()
     t_now, n_now, _ = g.state()
+    work_phase = g.work_counters(reset=True)   # the phase-timed steps only
 
     W = word_bytes(args.precision)
     N = spec.ncells
@@ -195,6 +198,11 @@ def main() -> int:
             "n": args.n, "precision": args.precision, "pre_steps": int(n_start),
             "t_start_trec": t_start / spec.t_rec, "t_end_trec": t_now / spec.t_rec,
             "r_ion_cells": diag["r_ion"] / spec.dx, "n_sub": spec.n_sub,
+            "substeps_per_cell_update": (work_phase["accepted"] + work_phase["rejected"])
+            / (spec.ncells * args.phase_steps),
+            "rejected_frac": work_phase["rejected"]
+            / max(1, work_phase["accepted"] + work_phase["rejected"]),
+            "fallbacks_per_cell_update": work_phase["fallbacks"] / (spec.ncells * args.phase_steps),
         },
         "roofline": roofline,
     }

@@ -160,6 +160,12 @@ pi_status pi_grid_state(pi_grid* grid, double* t, int64_t* nsteps, double* last_
  * out[5] number of non-finite cells, out[6] number of octants, out[7] time t. */
 pi_status pi_diagnostics(pi_grid* grid, double* out, void* stream);
 
+/* Work of the micro-physics updates since the last reset (SYNCHRONISES):
+ * out[0] accepted substeps, out[1] rejected substeps, out[2] stage solves that
+ * needed the bracketed fallback.  reset != 0 zeroes the counters after reading.
+ * Counters are summed over all pi_chem_step / step calls of the grid. */
+pi_status pi_work_counters(pi_grid* grid, int64_t* out, int reset, void* stream);
+
 /* Host-only: blackbody rate table of the TABLE spectrum (Sect. 2, rates
  * tabulated against optical depth): out[5*PI_NTAB] = node optical depths, P
  * (photons/s surviving a threshold column tau), -dP/dtau, H (excess energy

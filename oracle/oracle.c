@@ -39,6 +39,7 @@
  */
 #include "oracle.h"
 
+#include <float.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -693,8 +694,10 @@ static int stage_solve(const orc_desc* g, const cellenv* c, double xb, double Eb
         if (!(En > 0.0)) En = 0.5 * E;
         double e = fmax(fabs(xn - x) / fmax(xn, 1e-12), fabs(E - En) / En);
         /* x held on a bound while the residual puts the root inside [0, 1]
-         * (a negative slope of the x-residual): not a solution */
-        const int stuck = (xn >= 1.0 && Rx > 0.0) || (xn <= 0.0 && Rx < 0.0);
+         * (a negative slope of the x-residual): not a solution -- unless at 1
+         * the root lies within half a rounding step of 1 */
+        const int stuck = (xn >= 1.0 && Rx > 0.5 * (DBL_EPSILON / 2.0) * fabs(a11)) ||
+                          (xn <= 0.0 && Rx < 0.0);
         x = xn;
         E = En;
         /* converged; or stalled at the rounding floor of the residual */

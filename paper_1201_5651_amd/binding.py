@@ -29,7 +29,7 @@ PI_NTAB = 64
 ABI_SYMBOLS = (
     "pi_grid_create", "pi_grid_destroy", "pi_raytrace", "pi_chem_step", "pi_timestep",
     "pi_step_o2", "pi_step_o1", "pi_init_energy", "pi_set_time", "pi_grid_state",
-    "pi_diagnostics", "pi_table_build", "pi_last_error", "pi_abi_version",
+    "pi_diagnostics", "pi_work_counters", "pi_table_build", "pi_last_error", "pi_abi_version",
 )
 
 
@@ -90,6 +90,7 @@ def lib() -> C.CDLL:
         L.pi_set_time.argtypes = [vp, d, i64, vp]
         L.pi_grid_state.argtypes = [vp, dp, C.POINTER(C.c_int64), dp, vp]
         L.pi_diagnostics.argtypes = [vp, dp, vp]
+        L.pi_work_counters.argtypes = [vp, C.POINTER(C.c_int64), i32, vp]
         L.pi_table_build.argtypes = [d, d, dp]
         L.pi_last_error.restype = C.c_char_p
         L.pi_abi_version.restype = C.c_int
@@ -222,6 +223,11 @@ class Grid:
         check(lib().pi_diagnostics(self._h, out, self._stream()))
         keys = ("n_ion", "v_ion", "r_ion", "photo_rate", "recomb_rate", "nonfinite", "octants", "t")
         return dict(zip(keys, list(out)))
+
+    def work_counters(self, reset: bool = False):
+        out = (C.c_int64 * 3)()
+        check(lib().pi_work_counters(self._h, out, int(reset), self._stream()))
+        return {"accepted": out[0], "rejected": out[1], "fallbacks": out[2]}
 
     def run(self, t_end: float, order: int = 2, max_steps: int = 10**8, check_every: int = 64):
         """Step until t_end (order 2: algorithm 3; order 1: algorithm 2).

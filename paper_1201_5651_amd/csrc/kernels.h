@@ -23,6 +23,7 @@ struct DevState {
     long long nsteps;
     long long pad;
     double diag[8];   // see pi_diagnostics
+    unsigned long long work[4];   // micro-integration work: accepted, rejected substeps, fallbacks
 };
 
 template <typename R>
@@ -30,7 +31,8 @@ hipError_t launch_sweep_stage(const Params<R>& p, const R* nH, const R* x, R* ta
                               const int4* tiles, int first, int count, hipStream_t s);
 template <typename R>
 hipError_t launch_chem(const Params<R>& p, const R* nH, const R* x0, const R* E0, const R* tau,
-                       R* x1, R* E1, const DevState* st, double hscale, hipStream_t s);
+                       R* x1, R* E1, const DevState* st, double hscale, unsigned long long* ctr,
+                       hipStream_t s);
 template <typename R>
 hipError_t launch_dtdiag(const Params<R>& p, const R* nH, const R* x, const R* E, const R* tau,
                          double* part, int nblk, DevState* st, double t_end, double cell_vol,

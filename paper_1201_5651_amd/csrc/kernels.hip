@@ -125,22 +125,43 @@ k_sweep(Params<R> p, const R* __restrict__ nH, const R* __restrict__ xs, R* __re
 }
 
 // ---------------------------------------------------------------- chemistry
+// Work counters are summed per wavefront and added with one atomic per
+// counter per wavefront.
+__device__ __forceinline__ void add_work(unsigned long long* ctr, const Work& w)
+{
+    unsigned long long a = (unsigned long long)w.accepted, r = (unsigned long long)w.rejected,
+                       f = (unsigned long long)w.fallbacks;
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        r += __shfl_xor(r, o, 64);
+        f += __shfl_xor(f, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&ctr[0], a);
+        atomicAdd(&ctr[1], r);
+        atomicAdd(&ctr[2], f);
+    }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_chem(Params<R> p, const R* __restrict__ nH, const R* x0, const R* E0, const R* __restrict__ tau,
-       R* x1, R* E1, const DevState* __restrict__ st, double hscale)
+       R* x1, R* E1, const DevState* __restrict__ st, double hscale, unsigned long long* ctr)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= p.ncell) return;
-    const double hd = st ? hscale * st->dt : hscale;
-    const int i = q % p.nx, j = (q / p.nx) % p.ny, k = q / (p.nx * p.ny);
-    const CellGeom<R> cg = cell_geom(p, i, j, k);
-    const Env<R> e = make_env(p, nH[q], cg, tau[q]);
-    R x = x0[q];
-    R E = E0 ? E0[q] : R(0);
-    micro(p, e, R(hd), x, E);
-    x1[q] = x;
-    if (E1) E1[q] = E;
+    Work w{ 0, 0, 0 };
+    if (q < p.ncell) {
+        const double hd = st ? hscale * st->dt : hscale;
+        const int i = q % p.nx, j = (q / p.nx) % p.ny, k = q / (p.nx * p.ny);
+        const CellGeom<R> cg = cell_geom(p, i, j, k);
+        const Env<R> e = make_env(p, nH[q], cg, tau[q]);
+        R x = x0[q];
+        R E = E0 ? E0[q] : R(0);
+        micro(p, e, R(hd), x, E, w);
+        x1[q] = x;
+        if (E1) E1[q] = E;
+    }
+    add_work(ctr, w);
 }
 
 // ------------------------------------------------------ timestep + diagnostics
@@ -270,11 +291,12 @@ hipError_t launch_sweep_stage(const Params<R>& p, const R* nH, const R* x, R* ta
 
 template <typename R>
 hipError_t launch_chem(const Params<R>& p, const R* nH, const R* x0, const R* E0, const R* tau,
-                       R* x1, R* E1, const DevState* st, double hscale, hipStream_t s)
+                       R* x1, R* E1, const DevState* st, double hscale, unsigned long long* ctr,
+                       hipStream_t s)
 {
     const int nb = (int)((p.ncell + 255) / 256);
     hipLaunchKernelGGL((k_chem<R>), dim3(nb), dim3(256), 0, s, p, nH, x0, E0, tau, x1, E1, st,
-                       hscale);
+                       hscale, ctr);
     return hipGetLastError();
 }
 
@@ -306,7 +328,8 @@ hipError_t launch_energy(int64_t n, const R* nH, const R* x, R* E, double T0, hi
     template hipError_t launch_sweep_stage<R>(const Params<R>&, const R*, const R*, R*,           \
                                               const int4*, int, int, hipStream_t);                 \
     template hipError_t launch_chem<R>(const Params<R>&, const R*, const R*, const R*, const R*,  \
-                                       R*, R*, const DevState*, double, hipStream_t);              \
+                                       R*, R*, const DevState*, double, unsigned long long*,       \
+                                       hipStream_t);                                               \
     template hipError_t launch_dtdiag<R>(const Params<R>&, const R*, const R*, const R*,          \
                                          const R*, double*, int, DevState*, double, double, int,   \
                                          hipStream_t);                                             \

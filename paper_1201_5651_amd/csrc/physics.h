@@ -39,10 +39,12 @@ constexpr double REJ_E = 3.0;     // ... or changes E by more than this factor
 
 template <typename R> struct Tol;
 template <> struct Tol<double> {
+    static constexpr double half_ulp1 = 5.551115123125783e-17;   // half the spacing below 1
     static constexpr double rtol = 1e-13;   // Newton converged
     static constexpr double stall = 1e-11;  // correction stopped shrinking: rounding floor
 };
 template <> struct Tol<float> {
+    static constexpr float half_ulp1 = 2.98023224e-8f;
     static constexpr float rtol = 4e-7f;
     static constexpr float stall = 1e-4f;
 };
@@ -71,21 +73,33 @@ template <typename R> struct Params {
     const DevTable<R>* tab;
 };
 
+// Float arithmetic uses the hardware transcendental instructions (a few ulp,
+// far inside the 1e-4 float tolerance); double uses the correctly rounded
+// library routines.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define PI_FEXP(v) __expf(v)
+#define PI_FLOG(v) __logf(v)
+#define PI_FPOW(a, b) __powf(a, b)
+#else   // host-side unit harnesses
+#define PI_FEXP(v) expf(v)
+#define PI_FLOG(v) logf(v)
+#define PI_FPOW(a, b) powf(a, b)
+#endif
 template <typename R> PI_HD __forceinline__ R r_exp(R v);
 template <> PI_HD __forceinline__ double r_exp<double>(double v) { return exp(v); }
-template <> PI_HD __forceinline__ float r_exp<float>(float v) { return expf(v); }
+template <> PI_HD __forceinline__ float r_exp<float>(float v) { return PI_FEXP(v); }
 template <typename R> PI_HD __forceinline__ R r_expm1(R v);
 template <> PI_HD __forceinline__ double r_expm1<double>(double v) { return expm1(v); }
 template <> PI_HD __forceinline__ float r_expm1<float>(float v) { return expm1f(v); }
 template <typename R> PI_HD __forceinline__ R r_log(R v);
 template <> PI_HD __forceinline__ double r_log<double>(double v) { return log(v); }
-template <> PI_HD __forceinline__ float r_log<float>(float v) { return logf(v); }
+template <> PI_HD __forceinline__ float r_log<float>(float v) { return PI_FLOG(v); }
 template <typename R> PI_HD __forceinline__ R r_sqrt(R v);
 template <> PI_HD __forceinline__ double r_sqrt<double>(double v) { return sqrt(v); }
 template <> PI_HD __forceinline__ float r_sqrt<float>(float v) { return sqrtf(v); }
 template <typename R> PI_HD __forceinline__ R r_pow(R a, R b);
 template <> PI_HD __forceinline__ double r_pow<double>(double a, double b) { return pow(a, b); }
-template <> PI_HD __forceinline__ float r_pow<float>(float a, float b) { return powf(a, b); }
+template <> PI_HD __forceinline__ float r_pow<float>(float a, float b) { return PI_FPOW(a, b); }
 template <typename R> PI_HD __forceinline__ R r_abs(R v) { return v < R(0) ? -v : v; }
 template <typename R> PI_HD __forceinline__ R r_max(R a, R b) { return a > b ? a : b; }
 template <typename R> PI_HD __forceinline__ R r_min(R a, R b) { return a < b ? a : b; }
@@ -471,6 +485,12 @@ PI_HD void fallback_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg,
 // if it has not settled, a nested bracketed solve in (x, T): x at fixed T by the
 // scalar solve, and the energy residual bracketed in ln T from the floor
 // upwards and solved by the Illinois variant of regula falsi.
+// Work done by one micro-integration (accepted and rejected substeps, stage
+// fallbacks), summed per launch for the performance counters.
+struct Work {
+    int accepted, rejected, fallbacks;
+};
+
 template <typename R>
 PI_HD bool stage_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg, R& x, R& E)
 {
@@ -497,8 +517,10 @@ PI_HD bool stage_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg, R&
         if (!(En > R(0))) En = R(0.5) * E;
         const R err = r_max(r_abs(xn - x) / r_max(xn, R(1e-12)), r_abs(En - E) / En);
         // x held on a bound while the residual puts the root inside [0, 1]
-        // (a negative slope of the x-residual): not a solution
-        const bool stuck = (xn >= R(1) && Rx > R(0)) || (xn <= R(0) && Rx < R(0));
+        // (a negative slope of the x-residual): not a solution -- unless at 1
+        // the root lies within half a rounding step of 1
+        const bool stuck = (xn >= R(1) && Rx > Tol<R>::half_ulp1 * r_abs(a11)) ||
+                           (xn <= R(0) && Rx < R(0));
         x = xn;
         E = En;
         if (!stuck && (err <= Tol<R>::rtol || (err >= eprev && err <= Tol<R>::stall))) return false;
@@ -525,16 +547,16 @@ PI_HD __forceinline__ int substeps(const Params<R>& p, const Env<R>& e, R x0, R 
 // One step of the two-stage, L-stable, stiffly accurate SDIRK method
 // (gamma = 1 - 1/sqrt 2); the second stage starts from y + ((1-gamma)/gamma)(Y1 - y).
 template <typename R>
-PI_HD __forceinline__ bool sdirk_step(const Params<R>& p, const Env<R>& e, R hs, R& x, R& E)
+PI_HD __forceinline__ int sdirk_step(const Params<R>& p, const Env<R>& e, R hs, R& x, R& E)
 {
     const R gam = R(0.29289321881345247560);          // 1 - 1/sqrt(2)
     const R cst = R(2.41421356237309504880);          // (1 - gamma)/gamma
     R X1 = x, F1 = E;
-    bool fb = stage_solve(p, e, x, E, gam * hs, X1, F1);
+    int fb = stage_solve(p, e, x, E, gam * hs, X1, F1) ? 1 : 0;
     const R xb = x + cst * (X1 - x);
     const R Eb = E + cst * (F1 - E);
     R X2 = X1, F2 = F1;
-    fb |= stage_solve(p, e, xb, Eb, gam * hs, X2, F2);
+    fb += stage_solve(p, e, xb, Eb, gam * hs, X2, F2) ? 1 : 0;
     x = X2;
     E = F2;
     return fb;
@@ -547,7 +569,7 @@ PI_HD __forceinline__ bool sdirk_step(const Params<R>& p, const Env<R>& e, R hs,
 // when the position allows.  E is held at or above
 // the temperature floor between substeps.
 template <typename R>
-PI_HD void micro(const Params<R>& p, const Env<R>& e, R h, R& x, R& E)
+PI_HD void micro(const Params<R>& p, const Env<R>& e, R h, R& x, R& E, Work& w)
 {
     if (!(h > R(0))) return;
     const bool evolve = p.thermal == 1;
@@ -559,13 +581,15 @@ PI_HD void micro(const Params<R>& p, const Env<R>& e, R h, R& x, R& E)
     while (pos < U) {
         const R hs = R((double)h * (double)s / (double)U);
         R xn = x, En = E;
-        sdirk_step(p, e, hs, xn, En);
+        w.fallbacks += sdirk_step(p, e, hs, xn, En);
         const bool bad = r_abs(xn - x) > R(REJ_DX) ||
                          (evolve && (En > R(REJ_E) * E || En * R(REJ_E) < E));
         if (bad && s > 1) {
             s >>= 1;
+            ++w.rejected;
             continue;
         }
+        ++w.accepted;
         x = xn;
         E = En;
         if (evolve && E < e_floor(e.n, x)) E = e_floor(e.n, x);

@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -241,7 +242,10 @@ pi_status chem_t(pi_grid* g, bool dev_dt, double h, int tau_buf, int from, int t
         E0 = nullptr;
         E1 = nullptr;
     }
-    HIP_OR(launch_chem<R>(params<R>(g), nH, x0, E0, tau, x1, E1, dev_dt ? g->st : nullptr, h, s),
+    unsigned long long* ctr = reinterpret_cast<unsigned long long*>(
+        reinterpret_cast<char*>(g->st) + offsetof(DevState, work));
+    HIP_OR(launch_chem<R>(params<R>(g), nH, x0, E0, tau, x1, E1, dev_dt ? g->st : nullptr, h,
+                          ctr, s),
            "chemistry launch");
     return PI_OK;
 }
@@ -486,6 +490,22 @@ pi_status pi_grid_state(pi_grid* g, double* t, int64_t* nsteps, double* last_dt,
     if (t) *t = h.t;
     if (nsteps) *nsteps = h.nsteps;
     if (last_dt) *last_dt = h.last_dt;
+    return PI_OK;
+}
+
+pi_status pi_work_counters(pi_grid* g, int64_t* out, int reset, void* stream)
+{
+    if (!g || !out) return fail(PI_EINVAL, "null argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevState h{};
+    HIP_OR(hipMemcpyAsync(&h, g->st, sizeof(h), hipMemcpyDeviceToHost, s), "state read");
+    HIP_OR(hipStreamSynchronize(s), "state read sync");
+    for (int i = 0; i < 3; ++i) out[i] = (int64_t)h.work[i];
+    if (reset) {
+        for (int i = 0; i < 4; ++i) h.work[i] = 0;
+        HIP_OR(hipMemcpyAsync(g->st, &h, sizeof(h), hipMemcpyHostToDevice, s), "state write");
+        HIP_OR(hipStreamSynchronize(s), "state write sync");
+    }
     return PI_OK;
 }
 
