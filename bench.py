@@ -27,6 +27,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# MI355X vector peaks [TFLOP/s]
+VALU_PEAK = {"fp32": 157.3, "fp64": 78.6, "mixed": 157.3}
+# Algorithmic flops of the micro-physics, counted from the source (add, mul,
+# fma-half, reciprocal, square root and transcendental = 1 flop each): one
+# Newton iteration of the coupled (x, E) stage solve with the tabulated
+# spectrum, evolving temperature, power-law recombination, collisional
+# ionisation and cooling, optically thick branch; and the per-cell set-up of
+# one micro-integration (geometry, entering-column table lookup, initial rate).
+FLOP_NEWTON = 262
+FLOP_CELL_SETUP = 330
 
 
 def word_bytes(precision: str) -> int:
@@ -90,6 +100,9 @@ def main() -> int:
     ap.add_argument("--cpu-sample-n", type=int, default=32)
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (a known-size "
+                         "reference for hardware traffic counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -160,23 +173,46 @@ def main() -> int:
         torch.cuda.synchronize()
         for i, k in enumerate(phases):
             phases[k] += ev[i].elapsed_time(ev[i + 1]) / args.phase_steps
+    if args.calib_copy_mib > 0:
+        nel = args.calib_copy_mib * 2**20 // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     diag = g.diagnostics()
     t_now, n_now, _ = g.state()
     work_phase = g.work_counters(reset=True)   # the phase-timed steps only
 
     W = word_bytes(args.precision)
     N = spec.ncells
+    newton_per_launch = work_phase["newton"] / (2 * args.phase_steps)
     # algorithmic bytes per launch: chemistry reads n_H, x, E, tau and writes
     # x, E (6 words per cell); a raytrace reads n_H, x and writes tau (3 words);
     # the timestep reads n_H, x, E, tau (4 words)
     alg = {"chem_predictor": 6 * W * N, "chem_corrector": 6 * W * N,
            "raytrace_half": 3 * W * N, "raytrace": 3 * W * N, "timestep": 4 * W * N}
+    hbm = {k: alg[k] / (phases[k] * 1e-3) / 1e9 for k in phases}
     dom = max(phases, key=phases.get)
-    achieved = alg[dom] / (phases[dom] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": None,
-                "phase_ms": {k: round(v, 4) for k, v in phases.items()}}
+    if dom.startswith("chem"):
+        # the micro-physics is bound by vector arithmetic: its HBM traffic is
+        # a few words per cell against hundreds of flops
+        flops = newton_per_launch * FLOP_NEWTON + N * FLOP_CELL_SETUP
+        t_chem = 0.5 * (phases["chem_predictor"] + phases["chem_corrector"])
+        achieved = flops / (t_chem * 1e-3) / 1e12
+        peak = VALU_PEAK[args.precision]
+        roofline = {"bound": "alu", "kernel": "k_chem (" + dom + ")",
+                    "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(achieved / peak, 5), "traffic": None,
+                    "flops_per_launch": flops,
+                    "hbm_GBs_of_dominant": round(hbm[dom], 2)}
+    else:
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(hbm[dom], 2),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(hbm[dom] / HBM_PEAK_GBS, 5),
+                    "traffic": None}
+    roofline["phase_ms"] = {k: round(v, 4) for k, v in phases.items()}
+    roofline["raytrace_hbm"] = {"achieved": round(hbm["raytrace"], 2), "unit": "GB/s",
+                                "frac": round(hbm["raytrace"] / HBM_PEAK_GBS, 5)}
 
     out = {
         "metric": "cell-updates/s per raytrace+chemistry step at 256^3",
@@ -203,6 +239,7 @@ def main() -> int:
             "rejected_frac": work_phase["rejected"]
             / max(1, work_phase["accepted"] + work_phase["rejected"]),
             "fallbacks_per_cell_update": work_phase["fallbacks"] / (spec.ncells * args.phase_steps),
+            "newton_per_cell_update": work_phase["newton"] / (spec.ncells * args.phase_steps),
         },
         "roofline": roofline,
     }

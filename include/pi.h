@@ -162,7 +162,8 @@ pi_status pi_diagnostics(pi_grid* grid, double* out, void* stream);
 
 /* Work of the micro-physics updates since the last reset (SYNCHRONISES):
  * out[0] accepted substeps, out[1] rejected substeps, out[2] stage solves that
- * needed the bracketed fallback.  reset != 0 zeroes the counters after reading.
+ * needed the bracketed fallback, out[3] Newton iterations of the stage solves
+ * (out has 4 elements).  reset != 0 zeroes the counters after reading.
  * Counters are summed over all pi_chem_step / step calls of the grid. */
 pi_status pi_work_counters(pi_grid* grid, int64_t* out, int reset, void* stream);
 

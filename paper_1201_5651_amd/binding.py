@@ -225,9 +225,9 @@ class Grid:
         return dict(zip(keys, list(out)))
 
     def work_counters(self, reset: bool = False):
-        out = (C.c_int64 * 3)()
+        out = (C.c_int64 * 4)()
         check(lib().pi_work_counters(self._h, out, int(reset), self._stream()))
-        return {"accepted": out[0], "rejected": out[1], "fallbacks": out[2]}
+        return {"accepted": out[0], "rejected": out[1], "fallbacks": out[2], "newton": out[3]}
 
     def run(self, t_end: float, order: int = 2, max_steps: int = 10**8, check_every: int = 64):
         """Step until t_end (order 2: algorithm 3; order 1: algorithm 2).

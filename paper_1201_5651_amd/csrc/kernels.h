@@ -8,8 +8,11 @@
 
 namespace pi {
 
-// Tile of the raytrace wavefront (octant-local cells per workgroup).
-constexpr int SWEEP_TX = 8, SWEEP_TY = 8, SWEEP_TZ = 8;
+// Edge of the cubic tile of the raytrace wavefront (octant-local cells swept by
+// one workgroup, one thread per cell).
+constexpr int SWEEP_T = 8;
+// Threads per workgroup of the micro-physics kernel.
+constexpr int CHEM_BLOCK = 256;
 // Per-block partials of the timestep/diagnostics reduction:
 // [0] min dt limit, [1] sum n(1-x), [2] sum (1-x), [3] sum A, [4] sum recomb, [5] non-finite cells
 constexpr int NPART = 6;
@@ -23,8 +26,13 @@ struct DevState {
     long long nsteps;
     long long pad;
     double diag[8];   // see pi_diagnostics
-    unsigned long long work[4];   // micro-integration work: accepted, rejected substeps, fallbacks
 };
+
+// Micro-integration work counters (accepted, rejected substeps, fallback
+// solves, Newton iterations), each spread over WORK_SLOTS slots so that the
+// per-workgroup atomic additions do not all meet on one address; a reader sums
+// the slots.  Layout: counter c, slot s at [c * WORK_SLOTS + s].
+constexpr int WORK_COUNTERS = 4, WORK_SLOTS = 64;
 
 template <typename R>
 hipError_t launch_sweep_stage(const Params<R>& p, const R* nH, const R* x, R* tau,

@@ -16,6 +16,37 @@
 namespace pi {
 
 // ------------------------------------------------------------------ raytrace
+// Weighted upstream average of the short-characteristics interpolation:
+// sum w_i T_i / sum w_i with w_i = g_i (Mellema: divided by max(0.6, T_i)).
+template <typename R>
+__device__ __forceinline__ R sc_average(bool mellema, R g00, R g10, R g01, R g11, R T00, R T10,
+                                        R T01, R T11)
+{
+    R w00 = g00, w10 = g10, w01 = g01, w11 = g11;
+    if (mellema) {
+        w00 = g00 * r_rcp(r_max(R(W_FLOOR), T00));
+        w10 = g10 * r_rcp(r_max(R(W_FLOOR), T10));
+        w01 = g01 * r_rcp(r_max(R(W_FLOOR), T01));
+        w11 = g11 * r_rcp(r_max(R(W_FLOOR), T11));
+    }
+    return (w00 * T00 + w10 * T10 + w01 * T01 + w11 * T11) * r_rcp(w00 + w10 + w01 + w11);
+}
+// double keeps the divisions of the definition
+template <>
+__device__ __forceinline__ double sc_average<double>(bool mellema, double g00, double g10,
+                                                     double g01, double g11, double T00,
+                                                     double T10, double T01, double T11)
+{
+    double w00 = g00, w10 = g10, w01 = g01, w11 = g11;
+    if (mellema) {
+        w00 /= fmax(W_FLOOR, T00);
+        w10 /= fmax(W_FLOOR, T10);
+        w01 /= fmax(W_FLOOR, T01);
+        w11 /= fmax(W_FLOOR, T11);
+    }
+    return (w00 * T00 + w10 * T10 + w01 * T01 + w11 * T11) / (w00 + w10 + w01 + w11);
+}
+
 // One tile-diagonal stage of the octant sweeps.  Each workgroup owns one
 // TX*TY*TZ tile of one octant (one thread per cell) and needs only the tiles
 // of earlier stages, so a stage is one launch.  The tile's cells and its
@@ -31,11 +62,12 @@ namespace pi {
 // each carries T = tau_centre + (ds_C/2) kap, its depth at C's entry face, with
 // bilinear weights divided by max(0.6, T) (Mellema weighting).  Neighbours
 // across a source plane (octant-local index -1) get weight 0.
-template <typename R, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(TX * TY * TZ)
+template <typename R>
+__global__ void __launch_bounds__(SWEEP_T * SWEEP_T * SWEEP_T)
 k_sweep(Params<R> p, const R* __restrict__ nH, const R* __restrict__ xs, R* __restrict__ tau,
         const int4* __restrict__ tiles, int first)
 {
+    constexpr int TX = SWEEP_T, TY = SWEEP_T, TZ = SWEEP_T;
     constexpr int HX = TX + 1, HY = TY + 1, HZ = TZ + 1, NHALO = HX * HY * HZ;
     __shared__ R s_tc[NHALO];
     __shared__ R s_kap[NHALO];
@@ -103,14 +135,7 @@ k_sweep(Params<R> p, const R* __restrict__ nH, const R* __restrict__ xs, R* __re
                 const R T10 = s_tc[n10] + hds * s_kap[n10];
                 const R T01 = s_tc[n01] + hds * s_kap[n01];
                 const R T11 = s_tc[n11] + hds * s_kap[n11];
-                R w00 = g00, w10 = g10, w01 = g01, w11 = g11;
-                if (mellema) {
-                    w00 /= r_max(R(W_FLOOR), T00);
-                    w10 /= r_max(R(W_FLOOR), T10);
-                    w01 /= r_max(R(W_FLOOR), T01);
-                    w11 /= r_max(R(W_FLOOR), T11);
-                }
-                tin = (w00 * T00 + w10 * T10 + w01 * T01 + w11 * T11) / (w00 + w10 + w01 + w11);
+                tin = sc_average<R>(mellema, g00, g10, g01, g11, T00, T10, T01, T11);
             }
             s_tc[self] = tin + hds * s_kap[self];
         }
@@ -125,39 +150,60 @@ k_sweep(Params<R> p, const R* __restrict__ nH, const R* __restrict__ xs, R* __re
 }
 
 // ---------------------------------------------------------------- chemistry
-// Work counters are summed per wavefront and added with one atomic per
-// counter per wavefront.
+// Work counters: summed over the workgroup (wavefront shuffles, then LDS) and
+// added with one atomic per counter per workgroup, into the slot of the
+// workgroup.
 __device__ __forceinline__ void add_work(unsigned long long* ctr, const Work& w)
 {
-    unsigned long long a = (unsigned long long)w.accepted, r = (unsigned long long)w.rejected,
-                       f = (unsigned long long)w.fallbacks;
-    for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_xor(a, o, 64);
-        r += __shfl_xor(r, o, 64);
-        f += __shfl_xor(f, o, 64);
-    }
+    __shared__ unsigned long long s_w[WORK_COUNTERS];
+    if (threadIdx.x < WORK_COUNTERS) s_w[threadIdx.x] = 0;
+    __syncthreads();
+    unsigned long long v[WORK_COUNTERS] = {
+        (unsigned long long)w.accepted, (unsigned long long)w.rejected,
+        (unsigned long long)w.fallbacks, (unsigned long long)w.newton };
+#pragma unroll
+    for (int c = 0; c < WORK_COUNTERS; ++c)
+        for (int o = 32; o > 0; o >>= 1) v[c] += __shfl_xor(v[c], o, 64);
     if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&ctr[0], a);
-        atomicAdd(&ctr[1], r);
-        atomicAdd(&ctr[2], f);
+#pragma unroll
+        for (int c = 0; c < WORK_COUNTERS; ++c) atomicAdd(&s_w[c], v[c]);
     }
+    __syncthreads();
+    if (threadIdx.x < WORK_COUNTERS)
+        atomicAdd(&ctr[threadIdx.x * WORK_SLOTS + blockIdx.x % WORK_SLOTS], s_w[threadIdx.x]);
 }
 
+// Waves per SIMD the register allocation of k_chem aims at: the double
+// kernel otherwise needs more than the 256 registers that two waves share.
+template <typename R> struct ChemWaves { static constexpr int value = 3; };
+template <> struct ChemWaves<double> { static constexpr int value = 2; };
+
 template <typename R>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(CHEM_BLOCK) __attribute__((amdgpu_waves_per_eu(ChemWaves<R>::value)))
 k_chem(Params<R> p, const R* __restrict__ nH, const R* x0, const R* E0, const R* __restrict__ tau,
        R* x1, R* E1, const DevState* __restrict__ st, double hscale, unsigned long long* ctr)
 {
+    // the rate table is read at every rate evaluation: keep a copy in LDS
+    __shared__ DevTable<R> s_tab;
+    if (p.spectrum == 1) {
+        constexpr int NW = (int)(sizeof(DevTable<R>) / sizeof(R));
+        const R* src = reinterpret_cast<const R*>(p.tab);
+        R* dst = reinterpret_cast<R*>(&s_tab);
+        for (int i = threadIdx.x; i < NW; i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+    Params<R> pl = p;
+    pl.tab = &s_tab;   // (not read with the monochromatic spectrum)
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    Work w{ 0, 0, 0 };
+    Work w{ 0, 0, 0, 0 };
     if (q < p.ncell) {
         const double hd = st ? hscale * st->dt : hscale;
         const int i = q % p.nx, j = (q / p.nx) % p.ny, k = q / (p.nx * p.ny);
-        const CellGeom<R> cg = cell_geom(p, i, j, k);
-        const Env<R> e = make_env(p, nH[q], cg, tau[q]);
+        const CellGeom<R> cg = cell_geom(pl, i, j, k);
+        const Env<R> e = make_env(pl, nH[q], cg, tau[q]);
         R x = x0[q];
         R E = E0 ? E0[q] : R(0);
-        micro(p, e, R(hd), x, E, w);
+        micro(pl, e, R(hd), x, E, w);
         x1[q] = x;
         if (E1) E1[q] = E;
     }
@@ -284,8 +330,8 @@ hipError_t launch_sweep_stage(const Params<R>& p, const R* nH, const R* x, R* ta
                               const int4* tiles, int first, int count, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_sweep<R, SWEEP_TX, SWEEP_TY, SWEEP_TZ>), dim3(count),
-                       dim3(SWEEP_TX * SWEEP_TY * SWEEP_TZ), 0, s, p, nH, x, tau, tiles, first);
+    hipLaunchKernelGGL((k_sweep<R>), dim3(count), dim3(SWEEP_T * SWEEP_T * SWEEP_T), 0, s, p, nH, x,
+                       tau, tiles, first);
     return hipGetLastError();
 }
 
@@ -294,9 +340,9 @@ hipError_t launch_chem(const Params<R>& p, const R* nH, const R* x0, const R* E0
                        R* x1, R* E1, const DevState* st, double hscale, unsigned long long* ctr,
                        hipStream_t s)
 {
-    const int nb = (int)((p.ncell + 255) / 256);
-    hipLaunchKernelGGL((k_chem<R>), dim3(nb), dim3(256), 0, s, p, nH, x0, E0, tau, x1, E1, st,
-                       hscale, ctr);
+    const int nb = (int)((p.ncell + CHEM_BLOCK - 1) / CHEM_BLOCK);
+    hipLaunchKernelGGL((k_chem<R>), dim3(nb), dim3(CHEM_BLOCK), 0, s, p, nH, x0, E0, tau, x1, E1,
+                       st, hscale, ctr);
     return hipGetLastError();
 }
 

@@ -100,6 +100,15 @@ template <> PI_HD __forceinline__ float r_sqrt<float>(float v) { return sqrtf(v)
 template <typename R> PI_HD __forceinline__ R r_pow(R a, R b);
 template <> PI_HD __forceinline__ double r_pow<double>(double a, double b) { return pow(a, b); }
 template <> PI_HD __forceinline__ float r_pow<float>(float a, float b) { return PI_FPOW(a, b); }
+// Reciprocal: correctly rounded in double, the hardware reciprocal (1 ulp) in
+// float device code.
+template <typename R> PI_HD __forceinline__ R r_rcp(R v);
+template <> PI_HD __forceinline__ double r_rcp<double>(double v) { return 1.0 / v; }
+#if defined(__HIP_DEVICE_COMPILE__)
+template <> PI_HD __forceinline__ float r_rcp<float>(float v) { return __builtin_amdgcn_rcpf(v); }
+#else
+template <> PI_HD __forceinline__ float r_rcp<float>(float v) { return 1.0f / v; }
+#endif
 template <typename R> PI_HD __forceinline__ R r_abs(R v) { return v < R(0) ? -v : v; }
 template <typename R> PI_HD __forceinline__ R r_max(R a, R b) { return a > b ? a : b; }
 template <typename R> PI_HD __forceinline__ R r_min(R a, R b) { return a < b ? a : b; }
@@ -168,19 +177,20 @@ PI_HD __forceinline__ void table_pair(const DevTable<R>* __restrict__ T, R tau, 
     const R d00 = R(6) * t2 - R(6) * t, d10 = R(3) * t2 - R(4) * t + R(1);
     const R d01 = R(-6) * t2 + R(6) * t, d11 = R(3) * t2 - R(2) * t;
     const R dl = T->delta;
+    const R itau = r_rcp(tau);
     {
         const R L0 = T->lp[n0], L1 = T->lp[n1], m0 = T->mp[n0] * dl, m1 = T->mp[n1] * dl;
         const R L = h00 * L0 + h10 * m0 + h01 * L1 + h11 * m1;
         const R dL = (d00 * L0 + d10 * m0 + d01 * L1 + d11 * m1) * T->inv_delta;
         P = T->p0 * r_exp(L);
-        dP = P * dL / tau;
+        dP = P * dL * itau;
     }
     {
         const R L0 = T->lh[n0], L1 = T->lh[n1], m0 = T->mh[n0] * dl, m1 = T->mh[n1] * dl;
         const R L = h00 * L0 + h10 * m0 + h01 * L1 + h11 * m1;
         const R dL = (d00 * L0 + d10 * m0 + d01 * L1 + d11 * m1) * T->inv_delta;
         H = T->h0 * r_exp(L);
-        dH = H * dL / tau;
+        dH = H * dL * itau;
     }
 }
 
@@ -189,6 +199,8 @@ PI_HD __forceinline__ void table_pair(const DevTable<R>* __restrict__ T, R tau, 
 // entering column, fixed over the interval.
 template <typename R> struct Env {
     R n;        // n_H
+    R inv_n;    // 1 / n_H
+    R c3;       // 1 / (3 k_B n_H): T = 2 E c3 / (2 - x)
     R Qg;       // Q/dx^3 * g: photons entering per unit volume and time, unattenuated
     R k;        // cell optical depth per unit neutral fraction = n sigma0 dx ell
     R tau;      // entering column
@@ -202,6 +214,8 @@ PI_HD __forceinline__ Env<R> make_env(const Params<R>& p, R n, CellGeom<R> c, R 
 {
     Env<R> e;
     e.n = n;
+    e.inv_n = R(1) / n;
+    e.c3 = R(1) / (R(3.0 * KB) * n);
     e.Qg = p.QV * c.g;
     e.k = n * p.sdx * c.ell;
     e.tau = tau;
@@ -269,41 +283,49 @@ template <typename R> struct Coef {
     R cin, dcin;
 };
 
+// The power laws share one logarithm: with l = ln T,
+//   (T/1e4)^-0.7          = exp(-0.7 l + 0.7 ln 1e4)
+//   (T/1e6)^0.7           = exp( 0.7 l - 0.7 ln 1e6)
+//   T^1/2 (T/1e3)^-0.2    = 10^0.6 exp(0.3 l)
 template <typename R>
 PI_HD __forceinline__ Coef<R> coefs(const Params<R>& p, R T)
 {
     Coef<R> c;
-    if (p.recomb == 0) {
+    const R invT = r_rcp(T);
+    const bool pw = p.recomb != 0, cool = p.thermal == 1 && p.cooling != 0;
+    const R lT = (pw || cool) ? r_log(T) : R(0);
+    if (!pw) {
         c.alpha = p.alpha_B;
         c.dla = R(0);
     } else {
-        c.alpha = p.alpha_B * r_pow(T * R(1e-4), R(-0.7));
-        c.dla = R(-0.7) / T;
+        c.alpha = p.alpha_B * r_exp(R(-0.7) * lT + R(6.4472382603833282));   // 0.7 ln 1e4
+        c.dla = R(-0.7) * invT;
     }
     const R sT = r_sqrt(T);
     const R s5 = sT * R(0.0031622776601683794);   // sqrt(T/1e5)
-    const R q = R(1) + s5;
-    const R dlq = s5 * R(0.5) / (T * q);           // d ln q / dT
-    const R invT = R(1) / T;
+    const R invq = r_rcp(R(1) + s5);
+    const R dlq = R(0.5) * s5 * invT * invq;       // d ln q / dT, q = 1 + sqrt(T/1e5)
     const R eci = (p.collisional || p.cooling) ? r_exp(R(-157809.1) * invT) : R(0);
+    const R dle = R(157809.1) * invT * invT;       // d ln eci / dT
     c.aci = R(0);
     c.dlci = R(0);
     if (p.collisional) {
-        c.aci = R(5.85e-11) * sT / q * eci;
-        c.dlci = R(0.5) * invT - dlq + R(157809.1) * invT * invT;
+        c.aci = R(5.85e-11) * sT * invq * eci;
+        c.dlci = R(0.5) * invT - dlq + dle;
     }
     c.cii = c.dcii = c.cin = c.dcin = R(0);
-    if (p.thermal == 1 && p.cooling) {
-        const R t6 = r_pow(T * R(1e-6), R(0.7));
-        const R crec = R(8.70e-27) * sT * r_pow(T * R(1e-3), R(-0.2)) / (R(1) + t6);
-        const R dlrec = R(0.3) * invT - R(0.7) * t6 * invT / (R(1) + t6);
+    if (cool) {
+        const R t6 = r_exp(R(0.7) * lT - R(9.6708573905749923));           // 0.7 ln 1e6
+        const R i16 = r_rcp(R(1) + t6);
+        const R crec = R(8.70e-27 * 3.9810717055349722) * r_exp(R(0.3) * lT) * i16;
+        const R dlrec = (R(0.3) - R(0.7) * t6 * i16) * invT;
         const R cff = R(1.42e-27 * 1.3) * sT;
-        const R cce = R(7.50e-19) / q * r_exp(R(-118348.0) * invT);
+        const R cce = R(7.50e-19) * invq * r_exp(R(-118348.0) * invT);
         const R dlce = -dlq + R(118348.0) * invT * invT;
         R cci = R(0), dlci2 = R(0);
         if (p.collisional) {
-            cci = R(1.27e-21) * sT / q * eci;
-            dlci2 = R(0.5) * invT - dlq + R(157809.1) * invT * invT;
+            cci = R(1.27e-21) * sT * invq * eci;
+            dlci2 = R(0.5) * invT - dlq + dle;
         }
         c.cii = crec + cff;
         c.dcii = crec * dlrec + cff * R(0.5) * invT;
@@ -326,8 +348,8 @@ PI_HD __forceinline__ void rhs_xT(const Params<R>& p, const Env<R>& e, const Coe
     R A, dA, G, dG;
     photo(p, e, x, A, dA, G, dG);
     const R n = e.n, y = R(1) - x;
-    fx = -A / n - c.aci * n * x * y + c.alpha * n * y * y;
-    dfx = -dA / n - c.aci * n * (R(1) - R(2) * x) - R(2) * c.alpha * n * y;
+    fx = -A * e.inv_n - c.aci * n * x * y + c.alpha * n * y * y;
+    dfx = -dA * e.inv_n - c.aci * n * (R(1) - R(2) * x) - R(2) * c.alpha * n * y;
 }
 
 // Temperature floor: the coefficients see max(T, T_FLOOR) and the cooling is
@@ -341,9 +363,10 @@ PI_HD __forceinline__ void rhs_full(const Params<R>& p, const Env<R>& e, R x, R 
     if (p.thermal == 0) {
         T = Tc = p.T_fixed;
     } else {
-        T = R(2) * E / (R(3.0 * KB) * n * (R(2) - x));
-        dTdx = T / (R(2) - x);
-        dTdE = T / E;
+        const R i2mx = r_rcp(R(2) - x);
+        dTdE = R(2) * e.c3 * i2mx;
+        T = E * dTdE;
+        dTdx = T * i2mx;
         above = T > R(T_FLOOR) ? R(1) : R(0);
         Tc = T > R(T_FLOOR) ? T : R(T_FLOOR);
     }
@@ -356,16 +379,17 @@ PI_HD __forceinline__ void rhs_full(const Params<R>& p, const Env<R>& e, R x, R 
     r.A = A;
     r.rec = c.alpha * n * n * y * y;
     r.T = Tc;
-    r.fx = -A / n - c.aci * n * x * y + c.alpha * n * y * y;
+    r.fx = -A * e.inv_n - c.aci * n * x * y + c.alpha * n * y * y;
     const R dfx_dT = -c.aci * c.dlci * n * x * y + c.alpha * c.dla * n * y * y;
-    r.jxx = -dA / n - c.aci * n * (R(1) - R(2) * x) - R(2) * c.alpha * n * y + dfx_dT * dTdx;
+    r.jxx = -dA * e.inv_n - c.aci * n * (R(1) - R(2) * x) - R(2) * c.alpha * n * y + dfx_dT * dTdx;
     r.jxE = dfx_dT * dTdE;
     if (p.thermal == 0) {
         r.fE = r.jEx = r.jEE = R(0);
         return;
     }
-    const R w = T > R(T_FLOOR) ? R(1) - R(T_FLOOR) / T : R(0);
-    const R dw = T > R(T_FLOOR) ? R(T_FLOOR) / (T * T) : R(0);
+    const R iT = r_rcp(T);
+    const R w = T > R(T_FLOOR) ? R(1) - R(T_FLOOR) * iT : R(0);
+    const R dw = T > R(T_FLOOR) ? R(T_FLOOR) * iT * iT : R(0);
     const R n2 = n * n;
     const R lam0 = n2 * (y * y * c.cii + x * y * c.cin);
     const R dlam0_dx = n2 * (R(-2) * y * c.cii + (R(1) - R(2) * x) * c.cin);
@@ -385,12 +409,13 @@ template <typename R> PI_HD __forceinline__ R e_floor(R n, R x)
 // Newton safeguarded by the bracket [0, 1] (the residual increases with x); a
 // root outside [0, 1] is returned clamped.
 template <typename R>
-PI_HD R solve_x(const Params<R>& p, const Env<R>& e, const Coef<R>& c, R xb, R hg, R x)
+PI_HD R solve_x(const Params<R>& p, const Env<R>& e, const Coef<R>& c, R xb, R hg, R x, int& nit)
 {
     x = r_min(r_max(x, R(0)), R(1));
     R lo = R(0), hi = R(1);
     R eprev = R(1e30);
     for (int it = 0; it < NEWTON_MAXIT; ++it) {
+        ++nit;
         R fx, dfx;
         rhs_xT(p, e, c, x, fx, dfx);
         const R G = x - xb - hg * fx;
@@ -421,7 +446,8 @@ template <typename R>
 PI_HD R t_residual(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg, R T, R& xs)
 {
     const Coef<R> c = coefs(p, T);
-    const R x = solve_x(p, e, c, xb, hg, r_min(r_max(xb, R(0)), R(1)));
+    int nit = 0;
+    const R x = solve_x(p, e, c, xb, hg, r_min(r_max(xb, R(0)), R(1)), nit);
     const R E = R(1.5 * KB) * e.n * (R(2) - x) * T;
     Rhs<R> r;
     rhs_full(p, e, x, E, r);
@@ -479,7 +505,7 @@ PI_HD void fallback_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg,
 }
 
 
-// Stage solve Y = base + hg f(Y); returns true when the fallback was needed.
+// Stage solve Y = base + hg f(Y); counts Newton iterations and fallbacks in w.
 // T fixed: the scalar bracketed Newton.  T evolving: Newton on (x, E) with x
 // projected onto [0,1] and E kept positive, at most NEWTON_2D_MAXIT iterations;
 // if it has not settled, a nested bracketed solve in (x, T): x at fixed T by the
@@ -488,34 +514,36 @@ PI_HD void fallback_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg,
 // Work done by one micro-integration (accepted and rejected substeps, stage
 // fallbacks), summed per launch for the performance counters.
 struct Work {
-    int accepted, rejected, fallbacks;
+    int accepted, rejected, fallbacks, newton;
 };
 
 template <typename R>
-PI_HD bool stage_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg, R& x, R& E)
+PI_HD void stage_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg, R& x, R& E,
+                       Work& w)
 {
     if (p.thermal == 0) {
         const Coef<R> c = coefs(p, p.T_fixed);
-        x = solve_x(p, e, c, xb, hg, x);
-        return false;
+        x = solve_x(p, e, c, xb, hg, x, w.newton);
+        return;
     }
     x = r_min(r_max(x, R(0)), R(1));
     if (!(E > R(0))) E = e_floor(e.n, x);
     R eprev = R(1e30);
     for (int it = 0; it < NEWTON_2D_MAXIT; ++it) {
+        ++w.newton;
         Rhs<R> r;
         rhs_full(p, e, x, E, r);
         const R Rx = x - xb - hg * r.fx;
         const R RE = E - Eb - hg * r.fE;
         const R a11 = R(1) - hg * r.jxx, a12 = -hg * r.jxE;
         const R a21 = -hg * r.jEx, a22 = R(1) - hg * r.jEE;
-        const R det = a11 * a22 - a12 * a21;
-        R xn = x - (a22 * Rx - a12 * RE) / det;
-        R En = E - (a11 * RE - a21 * Rx) / det;
+        const R idet = r_rcp(a11 * a22 - a12 * a21);
+        R xn = x - (a22 * Rx - a12 * RE) * idet;
+        R En = E - (a11 * RE - a21 * Rx) * idet;
         if (!(xn >= R(0))) xn = R(0);
         if (xn > R(1)) xn = R(1);
         if (!(En > R(0))) En = R(0.5) * E;
-        const R err = r_max(r_abs(xn - x) / r_max(xn, R(1e-12)), r_abs(En - E) / En);
+        const R err = r_max(r_abs(xn - x) * r_rcp(r_max(xn, R(1e-12))), r_abs(En - E) * r_rcp(En));
         // x held on a bound while the residual puts the root inside [0, 1]
         // (a negative slope of the x-residual): not a solution -- unless at 1
         // the root lies within half a rounding step of 1
@@ -523,11 +551,11 @@ PI_HD bool stage_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg, R&
                            (xn <= R(0) && Rx < R(0));
         x = xn;
         E = En;
-        if (!stuck && (err <= Tol<R>::rtol || (err >= eprev && err <= Tol<R>::stall))) return false;
+        if (!stuck && (err <= Tol<R>::rtol || (err >= eprev && err <= Tol<R>::stall))) return;
         eprev = err;
     }
     fallback_solve(p, e, xb, Eb, hg, x, E);
-    return true;
+    ++w.fallbacks;
 }
 
 // Initial substep count of one micro-integration: at least n_sub, and enough
@@ -547,19 +575,19 @@ PI_HD __forceinline__ int substeps(const Params<R>& p, const Env<R>& e, R x0, R 
 // One step of the two-stage, L-stable, stiffly accurate SDIRK method
 // (gamma = 1 - 1/sqrt 2); the second stage starts from y + ((1-gamma)/gamma)(Y1 - y).
 template <typename R>
-PI_HD __forceinline__ int sdirk_step(const Params<R>& p, const Env<R>& e, R hs, R& x, R& E)
+PI_HD __forceinline__ void sdirk_step(const Params<R>& p, const Env<R>& e, R hs, R& x, R& E,
+                                      Work& w)
 {
     const R gam = R(0.29289321881345247560);          // 1 - 1/sqrt(2)
     const R cst = R(2.41421356237309504880);          // (1 - gamma)/gamma
     R X1 = x, F1 = E;
-    int fb = stage_solve(p, e, x, E, gam * hs, X1, F1) ? 1 : 0;
+    stage_solve(p, e, x, E, gam * hs, X1, F1, w);
     const R xb = x + cst * (X1 - x);
     const R Eb = E + cst * (F1 - E);
     R X2 = X1, F2 = F1;
-    fb += stage_solve(p, e, xb, Eb, gam * hs, X2, F2) ? 1 : 0;
+    stage_solve(p, e, xb, Eb, gam * hs, X2, F2, w);
     x = X2;
     E = F2;
-    return fb;
 }
 
 // Micro-integration M(x0, E0; tau, h) with deterministic substep control: the
@@ -581,7 +609,7 @@ PI_HD void micro(const Params<R>& p, const Env<R>& e, R h, R& x, R& E, Work& w)
     while (pos < U) {
         const R hs = R((double)h * (double)s / (double)U);
         R xn = x, En = E;
-        w.fallbacks += sdirk_step(p, e, hs, xn, En);
+        sdirk_step(p, e, hs, xn, En, w);
         const bool bad = r_abs(xn - x) > R(REJ_DX) ||
                          (evolve && (En > R(REJ_E) * E || En * R(REJ_E) < E));
         if (bad && s > 1) {

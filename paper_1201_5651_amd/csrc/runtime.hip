@@ -158,6 +158,7 @@ struct pi_grid {
     Params<float> pf;
     void* table = nullptr;
     DevState* st = nullptr;
+    unsigned long long* work = nullptr;   // WORK_COUNTERS x WORK_SLOTS
     double* part = nullptr;
     int nblk = 0;
     int4* tiles = nullptr;
@@ -205,6 +206,7 @@ void free_grid(pi_grid* g)
     if (!g) return;
     if (g->table) (void)hipFree(g->table);
     if (g->st) (void)hipFree(g->st);
+    if (g->work) (void)hipFree(g->work);
     if (g->part) (void)hipFree(g->part);
     if (g->tiles) (void)hipFree(g->tiles);
     delete g;
@@ -242,10 +244,8 @@ pi_status chem_t(pi_grid* g, bool dev_dt, double h, int tau_buf, int from, int t
         E0 = nullptr;
         E1 = nullptr;
     }
-    unsigned long long* ctr = reinterpret_cast<unsigned long long*>(
-        reinterpret_cast<char*>(g->st) + offsetof(DevState, work));
     HIP_OR(launch_chem<R>(params<R>(g), nH, x0, E0, tau, x1, E1, dev_dt ? g->st : nullptr, h,
-                          ctr, s),
+                          g->work, s),
            "chemistry launch");
     return PI_OK;
 }
@@ -351,6 +351,12 @@ pi_status pi_grid_create(const pi_grid_desc* desc, const pi_fields* fields, pi_g
         if (hipMemcpy(g->st, &s0, sizeof(s0), hipMemcpyHostToDevice) != hipSuccess)
             return bail(PI_EDEVICE, "state upload");
     }
+    // work counters
+    {
+        const size_t wb = sizeof(unsigned long long) * WORK_COUNTERS * WORK_SLOTS;
+        if (hipMalloc(&g->work, wb) != hipSuccess) return bail(PI_ENOMEM, "counter allocation");
+        if (hipMemset(g->work, 0, wb) != hipSuccess) return bail(PI_EDEVICE, "counter clear");
+    }
     // reduction partials
     const int64_t N = (int64_t)desc->n[0] * desc->n[1] * desc->n[2];
     g->nblk = (int)std::min<int64_t>((N + 255) / 256, 1024);
@@ -363,9 +369,9 @@ pi_status pi_grid_create(const pi_grid_desc* desc, const pi_fields* fields, pi_g
             int ext[3];
             for (int a = 0; a < 3; ++a) ext[a] = ((o >> a) & 1) ? desc->n[a] - desc->src[a] : desc->src[a];
             if (ext[0] <= 0 || ext[1] <= 0 || ext[2] <= 0) continue;
-            const int ntx = (ext[0] + SWEEP_TX - 1) / SWEEP_TX;
-            const int nty = (ext[1] + SWEEP_TY - 1) / SWEEP_TY;
-            const int ntz = (ext[2] + SWEEP_TZ - 1) / SWEEP_TZ;
+            const int ntx = (ext[0] + SWEEP_T - 1) / SWEEP_T;
+            const int nty = (ext[1] + SWEEP_T - 1) / SWEEP_T;
+            const int ntz = (ext[2] + SWEEP_T - 1) / SWEEP_T;
             for (int tz = 0; tz < ntz; ++tz)
                 for (int ty = 0; ty < nty; ++ty)
                     for (int tx = 0; tx < ntx; ++tx) {
@@ -497,14 +503,17 @@ pi_status pi_work_counters(pi_grid* g, int64_t* out, int reset, void* stream)
 {
     if (!g || !out) return fail(PI_EINVAL, "null argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    DevState h{};
-    HIP_OR(hipMemcpyAsync(&h, g->st, sizeof(h), hipMemcpyDeviceToHost, s), "state read");
-    HIP_OR(hipStreamSynchronize(s), "state read sync");
-    for (int i = 0; i < 3; ++i) out[i] = (int64_t)h.work[i];
+    unsigned long long h[WORK_COUNTERS * WORK_SLOTS];
+    HIP_OR(hipMemcpyAsync(h, g->work, sizeof(h), hipMemcpyDeviceToHost, s), "counter read");
+    HIP_OR(hipStreamSynchronize(s), "counter read sync");
+    for (int c = 0; c < WORK_COUNTERS; ++c) {
+        unsigned long long v = 0;
+        for (int k = 0; k < WORK_SLOTS; ++k) v += h[c * WORK_SLOTS + k];
+        out[c] = (int64_t)v;
+    }
     if (reset) {
-        for (int i = 0; i < 4; ++i) h.work[i] = 0;
-        HIP_OR(hipMemcpyAsync(g->st, &h, sizeof(h), hipMemcpyHostToDevice, s), "state write");
-        HIP_OR(hipStreamSynchronize(s), "state write sync");
+        HIP_OR(hipMemsetAsync(g->work, 0, sizeof(h), s), "counter clear");
+        HIP_OR(hipStreamSynchronize(s), "counter clear sync");
     }
     return PI_OK;
 }
