@@ -91,7 +91,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "mixed"])
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "fp32", "mixed"])
     ap.add_argument("--pre-trec", type=float, default=0.1,
                     help="untimed evolution before timing, in units of t_rec")
     ap.add_argument("--pre-steps-max", type=int, default=400)
@@ -240,6 +240,7 @@ def main() -> int:
             / max(1, work_phase["accepted"] + work_phase["rejected"]),
             "fallbacks_per_cell_update": work_phase["fallbacks"] / (spec.ncells * args.phase_steps),
             "newton_per_cell_update": work_phase["newton"] / (spec.ncells * args.phase_steps),
+            "fp64_resolved_frac": work_phase["resolved_fp64"] / (2 * spec.ncells * args.phase_steps),
         },
         "roofline": roofline,
     }

@@ -44,6 +44,13 @@ typedef enum {
     PI_ENAN = -5         /* a non-finite value was found in the grid's state  */
 } pi_status;
 
+/* PI_MIXED: float fields and float bulk arithmetic.  A cell is re-solved in
+ * double from the same float inputs when its float integration took a
+ * decision that the precision can flip: a substep-control decision within a
+ * relative 1e-3 of its threshold (initial substep count, rejection of a
+ * substep), a stage solve that needed the bracketed fallback, or a neutral
+ * fraction held at 1 on an unstable equilibrium.  Reductions (timestep,
+ * diagnostics) are double in every precision. */
 typedef enum { PI_FP64 = 0, PI_FP32 = 1, PI_MIXED = 2 } pi_precision;
 enum { PI_SPEC_MONO = 0, PI_SPEC_TABLE = 1 };
 enum { PI_T_FIXED = 0, PI_T_EVOLVE = 1 };
@@ -53,6 +60,8 @@ enum { PI_W_GEOMETRIC = 0, PI_W_MELLEMA = 1 };
 enum { PI_BUF_N = 0, PI_BUF_HALF = 1 };
 /* number of FP64 diagnostics returned by pi_diagnostics */
 #define PI_NDIAG 8
+/* number of work counters returned by pi_work_counters */
+#define PI_NWORK 5
 #define PI_NTAB 64
 
 /* Problem description (copied by pi_grid_create). */
@@ -162,8 +171,9 @@ pi_status pi_diagnostics(pi_grid* grid, double* out, void* stream);
 
 /* Work of the micro-physics updates since the last reset (SYNCHRONISES):
  * out[0] accepted substeps, out[1] rejected substeps, out[2] stage solves that
- * needed the bracketed fallback, out[3] Newton iterations of the stage solves
- * (out has 4 elements).  reset != 0 zeroes the counters after reading.
+ * needed the bracketed fallback, out[3] Newton iterations of the stage solves,
+ * out[4] cells re-solved in double by PI_MIXED grids (out has PI_NWORK
+ * elements).  reset != 0 zeroes the counters after reading.
  * Counters are summed over all pi_chem_step / step calls of the grid. */
 pi_status pi_work_counters(pi_grid* grid, int64_t* out, int reset, void* stream);
 
@@ -177,7 +187,9 @@ pi_status pi_table_build(double T_bb, double Q, double* out);
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char* pi_last_error(void);
 
-/* ABI version of this header (major * 100 + minor). */
+/* ABI version of this header (major * 100 + minor); the library returns the
+ * value it was built with. */
+#define PI_ABI_VERSION 101
 int pi_abi_version(void);
 
 #ifdef __cplusplus

@@ -677,7 +677,10 @@ static int stage_solve(const orc_desc* g, const cellenv* c, double xb, double Eb
         return 0;
     }
     /* T evolving, first: Newton on (x, E) with x projected onto [0, 1] and E
-     * kept positive, at most NEWTON_2D_MAXIT iterations. */
+     * kept positive, at most NEWTON_2D_MAXIT iterations.  When the step would
+     * take x out of [0, 1], x is held on the bound and E takes the step of
+     * the same linearisation with x fixed there, so that on a bound the
+     * iteration still converges to a zero of the energy residual. */
     if (!(E > 0.0)) E = e_floor(g, c->nH, x);
     double eprev = INFINITY;
     for (int it = 0; it < NEWTON_2D_MAXIT; ++it) {
@@ -689,8 +692,11 @@ static int stage_solve(const orc_desc* g, const cellenv* c, double xb, double Eb
         double det = a11 * a22 - a12 * a21;
         double xn = x - (a22 * Rx - a12 * RE) / det;
         double En = E - (a11 * RE - a21 * Rx) / det;
-        if (!(xn >= 0.0)) xn = 0.0;   /* also catches NaN */
-        if (xn > 1.0) xn = 1.0;
+        if (!(xn >= 0.0) || xn > 1.0) {   /* (also catches NaN) */
+            const double xbnd = xn > 1.0 ? 1.0 : 0.0;
+            En = E - (RE + a21 * (xbnd - x)) / a22;
+            xn = xbnd;
+        }
         if (!(En > 0.0)) En = 0.5 * E;
         double e = fmax(fabs(xn - x) / fmax(xn, 1e-12), fabs(E - En) / En);
         /* x held on a bound while the residual puts the root inside [0, 1]

@@ -23,6 +23,7 @@ PI_ALPHA_CONST, PI_ALPHA_POWER = 0, 1
 PI_W_GEOMETRIC, PI_W_MELLEMA = 0, 1
 PI_BUF_N, PI_BUF_HALF = 0, 1
 PI_NDIAG = 8
+PI_NWORK = 5
 PI_NTAB = 64
 
 # every symbol include/pi.h declares
@@ -225,9 +226,10 @@ class Grid:
         return dict(zip(keys, list(out)))
 
     def work_counters(self, reset: bool = False):
-        out = (C.c_int64 * 4)()
+        out = (C.c_int64 * PI_NWORK)()
         check(lib().pi_work_counters(self._h, out, int(reset), self._stream()))
-        return {"accepted": out[0], "rejected": out[1], "fallbacks": out[2], "newton": out[3]}
+        return {"accepted": out[0], "rejected": out[1], "fallbacks": out[2], "newton": out[3],
+                "resolved_fp64": out[4]}
 
     def run(self, t_end: float, order: int = 2, max_steps: int = 10**8, check_every: int = 64):
         """Step until t_end (order 2: algorithm 3; order 1: algorithm 2).

@@ -24,7 +24,8 @@ struct DevState {
     double t_end;
     double last_dt;
     long long nsteps;
-    long long pad;
+    unsigned int fix_n;   // mixed precision: cells listed for the double re-solve
+    unsigned int pad;
     double diag[8];   // see pi_diagnostics
 };
 
@@ -32,15 +33,21 @@ struct DevState {
 // solves, Newton iterations), each spread over WORK_SLOTS slots so that the
 // per-workgroup atomic additions do not all meet on one address; a reader sums
 // the slots.  Layout: counter c, slot s at [c * WORK_SLOTS + s].
-constexpr int WORK_COUNTERS = 4, WORK_SLOTS = 64;
+constexpr int WORK_COUNTERS = 5, WORK_SLOTS = 64;
 
 template <typename R>
 hipError_t launch_sweep_stage(const Params<R>& p, const R* nH, const R* x, R* tau,
                               const int4* tiles, int first, int count, hipStream_t s);
 template <typename R>
 hipError_t launch_chem(const Params<R>& p, const R* nH, const R* x0, const R* E0, const R* tau,
-                       R* x1, R* E1, const DevState* st, double hscale, unsigned long long* ctr,
-                       hipStream_t s);
+                       R* x1, R* E1, DevState* st, bool dev_dt, double hscale,
+                       unsigned long long* ctr, int* fix_list, hipStream_t s);
+// Mixed precision: double re-solve of the float cells listed by launch_chem
+// (fix_list, count in st->fix_n), from the unmodified float inputs.
+hipError_t launch_chem_fix(const Params<double>& p, const float* nH, const float* x0,
+                           const float* E0, const float* tau, float* x1, float* E1,
+                           DevState* st, bool dev_dt, double hscale, unsigned long long* ctr,
+                           const int* fix_list, int nblk, hipStream_t s);
 template <typename R>
 hipError_t launch_dtdiag(const Params<R>& p, const R* nH, const R* x, const R* E, const R* tau,
                          double* part, int nblk, DevState* st, double t_end, double cell_vol,

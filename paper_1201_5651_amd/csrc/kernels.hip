@@ -160,7 +160,8 @@ __device__ __forceinline__ void add_work(unsigned long long* ctr, const Work& w)
     __syncthreads();
     unsigned long long v[WORK_COUNTERS] = {
         (unsigned long long)w.accepted, (unsigned long long)w.rejected,
-        (unsigned long long)w.fallbacks, (unsigned long long)w.newton };
+        (unsigned long long)w.fallbacks, (unsigned long long)w.newton,
+        (unsigned long long)w.fixed };
 #pragma unroll
     for (int c = 0; c < WORK_COUNTERS; ++c)
         for (int o = 32; o > 0; o >>= 1) v[c] += __shfl_xor(v[c], o, 64);
@@ -178,13 +179,11 @@ __device__ __forceinline__ void add_work(unsigned long long* ctr, const Work& w)
 template <typename R> struct ChemWaves { static constexpr int value = 3; };
 template <> struct ChemWaves<double> { static constexpr int value = 2; };
 
+// Copy of the rate table in LDS (it is read at every rate evaluation); the
+// returned parameters point at it.  Every thread of the block must call it.
 template <typename R>
-__global__ void __launch_bounds__(CHEM_BLOCK) __attribute__((amdgpu_waves_per_eu(ChemWaves<R>::value)))
-k_chem(Params<R> p, const R* __restrict__ nH, const R* x0, const R* E0, const R* __restrict__ tau,
-       R* x1, R* E1, const DevState* __restrict__ st, double hscale, unsigned long long* ctr)
+__device__ __forceinline__ Params<R> table_to_lds(const Params<R>& p, DevTable<R>& s_tab)
 {
-    // the rate table is read at every rate evaluation: keep a copy in LDS
-    __shared__ DevTable<R> s_tab;
     if (p.spectrum == 1) {
         constexpr int NW = (int)(sizeof(DevTable<R>) / sizeof(R));
         const R* src = reinterpret_cast<const R*>(p.tab);
@@ -194,18 +193,84 @@ k_chem(Params<R> p, const R* __restrict__ nH, const R* x0, const R* E0, const R*
     __syncthreads();
     Params<R> pl = p;
     pl.tab = &s_tab;   // (not read with the monochromatic spectrum)
+    return pl;
+}
+
+// Micro-integration of cell q in arithmetic C from storage S.
+template <typename C, typename S>
+__device__ __forceinline__ void chem_cell(const Params<C>& p, int q, const S* __restrict__ nH,
+                                          const S* x0, const S* E0, const S* __restrict__ tau,
+                                          double hd, C& x, C& E, Work& w)
+{
+    const int i = q % p.nx, j = (q / p.nx) % p.ny, k = q / (p.nx * p.ny);
+    const CellGeom<C> cg = cell_geom(p, i, j, k);
+    const Env<C> e = make_env(p, C(nH[q]), cg, C(tau[q]));
+    x = C(x0[q]);
+    E = E0 ? C(E0[q]) : C(0);
+    micro(p, e, C(hd), x, E, w);
+}
+
+// Micro-physics of every cell.  With fix_list (mixed precision), a cell whose
+// substep control took a decision near its threshold is not written; it is
+// appended to fix_list (count in st->fix_n) for the double re-solve.
+template <typename R>
+__global__ void __launch_bounds__(CHEM_BLOCK) __attribute__((amdgpu_waves_per_eu(ChemWaves<R>::value)))
+k_chem(Params<R> p, const R* __restrict__ nH, const R* x0, const R* E0, const R* __restrict__ tau,
+       R* x1, R* E1, DevState* st, int dev_dt, double hscale, unsigned long long* ctr,
+       int* fix_list)
+{
+    __shared__ DevTable<R> s_tab;
+    const Params<R> pl = table_to_lds(p, s_tab);
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    Work w{ 0, 0, 0, 0 };
+    Work w{};
+    bool flag = false;
     if (q < p.ncell) {
-        const double hd = st ? hscale * st->dt : hscale;
-        const int i = q % p.nx, j = (q / p.nx) % p.ny, k = q / (p.nx * p.ny);
-        const CellGeom<R> cg = cell_geom(pl, i, j, k);
-        const Env<R> e = make_env(pl, nH[q], cg, tau[q]);
-        R x = x0[q];
-        R E = E0 ? E0[q] : R(0);
-        micro(pl, e, R(hd), x, E, w);
-        x1[q] = x;
-        if (E1) E1[q] = E;
+        const double hd = dev_dt ? hscale * st->dt : hscale;
+        R x, E;
+        chem_cell<R, R>(pl, q, nH, x0, E0, tau, hd, x, E, w);
+        flag = fix_list && w.close > 0;
+        if (!flag) {
+            x1[q] = x;
+            if (E1) E1[q] = E;
+        }
+    }
+    if (fix_list) {
+        // one atomic per wavefront for the flagged cells of the wavefront
+        const unsigned long long m = __ballot(flag);
+        if (m) {
+            const int lane = threadIdx.x & 63;
+            const int first = __ffsll((long long)m) - 1;
+            unsigned base = 0;
+            if (lane == first) base = atomicAdd(&st->fix_n, (unsigned)__popcll(m));
+            base = __shfl(base, first, 64);
+            if (flag) fix_list[base + __popcll(m & ((1ull << lane) - 1ull))] = q;
+        }
+    }
+    add_work(ctr, w);
+}
+
+__global__ void k_fix_reset(DevState* st)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->fix_n = 0u;
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ChemWaves<double>::value)))
+k_chem_fix(Params<double> p, const float* __restrict__ nH, const float* x0, const float* E0,
+           const float* __restrict__ tau, float* x1, float* E1, DevState* st, int dev_dt,
+           double hscale, unsigned long long* ctr, const int* __restrict__ fix_list)
+{
+    __shared__ DevTable<double> s_tab;
+    const Params<double> pl = table_to_lds(p, s_tab);
+    const unsigned n = st->fix_n;
+    const double hd = dev_dt ? hscale * st->dt : hscale;
+    Work w{};
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int q = fix_list[i];
+        double x, E;
+        chem_cell<double, float>(pl, q, nH, x0, E0, tau, hd, x, E, w);
+        x1[q] = (float)x;
+        if (E1) E1[q] = (float)E;
+        ++w.fixed;
     }
     add_work(ctr, w);
 }
@@ -337,12 +402,23 @@ hipError_t launch_sweep_stage(const Params<R>& p, const R* nH, const R* x, R* ta
 
 template <typename R>
 hipError_t launch_chem(const Params<R>& p, const R* nH, const R* x0, const R* E0, const R* tau,
-                       R* x1, R* E1, const DevState* st, double hscale, unsigned long long* ctr,
-                       hipStream_t s)
+                       R* x1, R* E1, DevState* st, bool dev_dt, double hscale,
+                       unsigned long long* ctr, int* fix_list, hipStream_t s)
 {
+    if (fix_list) hipLaunchKernelGGL(k_fix_reset, dim3(1), dim3(64), 0, s, st);
     const int nb = (int)((p.ncell + CHEM_BLOCK - 1) / CHEM_BLOCK);
     hipLaunchKernelGGL((k_chem<R>), dim3(nb), dim3(CHEM_BLOCK), 0, s, p, nH, x0, E0, tau, x1, E1,
-                       st, hscale, ctr);
+                       st, (int)dev_dt, hscale, ctr, fix_list);
+    return hipGetLastError();
+}
+
+hipError_t launch_chem_fix(const Params<double>& p, const float* nH, const float* x0,
+                           const float* E0, const float* tau, float* x1, float* E1,
+                           DevState* st, bool dev_dt, double hscale, unsigned long long* ctr,
+                           const int* fix_list, int nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_chem_fix, dim3(nblk), dim3(256), 0, s, p, nH, x0, E0, tau, x1, E1, st,
+                       (int)dev_dt, hscale, ctr, fix_list);
     return hipGetLastError();
 }
 
@@ -374,7 +450,7 @@ hipError_t launch_energy(int64_t n, const R* nH, const R* x, R* E, double T0, hi
     template hipError_t launch_sweep_stage<R>(const Params<R>&, const R*, const R*, R*,           \
                                               const int4*, int, int, hipStream_t);                 \
     template hipError_t launch_chem<R>(const Params<R>&, const R*, const R*, const R*, const R*,  \
-                                       R*, R*, const DevState*, double, unsigned long long*,       \
+                                       R*, R*, DevState*, bool, double, unsigned long long*, int*, \
                                        hipStream_t);                                               \
     template hipError_t launch_dtdiag<R>(const Params<R>&, const R*, const R*, const R*,          \
                                          const R*, double*, int, DevState*, double, double, int,   \

@@ -36,6 +36,11 @@ constexpr int SUB_MAX = 128;
 constexpr int SUB_LEVELS = 6;     // substep halvings allowed
 constexpr double REJ_DX = 0.3;    // reject a substep that moves x by more
 constexpr double REJ_E = 3.0;     // ... or changes E by more than this factor
+// A substep-control decision (initial substep count, rejection) whose deciding
+// quantity lies within this relative distance of its threshold could go the
+// other way under a change of precision; the mixed-precision path re-solves
+// such cells in double.
+constexpr double MIX_MARGIN = 1e-3;
 
 template <typename R> struct Tol;
 template <> struct Tol<double> {
@@ -507,7 +512,8 @@ PI_HD void fallback_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg,
 
 // Stage solve Y = base + hg f(Y); counts Newton iterations and fallbacks in w.
 // T fixed: the scalar bracketed Newton.  T evolving: Newton on (x, E) with x
-// projected onto [0,1] and E kept positive, at most NEWTON_2D_MAXIT iterations;
+// projected onto [0,1] (E then takes the step of the linearisation with x on
+// the bound) and E kept positive, at most NEWTON_2D_MAXIT iterations;
 // if it has not settled, a nested bracketed solve in (x, T): x at fixed T by the
 // scalar solve, and the energy residual bracketed in ln T from the floor
 // upwards and solved by the Illinois variant of regula falsi.
@@ -515,6 +521,8 @@ PI_HD void fallback_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg,
 // fallbacks), summed per launch for the performance counters.
 struct Work {
     int accepted, rejected, fallbacks, newton;
+    int close;   // substep-control decisions near their thresholds
+    int fixed;   // cells re-solved in double (mixed precision)
 };
 
 template <typename R>
@@ -540,8 +548,12 @@ PI_HD void stage_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg, R&
         const R idet = r_rcp(a11 * a22 - a12 * a21);
         R xn = x - (a22 * Rx - a12 * RE) * idet;
         R En = E - (a11 * RE - a21 * Rx) * idet;
-        if (!(xn >= R(0))) xn = R(0);
-        if (xn > R(1)) xn = R(1);
+        if (!(xn >= R(0)) || xn > R(1)) {
+            // x held on the bound; E takes the step of the linearisation there
+            const R xbnd = xn > R(1) ? R(1) : R(0);
+            En = E - (RE + a21 * (xbnd - x)) * r_rcp(a22);
+            xn = xbnd;
+        }
         if (!(En > R(0))) En = R(0.5) * E;
         const R err = r_max(r_abs(xn - x) * r_rcp(r_max(xn, R(1e-12))), r_abs(En - E) * r_rcp(En));
         // x held on a bound while the residual puts the root inside [0, 1]
@@ -551,23 +563,34 @@ PI_HD void stage_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg, R&
                            (xn <= R(0) && Rx < R(0));
         x = xn;
         E = En;
-        if (!stuck && (err <= Tol<R>::rtol || (err >= eprev && err <= Tol<R>::stall))) return;
+        if (!stuck && (err <= Tol<R>::rtol || (err >= eprev && err <= Tol<R>::stall))) {
+            // x = 1 held although it is an unstable equilibrium (a11 < 0) and
+            // the residual pushes x inside: the precision cannot resolve the
+            // seed that would start the runaway
+            if (xn >= R(1) && Rx > R(0) && a11 < R(0)) ++w.close;
+            return;
+        }
         eprev = err;
     }
     fallback_solve(p, e, xb, Eb, hg, x, E);
     ++w.fallbacks;
+    ++w.close;   // (its tolerance follows the precision: re-solved in double when mixed)
 }
 
 // Initial substep count of one micro-integration: at least n_sub, and enough
 // that at the initial rate no substep moves x by more than SUB_DX; at most
 // SUB_MAX.
 template <typename R>
-PI_HD __forceinline__ int substeps(const Params<R>& p, const Env<R>& e, R x0, R E0, R h)
+PI_HD __forceinline__ int substeps(const Params<R>& p, const Env<R>& e, R x0, R E0, R h, Work& w)
 {
     Rhs<R> r;
     rhs_full(p, e, x0, E0, r);
     const double s = (double)h * (double)r_abs(r.fx) / SUB_DX;
     int ns = p.n_sub > 0 ? p.n_sub : 1;
+    if (s > (double)ns * (1.0 - MIX_MARGIN) && s < (double)SUB_MAX * (1.0 + MIX_MARGIN)) {
+        const double fr = s - floor(s);   // ceil(s) changes at the integers
+        if (fr < MIX_MARGIN * s || 1.0 - fr < MIX_MARGIN * s) ++w.close;
+    }
     if (s > (double)ns) ns = s >= (double)SUB_MAX ? SUB_MAX : (int)ceil(s);
     return ns;
 }
@@ -602,7 +625,7 @@ PI_HD void micro(const Params<R>& p, const Env<R>& e, R h, R& x, R& E, Work& w)
     if (!(h > R(0))) return;
     const bool evolve = p.thermal == 1;
     if (evolve && E < e_floor(e.n, x)) E = e_floor(e.n, x);
-    const int ns = substeps(p, e, x, E, h);
+    const int ns = substeps(p, e, x, E, h, w);
     const int top = 1 << SUB_LEVELS;
     const int U = ns * top;
     int pos = 0, s = top;
@@ -610,8 +633,12 @@ PI_HD void micro(const Params<R>& p, const Env<R>& e, R h, R& x, R& E, Work& w)
         const R hs = R((double)h * (double)s / (double)U);
         R xn = x, En = E;
         sdirk_step(p, e, hs, xn, En, w);
-        const bool bad = r_abs(xn - x) > R(REJ_DX) ||
-                         (evolve && (En > R(REJ_E) * E || En * R(REJ_E) < E));
+        const R dx = r_abs(xn - x);
+        const bool bad = dx > R(REJ_DX) || (evolve && (En > R(REJ_E) * E || En * R(REJ_E) < E));
+        if (r_abs(dx - R(REJ_DX)) < R(MIX_MARGIN * REJ_DX) ||
+            (evolve && (r_abs(En - R(REJ_E) * E) < R(MIX_MARGIN * REJ_E) * E ||
+                        r_abs(En * R(REJ_E) - E) < R(MIX_MARGIN) * E)))
+            ++w.close;
         if (bad && s > 1) {
             s >>= 1;
             ++w.rejected;

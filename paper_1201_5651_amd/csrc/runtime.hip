@@ -154,9 +154,13 @@ struct pi_grid {
     pi_grid_desc d;
     pi_fields f;
     bool fp64;
+    bool mixed;                  // float bulk pass + double re-solve of listed cells
     Params<double> pd;
     Params<float> pf;
-    void* table = nullptr;
+    DevTable<double>* table_d = nullptr;   // FP64 and MIXED
+    DevTable<float>* table_f = nullptr;    // FP32 and MIXED
+    int* fix_list = nullptr;               // MIXED: cells for the double re-solve (ncell)
+    int fix_blocks = 0;
     DevState* st = nullptr;
     unsigned long long* work = nullptr;   // WORK_COUNTERS x WORK_SLOTS
     double* part = nullptr;
@@ -204,7 +208,9 @@ pi_status validate(const pi_grid_desc* d, const pi_fields* f)
 void free_grid(pi_grid* g)
 {
     if (!g) return;
-    if (g->table) (void)hipFree(g->table);
+    if (g->table_d) (void)hipFree(g->table_d);
+    if (g->table_f) (void)hipFree(g->table_f);
+    if (g->fix_list) (void)hipFree(g->fix_list);
     if (g->st) (void)hipFree(g->st);
     if (g->work) (void)hipFree(g->work);
     if (g->part) (void)hipFree(g->part);
@@ -244,9 +250,14 @@ pi_status chem_t(pi_grid* g, bool dev_dt, double h, int tau_buf, int from, int t
         E0 = nullptr;
         E1 = nullptr;
     }
-    HIP_OR(launch_chem<R>(params<R>(g), nH, x0, E0, tau, x1, E1, dev_dt ? g->st : nullptr, h,
-                          g->work, s),
+    HIP_OR(launch_chem<R>(params<R>(g), nH, x0, E0, tau, x1, E1, g->st, dev_dt, h, g->work,
+                          g->mixed ? g->fix_list : nullptr, s),
            "chemistry launch");
+    if (g->mixed)
+        HIP_OR(launch_chem_fix(g->pd, cp<float>(nH), cp<float>(x0), cp<float>(E0), cp<float>(tau),
+                               mp<float>(x1), mp<float>(E1), g->st, dev_dt, h, g->work,
+                               g->fix_list, g->fix_blocks, s),
+               "double re-solve launch");
     return PI_OK;
 }
 
@@ -279,7 +290,7 @@ template <typename R> pi_status step_t(pi_grid* g, double t_end, int order, hipS
 
 extern "C" {
 
-int pi_abi_version(void) { return 100; }
+int pi_abi_version(void) { return PI_ABI_VERSION; }
 
 const char* pi_last_error(void) { return g_err.c_str(); }
 
@@ -315,6 +326,7 @@ pi_status pi_grid_create(const pi_grid_desc* desc, const pi_fields* fields, pi_g
     g->d = *desc;
     g->f = *fields;
     g->fp64 = desc->precision == PI_FP64;
+    g->mixed = desc->precision == PI_MIXED;
     g->pd = make_params<double>(*desc);
     g->pf = make_params<float>(*desc);
     g->noct = octant_count(*desc);
@@ -328,21 +340,23 @@ pi_status pi_grid_create(const pi_grid_desc* desc, const pi_fields* fields, pi_g
     {
         std::vector<double> raw(5 * PI_NTAB, 0.0);
         if (desc->spectrum == PI_SPEC_TABLE) pi_table_build(desc->T_bb, desc->Q > 0 ? desc->Q : 1.0, raw.data());
-        size_t bytes = g->fp64 ? sizeof(DevTable<double>) : sizeof(DevTable<float>);
-        if (hipMalloc(&g->table, bytes) != hipSuccess) return bail(PI_ENOMEM, "table allocation");
-        if (g->fp64) {
+        const double Qn = desc->Q > 0 ? desc->Q : 1.0;
+        if (g->fp64 || g->mixed) {
             DevTable<double> T{};
-            if (desc->spectrum == PI_SPEC_TABLE) fill_table(T, raw.data(), desc->Q > 0 ? desc->Q : 1.0);
-            if (hipMemcpy(g->table, &T, bytes, hipMemcpyHostToDevice) != hipSuccess)
-                return bail(PI_EDEVICE, "table upload");
-        } else {
-            DevTable<float> T{};
-            if (desc->spectrum == PI_SPEC_TABLE) fill_table(T, raw.data(), desc->Q > 0 ? desc->Q : 1.0);
-            if (hipMemcpy(g->table, &T, bytes, hipMemcpyHostToDevice) != hipSuccess)
+            if (desc->spectrum == PI_SPEC_TABLE) fill_table(T, raw.data(), Qn);
+            if (hipMalloc(&g->table_d, sizeof(T)) != hipSuccess) return bail(PI_ENOMEM, "table allocation");
+            if (hipMemcpy(g->table_d, &T, sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
                 return bail(PI_EDEVICE, "table upload");
         }
-        g->pd.tab = static_cast<const DevTable<double>*>(g->table);
-        g->pf.tab = static_cast<const DevTable<float>*>(g->table);
+        if (!g->fp64) {
+            DevTable<float> T{};
+            if (desc->spectrum == PI_SPEC_TABLE) fill_table(T, raw.data(), Qn);
+            if (hipMalloc(&g->table_f, sizeof(T)) != hipSuccess) return bail(PI_ENOMEM, "table allocation");
+            if (hipMemcpy(g->table_f, &T, sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+                return bail(PI_EDEVICE, "table upload");
+        }
+        g->pd.tab = g->table_d;
+        g->pf.tab = g->table_f;
     }
     // clock
     if (hipMalloc(&g->st, sizeof(DevState)) != hipSuccess) return bail(PI_ENOMEM, "state allocation");
@@ -359,6 +373,12 @@ pi_status pi_grid_create(const pi_grid_desc* desc, const pi_fields* fields, pi_g
     }
     // reduction partials
     const int64_t N = (int64_t)desc->n[0] * desc->n[1] * desc->n[2];
+    // mixed precision: list of cells for the double re-solve
+    if (g->mixed) {
+        if (hipMalloc(&g->fix_list, sizeof(int) * N) != hipSuccess)
+            return bail(PI_ENOMEM, "re-solve list allocation");
+        g->fix_blocks = (int)std::min<int64_t>((N + 255) / 256, 2048);
+    }
     g->nblk = (int)std::min<int64_t>((N + 255) / 256, 1024);
     if (hipMalloc(&g->part, sizeof(double) * NPART * g->nblk) != hipSuccess)
         return bail(PI_ENOMEM, "partials allocation");

@@ -26,7 +26,11 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert decl == set(binding.ABI_SYMBOLS), decl ^ set(binding.ABI_SYMBOLS)
     for name in decl:
         assert hasattr(L, name), name
-    assert L.pi_abi_version() == 100
+    header = open(os.path.join(ROOT, "include", "pi.h")).read()
+    assert L.pi_abi_version() == int(re.search(r"#define PI_ABI_VERSION (\d+)", header).group(1))
+    # the binding's constants mirror the header's
+    for name in ("PI_NDIAG", "PI_NWORK", "PI_NTAB"):
+        assert getattr(binding, name) == int(re.search(r"#define %s (\d+)" % name, header).group(1))
 
 
 def test_descriptor_validation_rejects_bad_input():

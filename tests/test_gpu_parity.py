@@ -145,6 +145,32 @@ def test_chem_parity_fp32(oracle_lib, thermal, spectrum):
         assert np.quantile(rel(Tg, Tw)[well], 0.999) < 1e-4
 
 
+@pytest.mark.parametrize("thermal,spectrum", [("evolve", "mono"), ("evolve", "table")])
+@pytest.mark.parametrize("h", [1e10, 3e10])
+def test_chem_parity_mixed(oracle_lib, thermal, spectrum, h):
+    """PI_MIXED: float bulk, and a double re-solve of every cell whose substep
+    control decided within 1e-3 of a threshold.  The largest float errors come
+    from such decisions going the other way (a different, equally valid choice
+    of substeps), not from conditioning; with the re-solve every
+    well-conditioned cell is within 1e-4 of the oracle on the same inputs."""
+    spec, g, pb, nH, x, E, tau = _chem_case(11, thermal, spectrum, "mixed")
+    g.work_counters(reset=True)
+    g.chem_step(h, binding.PI_BUF_N, binding.PI_BUF_N, binding.PI_BUF_HALF)
+    w = g.work_counters(reset=True)
+    xw, Ew = pb.chem(nH, x, E, tau, h)
+    well = _sensitivity(pb, nH, x, E, tau, h, xw) <= 1e-10
+    err = rel_x(to_np(g.x_half), xw)[well]
+    Tg = pb.temperature(nH, to_np(g.x_half), to_np(g.E_half))
+    Tw = pb.temperature(nH, xw, Ew)
+    print("mixed: %d of %d cells re-solved in double; x err max %.3g, T err max %.3g"
+          % (w["resolved_fp64"], spec.ncells, err.max(), rel(Tg, Tw)[well].max()))
+    assert 0 <= w["resolved_fp64"] < spec.ncells // 10
+    assert err.max() < 1e-4
+    assert rel(Tg, Tw)[well].max() < 1e-4
+    # the input state is untouched (the re-solve reads it after the bulk pass)
+    assert np.array_equal(to_np(g.x), x)
+
+
 @pytest.mark.parametrize("thermal,spectrum", [("fixed", "mono"), ("evolve", "table")])
 def test_timestep_parity(oracle_lib, thermal, spectrum):
     """eq. (4) reduced in FP64 on the device: the dt of one A2 step equals the
@@ -196,18 +222,20 @@ def test_cfg2_physics_steps_parity_fp64(oracle_lib):
     assert np.max(rel(Tg, Tw)) < 1e-9
 
 
-def test_cfg2_physics_steps_fp32(oracle_lib):
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_cfg2_physics_steps_fp32(oracle_lib, precision):
+    """Float and mixed A3 steps (the corrector updates the state in place)."""
     spec = synth.cfg2(n=24)
     nH = synth.lognormal_density(spec.shape, 10.0, 1.0, 3)
-    g, pb, st = pair(spec, nH, T0=50.0, precision="fp32")
+    g, pb, st = pair(spec, nH, T0=50.0, precision=precision)
     for _ in range(8):
         g.step_o2(spec.t_end)
         pb.step(st, spec.t_end)
     errx = rel_x(to_np(g.x), st["x"])
     Tg = pb.temperature(st["nH"], to_np(g.x), to_np(g.E))
     Tw = pb.temperature(st["nH"], st["x"], st["E"])
-    print("fp32 x err max %.3g p999 %.3g; T err max %.3g" % (errx.max(), np.quantile(errx, .999),
-                                                           rel(Tg, Tw).max()))
+    print("%s x err max %.3g p999 %.3g; T err max %.3g" % (precision, errx.max(),
+                                                         np.quantile(errx, .999), rel(Tg, Tw).max()))
     assert np.quantile(errx, 0.999) < 1e-4
     assert np.quantile(rel(Tg, Tw), 0.999) < 1e-4
 
