@@ -177,6 +177,43 @@ pi_status pi_diagnostics(pi_grid* grid, double* out, void* stream);
  * Counters are summed over all pi_chem_step / step calls of the grid. */
 pi_status pi_work_counters(pi_grid* grid, int64_t* out, int reset, void* stream);
 
+/* ------------------------------------------------------------- batches
+ * A batch advances many grids together: every kernel of a step is one launch
+ * over the cells (or raytrace tiles) of all grids, and the step is replayed
+ * from a captured HIP graph.  Each grid keeps its own descriptor, fields,
+ * clock, timestep (eq. 4 reduced over its own cells) and t_end; a grid at its
+ * t_end takes dt = 0 while the others go on.  A grid advanced in a batch goes
+ * through the same per-cell arithmetic as the same grid advanced alone with
+ * pi_step_o2, so its results do not depend on the composition of the batch
+ * (up to the summation order of the diagnostics). */
+typedef struct pi_batch pi_batch;
+
+/* ngrids descriptors and fields (arrays of ngrids, copied; the fields stay
+ * owned by the caller and valid until pi_batch_destroy).  All descriptors
+ * share one precision.  Errors as pi_grid_create, prefixed with the grid. */
+pi_status pi_batch_create(int ngrids, const pi_grid_desc* descs, const pi_fields* fields,
+                          pi_batch** out);
+/* Synchronises the device and frees the batch; NULL is accepted. */
+pi_status pi_batch_destroy(pi_batch* batch);
+/* Per grid (host arrays of ngrids): clock t, step count (NULL: 0) and t_end
+ * of the steps to come.  SYNCHRONISES the stream. */
+pi_status pi_batch_set_time(pi_batch* batch, const double* t, const int64_t* nsteps,
+                            const double* t_end, void* stream);
+/* pi_init_energy for every grid, T0 a host array of ngrids. */
+pi_status pi_batch_init_energy(pi_batch* batch, const double* T0, int state, void* stream);
+/* pi_raytrace of every grid. */
+pi_status pi_batch_raytrace(pi_batch* batch, int state, int tau_buf, void* stream);
+/* One algorithm-3 step of every grid toward its own t_end (pi_step_o2 with the
+ * t_end set by pi_batch_set_time), enqueued as one graph launch on stream. */
+pi_status pi_batch_step_o2(pi_batch* batch, void* stream);
+/* Per grid clock (host arrays of ngrids; NULL skips).  SYNCHRONISES. */
+pi_status pi_batch_state(pi_batch* batch, double* t, int64_t* nsteps, double* last_dt,
+                         void* stream);
+/* pi_diagnostics of every grid: out[ngrids * PI_NDIAG], grid-major.  SYNCHRONISES. */
+pi_status pi_batch_diagnostics(pi_batch* batch, double* out, void* stream);
+/* pi_work_counters summed over the grids of the batch.  SYNCHRONISES. */
+pi_status pi_batch_work_counters(pi_batch* batch, int64_t* out, int reset, void* stream);
+
 /* Host-only: blackbody rate table of the TABLE spectrum (Sect. 2, rates
  * tabulated against optical depth): out[5*PI_NTAB] = node optical depths, P
  * (photons/s surviving a threshold column tau), -dP/dtau, H (excess energy
@@ -189,7 +226,7 @@ const char* pi_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns the
  * value it was built with. */
-#define PI_ABI_VERSION 101
+#define PI_ABI_VERSION 102
 int pi_abi_version(void);
 
 #ifdef __cplusplus

@@ -9,8 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpi.so")
-SOURCES = ["kernels.hip", "runtime.hip"]
-HEADERS = ["physics.h", "kernels.h"]
+SOURCES = ["kernels.hip", "engine.hip", "runtime.hip"]
+HEADERS = ["physics.h", "kernels.h", "engine.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -31,6 +31,9 @@ ABI_SYMBOLS = (
     "pi_grid_create", "pi_grid_destroy", "pi_raytrace", "pi_chem_step", "pi_timestep",
     "pi_step_o2", "pi_step_o1", "pi_init_energy", "pi_set_time", "pi_grid_state",
     "pi_diagnostics", "pi_work_counters", "pi_table_build", "pi_last_error", "pi_abi_version",
+    "pi_batch_create", "pi_batch_destroy", "pi_batch_set_time", "pi_batch_init_energy",
+    "pi_batch_raytrace", "pi_batch_step_o2", "pi_batch_state", "pi_batch_diagnostics",
+    "pi_batch_work_counters",
 )
 
 
@@ -93,6 +96,16 @@ def lib() -> C.CDLL:
         L.pi_diagnostics.argtypes = [vp, dp, vp]
         L.pi_work_counters.argtypes = [vp, C.POINTER(C.c_int64), i32, vp]
         L.pi_table_build.argtypes = [d, d, dp]
+        i64p = C.POINTER(C.c_int64)
+        L.pi_batch_create.argtypes = [i32, C.POINTER(GridDesc), C.POINTER(Fields), C.POINTER(vp)]
+        L.pi_batch_destroy.argtypes = [vp]
+        L.pi_batch_set_time.argtypes = [vp, dp, i64p, dp, vp]
+        L.pi_batch_init_energy.argtypes = [vp, dp, i32, vp]
+        L.pi_batch_raytrace.argtypes = [vp, i32, i32, vp]
+        L.pi_batch_step_o2.argtypes = [vp, vp]
+        L.pi_batch_state.argtypes = [vp, dp, i64p, dp, vp]
+        L.pi_batch_diagnostics.argtypes = [vp, dp, vp]
+        L.pi_batch_work_counters.argtypes = [vp, i64p, i32, vp]
         L.pi_last_error.restype = C.c_char_p
         L.pi_abi_version.restype = C.c_int
         for name in ABI_SYMBOLS:
@@ -141,6 +154,43 @@ def desc_from_spec(spec, precision: Optional[str] = None, sigma0: float = 6.3e-1
     return d
 
 
+FIELD_NAMES = ("nH", "x", "E", "tau", "x_half", "E_half", "tau_half")
+
+
+class GridFields:
+    """Device field tensors of one grid (torch, caller-owned memory of the ABI)."""
+
+    def __init__(self, spec, precision: str, device):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the photoionisation library needs a GPU (no CPU fallback)")
+        self.spec = spec
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.device = torch.device(device)
+        z = lambda: torch.zeros(spec.shape, dtype=self.dtype, device=self.device)
+        self.nH, self.x, self.tau = z(), z(), z()
+        self.x_half, self.tau_half = z(), z()
+        evolve = spec.thermal == "evolve"
+        self.E = z() if evolve else None
+        self.E_half = z() if evolve else None
+
+    def abi_fields(self) -> Fields:
+        f = Fields()
+        for k in FIELD_NAMES:
+            t = getattr(self, k)
+            setattr(f, k, t.data_ptr() if t is not None else None)
+        return f
+
+    def fill(self, nH, x=1.0):
+        import torch
+        self.nH.copy_(torch.as_tensor(nH, dtype=self.dtype).reshape(self.spec.shape))
+        if isinstance(x, (int, float)):
+            self.x.fill_(float(x))
+        else:
+            self.x.copy_(torch.as_tensor(x, dtype=self.dtype).reshape(self.spec.shape))
+
+
 class Grid:
     """One photoionisation problem resident on the GPU.
 
@@ -149,24 +199,13 @@ class Grid:
     """
 
     def __init__(self, spec, device: str = "cuda:0", precision: Optional[str] = None):
-        import torch
-        if not torch.cuda.is_available():
-            raise RuntimeError("the photoionisation library needs a GPU (no CPU fallback)")
         self.spec = spec
         self.precision = precision or spec.precision
-        self.dtype = torch.float64 if self.precision == "fp64" else torch.float32
-        self.device = torch.device(device)
-        shape = spec.shape
-        z = lambda: torch.zeros(shape, dtype=self.dtype, device=self.device)
-        self.nH, self.x, self.tau = z(), z(), z()
-        self.x_half, self.tau_half = z(), z()
-        evolve = spec.thermal == "evolve"
-        self.E = z() if evolve else None
-        self.E_half = z() if evolve else None
-        f = Fields()
-        for k in ("nH", "x", "E", "tau", "x_half", "E_half", "tau_half"):
-            t = getattr(self, k)
-            setattr(f, k, t.data_ptr() if t is not None else None)
+        self._fl = GridFields(spec, self.precision, device)
+        self.dtype, self.device = self._fl.dtype, self._fl.device
+        for k in FIELD_NAMES:
+            setattr(self, k, getattr(self._fl, k))
+        f = self._fl.abi_fields()
         self._fields = f
         self._desc = desc_from_spec(spec, self.precision)
         h = C.c_void_p()
@@ -183,12 +222,7 @@ class Grid:
     def load(self, nH, x=1.0, T0: Optional[float] = None, t: float = 0.0, nsteps: int = 0):
         """Copy density and neutral fraction in, set E from T0 (T-evolving
         grids), raytrace the initial columns and set the clock."""
-        import torch
-        self.nH.copy_(torch.as_tensor(nH, dtype=self.dtype).reshape(self.spec.shape))
-        if isinstance(x, (int, float)):
-            self.x.fill_(float(x))
-        else:
-            self.x.copy_(torch.as_tensor(x, dtype=self.dtype).reshape(self.spec.shape))
+        self._fl.fill(nH, x)
         s = self._stream()
         if self.E is not None:
             check(lib().pi_init_energy(self._h, float(T0 if T0 is not None else self.spec.T0),
@@ -249,6 +283,99 @@ class Grid:
     def close(self):
         if getattr(self, "_h", None):
             check(lib().pi_grid_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many grids advanced together (one launch per kernel for all of them,
+    each step replayed from a captured HIP graph).  ``grids[i]`` holds the
+    field tensors of grid i; every grid keeps its own clock and t_end."""
+
+    def __init__(self, specs, device: str = "cuda:0", precision: Optional[str] = None):
+        self.specs = list(specs)
+        self.precision = precision or self.specs[0].precision
+        self.grids = [GridFields(s, self.precision, device) for s in self.specs]
+        n = len(self.specs)
+        self._descs = (GridDesc * n)(*[desc_from_spec(s, self.precision) for s in self.specs])
+        self._fields = (Fields * n)(*[g.abi_fields() for g in self.grids])
+        h = C.c_void_p()
+        check(lib().pi_batch_create(n, self._descs, self._fields, C.byref(h)))
+        self._h = h
+
+    @property
+    def n(self) -> int:
+        return len(self.specs)
+
+    _stream = staticmethod(Grid._stream)
+
+    def _arr(self, vals, ctype=C.c_double):
+        vals = list(vals)
+        assert len(vals) == self.n
+        return (ctype * self.n)(*vals)
+
+    def load(self, nHs, x0s=None, T0s=None, t=0.0, t_end=None):
+        """Density and neutral fraction of every grid, energies from T0,
+        initial columns, clocks at t and the t_end of each grid."""
+        for i, g in enumerate(self.grids):
+            g.fill(nHs[i], 1.0 if x0s is None else x0s[i])
+        s = self._stream()
+        if any(sp.thermal == "evolve" for sp in self.specs):
+            T0 = [float(T0s[i] if T0s is not None else sp.T0) for i, sp in enumerate(self.specs)]
+            check(lib().pi_batch_init_energy(self._h, self._arr(T0), PI_BUF_N, s))
+        check(lib().pi_batch_raytrace(self._h, PI_BUF_N, PI_BUF_N, s))
+        t_end = [sp.t_end for sp in self.specs] if t_end is None else t_end
+        self.set_time([t] * self.n if isinstance(t, (int, float)) else t, t_end)
+
+    def set_time(self, t, t_end, nsteps=None):
+        self._t_end = [float(v) for v in t_end]
+        ns = None if nsteps is None else self._arr(nsteps, C.c_int64)
+        check(lib().pi_batch_set_time(self._h, self._arr(t), ns, self._arr(t_end), self._stream()))
+
+    def raytrace(self, state=PI_BUF_N, tau_buf=PI_BUF_N):
+        check(lib().pi_batch_raytrace(self._h, state, tau_buf, self._stream()))
+
+    def step_o2(self):
+        check(lib().pi_batch_step_o2(self._h, self._stream()))
+
+    def state(self):
+        t, dt = (C.c_double * self.n)(), (C.c_double * self.n)()
+        k = (C.c_int64 * self.n)()
+        check(lib().pi_batch_state(self._h, t, k, dt, self._stream()))
+        return list(t), list(k), list(dt)
+
+    def diagnostics(self):
+        out = (C.c_double * (PI_NDIAG * self.n))()
+        check(lib().pi_batch_diagnostics(self._h, out, self._stream()))
+        keys = ("n_ion", "v_ion", "r_ion", "photo_rate", "recomb_rate", "nonfinite", "octants", "t")
+        return [dict(zip(keys, list(out)[i * PI_NDIAG:(i + 1) * PI_NDIAG])) for i in range(self.n)]
+
+    def work_counters(self, reset: bool = False):
+        out = (C.c_int64 * PI_NWORK)()
+        check(lib().pi_batch_work_counters(self._h, out, int(reset), self._stream()))
+        return {"accepted": out[0], "rejected": out[1], "fallbacks": out[2], "newton": out[3],
+                "resolved_fp64": out[4]}
+
+    def run(self, max_steps: int = 10**8, check_every: int = 32):
+        """Step until every grid is at its t_end; returns the steps launched."""
+        launched = 0
+        while launched < max_steps:
+            for _ in range(min(check_every, max_steps - launched)):
+                self.step_o2()
+                launched += 1
+            t, _, _ = self.state()
+            if all(ti >= te for ti, te in zip(t, self._t_end)):
+                break
+        return launched
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(lib().pi_batch_destroy(self._h))
             self._h = None
 
     def __del__(self):

@@ -1,0 +1,99 @@
+// engine.h -- host side of a batch of grids advanced together.
+//
+// A GridHost holds one grid: its descriptor, the caller's field pointers, and
+// the small device buffers that belong to the grid alone (clock, reduction
+// partials).  An Engine advances a set of GridHost of one precision with one
+// launch per kernel for the whole set: it owns the device descriptor array,
+// the launch geometry, the combined raytrace tile schedule, the mixed-precision
+// re-solve list, the work counters and the rate tables (shared between grids
+// with the same spectrum).  A single grid is an Engine over one GridHost.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pi.h"
+#include "kernels.h"
+
+namespace pi {
+
+// Sets the thread-local message returned by pi_last_error.
+pi_status fail(pi_status s, const std::string& msg);
+const std::string& last_error();
+pi_status validate_desc(const pi_grid_desc* d);
+pi_status validate_fields(const pi_grid_desc* d, const pi_fields* f);
+
+struct GridHost {
+    pi_grid_desc d{};
+    pi_fields f{};
+    DevState* st = nullptr;   // device clock and diagnostics
+    double* part = nullptr;   // device timestep partials (nblk_dt * NPART)
+    int nblk_dt = 0;
+    int noct = 0;
+    double cell_vol = 0.0;
+    int64_t ncell = 0;
+    std::vector<std::vector<int4>> tiles;   // per tile diagonal: (octant, tx, ty, tz)
+};
+
+pi_status grid_host_init(GridHost& h, const pi_grid_desc& d, const pi_fields& f);
+void grid_host_free(GridHost& h);
+
+struct Engine {
+    int precision = PI_FP64;
+    std::vector<GridHost*> grids;
+    void* gdev = nullptr;            // GridDev<R>[ngrids]
+    size_t gdev_cap = 0;
+    int* first = nullptr;            // chem_first[ngrids+1], then dt_first[ngrids+1]
+    size_t first_cap = 0;
+    int chem_blocks = 0, dt_blocks = 0;
+    int4* tiles = nullptr;
+    size_t tiles_cap = 0;
+    std::vector<int> stage_first, stage_count;
+    unsigned int* fix_n = nullptr;
+    long long* fix_list = nullptr;
+    size_t fix_cap = 0;
+    int fix_blocks = 0;
+    unsigned long long* work = nullptr;
+    struct Table {
+        int spectrum;
+        double T_bb;
+        void* d;   // DevTable<double>
+        void* f;   // DevTable<float>
+    };
+    std::vector<Table> tables;
+    hipStream_t cap = nullptr;       // capture stream of the step graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    bool fp64() const { return precision == PI_FP64; }
+    bool mixed() const { return precision == PI_MIXED; }
+    int ngrids() const { return (int)grids.size(); }
+    BatchDev bd() const;
+};
+
+// (Re)builds the device structures of e for `grids` (all of e.precision);
+// keeps allocations whose capacity suffices and drops a captured step graph.
+pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids);
+void engine_free(Engine& e);
+
+pi_status engine_raytrace(Engine& e, int state, int tau_buf, hipStream_t s);
+pi_status engine_chem(Engine& e, bool dev_dt, double h, int tau_buf, int from, int to,
+                      hipStream_t s);
+// t_end_arg finite: the common t_end, else each grid's stored t_end.
+pi_status engine_timestep(Engine& e, double t_end_arg, hipStream_t s);
+pi_status engine_step(Engine& e, double t_end_arg, int order, hipStream_t s);
+// One A3 step of every grid toward its stored t_end, as a captured graph
+// (captured on first use, replayed on s).
+pi_status engine_step_graph(Engine& e, hipStream_t s);
+pi_status engine_init_energy(Engine& e, int grid, double T0, int state, hipStream_t s);
+// Clock and diagnostics of every grid (synchronise s).
+pi_status engine_read_states(Engine& e, std::vector<DevState>& out, hipStream_t s);
+pi_status engine_write_states(Engine& e, const std::vector<DevState>& in, hipStream_t s);
+// Recomputed diagnostics of state n of every grid (ngrids * PI_NDIAG), leaving
+// the clocks and the stored timesteps as they were (synchronises s).
+pi_status engine_diagnostics(Engine& e, std::vector<double>& out, hipStream_t s);
+pi_status engine_work(Engine& e, int64_t* out, int reset, hipStream_t s);
+
+}  // namespace pi

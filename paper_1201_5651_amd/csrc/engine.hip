@@ -1,0 +1,499 @@
+// engine.hip -- batch engine: device structures of a set of grids and the
+// composition of the kernels into the operations of the C ABI (raytrace,
+// micro-physics update, timestep, and the second-order (algorithm 3) and
+// first-order (algorithm 2) steps of Sect. 2.2 of Mackey (A&A 2012)).
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace pi {
+
+#define HIP_OR(expr, msg)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(PI_EDEVICE, std::string(msg) + ": " + hipGetErrorString(e_));              \
+    } while (0)
+
+namespace {
+
+int octant_count(const pi_grid_desc& d)
+{
+    int noct = 0;
+    for (int o = 0; o < 8; ++o) {
+        bool ok = true;
+        for (int a = 0; a < 3; ++a) {
+            const int ext = ((o >> a) & 1) ? d.n[a] - d.src[a] : d.src[a];
+            ok = ok && ext > 0;
+        }
+        noct += ok;
+    }
+    return noct;
+}
+
+// Rate table in the form the kernels use: values normalised by Q, logarithms
+// of the values relative to tau = 0 and logarithmic slopes at the nodes.
+template <typename R> void fill_table(DevTable<R>& T, const double* tab, double Q)
+{
+    const double* tn = tab;
+    const double* P = tab + PI_NTAB;
+    const double* P1 = tab + 2 * PI_NTAB;
+    const double* H = tab + 3 * PI_NTAB;
+    const double* H1 = tab + 4 * PI_NTAB;
+    const double q = Q > 0 ? Q : 1.0;
+    T.p0 = R(P[0] / q);
+    T.p1_0 = R(P1[0] / q);
+    T.h0 = R(H[0] / q);
+    T.h1_0 = R(H1[0] / q);
+    const double s1 = std::log(tn[1]);
+    const double delta = std::log(tn[2]) - std::log(tn[1]);
+    T.s1 = R(s1);
+    T.delta = R(delta);
+    T.inv_delta = R(1.0 / delta);
+    T.tau1 = R(tn[1]);
+    T.tau_last = R(tn[PI_NTAB - 1]);
+    for (int j = 0; j < PI_NTAB; ++j) {
+        if (j == 0 || P[j] <= 0 || H[j] <= 0) {
+            T.lp[j] = T.mp[j] = T.lh[j] = T.mh[j] = R(0);
+            continue;
+        }
+        T.lp[j] = R(std::log(P[j] / P[0]));
+        T.mp[j] = R(-tn[j] * P1[j] / P[j]);
+        T.lh[j] = R(std::log(H[j] / H[0]));
+        T.mh[j] = R(-tn[j] * H1[j] / H[j]);
+    }
+}
+
+template <typename R> Params<R> make_params(const pi_grid_desc& d)
+{
+    Params<R> p;
+    p.nx = d.n[0];
+    p.ny = d.n[1];
+    p.nz = d.n[2];
+    p.sx = d.src[0];
+    p.sy = d.src[1];
+    p.sz = d.src[2];
+    p.ncell = (int64_t)d.n[0] * d.n[1] * d.n[2];
+    p.QV = R(d.Q / (d.dx * d.dx * d.dx));
+    p.sdx = R(d.sigma0 * d.dx);
+    p.eps = R(d.e_excess);
+    p.T_fixed = R(d.T_fixed);
+    p.alpha_B = R(d.alpha_B);
+    for (int i = 0; i < 4; ++i) p.K[i] = std::isfinite(d.K[i]) ? R(d.K[i]) : R(INFINITY);
+    p.spectrum = d.spectrum;
+    p.thermal = d.thermal;
+    p.recomb = d.recomb;
+    p.collisional = d.collisional;
+    p.cooling = d.cooling;
+    p.weights = d.weights;
+    p.src_rule = d.source_cell_rule;
+    p.n_sub = d.n_sub;
+    p.tab = nullptr;
+    return p;
+}
+
+// Device copies of the rate table of (spectrum, T_bb), shared by the grids of
+// the engine that use it.  The table is normalised by Q, so Q does not enter.
+pi_status table_for(Engine& e, const pi_grid_desc& d, void** td, void** tf)
+{
+    *td = *tf = nullptr;
+    if (d.spectrum != PI_SPEC_TABLE) return PI_OK;
+    for (const Engine::Table& t : e.tables)
+        if (t.spectrum == d.spectrum && t.T_bb == d.T_bb) {
+            *td = t.d;
+            *tf = t.f;
+            return PI_OK;
+        }
+    std::vector<double> raw(5 * PI_NTAB, 0.0);
+    pi_status r = pi_table_build(d.T_bb, 1.0, raw.data());
+    if (r != PI_OK) return r;
+    Engine::Table t{ d.spectrum, d.T_bb, nullptr, nullptr };
+    DevTable<double> Td{};
+    fill_table(Td, raw.data(), 1.0);
+    DevTable<float> Tf{};
+    fill_table(Tf, raw.data(), 1.0);
+    HIP_OR(hipMalloc(&t.d, sizeof(Td)), "table allocation");
+    if (hipMalloc(&t.f, sizeof(Tf)) != hipSuccess) {
+        (void)hipFree(t.d);
+        return fail(PI_ENOMEM, "table allocation");
+    }
+    e.tables.push_back(t);
+    HIP_OR(hipMemcpy(t.d, &Td, sizeof(Td), hipMemcpyHostToDevice), "table upload");
+    HIP_OR(hipMemcpy(t.f, &Tf, sizeof(Tf), hipMemcpyHostToDevice), "table upload");
+    *td = t.d;
+    *tf = t.f;
+    return PI_OK;
+}
+
+template <typename R> R* fld(void* v) { return static_cast<R*>(v); }
+
+template <typename R> pi_status upload_grids(Engine& e)
+{
+    std::vector<GridDev<R>> h(e.grids.size());
+    for (size_t g = 0; g < e.grids.size(); ++g) {
+        const GridHost& G = *e.grids[g];
+        void *td, *tf;
+        pi_status r = table_for(e, G.d, &td, &tf);
+        if (r != PI_OK) return r;
+        GridDev<R>& D = h[g];
+        D.p = make_params<R>(G.d);
+        D.pd = make_params<double>(G.d);
+        D.pd.tab = static_cast<const DevTable<double>*>(td);
+        D.p.tab = static_cast<const DevTable<R>*>(sizeof(R) == sizeof(double) ? td : tf);
+        D.nH = fld<R>(G.f.nH);
+        D.x[0] = fld<R>(G.f.x);
+        D.x[1] = fld<R>(G.f.x_half);
+        const bool ev = G.d.thermal == PI_T_EVOLVE;
+        D.E[0] = ev ? fld<R>(G.f.E) : nullptr;
+        D.E[1] = ev ? fld<R>(G.f.E_half) : nullptr;
+        D.tau[0] = fld<R>(G.f.tau);
+        D.tau[1] = fld<R>(G.f.tau_half);
+        D.st = G.st;
+        D.part = G.part;
+        D.cell_vol = G.cell_vol;
+        D.noct = G.noct;
+    }
+    const size_t bytes = sizeof(GridDev<R>) * std::max<size_t>(1, h.size());
+    if (bytes > e.gdev_cap) {
+        if (e.gdev) (void)hipFree(e.gdev);
+        e.gdev = nullptr;
+        e.gdev_cap = 0;
+        HIP_OR(hipMalloc(&e.gdev, bytes), "grid table allocation");
+        e.gdev_cap = bytes;
+    }
+    if (!h.empty())
+        HIP_OR(hipMemcpy(e.gdev, h.data(), sizeof(GridDev<R>) * h.size(), hipMemcpyHostToDevice),
+               "grid table upload");
+    return PI_OK;
+}
+
+void drop_graph(Engine& e)
+{
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+    e.exec = nullptr;
+    e.graph = nullptr;
+}
+
+template <typename R> const GridDev<R>* gd(const Engine& e)
+{
+    return static_cast<const GridDev<R>*>(e.gdev);
+}
+
+template <typename R> pi_status raytrace_t(Engine& e, int state, int tau_buf, hipStream_t s)
+{
+    for (size_t k = 0; k < e.stage_first.size(); ++k)
+        HIP_OR(launch_sweep_stage<R>(gd<R>(e), state, tau_buf, e.tiles, e.stage_first[k],
+                                     e.stage_count[k], s),
+               "raytrace launch");
+    return PI_OK;
+}
+
+template <typename R>
+pi_status chem_t(Engine& e, bool dev_dt, double h, int tau_buf, int from, int to, hipStream_t s)
+{
+    const BatchDev b = e.bd();
+    HIP_OR(launch_chem<R>(gd<R>(e), b, e.chem_blocks, from, to, tau_buf, dev_dt, h, e.work,
+                          e.mixed(), s),
+           "chemistry launch");
+    if (e.mixed())
+        HIP_OR(launch_chem_fix(gd<float>(e), b, e.fix_blocks, from, to, tau_buf, dev_dt, h, e.work,
+                               s),
+               "double re-solve launch");
+    return PI_OK;
+}
+
+template <typename R> pi_status timestep_t(Engine& e, double t_end_arg, hipStream_t s)
+{
+    HIP_OR(launch_dtdiag<R>(gd<R>(e), e.bd(), e.dt_blocks, t_end_arg, s), "timestep launch");
+    return PI_OK;
+}
+
+template <typename R> pi_status step_t(Engine& e, double t_end_arg, int order, hipStream_t s)
+{
+    pi_status r = timestep_t<R>(e, t_end_arg, s);
+    if (r != PI_OK) return r;
+    if (order == 2) {
+        if ((r = chem_t<R>(e, true, 0.5, PI_BUF_N, PI_BUF_N, PI_BUF_HALF, s)) != PI_OK) return r;
+        if ((r = raytrace_t<R>(e, PI_BUF_HALF, PI_BUF_HALF, s)) != PI_OK) return r;
+        if ((r = chem_t<R>(e, true, 1.0, PI_BUF_HALF, PI_BUF_N, PI_BUF_N, s)) != PI_OK) return r;
+    } else {
+        if ((r = chem_t<R>(e, true, 1.0, PI_BUF_N, PI_BUF_N, PI_BUF_N, s)) != PI_OK) return r;
+    }
+    if ((r = raytrace_t<R>(e, PI_BUF_N, PI_BUF_N, s)) != PI_OK) return r;
+    HIP_OR(launch_advance<R>(gd<R>(e), e.ngrids(), s), "advance launch");
+    return PI_OK;
+}
+
+}  // namespace
+
+BatchDev Engine::bd() const
+{
+    BatchDev b;
+    b.ngrids = ngrids();
+    b.chem_first = first;
+    b.dt_first = first ? first + ngrids() + 1 : nullptr;
+    b.fix_n = fix_n;
+    b.fix_list = fix_list;
+    return b;
+}
+
+pi_status grid_host_init(GridHost& h, const pi_grid_desc& d, const pi_fields& f)
+{
+    h.d = d;
+    h.f = f;
+    h.ncell = (int64_t)d.n[0] * d.n[1] * d.n[2];
+    h.noct = octant_count(d);
+    h.cell_vol = d.dx * d.dx * d.dx;
+    h.nblk_dt = (int)std::min<int64_t>((h.ncell + DT_BLOCK - 1) / DT_BLOCK, DT_MAX_BLOCKS);
+    if (hipMalloc(&h.st, sizeof(DevState)) != hipSuccess) return fail(PI_ENOMEM, "state allocation");
+    DevState s0{};
+    if (hipMemcpy(h.st, &s0, sizeof(s0), hipMemcpyHostToDevice) != hipSuccess) {
+        grid_host_free(h);
+        return fail(PI_EDEVICE, "state upload");
+    }
+    if (hipMalloc(&h.part, sizeof(double) * NPART * h.nblk_dt) != hipSuccess) {
+        grid_host_free(h);
+        return fail(PI_ENOMEM, "partials allocation");
+    }
+    // tile schedule: every octant's tiles, grouped by tile diagonal tx+ty+tz
+    h.tiles.clear();
+    for (int o = 0; o < 8; ++o) {
+        int ext[3];
+        for (int a = 0; a < 3; ++a) ext[a] = ((o >> a) & 1) ? d.n[a] - d.src[a] : d.src[a];
+        if (ext[0] <= 0 || ext[1] <= 0 || ext[2] <= 0) continue;
+        const int ntx = (ext[0] + SWEEP_T - 1) / SWEEP_T;
+        const int nty = (ext[1] + SWEEP_T - 1) / SWEEP_T;
+        const int ntz = (ext[2] + SWEEP_T - 1) / SWEEP_T;
+        for (int tz = 0; tz < ntz; ++tz)
+            for (int ty = 0; ty < nty; ++ty)
+                for (int tx = 0; tx < ntx; ++tx) {
+                    const int D = tx + ty + tz;
+                    if ((int)h.tiles.size() <= D) h.tiles.resize(D + 1);
+                    h.tiles[D].push_back(make_int4(o, tx, ty, tz));
+                }
+    }
+    return PI_OK;
+}
+
+void grid_host_free(GridHost& h)
+{
+    if (h.st) (void)hipFree(h.st);
+    if (h.part) (void)hipFree(h.part);
+    h.st = nullptr;
+    h.part = nullptr;
+}
+
+pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
+{
+    drop_graph(e);
+    e.grids = grids;
+    const int G = e.ngrids();
+    // launch geometry
+    std::vector<int> first(2 * (G + 1), 0);
+    int64_t cells = 0;
+    for (int g = 0; g < G; ++g) {
+        const int64_t n = e.grids[g]->ncell;
+        const int64_t cb = (n + CHEM_BLOCK - 1) / CHEM_BLOCK;
+        if ((int64_t)first[g] + cb > 2147483647LL) return fail(PI_EINVAL, "batch too large");
+        first[g + 1] = first[g] + (int)cb;
+        first[G + 1 + g + 1] = first[G + 1 + g] + e.grids[g]->nblk_dt;
+        cells += n;
+    }
+    e.chem_blocks = first[G];
+    e.dt_blocks = first[2 * G + 1];
+    const size_t fb = sizeof(int) * first.size();
+    if (fb > e.first_cap) {
+        if (e.first) (void)hipFree(e.first);
+        e.first = nullptr;
+        e.first_cap = 0;
+        HIP_OR(hipMalloc(&e.first, fb), "launch table allocation");
+        e.first_cap = fb;
+    }
+    HIP_OR(hipMemcpy(e.first, first.data(), fb, hipMemcpyHostToDevice), "launch table upload");
+    // combined tile schedule: stage k holds tile diagonal k of every grid
+    e.stage_first.clear();
+    e.stage_count.clear();
+    std::vector<int4> flat;
+    size_t nst = 0;
+    for (GridHost* h : e.grids) nst = std::max(nst, h->tiles.size());
+    for (size_t k = 0; k < nst; ++k) {
+        e.stage_first.push_back((int)flat.size());
+        for (int g = 0; g < G; ++g) {
+            const GridHost& h = *e.grids[g];
+            if (k >= h.tiles.size()) continue;
+            for (const int4& t : h.tiles[k]) flat.push_back(make_int4((g << 3) | t.x, t.y, t.z, t.w));
+        }
+        e.stage_count.push_back((int)flat.size() - e.stage_first.back());
+    }
+    if (flat.size() > e.tiles_cap) {
+        if (e.tiles) (void)hipFree(e.tiles);
+        e.tiles = nullptr;
+        e.tiles_cap = 0;
+        HIP_OR(hipMalloc(&e.tiles, sizeof(int4) * flat.size()), "tile schedule allocation");
+        e.tiles_cap = flat.size();
+    }
+    if (!flat.empty())
+        HIP_OR(hipMemcpy(e.tiles, flat.data(), sizeof(int4) * flat.size(), hipMemcpyHostToDevice),
+               "tile schedule upload");
+    // work counters
+    if (!e.work) {
+        const size_t wb = sizeof(unsigned long long) * WORK_COUNTERS * WORK_SLOTS;
+        HIP_OR(hipMalloc(&e.work, wb), "counter allocation");
+        HIP_OR(hipMemset(e.work, 0, wb), "counter clear");
+    }
+    // mixed precision: re-solve list for every cell of the batch
+    if (e.mixed()) {
+        if (!e.fix_n) HIP_OR(hipMalloc(&e.fix_n, sizeof(unsigned int)), "re-solve count allocation");
+        if ((size_t)cells > e.fix_cap) {
+            if (e.fix_list) (void)hipFree(e.fix_list);
+            e.fix_list = nullptr;
+            e.fix_cap = 0;
+            HIP_OR(hipMalloc(&e.fix_list, sizeof(long long) * std::max<int64_t>(cells, 1)),
+                   "re-solve list allocation");
+            e.fix_cap = (size_t)cells;
+        }
+        e.fix_blocks = (int)std::min<int64_t>((cells + 255) / 256, 2048);
+    }
+    return e.fp64() ? upload_grids<double>(e) : upload_grids<float>(e);
+}
+
+void engine_free(Engine& e)
+{
+    drop_graph(e);
+    if (e.cap) (void)hipStreamDestroy(e.cap);
+    e.cap = nullptr;
+    for (void* p : { e.gdev, (void*)e.first, (void*)e.tiles, (void*)e.fix_n, (void*)e.fix_list,
+                     (void*)e.work })
+        if (p) (void)hipFree(p);
+    for (const Engine::Table& t : e.tables) {
+        if (t.d) (void)hipFree(t.d);
+        if (t.f) (void)hipFree(t.f);
+    }
+    e.tables.clear();
+    e.gdev = nullptr;
+    e.first = nullptr;
+    e.tiles = nullptr;
+    e.fix_n = nullptr;
+    e.fix_list = nullptr;
+    e.work = nullptr;
+    e.gdev_cap = e.first_cap = e.tiles_cap = e.fix_cap = 0;
+}
+
+pi_status engine_raytrace(Engine& e, int state, int tau_buf, hipStream_t s)
+{
+    return e.fp64() ? raytrace_t<double>(e, state, tau_buf, s) : raytrace_t<float>(e, state, tau_buf, s);
+}
+
+pi_status engine_chem(Engine& e, bool dev_dt, double h, int tau_buf, int from, int to, hipStream_t s)
+{
+    return e.fp64() ? chem_t<double>(e, dev_dt, h, tau_buf, from, to, s)
+                    : chem_t<float>(e, dev_dt, h, tau_buf, from, to, s);
+}
+
+pi_status engine_timestep(Engine& e, double t_end_arg, hipStream_t s)
+{
+    return e.fp64() ? timestep_t<double>(e, t_end_arg, s) : timestep_t<float>(e, t_end_arg, s);
+}
+
+pi_status engine_step(Engine& e, double t_end_arg, int order, hipStream_t s)
+{
+    return e.fp64() ? step_t<double>(e, t_end_arg, order, s) : step_t<float>(e, t_end_arg, order, s);
+}
+
+pi_status engine_step_graph(Engine& e, hipStream_t s)
+{
+    if (e.ngrids() == 0) return PI_OK;
+    if (!e.exec) {
+        if (!e.cap) HIP_OR(hipStreamCreateWithFlags(&e.cap, hipStreamNonBlocking), "capture stream");
+        HIP_OR(hipStreamBeginCapture(e.cap, hipStreamCaptureModeThreadLocal), "begin capture");
+        pi_status r = engine_step(e, NAN, 2, e.cap);
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(e.cap, &g);
+        if (r != PI_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return r;
+        }
+        HIP_OR(ce, "end capture");
+        e.graph = g;
+        HIP_OR(hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0), "graph instantiation");
+    }
+    HIP_OR(hipGraphLaunch(e.exec, s), "graph launch");
+    return PI_OK;
+}
+
+pi_status engine_init_energy(Engine& e, int grid, double T0, int state, hipStream_t s)
+{
+    const GridHost& G = *e.grids[grid];
+    if (G.d.thermal != PI_T_EVOLVE) return PI_OK;
+    void* E = state == PI_BUF_HALF ? G.f.E_half : G.f.E;
+    const void* x = state == PI_BUF_HALF ? G.f.x_half : G.f.x;
+    if (e.fp64())
+        HIP_OR(launch_energy<double>(G.ncell, static_cast<const double*>(G.f.nH),
+                                     static_cast<const double*>(x), static_cast<double*>(E), T0, s),
+               "energy launch");
+    else
+        HIP_OR(launch_energy<float>(G.ncell, static_cast<const float*>(G.f.nH),
+                                    static_cast<const float*>(x), static_cast<float*>(E), T0, s),
+               "energy launch");
+    return PI_OK;
+}
+
+pi_status engine_read_states(Engine& e, std::vector<DevState>& out, hipStream_t s)
+{
+    out.assign(e.grids.size(), DevState{});
+    for (size_t g = 0; g < e.grids.size(); ++g)
+        HIP_OR(hipMemcpyAsync(&out[g], e.grids[g]->st, sizeof(DevState), hipMemcpyDeviceToHost, s),
+               "state read");
+    HIP_OR(hipStreamSynchronize(s), "state read sync");
+    return PI_OK;
+}
+
+pi_status engine_write_states(Engine& e, const std::vector<DevState>& in, hipStream_t s)
+{
+    for (size_t g = 0; g < e.grids.size(); ++g)
+        HIP_OR(hipMemcpyAsync(e.grids[g]->st, &in[g], sizeof(DevState), hipMemcpyHostToDevice, s),
+               "state write");
+    HIP_OR(hipStreamSynchronize(s), "state write sync");
+    return PI_OK;
+}
+
+pi_status engine_diagnostics(Engine& e, std::vector<double>& out, hipStream_t s)
+{
+    std::vector<DevState> keep, now;
+    pi_status r = engine_read_states(e, keep, s);
+    if (r != PI_OK) return r;
+    if ((r = engine_timestep(e, NAN, s)) != PI_OK) return r;
+    if ((r = engine_read_states(e, now, s)) != PI_OK) return r;
+    out.assign(e.grids.size() * PI_NDIAG, 0.0);
+    bool bad = false;
+    for (size_t g = 0; g < e.grids.size(); ++g) {
+        for (int i = 0; i < PI_NDIAG; ++i) out[g * PI_NDIAG + i] = now[g].diag[i];
+        bad = bad || now[g].diag[5] > 0;
+        for (int i = 0; i < 8; ++i) keep[g].diag[i] = now[g].diag[i];
+    }
+    if ((r = engine_write_states(e, keep, s)) != PI_OK) return r;
+    if (bad) return fail(PI_ENAN, "non-finite values in the grid state");
+    return PI_OK;
+}
+
+pi_status engine_work(Engine& e, int64_t* out, int reset, hipStream_t s)
+{
+    unsigned long long h[WORK_COUNTERS * WORK_SLOTS];
+    HIP_OR(hipMemcpyAsync(h, e.work, sizeof(h), hipMemcpyDeviceToHost, s), "counter read");
+    HIP_OR(hipStreamSynchronize(s), "counter read sync");
+    for (int c = 0; c < WORK_COUNTERS; ++c) {
+        unsigned long long v = 0;
+        for (int k = 0; k < WORK_SLOTS; ++k) v += h[c * WORK_SLOTS + k];
+        out[c] = (int64_t)v;
+    }
+    if (reset) {
+        HIP_OR(hipMemsetAsync(e.work, 0, sizeof(h), s), "counter clear");
+        HIP_OR(hipStreamSynchronize(s), "counter clear sync");
+    }
+    return PI_OK;
+}
+
+}  // namespace pi

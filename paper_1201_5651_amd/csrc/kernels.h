@@ -1,4 +1,8 @@
 // kernels.h -- launch interface between the C-ABI runtime and the kernels.
+//
+// Every kernel works on a batch of grids described by an array of GridDev in
+// device memory; a single grid is a batch of one, so one grid advanced alone
+// and the same grid advanced inside a batch run the same per-cell arithmetic.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -13,6 +17,9 @@ namespace pi {
 constexpr int SWEEP_T = 8;
 // Threads per workgroup of the micro-physics kernel.
 constexpr int CHEM_BLOCK = 256;
+// Threads per workgroup and largest number of workgroups per grid of the
+// timestep/diagnostics reduction.
+constexpr int DT_BLOCK = 256, DT_MAX_BLOCKS = 1024;
 // Per-block partials of the timestep/diagnostics reduction:
 // [0] min dt limit, [1] sum n(1-x), [2] sum (1-x), [3] sum A, [4] sum recomb, [5] non-finite cells
 constexpr int NPART = 6;
@@ -24,35 +31,66 @@ struct DevState {
     double t_end;
     double last_dt;
     long long nsteps;
-    unsigned int fix_n;   // mixed precision: cells listed for the double re-solve
-    unsigned int pad;
+    long long pad;
     double diag[8];   // see pi_diagnostics
 };
 
 // Micro-integration work counters (accepted, rejected substeps, fallback
-// solves, Newton iterations), each spread over WORK_SLOTS slots so that the
-// per-workgroup atomic additions do not all meet on one address; a reader sums
-// the slots.  Layout: counter c, slot s at [c * WORK_SLOTS + s].
+// solves, Newton iterations, cells re-solved in double), each spread over
+// WORK_SLOTS slots so that the per-workgroup atomic additions do not all meet
+// on one address; a reader sums the slots.  Layout: counter c, slot s at
+// [c * WORK_SLOTS + s].
 constexpr int WORK_COUNTERS = 5, WORK_SLOTS = 64;
 
+// Device view of one grid.  Field arrays are indexed by the buffer selectors
+// of include/pi.h (0: state n, 1: half-step state).
+template <typename R> struct GridDev {
+    Params<R> p;          // parameters in the grid's arithmetic
+    Params<double> pd;    // double parameters (mixed-precision re-solve)
+    const R* nH;
+    R* x[2];
+    R* E[2];              // null when the temperature is fixed
+    R* tau[2];
+    DevState* st;
+    double* part;         // timestep partials of the grid's blocks
+    double cell_vol;
+    int noct;
+};
+
+// Launch geometry of a batch: grid g owns the workgroups [first[g], first[g+1])
+// of a launch over all grids.
+struct BatchDev {
+    int ngrids;
+    const int* chem_first;   // micro-physics workgroups (CHEM_BLOCK cells each)
+    const int* dt_first;     // timestep workgroups
+    unsigned int* fix_n;     // mixed precision: length of fix_list
+    long long* fix_list;     // mixed precision: (grid << 32) | cell, for the double re-solve
+};
+
+// One tile-diagonal stage of the raytrace of every grid: tiles[first ..
+// first + count) are (grid << 3 | octant, tx, ty, tz).
 template <typename R>
-hipError_t launch_sweep_stage(const Params<R>& p, const R* nH, const R* x, R* tau,
-                              const int4* tiles, int first, int count, hipStream_t s);
+hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,
+                              int first, int count, hipStream_t s);
+// Micro-physics of every cell of every grid from state `from` on columns
+// `tau_buf` into state `to`, over h = hscale * (st->dt if dev_dt else 1).
+// With mixed, precision-sensitive cells are listed for launch_chem_fix.
 template <typename R>
-hipError_t launch_chem(const Params<R>& p, const R* nH, const R* x0, const R* E0, const R* tau,
-                       R* x1, R* E1, DevState* st, bool dev_dt, double hscale,
-                       unsigned long long* ctr, int* fix_list, hipStream_t s);
-// Mixed precision: double re-solve of the float cells listed by launch_chem
-// (fix_list, count in st->fix_n), from the unmodified float inputs.
-hipError_t launch_chem_fix(const Params<double>& p, const float* nH, const float* x0,
-                           const float* E0, const float* tau, float* x1, float* E1,
-                           DevState* st, bool dev_dt, double hscale, unsigned long long* ctr,
-                           const int* fix_list, int nblk, hipStream_t s);
+hipError_t launch_chem(const GridDev<R>* grids, const BatchDev& b, int nblocks, int from, int to,
+                       int tau_buf, bool dev_dt, double hscale, unsigned long long* ctr,
+                       bool mixed, hipStream_t s);
+// Mixed precision: double re-solve of the cells listed by launch_chem, from the
+// unmodified float inputs.
+hipError_t launch_chem_fix(const GridDev<float>* grids, const BatchDev& b, int nblk, int from,
+                           int to, int tau_buf, bool dev_dt, double hscale,
+                           unsigned long long* ctr, hipStream_t s);
+// Timestep limit (eq. 4) and diagnostics of state n of every grid, reduced per
+// grid; t_end_arg finite: the t_end of every grid, else each grid's st->t_end.
 template <typename R>
-hipError_t launch_dtdiag(const Params<R>& p, const R* nH, const R* x, const R* E, const R* tau,
-                         double* part, int nblk, DevState* st, double t_end, double cell_vol,
-                         int noct, hipStream_t s);
-hipError_t launch_advance(DevState* st, hipStream_t s);
+hipError_t launch_dtdiag(const GridDev<R>* grids, const BatchDev& b, int nblocks, double t_end_arg,
+                         hipStream_t s);
+template <typename R>
+hipError_t launch_advance(const GridDev<R>* grids, int ngrids, hipStream_t s);
 template <typename R>
 hipError_t launch_energy(int64_t n, const R* nH, const R* x, R* E, double T0, hipStream_t s);
 

@@ -47,9 +47,9 @@ __device__ __forceinline__ double sc_average<double>(bool mellema, double g00, d
     return (w00 * T00 + w10 * T10 + w01 * T01 + w11 * T11) / (w00 + w10 + w01 + w11);
 }
 
-// One tile-diagonal stage of the octant sweeps.  Each workgroup owns one
-// TX*TY*TZ tile of one octant (one thread per cell) and needs only the tiles
-// of earlier stages, so a stage is one launch.  The tile's cells and its
+// One tile-diagonal stage of the octant sweeps of every grid of a batch.  Each
+// workgroup owns one TX*TY*TZ tile of one octant of one grid (one thread per
+// cell) and needs only the tiles of earlier stages, so a stage is one launch.  The tile's cells and its
 // upstream halo (octant-local index -1 on any axis) are staged in LDS as
 //   s_kap: sigma0 n_H x dx (optical depth per cell length),
 //   s_tc : optical depth from the source to the cell centre (halo only, from
@@ -64,7 +64,7 @@ __device__ __forceinline__ double sc_average<double>(bool mellema, double g00, d
 // across a source plane (octant-local index -1) get weight 0.
 template <typename R>
 __global__ void __launch_bounds__(SWEEP_T * SWEEP_T * SWEEP_T)
-k_sweep(Params<R> p, const R* __restrict__ nH, const R* __restrict__ xs, R* __restrict__ tau,
+k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
         const int4* __restrict__ tiles, int first)
 {
     constexpr int TX = SWEEP_T, TY = SWEEP_T, TZ = SWEEP_T;
@@ -73,7 +73,12 @@ k_sweep(Params<R> p, const R* __restrict__ nH, const R* __restrict__ xs, R* __re
     __shared__ R s_kap[NHALO];
 
     const int4 tl = tiles[first + blockIdx.x];
-    const int oct = tl.x;
+    const GridDev<R>& G = grids[tl.x >> 3];
+    const Params<R> p = G.p;
+    const R* __restrict__ nH = G.nH;
+    const R* __restrict__ xs = G.x[state];
+    R* __restrict__ tau = G.tau[tau_buf];
+    const int oct = tl.x & 7;
     const bool px = oct & 1, py = oct & 2, pz = oct & 4;
     const int ex = px ? p.nx - p.sx : p.sx;
     const int ey = py ? p.ny - p.sy : p.sy;
@@ -150,6 +155,18 @@ k_sweep(Params<R> p, const R* __restrict__ nH, const R* __restrict__ xs, R* __re
 }
 
 // ---------------------------------------------------------------- chemistry
+// Grid of workgroup b of a launch over a batch (first[g] <= b < first[g+1]).
+__device__ __forceinline__ int find_grid(const int* __restrict__ first, int ngrids, int b)
+{
+    int lo = 0, hi = ngrids - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Work counters: summed over the workgroup (wavefront shuffles, then LDS) and
 // added with one atomic per counter per workgroup, into the slot of the
 // workgroup.
@@ -210,66 +227,70 @@ __device__ __forceinline__ void chem_cell(const Params<C>& p, int q, const S* __
     micro(p, e, C(hd), x, E, w);
 }
 
-// Micro-physics of every cell.  With fix_list (mixed precision), a cell whose
-// substep control took a decision near its threshold is not written; it is
-// appended to fix_list (count in st->fix_n) for the double re-solve.
+// Micro-physics of every cell of every grid.  With mixed precision, a cell
+// whose float integration took a precision-sensitive decision is not written;
+// it is appended to the batch's re-solve list for the double pass.
 template <typename R>
 __global__ void __launch_bounds__(CHEM_BLOCK) __attribute__((amdgpu_waves_per_eu(ChemWaves<R>::value)))
-k_chem(Params<R> p, const R* __restrict__ nH, const R* x0, const R* E0, const R* __restrict__ tau,
-       R* x1, R* E1, DevState* st, int dev_dt, double hscale, unsigned long long* ctr,
-       int* fix_list)
+k_chem(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int tau_buf,
+       int dev_dt, double hscale, unsigned long long* ctr, int mixed)
 {
     __shared__ DevTable<R> s_tab;
-    const Params<R> pl = table_to_lds(p, s_tab);
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = find_grid(bd.chem_first, bd.ngrids, blockIdx.x);
+    const GridDev<R>& G = grids[g];
+    const Params<R> pl = table_to_lds(G.p, s_tab);
+    const int q = (blockIdx.x - bd.chem_first[g]) * CHEM_BLOCK + threadIdx.x;
     Work w{};
     bool flag = false;
-    if (q < p.ncell) {
-        const double hd = dev_dt ? hscale * st->dt : hscale;
+    if (q < pl.ncell) {
+        const double hd = dev_dt ? hscale * G.st->dt : hscale;
         R x, E;
-        chem_cell<R, R>(pl, q, nH, x0, E0, tau, hd, x, E, w);
-        flag = fix_list && w.close > 0;
+        chem_cell<R, R>(pl, q, G.nH, G.x[from], G.E[from], G.tau[tau_buf], hd, x, E, w);
+        flag = mixed && w.close > 0;
         if (!flag) {
-            x1[q] = x;
-            if (E1) E1[q] = E;
+            G.x[to][q] = x;
+            if (G.E[to]) G.E[to][q] = E;
         }
     }
-    if (fix_list) {
+    if (mixed) {
         // one atomic per wavefront for the flagged cells of the wavefront
         const unsigned long long m = __ballot(flag);
         if (m) {
             const int lane = threadIdx.x & 63;
-            const int first = __ffsll((long long)m) - 1;
+            const int lead = __ffsll((long long)m) - 1;
             unsigned base = 0;
-            if (lane == first) base = atomicAdd(&st->fix_n, (unsigned)__popcll(m));
-            base = __shfl(base, first, 64);
-            if (flag) fix_list[base + __popcll(m & ((1ull << lane) - 1ull))] = q;
+            if (lane == lead) base = atomicAdd(bd.fix_n, (unsigned)__popcll(m));
+            base = __shfl(base, lead, 64);
+            if (flag)
+                bd.fix_list[base + __popcll(m & ((1ull << lane) - 1ull))] =
+                    ((long long)g << 32) | (long long)q;
         }
     }
     add_work(ctr, w);
 }
 
-__global__ void k_fix_reset(DevState* st)
+__global__ void k_fix_reset(unsigned int* fix_n)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) st->fix_n = 0u;
+    if (threadIdx.x == 0 && blockIdx.x == 0) *fix_n = 0u;
 }
 
+// Double re-solve of the listed cells (mixed precision): each entry names its
+// grid, so the rate table is read from global memory here.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ChemWaves<double>::value)))
-k_chem_fix(Params<double> p, const float* __restrict__ nH, const float* x0, const float* E0,
-           const float* __restrict__ tau, float* x1, float* E1, DevState* st, int dev_dt,
-           double hscale, unsigned long long* ctr, const int* __restrict__ fix_list)
+k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int to, int tau_buf,
+           int dev_dt, double hscale, unsigned long long* ctr)
 {
-    __shared__ DevTable<double> s_tab;
-    const Params<double> pl = table_to_lds(p, s_tab);
-    const unsigned n = st->fix_n;
-    const double hd = dev_dt ? hscale * st->dt : hscale;
+    const unsigned n = *bd.fix_n;
     Work w{};
     for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int q = fix_list[i];
+        const long long e = bd.fix_list[i];
+        const GridDev<float>& G = grids[(int)(e >> 32)];
+        const int q = (int)(e & 0xffffffffll);
+        const double hd = dev_dt ? hscale * G.st->dt : hscale;
         double x, E;
-        chem_cell<double, float>(pl, q, nH, x0, E0, tau, hd, x, E, w);
-        x1[q] = (float)x;
-        if (E1) E1[q] = (float)E;
+        chem_cell<double, float>(G.pd, q, G.nH, G.x[from], G.E[from], G.tau[tau_buf], hd, x, E, w);
+        G.x[to][q] = (float)x;
+        if (G.E[to]) G.E[to][q] = (float)E;
         ++w.fixed;
     }
     add_work(ctr, w);
@@ -287,13 +308,22 @@ template <typename T> __device__ __forceinline__ T wave_min(T v)
     return v;
 }
 
+// Per-workgroup partials of the timestep limit and diagnostics of state n; the
+// workgroups of grid g stride over its cells.
 template <typename R>
-__global__ void __launch_bounds__(256)
-k_dtdiag(Params<R> p, const R* __restrict__ nH, const R* __restrict__ x, const R* __restrict__ E,
-         const R* __restrict__ tau, double* __restrict__ part)
+__global__ void __launch_bounds__(DT_BLOCK)
+k_dtdiag(const GridDev<R>* __restrict__ grids, BatchDev bd)
 {
+    const int g = find_grid(bd.dt_first, bd.ngrids, blockIdx.x);
+    const GridDev<R>& G = grids[g];
+    const Params<R> p = G.p;
+    const int lb = blockIdx.x - bd.dt_first[g], nb = bd.dt_first[g + 1] - bd.dt_first[g];
+    const R* __restrict__ nH = G.nH;
+    const R* __restrict__ x = G.x[0];
+    const R* __restrict__ E = G.E[0];
+    const R* __restrict__ tau = G.tau[0];
     double v[NPART] = { __builtin_huge_val(), 0.0, 0.0, 0.0, 0.0, 0.0 };
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < p.ncell; q += gridDim.x * blockDim.x) {
+    for (int q = lb * DT_BLOCK + threadIdx.x; q < p.ncell; q += nb * DT_BLOCK) {
         const int i = q % p.nx, j = (q / p.nx) % p.ny, k = q / (p.nx * p.ny);
         const CellGeom<R> cg = cell_geom(p, i, j, k);
         const R n = nH[q], xq = x[q], tq = tau[q];
@@ -310,7 +340,7 @@ k_dtdiag(Params<R> p, const R* __restrict__ nH, const R* __restrict__ x, const R
                          (E && !isfinite((double)Eq));
         v[5] += bad ? 1.0 : 0.0;
     }
-    __shared__ double sm[NPART][4];
+    __shared__ double sm[NPART][DT_BLOCK / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     v[0] = wave_min(v[0]);
     for (int m = 1; m < NPART; ++m) v[m] = wave_sum(v[m]);
@@ -321,17 +351,21 @@ k_dtdiag(Params<R> p, const R* __restrict__ nH, const R* __restrict__ x, const R
         double o[NPART];
         o[0] = fmin(fmin(sm[0][0], sm[0][1]), fmin(sm[0][2], sm[0][3]));
         for (int m = 1; m < NPART; ++m) o[m] = ((sm[m][0] + sm[m][1]) + sm[m][2]) + sm[m][3];
-        for (int m = 0; m < NPART; ++m) part[blockIdx.x * NPART + m] = o[m];
+        for (int m = 0; m < NPART; ++m) G.part[lb * NPART + m] = o[m];
     }
 }
 
-// Fixed-order reduction of the per-block partials (deterministic for a given
-// grid), then dt = min(limit, t_end - t) with a remainder below 1e-12 t_end
-// absorbed into the step.
+// One workgroup per grid: fixed-order reduction of the grid's partials
+// (deterministic for a given grid), then dt = min(limit, t_end - t) with a
+// remainder below 1e-12 t_end absorbed into the step.
+template <typename R>
 __global__ void __launch_bounds__(256)
-k_finalize(const double* __restrict__ part, int nblk, DevState* st, double t_end, double cell_vol,
-           int noct)
+k_finalize(const GridDev<R>* __restrict__ grids, BatchDev bd, double t_end_arg)
 {
+    const GridDev<R>& G = grids[blockIdx.x];
+    const int nblk = bd.dt_first[blockIdx.x + 1] - bd.dt_first[blockIdx.x];
+    const double* __restrict__ part = G.part;
+    DevState* st = G.st;
     __shared__ double sm[NPART][256];
     double v[NPART] = { __builtin_huge_val(), 0.0, 0.0, 0.0, 0.0, 0.0 };
     for (int b = threadIdx.x; b < nblk; b += 256) {
@@ -348,6 +382,7 @@ k_finalize(const double* __restrict__ part, int nblk, DevState* st, double t_end
         __syncthreads();
     }
     if (threadIdx.x == 0) {
+        const double t_end = isfinite(t_end_arg) ? t_end_arg : st->t_end;
         double dt = sm[0][0];
         const double rem = t_end - st->t;
         if (!(rem > 0.0)) {
@@ -356,22 +391,26 @@ k_finalize(const double* __restrict__ part, int nblk, DevState* st, double t_end
             if (dt > rem) dt = rem;
             if (rem - dt <= 1e-12 * t_end) dt = rem;
         }
+        const double cv = G.cell_vol;
         st->dt = dt;
         st->t_end = t_end;
-        st->diag[0] = sm[1][0] * cell_vol;
-        st->diag[1] = sm[2][0] * cell_vol;
-        st->diag[2] = cbrt(3.0 * sm[2][0] * cell_vol * 8.0 / (4.0 * 3.14159265358979323846 * noct));
-        st->diag[3] = sm[3][0] * cell_vol;
-        st->diag[4] = sm[4][0] * cell_vol;
+        st->diag[0] = sm[1][0] * cv;
+        st->diag[1] = sm[2][0] * cv;
+        st->diag[2] = cbrt(3.0 * sm[2][0] * cv * 8.0 / (4.0 * 3.14159265358979323846 * G.noct));
+        st->diag[3] = sm[3][0] * cv;
+        st->diag[4] = sm[4][0] * cv;
         st->diag[5] = sm[5][0];
-        st->diag[6] = noct;
+        st->diag[6] = G.noct;
         st->diag[7] = st->t;
     }
 }
 
-__global__ void k_advance(DevState* st)
+template <typename R>
+__global__ void k_advance(const GridDev<R>* __restrict__ grids, int ngrids)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < ngrids) {
+        DevState* st = grids[g].st;
         const double dt = st->dt;
         if (dt > 0.0) {
             st->t = (st->t_end - st->t - dt <= 0.0) ? st->t_end : st->t + dt;
@@ -391,50 +430,52 @@ k_energy(int64_t n, const R* __restrict__ nH, const R* __restrict__ x, R* __rest
 
 // ---------------------------------------------------------------- launchers
 template <typename R>
-hipError_t launch_sweep_stage(const Params<R>& p, const R* nH, const R* x, R* tau,
-                              const int4* tiles, int first, int count, hipStream_t s)
+hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,
+                              int first, int count, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_sweep<R>), dim3(count), dim3(SWEEP_T * SWEEP_T * SWEEP_T), 0, s, p, nH, x,
-                       tau, tiles, first);
+    hipLaunchKernelGGL((k_sweep<R>), dim3(count), dim3(SWEEP_T * SWEEP_T * SWEEP_T), 0, s, grids,
+                       state, tau_buf, tiles, first);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_chem(const Params<R>& p, const R* nH, const R* x0, const R* E0, const R* tau,
-                       R* x1, R* E1, DevState* st, bool dev_dt, double hscale,
-                       unsigned long long* ctr, int* fix_list, hipStream_t s)
+hipError_t launch_chem(const GridDev<R>* grids, const BatchDev& b, int nblocks, int from, int to,
+                       int tau_buf, bool dev_dt, double hscale, unsigned long long* ctr,
+                       bool mixed, hipStream_t s)
 {
-    if (fix_list) hipLaunchKernelGGL(k_fix_reset, dim3(1), dim3(64), 0, s, st);
-    const int nb = (int)((p.ncell + CHEM_BLOCK - 1) / CHEM_BLOCK);
-    hipLaunchKernelGGL((k_chem<R>), dim3(nb), dim3(CHEM_BLOCK), 0, s, p, nH, x0, E0, tau, x1, E1,
-                       st, (int)dev_dt, hscale, ctr, fix_list);
+    if (nblocks <= 0) return hipSuccess;
+    if (mixed) hipLaunchKernelGGL(k_fix_reset, dim3(1), dim3(64), 0, s, b.fix_n);
+    hipLaunchKernelGGL((k_chem<R>), dim3(nblocks), dim3(CHEM_BLOCK), 0, s, grids, b, from, to,
+                       tau_buf, (int)dev_dt, hscale, ctr, (int)mixed);
     return hipGetLastError();
 }
 
-hipError_t launch_chem_fix(const Params<double>& p, const float* nH, const float* x0,
-                           const float* E0, const float* tau, float* x1, float* E1,
-                           DevState* st, bool dev_dt, double hscale, unsigned long long* ctr,
-                           const int* fix_list, int nblk, hipStream_t s)
+hipError_t launch_chem_fix(const GridDev<float>* grids, const BatchDev& b, int nblk, int from,
+                           int to, int tau_buf, bool dev_dt, double hscale,
+                           unsigned long long* ctr, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_chem_fix, dim3(nblk), dim3(256), 0, s, p, nH, x0, E0, tau, x1, E1, st,
-                       (int)dev_dt, hscale, ctr, fix_list);
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chem_fix, dim3(nblk), dim3(256), 0, s, grids, b, from, to, tau_buf,
+                       (int)dev_dt, hscale, ctr);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_dtdiag(const Params<R>& p, const R* nH, const R* x, const R* E, const R* tau,
-                         double* part, int nblk, DevState* st, double t_end, double cell_vol,
-                         int noct, hipStream_t s)
+hipError_t launch_dtdiag(const GridDev<R>* grids, const BatchDev& b, int nblocks, double t_end_arg,
+                         hipStream_t s)
 {
-    hipLaunchKernelGGL((k_dtdiag<R>), dim3(nblk), dim3(256), 0, s, p, nH, x, E, tau, part);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, part, nblk, st, t_end, cell_vol, noct);
+    if (nblocks <= 0 || b.ngrids <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_dtdiag<R>), dim3(nblocks), dim3(DT_BLOCK), 0, s, grids, b);
+    hipLaunchKernelGGL((k_finalize<R>), dim3(b.ngrids), dim3(256), 0, s, grids, b, t_end_arg);
     return hipGetLastError();
 }
 
-hipError_t launch_advance(DevState* st, hipStream_t s)
+template <typename R>
+hipError_t launch_advance(const GridDev<R>* grids, int ngrids, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, st);
+    if (ngrids <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_advance<R>), dim3((ngrids + 63) / 64), dim3(64), 0, s, grids, ngrids);
     return hipGetLastError();
 }
 
@@ -447,14 +488,13 @@ hipError_t launch_energy(int64_t n, const R* nH, const R* x, R* E, double T0, hi
 }
 
 #define PI_INSTANTIATE(R)                                                                          \
-    template hipError_t launch_sweep_stage<R>(const Params<R>&, const R*, const R*, R*,           \
-                                              const int4*, int, int, hipStream_t);                 \
-    template hipError_t launch_chem<R>(const Params<R>&, const R*, const R*, const R*, const R*,  \
-                                       R*, R*, DevState*, bool, double, unsigned long long*, int*, \
-                                       hipStream_t);                                               \
-    template hipError_t launch_dtdiag<R>(const Params<R>&, const R*, const R*, const R*,          \
-                                         const R*, double*, int, DevState*, double, double, int,   \
+    template hipError_t launch_sweep_stage<R>(const GridDev<R>*, int, int, const int4*, int, int,  \
+                                              hipStream_t);                                        \
+    template hipError_t launch_chem<R>(const GridDev<R>*, const BatchDev&, int, int, int, int,    \
+                                       bool, double, unsigned long long*, bool, hipStream_t);      \
+    template hipError_t launch_dtdiag<R>(const GridDev<R>*, const BatchDev&, int, double,         \
                                          hipStream_t);                                             \
+    template hipError_t launch_advance<R>(const GridDev<R>*, int, hipStream_t);                   \
     template hipError_t launch_energy<R>(int64_t, const R*, const R*, R*, double, hipStream_t);
 PI_INSTANTIATE(double)
 PI_INSTANTIATE(float)
