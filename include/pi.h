@@ -38,10 +38,13 @@ extern "C" {
 
 typedef enum {
     PI_OK = 0,
+    PI_PENDING = 1,      /* served request queued or running                  */
     PI_EINVAL = -1,      /* invalid argument or descriptor                    */
     PI_ENOMEM = -2,      /* device allocation failed                          */
     PI_EDEVICE = -3,     /* HIP runtime error                                 */
-    PI_ENAN = -5         /* a non-finite value was found in the grid's state  */
+    PI_EREJECTED = -4,   /* served request larger than the server's budget    */
+    PI_ENAN = -5,        /* a non-finite value was found in the grid's state  */
+    PI_ECANCELLED = -6   /* served request cancelled                          */
 } pi_status;
 
 /* PI_MIXED: float fields and float bulk arithmetic.  A cell is re-solved in
@@ -214,6 +217,62 @@ pi_status pi_batch_diagnostics(pi_batch* batch, double* out, void* stream);
 /* pi_work_counters summed over the grids of the batch.  SYNCHRONISES. */
 pi_status pi_batch_work_counters(pi_batch* batch, int64_t* out, int reset, void* stream);
 
+/* -------------------------------------------------------------- serving
+ * A server owns a worker thread, a HIP stream and one device allocation of
+ * hbm_budget bytes (an arena for the fields of the requests it holds).
+ * Submitted requests are admitted in arrival order while fewer than max_active
+ * grids are running and their fields fit in the arena; all admitted grids are
+ * advanced together as one batch (steps_per_tick algorithm-3 steps between
+ * admission checks) until each reaches its t_end, then their results are
+ * copied to host memory and their arena space is reused.  Calls that overlap
+ * on one server are safe (a mutex guards its queues). */
+typedef struct pi_server pi_server;
+
+typedef struct {
+    size_t  hbm_budget;       /* arena bytes; 0: 80% of the free device memory    */
+    int32_t max_active;       /* grids advanced together at most, >= 1           */
+    int32_t precision;        /* pi_precision of every request                   */
+    int32_t steps_per_tick;   /* batch steps between admission checks, >= 1      */
+} pi_server_desc;
+
+typedef struct {
+    pi_grid_desc  desc;       /* precision must be the server's                  */
+    const double* nH;         /* host, n[0]*n[1]*n[2] cells, > 0 (copied)         */
+    const double* x0;         /* host initial neutral fraction, or NULL: 1       */
+    double        T0;         /* initial temperature [K] (T evolving)            */
+    double        t_end;      /* time to advance to from t = 0 [s]               */
+} pi_request;
+
+typedef struct {
+    int32_t status;           /* PI_OK, PI_PENDING or the failure status         */
+    double  t;                /* time reached                                    */
+    int64_t nsteps;           /* steps taken                                     */
+    double  latency_s;        /* submission to completion (or to now)            */
+    double  queue_s;          /* submission to admission (or to now)             */
+} pi_result;
+
+/* Starts the worker thread on the current device.  PI_ENOMEM if the arena
+ * cannot be allocated. */
+pi_status pi_server_create(const pi_server_desc* desc, pi_server** out);
+/* Validates and copies the request (host arrays); returns a ticket.
+ * PI_EREJECTED if its fields can never fit in the arena. */
+pi_status pi_submit(pi_server* server, const pi_request* request, uint64_t* ticket);
+/* Status of a ticket.  PI_PENDING while queued or running; once finished,
+ * returns PI_OK and copies the final neutral fraction and temperature into
+ * x_out and T_out (host arrays of the grid's cells, either may be NULL), or
+ * returns the failure status; the ticket is released in both cases. */
+pi_status pi_poll(pi_server* server, uint64_t ticket, pi_result* out, double* x_out,
+                  double* T_out);
+/* Asks for a ticket to be dropped (queued: at once; running: at the next tick).
+ * Its poll then returns PI_ECANCELLED. */
+pi_status pi_cancel(pi_server* server, uint64_t ticket);
+/* out[8]: completed requests, cell-updates done, busy seconds of the worker,
+ * batch steps, running grids, queued requests, arena bytes in use, batch
+ * rebuilds. */
+pi_status pi_server_stats(pi_server* server, double* out);
+/* Stops the worker (running requests are dropped) and frees everything. */
+pi_status pi_server_destroy(pi_server* server);
+
 /* Host-only: blackbody rate table of the TABLE spectrum (Sect. 2, rates
  * tabulated against optical depth): out[5*PI_NTAB] = node optical depths, P
  * (photons/s surviving a threshold column tau), -dP/dtau, H (excess energy
@@ -226,7 +285,7 @@ const char* pi_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns the
  * value it was built with. */
-#define PI_ABI_VERSION 102
+#define PI_ABI_VERSION 103
 int pi_abi_version(void);
 
 #ifdef __cplusplus

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpi.so")
-SOURCES = ["kernels.hip", "engine.hip", "runtime.hip"]
+SOURCES = ["kernels.hip", "engine.hip", "runtime.hip", "server.hip"]
 HEADERS = ["physics.h", "kernels.h", "engine.h"]
 
 HIPCC_FLAGS = [

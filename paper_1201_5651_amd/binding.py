@@ -15,7 +15,8 @@ from typing import Optional
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpi.so")
 
-PI_OK, PI_EINVAL, PI_ENOMEM, PI_EDEVICE, PI_ENAN = 0, -1, -2, -3, -5
+PI_OK, PI_PENDING = 0, 1
+PI_EINVAL, PI_ENOMEM, PI_EDEVICE, PI_EREJECTED, PI_ENAN, PI_ECANCELLED = -1, -2, -3, -4, -5, -6
 PI_FP64, PI_FP32, PI_MIXED = 0, 1, 2
 PI_SPEC_MONO, PI_SPEC_TABLE = 0, 1
 PI_T_FIXED, PI_T_EVOLVE = 0, 1
@@ -34,6 +35,7 @@ ABI_SYMBOLS = (
     "pi_batch_create", "pi_batch_destroy", "pi_batch_set_time", "pi_batch_init_energy",
     "pi_batch_raytrace", "pi_batch_step_o2", "pi_batch_state", "pi_batch_diagnostics",
     "pi_batch_work_counters",
+    "pi_server_create", "pi_submit", "pi_poll", "pi_cancel", "pi_server_stats", "pi_server_destroy",
 )
 
 
@@ -71,6 +73,21 @@ class Fields(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("nH", "x", "E", "tau", "x_half", "E_half", "tau_half")]
 
 
+class ServerDesc(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int32), ("precision", C.c_int32),
+                ("steps_per_tick", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("desc", GridDesc), ("nH", C.POINTER(C.c_double)), ("x0", C.POINTER(C.c_double)),
+                ("T0", C.c_double), ("t_end", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("t", C.c_double), ("nsteps", C.c_int64),
+                ("latency_s", C.c_double), ("queue_s", C.c_double)]
+
+
 _lib = None
 
 
@@ -106,6 +123,12 @@ def lib() -> C.CDLL:
         L.pi_batch_state.argtypes = [vp, dp, i64p, dp, vp]
         L.pi_batch_diagnostics.argtypes = [vp, dp, vp]
         L.pi_batch_work_counters.argtypes = [vp, i64p, i32, vp]
+        L.pi_server_create.argtypes = [C.POINTER(ServerDesc), C.POINTER(vp)]
+        L.pi_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]
+        L.pi_poll.argtypes = [vp, C.c_uint64, C.POINTER(Result), dp, dp]
+        L.pi_cancel.argtypes = [vp, C.c_uint64]
+        L.pi_server_stats.argtypes = [vp, dp]
+        L.pi_server_destroy.argtypes = [vp]
         L.pi_last_error.restype = C.c_char_p
         L.pi_abi_version.restype = C.c_int
         for name in ABI_SYMBOLS:
@@ -376,6 +399,80 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             check(lib().pi_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Served form: a worker thread in the library admits submitted grids into
+    a device-memory arena and advances the running ones together.  Inputs and
+    results are host arrays (copied by the library)."""
+
+    def __init__(self, precision: str = "mixed", hbm_budget: int = 0, max_active: int = 64,
+                 steps_per_tick: int = 4):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the photoionisation library needs a GPU (no CPU fallback)")
+        torch.cuda.init()
+        self.precision = precision
+        d = ServerDesc(hbm_budget, max_active, {"fp64": PI_FP64, "fp32": PI_FP32, "mixed": PI_MIXED}[precision],
+                       steps_per_tick)
+        h = C.c_void_p()
+        check(lib().pi_server_create(C.byref(d), C.byref(h)))
+        self._h = h
+        self._specs = {}
+
+    def submit(self, spec, nH, x0=None, T0: Optional[float] = None, t_end: Optional[float] = None) -> int:
+        import numpy as np
+        nH = np.ascontiguousarray(nH, dtype=np.float64).reshape(-1)
+        x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64).reshape(-1)
+        dp = C.POINTER(C.c_double)
+        r = Request(desc_from_spec(spec, self.precision), nH.ctypes.data_as(dp),
+                    None if x0a is None else x0a.ctypes.data_as(dp),
+                    float(T0 if T0 is not None else spec.T0),
+                    float(t_end if t_end is not None else spec.t_end))
+        t = C.c_uint64()
+        check(lib().pi_submit(self._h, C.byref(r), C.byref(t)))
+        self._specs[t.value] = spec
+        return t.value
+
+    def poll(self, ticket: int):
+        """(status, info, x, T): x and T are arrays of the grid's shape once
+        status is PI_OK, else None."""
+        import numpy as np
+        spec = self._specs[ticket]
+        res = Result()
+        x = np.empty(spec.ncells)
+        T = np.empty(spec.ncells)
+        dp = C.POINTER(C.c_double)
+        st = lib().pi_poll(self._h, ticket, C.byref(res), x.ctypes.data_as(dp), T.ctypes.data_as(dp))
+        info = {"t": res.t, "nsteps": res.nsteps, "latency_s": res.latency_s, "queue_s": res.queue_s}
+        if st == PI_PENDING:
+            return st, info, None, None
+        del self._specs[ticket]
+        if st != PI_OK:
+            info["error"] = lib().pi_last_error().decode()
+            return st, info, None, None
+        return st, info, x.reshape(spec.shape), T.reshape(spec.shape)
+
+    def cancel(self, ticket: int):
+        check(lib().pi_cancel(self._h, ticket))
+
+    def stats(self):
+        out = (C.c_double * 8)()
+        check(lib().pi_server_stats(self._h, out))
+        keys = ("completed", "cell_updates", "busy_s", "steps", "running", "queued", "arena_bytes",
+                "rebuilds")
+        return dict(zip(keys, list(out)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(lib().pi_server_destroy(self._h))
             self._h = None
 
     def __del__(self):

@@ -63,6 +63,9 @@ struct Engine {
         void* f;   // DevTable<float>
     };
     std::vector<Table> tables;
+    // When set, tables are looked up in and added to this cache instead, which
+    // outlives the engine (engine_free then leaves them alone).
+    std::vector<Table>* table_cache = nullptr;
     hipStream_t cap = nullptr;       // capture stream of the step graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -77,6 +80,7 @@ struct Engine {
 // keeps allocations whose capacity suffices and drops a captured step graph.
 pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids);
 void engine_free(Engine& e);
+void free_tables(std::vector<Engine::Table>& tables);
 
 pi_status engine_raytrace(Engine& e, int state, int tau_buf, hipStream_t s);
 pi_status engine_chem(Engine& e, bool dev_dt, double h, int tau_buf, int from, int to,

@@ -100,7 +100,8 @@ pi_status table_for(Engine& e, const pi_grid_desc& d, void** td, void** tf)
 {
     *td = *tf = nullptr;
     if (d.spectrum != PI_SPEC_TABLE) return PI_OK;
-    for (const Engine::Table& t : e.tables)
+    std::vector<Engine::Table>& tables = e.table_cache ? *e.table_cache : e.tables;
+    for (const Engine::Table& t : tables)
         if (t.spectrum == d.spectrum && t.T_bb == d.T_bb) {
             *td = t.d;
             *tf = t.f;
@@ -119,7 +120,7 @@ pi_status table_for(Engine& e, const pi_grid_desc& d, void** td, void** tf)
         (void)hipFree(t.d);
         return fail(PI_ENOMEM, "table allocation");
     }
-    e.tables.push_back(t);
+    tables.push_back(t);
     HIP_OR(hipMemcpy(t.d, &Td, sizeof(Td), hipMemcpyHostToDevice), "table upload");
     HIP_OR(hipMemcpy(t.f, &Tf, sizeof(Tf), hipMemcpyHostToDevice), "table upload");
     *td = t.d;
@@ -368,11 +369,7 @@ void engine_free(Engine& e)
     for (void* p : { e.gdev, (void*)e.first, (void*)e.tiles, (void*)e.fix_n, (void*)e.fix_list,
                      (void*)e.work })
         if (p) (void)hipFree(p);
-    for (const Engine::Table& t : e.tables) {
-        if (t.d) (void)hipFree(t.d);
-        if (t.f) (void)hipFree(t.f);
-    }
-    e.tables.clear();
+    free_tables(e.tables);
     e.gdev = nullptr;
     e.first = nullptr;
     e.tiles = nullptr;
@@ -380,6 +377,15 @@ void engine_free(Engine& e)
     e.fix_list = nullptr;
     e.work = nullptr;
     e.gdev_cap = e.first_cap = e.tiles_cap = e.fix_cap = 0;
+}
+
+void free_tables(std::vector<Engine::Table>& tables)
+{
+    for (const Engine::Table& t : tables) {
+        if (t.d) (void)hipFree(t.d);
+        if (t.f) (void)hipFree(t.f);
+    }
+    tables.clear();
 }
 
 pi_status engine_raytrace(Engine& e, int state, int tau_buf, hipStream_t s)

@@ -1,0 +1,484 @@
+// server.hip -- served form of the library: a worker thread that admits
+// requests (one grid each) into a device-memory arena as room frees up and
+// advances every admitted grid together with the batch engine, one A3 step of
+// all of them per graph replay, until each reaches its own t_end.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/pi.h"
+#include "engine.h"
+
+using namespace pi;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double seconds(Clock::time_point a, Clock::time_point b)
+{
+    return std::chrono::duration<double>(b - a).count();
+}
+
+// First-fit allocator over one device allocation (offsets in bytes, 256-byte
+// granules).  Host bookkeeping only; the device block is allocated once.
+struct Arena {
+    char* base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free_;   // offset -> length
+    size_t used = 0;
+
+    static size_t round(size_t n) { return (n + 255) & ~size_t(255); }
+    bool init(size_t bytes)
+    {
+        size = bytes & ~size_t(255);
+        if (size == 0 || hipMalloc(reinterpret_cast<void**>(&base), size) != hipSuccess) return false;
+        free_[0] = size;
+        return true;
+    }
+    void release()
+    {
+        if (base) (void)hipFree(base);
+        base = nullptr;
+    }
+    void* alloc(size_t n)
+    {
+        n = round(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            const size_t off = it->first, len = it->second;
+            free_.erase(it);
+            if (len > n) free_[off + n] = len - n;
+            used += n;
+            return base + off;
+        }
+        return nullptr;
+    }
+    void free(void* p, size_t n)
+    {
+        n = round(n);
+        size_t off = static_cast<char*>(p) - base;
+        used -= n;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + n == next->first) {
+            n += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += n;
+                return;
+            }
+        }
+        free_[off] = n;
+    }
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    pi_grid_desc d{};
+    std::vector<double> nH, x0;
+    double T0 = 0, t_end = 0;
+    int status = PI_PENDING;
+    std::string error;
+    Clock::time_point submitted, admitted, completed;
+    // while active
+    GridHost grid;
+    void* block = nullptr;
+    size_t bytes = 0;
+    bool active = false;
+    bool was_admitted = false;
+    bool cancel = false;
+    // results
+    std::vector<double> x_out, T_out;
+    double t = 0;
+    int64_t nsteps = 0;
+};
+
+size_t word_bytes(int precision) { return precision == PI_FP64 ? 8 : 4; }
+
+int nfields(const pi_grid_desc& d) { return d.thermal == PI_T_EVOLVE ? 7 : 5; }
+
+size_t footprint(const pi_grid_desc& d)
+{
+    const size_t n = (size_t)d.n[0] * d.n[1] * d.n[2];
+    return (size_t)nfields(d) * Arena::round(n * word_bytes(d.precision));
+}
+
+}  // namespace
+
+struct pi_server {
+    pi_server_desc desc{};
+    int device = 0;
+    Arena arena;
+    hipStream_t stream = nullptr;
+    Engine engine;
+    std::vector<Engine::Table> tables;   // rate tables shared by every engine of the server
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<std::shared_ptr<Request>> queue;               // submitted, not admitted
+    std::map<uint64_t, std::shared_ptr<Request>> requests;    // every live ticket
+    std::vector<std::shared_ptr<Request>> active;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread worker;
+    // statistics
+    double cell_updates = 0, busy_s = 0;
+    uint64_t done = 0, steps = 0, rebuilds = 0;
+    std::string worker_error;
+
+    void run();
+    bool admit_locked(std::shared_ptr<Request>& r);
+    pi_status start(Request& r);
+    void retire(Request& r, bool ok, const std::string& why);
+};
+
+// Places a request's fields in the arena (mutex held); false if it does not fit now.
+bool pi_server::admit_locked(std::shared_ptr<Request>& r)
+{
+    r->bytes = footprint(r->d);
+    r->block = arena.alloc(r->bytes);
+    return r->block != nullptr;
+}
+
+// Uploads the request's state and prepares its grid (worker thread, no lock).
+pi_status pi_server::start(Request& r)
+{
+    const pi_grid_desc& d = r.d;
+    const size_t n = (size_t)d.n[0] * d.n[1] * d.n[2];
+    const size_t fb = Arena::round(n * word_bytes(d.precision));
+    char* p = static_cast<char*>(r.block);
+    pi_fields f{};
+    void** slots[7] = { &f.nH, &f.x, &f.tau, &f.x_half, &f.tau_half, &f.E, &f.E_half };
+    for (int k = 0; k < nfields(d); ++k) *slots[k] = p + k * fb;
+    pi_status s = grid_host_init(r.grid, d, f);
+    if (s != PI_OK) return s;
+    // initial state, converted to the field precision on the host
+    std::vector<double> x(n, 1.0);
+    if (!r.x0.empty()) x = r.x0;
+    if (d.precision == PI_FP64) {
+        if (hipMemcpyAsync(f.nH, r.nH.data(), n * 8, hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(f.x, x.data(), n * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
+            return fail(PI_EDEVICE, "request upload");
+        if (hipStreamSynchronize(stream) != hipSuccess) return fail(PI_EDEVICE, "request upload sync");
+    } else {
+        std::vector<float> a(r.nH.begin(), r.nH.end()), b(x.begin(), x.end());
+        if (hipMemcpyAsync(f.nH, a.data(), n * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(f.x, b.data(), n * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
+            return fail(PI_EDEVICE, "request upload");
+        if (hipStreamSynchronize(stream) != hipSuccess) return fail(PI_EDEVICE, "request upload sync");
+    }
+    // energy, initial columns and clock through a one-grid engine on the same fields
+    Engine one;
+    one.precision = d.precision;
+    one.table_cache = &tables;
+    s = engine_build(one, { &r.grid });
+    if (s == PI_OK) s = engine_init_energy(one, 0, r.T0, PI_BUF_N, stream);
+    if (s == PI_OK) s = engine_raytrace(one, PI_BUF_N, PI_BUF_N, stream);
+    std::vector<DevState> st;
+    if (s == PI_OK) s = engine_read_states(one, st, stream);
+    if (s == PI_OK) {
+        st[0].t = 0.0;
+        st[0].nsteps = 0;
+        st[0].t_end = r.t_end;
+        st[0].dt = 0.0;
+        s = engine_write_states(one, st, stream);
+    }
+    engine_free(one);
+    return s;
+}
+
+// Copies the results of a finished request out and frees its device memory
+// (worker thread, mutex held).
+void pi_server::retire(Request& r, bool ok, const std::string& why)
+{
+    if (ok) {
+        const size_t n = (size_t)r.d.n[0] * r.d.n[1] * r.d.n[2];
+        r.x_out.assign(n, 0.0);
+        r.T_out.assign(n, r.d.T_fixed);
+        std::vector<double> E(n, 0.0);
+        bool good = true;
+        if (r.d.precision == PI_FP64) {
+            good = hipMemcpy(r.x_out.data(), r.grid.f.x, n * 8, hipMemcpyDeviceToHost) == hipSuccess;
+            if (good && r.d.thermal == PI_T_EVOLVE)
+                good = hipMemcpy(E.data(), r.grid.f.E, n * 8, hipMemcpyDeviceToHost) == hipSuccess;
+        } else {
+            std::vector<float> a(n), b(n);
+            good = hipMemcpy(a.data(), r.grid.f.x, n * 4, hipMemcpyDeviceToHost) == hipSuccess;
+            if (good && r.d.thermal == PI_T_EVOLVE)
+                good = hipMemcpy(b.data(), r.grid.f.E, n * 4, hipMemcpyDeviceToHost) == hipSuccess;
+            std::copy(a.begin(), a.end(), r.x_out.begin());
+            std::copy(b.begin(), b.end(), E.begin());
+        }
+        if (good && r.d.thermal == PI_T_EVOLVE) {
+            // T from the stored state (the density as the grid holds it)
+            const double kB = 1.380649e-16;
+            const bool f32 = r.d.precision != PI_FP64;
+            for (size_t q = 0; q < n; ++q) {
+                const double nq = f32 ? (double)(float)r.nH[q] : r.nH[q];
+                r.T_out[q] = 2.0 * E[q] / (3.0 * kB * nq * (2.0 - r.x_out[q]));
+            }
+        }
+        r.status = good ? PI_OK : PI_EDEVICE;
+        if (!good) r.error = "result download";
+        else done++;
+    } else {
+        r.status = r.cancel ? PI_ECANCELLED : PI_EDEVICE;
+        r.error = why;
+    }
+    r.completed = Clock::now();
+    grid_host_free(r.grid);
+    if (r.block) arena.free(r.block, r.bytes);
+    r.block = nullptr;
+    r.active = false;
+}
+
+void pi_server::run()
+{
+    (void)hipSetDevice(device);
+    for (;;) {
+        std::vector<std::shared_ptr<Request>> admitted;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+            if (stop) break;
+            // cancelled requests leave the queue; the rest are admitted in order
+            // while a slot and room in the arena are free
+            for (auto it = queue.begin(); it != queue.end();) {
+                if ((*it)->cancel) {
+                    (*it)->status = PI_ECANCELLED;
+                    (*it)->completed = Clock::now();
+                    it = queue.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+            while (!queue.empty() && (int)(active.size() + admitted.size()) < desc.max_active) {
+                std::shared_ptr<Request>& r = queue.front();
+                if (!admit_locked(r)) break;   // head-of-line: keep arrival order
+                r->admitted = Clock::now();
+                r->was_admitted = true;
+                admitted.push_back(r);
+                queue.pop_front();
+            }
+        }
+        bool changed = !admitted.empty();
+        for (auto& r : admitted) {
+            const pi_status s = start(*r);
+            std::lock_guard<std::mutex> lk(mu);
+            if (s != PI_OK) {
+                retire(*r, false, last_error());
+            } else {
+                r->active = true;
+                active.push_back(r);
+            }
+        }
+        const Clock::time_point t0 = Clock::now();
+        std::vector<GridHost*> grids;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (auto& r : active) grids.push_back(&r->grid);
+        }
+        if (grids.empty()) continue;
+        pi_status s = PI_OK;
+        if (changed || engine.ngrids() != (int)grids.size()) {
+            s = engine_build(engine, grids);
+            rebuilds++;
+        }
+        int64_t cells = 0;
+        for (GridHost* g : grids) cells += g->ncell;
+        std::vector<DevState> st;
+        if (s == PI_OK) {
+            for (int k = 0; k < desc.steps_per_tick && s == PI_OK; ++k) s = engine_step_graph(engine, stream);
+            if (s == PI_OK) s = engine_read_states(engine, st, stream);
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        busy_s += seconds(t0, Clock::now());
+        if (s != PI_OK) {
+            // a device error ends every active request
+            worker_error = last_error();
+            for (auto& r : active) retire(*r, false, worker_error);
+            active.clear();
+            engine_build(engine, {});
+            continue;
+        }
+        steps += desc.steps_per_tick;
+        std::vector<std::shared_ptr<Request>> keep;
+        for (size_t g = 0; g < active.size(); ++g) {
+            Request& r = *active[g];
+            cell_updates += (double)r.grid.ncell * (double)(st[g].nsteps - r.nsteps);
+            r.t = st[g].t;
+            r.nsteps = st[g].nsteps;
+            if (r.cancel) {
+                retire(r, false, "cancelled");
+            } else if (st[g].diag[5] > 0) {
+                retire(r, false, "non-finite values in the grid state");
+            } else if (st[g].t >= r.t_end) {
+                retire(r, true, "");
+            } else {
+                keep.push_back(active[g]);
+            }
+        }
+        if (keep.size() != active.size()) {
+            active = keep;
+            grids.clear();
+            for (auto& r : active) grids.push_back(&r->grid);
+            engine_build(engine, grids);
+            rebuilds++;
+        }
+    }
+}
+
+extern "C" {
+
+pi_status pi_server_create(const pi_server_desc* desc, pi_server** out)
+{
+    if (!out || !desc) return fail(PI_EINVAL, "null argument");
+    *out = nullptr;
+    if (desc->max_active < 1 || desc->steps_per_tick < 1)
+        return fail(PI_EINVAL, "max_active and steps_per_tick must be >= 1");
+    if (desc->precision != PI_FP64 && desc->precision != PI_FP32 && desc->precision != PI_MIXED)
+        return fail(PI_EINVAL, "precision");
+    std::unique_ptr<pi_server> s(new pi_server());
+    s->desc = *desc;
+    if (hipGetDevice(&s->device) != hipSuccess) return fail(PI_EDEVICE, "no device");
+    size_t budget = desc->hbm_budget;
+    if (budget == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(PI_EDEVICE, "memory query");
+        budget = (size_t)(0.8 * (double)fr);
+    }
+    if (!s->arena.init(budget)) return fail(PI_ENOMEM, "arena allocation of the HBM budget");
+    s->engine.precision = desc->precision;
+    s->engine.table_cache = &s->tables;
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+        s->arena.release();
+        return fail(PI_EDEVICE, "stream creation");
+    }
+    pi_server* p = s.release();
+    p->worker = std::thread([p] { p->run(); });
+    *out = p;
+    return PI_OK;
+}
+
+pi_status pi_submit(pi_server* s, const pi_request* req, uint64_t* ticket)
+{
+    if (!s || !req || !ticket) return fail(PI_EINVAL, "null argument");
+    pi_status v = validate_desc(&req->desc);
+    if (v != PI_OK) return v;
+    if (req->desc.precision != s->desc.precision) return fail(PI_EINVAL, "precision differs from the server's");
+    if (!req->nH) return fail(PI_EINVAL, "nH is required");
+    if (!std::isfinite(req->t_end) || !(req->t_end >= 0)) return fail(PI_EINVAL, "t_end must be finite and >= 0");
+    if (req->desc.thermal == PI_T_EVOLVE && !(req->T0 > 0)) return fail(PI_EINVAL, "T0 must be > 0");
+    if (footprint(req->desc) > s->arena.size)
+        return fail(PI_EREJECTED, "request larger than the server's device-memory budget");
+    auto r = std::make_shared<Request>();
+    const size_t n = (size_t)req->desc.n[0] * req->desc.n[1] * req->desc.n[2];
+    r->d = req->desc;
+    r->nH.assign(req->nH, req->nH + n);
+    for (double v2 : r->nH)
+        if (!(v2 > 0) || !std::isfinite(v2)) return fail(PI_EINVAL, "nH must be finite and > 0");
+    if (req->x0) {
+        r->x0.assign(req->x0, req->x0 + n);
+        for (double v2 : r->x0)
+            if (!(v2 >= 0 && v2 <= 1)) return fail(PI_EINVAL, "x0 must lie in [0, 1]");
+    }
+    r->T0 = req->desc.thermal == PI_T_EVOLVE ? req->T0 : 1.0;
+    r->t_end = req->t_end;
+    r->submitted = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        r->ticket = s->next_ticket++;
+        s->requests[r->ticket] = r;
+        s->queue.push_back(r);
+    }
+    s->cv.notify_one();
+    *ticket = r->ticket;
+    return PI_OK;
+}
+
+pi_status pi_poll(pi_server* s, uint64_t ticket, pi_result* out, double* x_out, double* T_out)
+{
+    if (!s || !out) return fail(PI_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->requests.find(ticket);
+    if (it == s->requests.end()) return fail(PI_EINVAL, "unknown ticket");
+    Request& r = *it->second;
+    out->status = r.status;
+    out->t = r.t;
+    out->nsteps = r.nsteps;
+    out->queue_s = r.was_admitted ? seconds(r.submitted, r.admitted) : seconds(r.submitted, Clock::now());
+    out->latency_s = r.status == PI_PENDING ? seconds(r.submitted, Clock::now())
+                                            : seconds(r.submitted, r.completed);
+    if (r.status == PI_PENDING) return PI_PENDING;
+    if (r.status != PI_OK) {
+        const pi_status st = (pi_status)r.status;
+        const std::string e = r.error;
+        s->requests.erase(it);
+        return fail(st, e);
+    }
+    if (x_out) std::copy(r.x_out.begin(), r.x_out.end(), x_out);
+    if (T_out) std::copy(r.T_out.begin(), r.T_out.end(), T_out);
+    s->requests.erase(it);
+    return PI_OK;
+}
+
+pi_status pi_cancel(pi_server* s, uint64_t ticket)
+{
+    if (!s) return fail(PI_EINVAL, "null server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->requests.find(ticket);
+    if (it == s->requests.end()) return fail(PI_EINVAL, "unknown ticket");
+    it->second->cancel = true;
+    s->cv.notify_one();
+    return PI_OK;
+}
+
+pi_status pi_server_stats(pi_server* s, double* out)
+{
+    if (!s || !out) return fail(PI_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    out[0] = (double)s->done;
+    out[1] = s->cell_updates;
+    out[2] = s->busy_s;
+    out[3] = (double)s->steps;
+    out[4] = (double)s->active.size();
+    out[5] = (double)s->queue.size();
+    out[6] = (double)s->arena.used;
+    out[7] = (double)s->rebuilds;
+    return PI_OK;
+}
+
+pi_status pi_server_destroy(pi_server* s)
+{
+    if (!s) return PI_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv.notify_one();
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipStreamSynchronize(s->stream);
+    for (auto& r : s->active) {
+        grid_host_free(r->grid);
+    }
+    engine_free(s->engine);
+    free_tables(s->tables);
+    (void)hipStreamDestroy(s->stream);
+    s->arena.release();
+    delete s;
+    return PI_OK;
+}
+
+}  // extern "C"

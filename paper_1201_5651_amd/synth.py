@@ -100,7 +100,7 @@ def lognormal_density(shape, mean: float, sigma_ln: float, seed: int,
     k[0, 0, 0] = 1.0
     filt = k ** (spectral_index / 2.0)
     filt[0, 0, 0] = 0.0
-    g = np.fft.irfftn(F * filt, s=shape)
+    g = np.fft.irfftn(F * filt, s=shape, axes=(0, 1, 2))
     g = (g - g.mean()) / g.std()
     n = np.exp(sigma_ln * g - 0.5 * sigma_ln * sigma_ln)
     return n * (mean / n.mean())

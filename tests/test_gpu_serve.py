@@ -1,0 +1,103 @@
+"""Served form on the GPU: requests admitted into a device-memory arena as
+room frees up, advanced together, returned when each reaches its t_end.  A
+served grid goes through the same arithmetic as the grid advanced alone, so
+its result is compared bit for bit; admission under a small budget, rejection
+and cancellation are exercised."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1201_5651_amd import binding, synth
+from gpu_util import to_np
+
+pytestmark = pytest.mark.gpu
+
+KB = 1.380649e-16
+
+
+def _requests(precision):
+    out = []
+    for i, (n, src) in enumerate((((14, 12, 16), (7, 6, 8)), ((18, 18, 18), (9, 9, 9)),
+                                  ((12, 20, 10), (3, 10, 5)), ((16, 16, 16), (8, 8, 8)),
+                                  ((10, 10, 10), (5, 5, 5)))):
+        s = synth.cfg2(n=n[0])
+        s = synth.GridSpec(**{**s.__dict__, "name": f"r{i}", "n": n, "src": src,
+                              "Q": 1e48 * (1 + i), "precision": precision})
+        nH = synth.lognormal_density(s.shape, s.nH_mean, 1.0, 40 + i)
+        out.append((s, nH, 2e-3 * s.t_rec * (1 + 0.5 * i)))
+    return out
+
+
+def _alone(spec, nH, t_end, precision):
+    g = binding.Grid(spec, precision=precision)
+    g.load(nH, 1.0, T0=spec.T0)
+    g.run(t_end, check_every=8)
+    t, n, _ = g.state()
+    x, E = to_np(g.x), to_np(g.E)
+    g.close()
+    return t, n, x, E
+
+
+def _wait(srv, tickets, timeout=120.0):
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets):
+        assert time.time() - t0 < timeout, "served requests did not finish"
+        for tk in tickets:
+            if tk in done:
+                continue
+            st, info, x, T = srv.poll(tk)
+            if st != binding.PI_PENDING:
+                done[tk] = (st, info, x, T)
+        time.sleep(0.005)
+    return done
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_served_results_match_grids_alone(precision):
+    reqs = _requests(precision)
+    word = 8 if precision == "fp64" else 4
+    biggest = max(s.ncells for s, _, _ in reqs) * 7 * word
+    # room for about two requests at a time: the rest wait for admission
+    srv = binding.Server(precision=precision, hbm_budget=int(2.2 * biggest) + 4096, max_active=4,
+                         steps_per_tick=3)
+    tickets = [srv.submit(s, nH, T0=s.T0, t_end=te) for s, nH, te in reqs]
+    done = _wait(srv, tickets)
+    stats = srv.stats()
+    srv.close()
+    assert stats["completed"] == len(reqs)
+    # the budget holds about two grids: a later request waited for an earlier
+    # one to finish before it was admitted
+    queue = [done[tk][1]["queue_s"] for tk in tickets]
+    lat = [done[tk][1]["latency_s"] for tk in tickets]
+    assert max(queue) > 0.5 * min(lat)
+    for tk, (s, nH, te) in zip(tickets, reqs):
+        st, info, x, T = done[tk]
+        assert st == binding.PI_OK, info
+        ta, na, xa, Ea = _alone(s, nH, te, precision)
+        assert info["t"] == ta == te
+        assert info["nsteps"] == na
+        assert np.array_equal(x, xa)
+        nHs = np.asarray(nH, dtype=np.float32 if precision != "fp64" else np.float64).astype(np.float64)
+        Ta = 2.0 * Ea / (3.0 * KB * nHs * (2.0 - xa))
+        assert np.allclose(T, Ta, rtol=1e-12, atol=0)
+        assert info["latency_s"] >= info["queue_s"] >= 0
+
+
+def test_oversized_request_is_rejected_and_cancel_works():
+    s, nH, te = _requests("fp64")[1]
+    srv = binding.Server(precision="fp64", hbm_budget=s.ncells * 7 * 8 // 2, max_active=2)
+    with pytest.raises(binding.PiError) as e:
+        srv.submit(s, nH, T0=s.T0, t_end=te)
+    assert e.value.status == binding.PI_EREJECTED
+    srv.close()
+    srv = binding.Server(precision="fp64", hbm_budget=s.ncells * 7 * 8 * 4, max_active=2,
+                         steps_per_tick=1)
+    tk = srv.submit(s, nH, T0=s.T0, t_end=10 * s.t_rec)   # far longer than the test
+    time.sleep(0.2)
+    srv.cancel(tk)
+    st, info, _, _ = _wait(srv, [tk])[tk]
+    assert st == binding.PI_ECANCELLED
+    assert srv.stats()["arena_bytes"] == 0
+    srv.close()
