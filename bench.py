@@ -85,6 +85,132 @@ def cpu_baseline(n: int, budget_s: float):
     }
 
 
+def bench_batch(args, torch, binding, synth) -> dict:
+    """Batched form: the generated set of uneven grids (n uniform in 32..160,
+    uniform or lognormal media, Q log-uniform in 1e47..1e50) advanced together,
+    one graph replay per step; beside it the FP64 single-grid path on a
+    sample of the same grids, one grid at a time."""
+    specs = synth.batch_specs(args.batch_grids, seed=0, precision=args.precision)
+    tick = time.time()
+    nHs = [synth.density(s) for s in specs]
+    print(f"# batch: {len(specs)} grids, {sum(s.ncells for s in specs) / 1e6:.1f} M cells, "
+          f"densities in {time.time() - tick:.1f} s", file=sys.stderr, flush=True)
+    bt = binding.Batch(specs, precision=args.precision)
+    bt.load(nHs, T0s=[s.T0 for s in specs], t_end=[s.t_end for s in specs])
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        bt.step_o2()
+    torch.cuda.synchronize()
+    _, n0, _ = bt.state()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        bt.step_o2()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    _, n1, _ = bt.state()
+    cells = sum(s.ncells * (b - a) for s, a, b in zip(specs, n0, n1))
+    value = cells / (ms * 1e-3)
+    work = bt.work_counters(reset=True)
+    bt.close()
+    del bt
+    torch.cuda.empty_cache()
+    # FP64 single-grid path on a sample of the same grids
+    sample = specs[:args.batch_fp64_sample]
+    tot_cells, tot_ms = 0.0, 0.0
+    for s, nH in zip(sample, nHs):
+        g = binding.Grid(s, precision="fp64")
+        g.load(nH, 1.0, T0=s.T0)
+        g.step_o2(s.t_end)
+        torch.cuda.synchronize()
+        a, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(3):
+            g.step_o2(s.t_end)
+        b2.record(stream)
+        torch.cuda.synchronize()
+        tot_cells += 3 * s.ncells
+        tot_ms += a.elapsed_time(b2)
+        g.close()
+    fp64_plain = tot_cells / (tot_ms * 1e-3)
+    return {
+        "metric": "cell-updates/s of the batched A3 step, 64 uneven grids",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype_name(args.precision),
+        "data": "synthetic",
+        "config": {"workload": f"batch of {len(specs)} grids, n uniform in 32..160, uniform or "
+                               "lognormal media, Q log-uniform 1e47..1e50, 1e5 K blackbody table, "
+                               "T evolving, A3-dt02, from a neutral start",
+                   "cells": sum(s.ncells for s in specs), "precision": args.precision,
+                   "fp64_single_grid_rate": fp64_plain,
+                   "fp64_single_grid_sample": len(sample),
+                   "ratio_to_fp64_single_grid": value / fp64_plain,
+                   "fp64_resolved_frac": work["resolved_fp64"] / max(1, cells)},
+    }
+
+
+def bench_serve(args, torch, binding, synth) -> dict:
+    """Served form: Poisson arrivals of single-grid requests submitted to the
+    library's server at their arrival times; latency from submission to
+    completion."""
+    import numpy as np
+    reqs = synth.poisson_requests(args.serve_requests, rate=args.serve_rate, seed=5651,
+                                  nmin=args.serve_nmin, nmax=args.serve_nmax,
+                                  n_outlier=2 * args.serve_nmax, p_outlier=0.01,
+                                  precision=args.precision)
+    reqs = [(t, synth.GridSpec(**{**s.__dict__, "t_end": args.serve_trec * s.t_rec})) for t, s in reqs]
+    tick = time.time()
+    nHs = [synth.density(s) for _, s in reqs]
+    print(f"# serve: {len(reqs)} requests, densities in {time.time() - tick:.1f} s",
+          file=sys.stderr, flush=True)
+    srv = binding.Server(precision=args.precision, hbm_budget=0, max_active=args.serve_max_active,
+                         steps_per_tick=args.serve_steps_per_tick)
+    pending, done = {}, {}
+    t0 = time.perf_counter()
+    i = 0
+    last = t0
+    while i < len(reqs) or pending:
+        now = time.perf_counter() - t0
+        while i < len(reqs) and reqs[i][0] <= now:
+            s = reqs[i][1]
+            pending[srv.submit(s, nHs[i], T0=s.T0, t_end=s.t_end)] = i
+            i += 1
+        for tk in list(pending):
+            st, info, _, _ = srv.poll(tk)
+            if st != binding.PI_PENDING:
+                done[pending.pop(tk)] = (st, info)
+        if time.perf_counter() - last > 20:
+            last = time.perf_counter()
+            print(f"# serve: {len(done)} done, {len(pending)} pending, {now:.0f} s",
+                  file=sys.stderr, flush=True)
+        time.sleep(0.002)
+    wall = time.perf_counter() - t0
+    stats = srv.stats()
+    srv.close()
+    lat = np.array([info["latency_s"] for st, info in done.values()])
+    que = np.array([info["queue_s"] for st, info in done.values()])
+    ok = sum(1 for st, _ in done.values() if st == binding.PI_OK)
+    return {
+        "metric": "served A3 solves: cell-updates/s and p50/p99 latency",
+        "value": stats["cell_updates"] / wall, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": int(stats["steps"]), "warmup": 0, "ms_per_step": 1e3 * stats["busy_s"] / max(1, stats["steps"]),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dtype_name(args.precision), "data": "synthetic",
+        "config": {"workload": f"{len(reqs)} requests, Poisson arrivals at {args.serve_rate}/s, n "
+                               f"uniform in {args.serve_nmin}..{args.serve_nmax} (1% at "
+                               f"{2 * args.serve_nmax}), source in the central half, cfg2 physics, "
+                               f"each to {args.serve_trec} t_rec(mean)",
+                   "completed_ok": ok, "wall_s": wall, "busy_s": stats["busy_s"],
+                   "latency_p50_s": float(np.quantile(lat, 0.5)),
+                   "latency_p99_s": float(np.quantile(lat, 0.99)),
+                   "queue_p50_s": float(np.quantile(que, 0.5)),
+                   "queue_p99_s": float(np.quantile(que, 0.99)),
+                   "batch_rebuilds": int(stats["rebuilds"])},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +226,18 @@ def main() -> int:
     ap.add_argument("--cpu-sample-n", type=int, default=32)
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="cfg3", choices=["cfg3", "batch", "serve"],
+                    help="cfg3: the 256^3 single grid (default); batch / serve: the batched and "
+                         "served forms (their own JSON line)")
+    ap.add_argument("--batch-grids", type=int, default=64)
+    ap.add_argument("--batch-fp64-sample", type=int, default=8)
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-nmin", type=int, default=32)
+    ap.add_argument("--serve-nmax", type=int, default=96)
+    ap.add_argument("--serve-trec", type=float, default=0.05)
+    ap.add_argument("--serve-max-active", type=int, default=64)
+    ap.add_argument("--serve-steps-per-tick", type=int, default=4)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (a known-size "
                          "reference for hardware traffic counters)")
@@ -115,6 +253,10 @@ def main() -> int:
     from paper_1201_5651_amd import binding, synth
 
     torch.cuda.set_device(0)
+    if args.workload != "cfg3":
+        fn = bench_batch if args.workload == "batch" else bench_serve
+        print(json.dumps(fn(args, torch, binding, synth)))
+        return 0
     spec = synth.cfg3(n=args.n)
     nH = synth.density(spec)
     g = binding.Grid(spec, precision=args.precision)

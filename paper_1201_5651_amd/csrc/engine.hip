@@ -7,6 +7,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 namespace pi {
 
@@ -107,9 +109,22 @@ pi_status table_for(Engine& e, const pi_grid_desc& d, void** td, void** tf)
             *tf = t.f;
             return PI_OK;
         }
-    std::vector<double> raw(5 * PI_NTAB, 0.0);
-    pi_status r = pi_table_build(d.T_bb, 1.0, raw.data());
-    if (r != PI_OK) return r;
+    // the host quadrature is shared by every engine of the process
+    static std::mutex mu;
+    static std::map<double, std::vector<double>> cache;   // T_bb -> table for Q = 1
+    std::vector<double> raw;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(d.T_bb);
+        if (it != cache.end()) raw = it->second;
+    }
+    if (raw.empty()) {
+        raw.assign(5 * PI_NTAB, 0.0);
+        pi_status r = pi_table_build(d.T_bb, 1.0, raw.data());
+        if (r != PI_OK) return r;
+        std::lock_guard<std::mutex> lk(mu);
+        cache[d.T_bb] = raw;
+    }
     Engine::Table t{ d.spectrum, d.T_bb, nullptr, nullptr };
     DevTable<double> Td{};
     fill_table(Td, raw.data(), 1.0);
