@@ -39,6 +39,30 @@ FLOP_NEWTON = 262
 FLOP_CELL_SETUP = 330
 
 
+KERNEL_SOURCES = ("paper_1201_5651_amd/csrc/physics.h", "paper_1201_5651_amd/csrc/kernels.h",
+                  "paper_1201_5651_amd/csrc/kernels.hip")
+TRAFFIC_PROFILE = "profiles/cfg3_256_mixed_k_chem_traffic.md"
+
+
+def measured_traffic():
+    """HBM bytes per micro-physics launch from the committed hardware-counter
+    summary, or None when the kernel sources have changed since it was taken."""
+    import hashlib
+    import re
+    try:
+        text = open(os.path.join(ROOT, TRAFFIC_PROFILE)).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    m = re.search(r"kernel_source_sha256: ([0-9a-f]+)", text)
+    t = re.search(r"k_chem_traffic_bytes_per_launch: ([0-9.eE+-]+)", text)
+    if not m or not t or m.group(1) != h.hexdigest():
+        return None
+    return float(t.group(1))
+
+
 def word_bytes(precision: str) -> int:
     return 8 if precision == "fp64" else 4
 
@@ -345,7 +369,8 @@ def main() -> int:
         peak = VALU_PEAK[args.precision]
         roofline = {"bound": "alu", "kernel": "k_chem (" + dom + ")",
                     "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                    "frac": round(achieved / peak, 5), "traffic": None,
+                    "frac": round(achieved / peak, 5),
+                    "traffic": measured_traffic() if (args.precision == "mixed" and args.n == 256) else None,
                     "flops_per_launch": flops,
                     "hbm_GBs_of_dominant": round(hbm[dom], 2)}
     else:
