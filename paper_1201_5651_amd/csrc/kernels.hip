@@ -16,6 +16,30 @@
 namespace pi {
 
 // ------------------------------------------------------------------ raytrace
+// Thread -> cell map of a T^3 tile in diagonal-plane order (lx + ly + lz
+// ascending), built at compile time: the cells of one plane are consecutive
+// threads, so a plane occupies one or two wavefronts instead of one lane in
+// each of T wavefronts.  Packed as lx | ly << 4 | lz << 8.
+template <int T> struct PlaneOrder {
+    unsigned short cell[T * T * T];
+};
+
+template <int T> constexpr PlaneOrder<T> make_plane_order()
+{
+    PlaneOrder<T> o{};
+    int q = 0;
+    for (int s = 0; s < 3 * T - 2; ++s)
+        for (int lz = 0; lz < T; ++lz)
+            for (int ly = 0; ly < T; ++ly) {
+                const int lx = s - ly - lz;
+                if (lx >= 0 && lx < T) o.cell[q++] = (unsigned short)(lx | ly << 4 | lz << 8);
+            }
+    return o;
+}
+static_assert(SWEEP_T < 16, "tile coordinates are packed in 4 bits");
+
+__constant__ PlaneOrder<SWEEP_T> c_plane_order = make_plane_order<SWEEP_T>();
+
 // Weighted upstream average of the short-characteristics interpolation:
 // sum w_i T_i / sum w_i with w_i = g_i (Mellema: divided by max(0.6, T_i)).
 template <typename R>
@@ -107,8 +131,8 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     }
     __syncthreads();
 
-    const int t = threadIdx.x;
-    const int lx = t % TX, ly = (t / TX) % TY, lz = t / (TX * TY);
+    const int cl = c_plane_order.cell[threadIdx.x];
+    const int lx = cl & 15, ly = (cl >> 4) & 15, lz = cl >> 8;
     const int L[3] = { X0 + lx, Y0 + ly, Z0 + lz };
     const bool active = L[0] < ex && L[1] < ey && L[2] < ez;
     const R ad[3] = { R(L[0]) + R(0.5), R(L[1]) + R(0.5), R(L[2]) + R(0.5) };
@@ -132,6 +156,7 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     const bool mellema = p.weights == 1;
     const int diag = lx + ly + lz;
 
+    const R own = hds * s_kap[self];   // the cell's half chord, entry face to centre
     R tin = R(0);
     for (int s = 0; s < TX + TY + TZ - 2; ++s) {
         if (active && diag == s) {
@@ -142,15 +167,24 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
                 const R T11 = s_tc[n11] + hds * s_kap[n11];
                 tin = sc_average<R>(mellema, g00, g10, g01, g11, T00, T10, T01, T11);
             }
-            s_tc[self] = tin + hds * s_kap[self];
+            s_tc[self] = tin + own;
         }
         __syncthreads();
     }
-    if (active) {
-        const int gi = px ? p.sx + L[0] : p.sx - 1 - L[0];
-        const int gj = py ? p.sy + L[1] : p.sy - 1 - L[1];
-        const int gk = pz ? p.sz + L[2] : p.sz - 1 - L[2];
-        tau[gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk)] = tin;
+    // entering columns back to natural order for a coalesced store
+    __shared__ R s_out[TX * TY * TZ];
+    s_out[lx + TX * (ly + TY * lz)] = tin;
+    __syncthreads();
+    {
+        const int t = threadIdx.x;
+        const int ox = t % TX, oy = (t / TX) % TY, oz = t / (TX * TY);
+        const int Lx = X0 + ox, Ly = Y0 + oy, Lz = Z0 + oz;
+        if (Lx < ex && Ly < ey && Lz < ez) {
+            const int gi = px ? p.sx + Lx : p.sx - 1 - Lx;
+            const int gj = py ? p.sy + Ly : p.sy - 1 - Ly;
+            const int gk = pz ? p.sz + Lz : p.sz - 1 - Lz;
+            tau[gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk)] = s_out[t];
+        }
     }
 }
 
