@@ -137,6 +137,7 @@ def bench_batch(args, torch, binding, synth) -> dict:
     cells = sum(s.ncells * (b - a) for s, a, b in zip(specs, n0, n1))
     value = cells / (ms * 1e-3)
     work = bt.work_counters(reset=True)
+    tile = bt.raytrace_tile
     bt.close()
     del bt
     torch.cuda.empty_cache()
@@ -168,6 +169,7 @@ def bench_batch(args, torch, binding, synth) -> dict:
                                "lognormal media, Q log-uniform 1e47..1e50, 1e5 K blackbody table, "
                                "T evolving, A3-dt02, from a neutral start",
                    "cells": sum(s.ncells for s in specs), "precision": args.precision,
+                   "raytrace_tile": tile,
                    "fp64_single_grid_rate": fp64_plain,
                    "fp64_single_grid_sample": len(sample),
                    "ratio_to_fp64_single_grid": value / fp64_plain,
@@ -401,6 +403,7 @@ def main() -> int:
             "n": args.n, "precision": args.precision, "pre_steps": int(n_start),
             "t_start_trec": t_start / spec.t_rec, "t_end_trec": t_now / spec.t_rec,
             "r_ion_cells": diag["r_ion"] / spec.dx, "n_sub": spec.n_sub,
+            "raytrace_tile": g.raytrace_tile,
             "substeps_per_cell_update": (work_phase["accepted"] + work_phase["rejected"])
             / (spec.ncells * args.phase_steps),
             "rejected_frac": work_phase["rejected"]

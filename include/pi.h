@@ -280,12 +280,22 @@ pi_status pi_server_destroy(pi_server* server);
  * cross-section sigma0 (nu0/nu)^3.  Nodes: 0, then 63 log-spaced in [1e-4, 1e4]. */
 pi_status pi_table_build(double T_bb, double Q, double* out);
 
+/* Raytrace tile edge: 4 or 8 (cells of the cubic tile one workgroup sweeps),
+ * or 0 to time both on the next raytrace outside graph capture and keep the
+ * faster (the default; that first raytrace then SYNCHRONISES its stream).  The
+ * edge does not change any result: every cell's interpolation is the same.
+ * pi_get_raytrace_tile returns 0 while untuned.  PI_EINVAL for other edges. */
+pi_status pi_set_raytrace_tile(pi_grid* grid, int edge);
+pi_status pi_get_raytrace_tile(pi_grid* grid, int* edge);
+pi_status pi_batch_set_raytrace_tile(pi_batch* batch, int edge);
+pi_status pi_batch_get_raytrace_tile(pi_batch* batch, int* edge);
+
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char* pi_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns the
  * value it was built with. */
-#define PI_ABI_VERSION 103
+#define PI_ABI_VERSION 104
 int pi_abi_version(void);
 
 #ifdef __cplusplus

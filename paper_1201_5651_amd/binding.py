@@ -36,6 +36,8 @@ ABI_SYMBOLS = (
     "pi_batch_raytrace", "pi_batch_step_o2", "pi_batch_state", "pi_batch_diagnostics",
     "pi_batch_work_counters",
     "pi_server_create", "pi_submit", "pi_poll", "pi_cancel", "pi_server_stats", "pi_server_destroy",
+    "pi_set_raytrace_tile", "pi_get_raytrace_tile", "pi_batch_set_raytrace_tile",
+    "pi_batch_get_raytrace_tile",
 )
 
 
@@ -129,6 +131,11 @@ def lib() -> C.CDLL:
         L.pi_cancel.argtypes = [vp, C.c_uint64]
         L.pi_server_stats.argtypes = [vp, dp]
         L.pi_server_destroy.argtypes = [vp]
+        ip = C.POINTER(C.c_int)
+        L.pi_set_raytrace_tile.argtypes = [vp, i32]
+        L.pi_get_raytrace_tile.argtypes = [vp, ip]
+        L.pi_batch_set_raytrace_tile.argtypes = [vp, i32]
+        L.pi_batch_get_raytrace_tile.argtypes = [vp, ip]
         L.pi_last_error.restype = C.c_char_p
         L.pi_abi_version.restype = C.c_int
         for name in ABI_SYMBOLS:
@@ -282,6 +289,16 @@ class Grid:
         keys = ("n_ion", "v_ion", "r_ion", "photo_rate", "recomb_rate", "nonfinite", "octants", "t")
         return dict(zip(keys, list(out)))
 
+    @property
+    def raytrace_tile(self) -> int:
+        v = C.c_int()
+        check(lib().pi_get_raytrace_tile(self._h, C.byref(v)))
+        return v.value
+
+    @raytrace_tile.setter
+    def raytrace_tile(self, edge: int):
+        check(lib().pi_set_raytrace_tile(self._h, int(edge)))
+
     def work_counters(self, reset: bool = False):
         out = (C.c_int64 * PI_NWORK)()
         check(lib().pi_work_counters(self._h, out, int(reset), self._stream()))
@@ -365,6 +382,16 @@ class Batch:
 
     def step_o2(self):
         check(lib().pi_batch_step_o2(self._h, self._stream()))
+
+    @property
+    def raytrace_tile(self) -> int:
+        v = C.c_int()
+        check(lib().pi_batch_get_raytrace_tile(self._h, C.byref(v)))
+        return v.value
+
+    @raytrace_tile.setter
+    def raytrace_tile(self, edge: int):
+        check(lib().pi_batch_set_raytrace_tile(self._h, int(edge)))
 
     def state(self):
         t, dt = (C.c_double * self.n)(), (C.c_double * self.n)()

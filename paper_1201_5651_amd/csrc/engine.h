@@ -34,7 +34,8 @@ struct GridHost {
     int noct = 0;
     double cell_vol = 0.0;
     int64_t ncell = 0;
-    std::vector<std::vector<int4>> tiles;   // per tile diagonal: (octant, tx, ty, tz)
+    // per tile edge (SWEEP_TILES), per tile diagonal: (octant, tx, ty, tz)
+    std::vector<std::vector<int4>> tiles[2];
 };
 
 pi_status grid_host_init(GridHost& h, const pi_grid_desc& d, const pi_fields& f);
@@ -48,9 +49,11 @@ struct Engine {
     int* first = nullptr;            // chem_first[ngrids+1], then dt_first[ngrids+1]
     size_t first_cap = 0;
     int chem_blocks = 0, dt_blocks = 0;
-    int4* tiles = nullptr;
-    size_t tiles_cap = 0;
-    std::vector<int> stage_first, stage_count;
+    // raytrace schedules, one per tile edge of SWEEP_TILES
+    int4* tiles[2] = { nullptr, nullptr };
+    size_t tiles_cap[2] = { 0, 0 };
+    std::vector<int> stage_first[2], stage_count[2];
+    int sweep = -1;                  // index into SWEEP_TILES; -1 until tuned
     unsigned int* fix_n = nullptr;
     long long* fix_list = nullptr;
     size_t fix_cap = 0;
@@ -82,7 +85,12 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids);
 void engine_free(Engine& e);
 void free_tables(std::vector<Engine::Table>& tables);
 
+// Raytrace with the tuned tile edge; the first call outside graph capture times
+// both tile edges on s (synchronising it) and keeps the faster.  Tiling does
+// not change the arithmetic of any cell, so every edge gives the same columns.
 pi_status engine_raytrace(Engine& e, int state, int tau_buf, hipStream_t s);
+// The timing itself: raytraces of (state -> tau_buf) with each tile edge.
+pi_status engine_autotune(Engine& e, int state, int tau_buf, hipStream_t s);
 pi_status engine_chem(Engine& e, bool dev_dt, double h, int tau_buf, int from, int to,
                       hipStream_t s);
 // t_end_arg finite: the common t_end, else each grid's stored t_end.

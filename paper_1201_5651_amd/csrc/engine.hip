@@ -198,14 +198,25 @@ template <typename R> const GridDev<R>* gd(const Engine& e)
     return static_cast<const GridDev<R>*>(e.gdev);
 }
 
-template <typename R> pi_status raytrace_t(Engine& e, int state, int tau_buf, hipStream_t s)
+template <typename R>
+pi_status raytrace_t(Engine& e, int state, int tau_buf, int which, hipStream_t s)
 {
-    for (size_t k = 0; k < e.stage_first.size(); ++k)
-        HIP_OR(launch_sweep_stage<R>(gd<R>(e), state, tau_buf, e.tiles, e.stage_first[k],
-                                     e.stage_count[k], s),
+    for (size_t k = 0; k < e.stage_first[which].size(); ++k)
+        HIP_OR(launch_sweep_stage<R>(gd<R>(e), state, tau_buf, e.tiles[which],
+                                     e.stage_first[which][k], e.stage_count[which][k],
+                                     SWEEP_TILES[which], s),
                "raytrace launch");
     return PI_OK;
 }
+
+pi_status raytrace_any(Engine& e, int state, int tau_buf, int which, hipStream_t s)
+{
+    return e.fp64() ? raytrace_t<double>(e, state, tau_buf, which, s)
+                    : raytrace_t<float>(e, state, tau_buf, which, s);
+}
+
+// Tile edge used inside graph capture before any tuning.
+constexpr int SWEEP_DEFAULT = 1;
 
 template <typename R>
 pi_status chem_t(Engine& e, bool dev_dt, double h, int tau_buf, int from, int to, hipStream_t s)
@@ -233,12 +244,14 @@ template <typename R> pi_status step_t(Engine& e, double t_end_arg, int order, h
     if (r != PI_OK) return r;
     if (order == 2) {
         if ((r = chem_t<R>(e, true, 0.5, PI_BUF_N, PI_BUF_N, PI_BUF_HALF, s)) != PI_OK) return r;
-        if ((r = raytrace_t<R>(e, PI_BUF_HALF, PI_BUF_HALF, s)) != PI_OK) return r;
+        const int w = e.sweep >= 0 ? e.sweep : SWEEP_DEFAULT;
+    if ((r = raytrace_t<R>(e, PI_BUF_HALF, PI_BUF_HALF, w, s)) != PI_OK) return r;
         if ((r = chem_t<R>(e, true, 1.0, PI_BUF_HALF, PI_BUF_N, PI_BUF_N, s)) != PI_OK) return r;
     } else {
         if ((r = chem_t<R>(e, true, 1.0, PI_BUF_N, PI_BUF_N, PI_BUF_N, s)) != PI_OK) return r;
     }
-    if ((r = raytrace_t<R>(e, PI_BUF_N, PI_BUF_N, s)) != PI_OK) return r;
+    if ((r = raytrace_t<R>(e, PI_BUF_N, PI_BUF_N, e.sweep >= 0 ? e.sweep : SWEEP_DEFAULT, s)) != PI_OK)
+        return r;
     HIP_OR(launch_advance<R>(gd<R>(e), e.ngrids(), s), "advance launch");
     return PI_OK;
 }
@@ -274,22 +287,25 @@ pi_status grid_host_init(GridHost& h, const pi_grid_desc& d, const pi_fields& f)
         grid_host_free(h);
         return fail(PI_ENOMEM, "partials allocation");
     }
-    // tile schedule: every octant's tiles, grouped by tile diagonal tx+ty+tz
-    h.tiles.clear();
-    for (int o = 0; o < 8; ++o) {
-        int ext[3];
-        for (int a = 0; a < 3; ++a) ext[a] = ((o >> a) & 1) ? d.n[a] - d.src[a] : d.src[a];
-        if (ext[0] <= 0 || ext[1] <= 0 || ext[2] <= 0) continue;
-        const int ntx = (ext[0] + SWEEP_T - 1) / SWEEP_T;
-        const int nty = (ext[1] + SWEEP_T - 1) / SWEEP_T;
-        const int ntz = (ext[2] + SWEEP_T - 1) / SWEEP_T;
-        for (int tz = 0; tz < ntz; ++tz)
-            for (int ty = 0; ty < nty; ++ty)
-                for (int tx = 0; tx < ntx; ++tx) {
-                    const int D = tx + ty + tz;
-                    if ((int)h.tiles.size() <= D) h.tiles.resize(D + 1);
-                    h.tiles[D].push_back(make_int4(o, tx, ty, tz));
-                }
+    // tile schedules: every octant's tiles, grouped by tile diagonal tx+ty+tz
+    for (int w = 0; w < 2; ++w) {
+        const int T = SWEEP_TILES[w];
+        h.tiles[w].clear();
+        for (int o = 0; o < 8; ++o) {
+            int ext[3];
+            for (int a = 0; a < 3; ++a) ext[a] = ((o >> a) & 1) ? d.n[a] - d.src[a] : d.src[a];
+            if (ext[0] <= 0 || ext[1] <= 0 || ext[2] <= 0) continue;
+            const int ntx = (ext[0] + T - 1) / T;
+            const int nty = (ext[1] + T - 1) / T;
+            const int ntz = (ext[2] + T - 1) / T;
+            for (int tz = 0; tz < ntz; ++tz)
+                for (int ty = 0; ty < nty; ++ty)
+                    for (int tx = 0; tx < ntx; ++tx) {
+                        const int D = tx + ty + tz;
+                        if ((int)h.tiles[w].size() <= D) h.tiles[w].resize(D + 1);
+                        h.tiles[w][D].push_back(make_int4(o, tx, ty, tz));
+                    }
+        }
     }
     return PI_OK;
 }
@@ -329,31 +345,35 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
         e.first_cap = fb;
     }
     HIP_OR(hipMemcpy(e.first, first.data(), fb, hipMemcpyHostToDevice), "launch table upload");
-    // combined tile schedule: stage k holds tile diagonal k of every grid
-    e.stage_first.clear();
-    e.stage_count.clear();
-    std::vector<int4> flat;
-    size_t nst = 0;
-    for (GridHost* h : e.grids) nst = std::max(nst, h->tiles.size());
-    for (size_t k = 0; k < nst; ++k) {
-        e.stage_first.push_back((int)flat.size());
-        for (int g = 0; g < G; ++g) {
-            const GridHost& h = *e.grids[g];
-            if (k >= h.tiles.size()) continue;
-            for (const int4& t : h.tiles[k]) flat.push_back(make_int4((g << 3) | t.x, t.y, t.z, t.w));
+    // combined tile schedules: stage k holds tile diagonal k of every grid
+    for (int w = 0; w < 2; ++w) {
+        e.stage_first[w].clear();
+        e.stage_count[w].clear();
+        std::vector<int4> flat;
+        size_t nst = 0;
+        for (GridHost* h : e.grids) nst = std::max(nst, h->tiles[w].size());
+        for (size_t k = 0; k < nst; ++k) {
+            e.stage_first[w].push_back((int)flat.size());
+            for (int g = 0; g < G; ++g) {
+                const GridHost& h = *e.grids[g];
+                if (k >= h.tiles[w].size()) continue;
+                for (const int4& t : h.tiles[w][k])
+                    flat.push_back(make_int4((g << 3) | t.x, t.y, t.z, t.w));
+            }
+            e.stage_count[w].push_back((int)flat.size() - e.stage_first[w].back());
         }
-        e.stage_count.push_back((int)flat.size() - e.stage_first.back());
+        if (flat.size() > e.tiles_cap[w]) {
+            if (e.tiles[w]) (void)hipFree(e.tiles[w]);
+            e.tiles[w] = nullptr;
+            e.tiles_cap[w] = 0;
+            HIP_OR(hipMalloc(&e.tiles[w], sizeof(int4) * flat.size()), "tile schedule allocation");
+            e.tiles_cap[w] = flat.size();
+        }
+        if (!flat.empty())
+            HIP_OR(hipMemcpy(e.tiles[w], flat.data(), sizeof(int4) * flat.size(),
+                             hipMemcpyHostToDevice),
+                   "tile schedule upload");
     }
-    if (flat.size() > e.tiles_cap) {
-        if (e.tiles) (void)hipFree(e.tiles);
-        e.tiles = nullptr;
-        e.tiles_cap = 0;
-        HIP_OR(hipMalloc(&e.tiles, sizeof(int4) * flat.size()), "tile schedule allocation");
-        e.tiles_cap = flat.size();
-    }
-    if (!flat.empty())
-        HIP_OR(hipMemcpy(e.tiles, flat.data(), sizeof(int4) * flat.size(), hipMemcpyHostToDevice),
-               "tile schedule upload");
     // work counters
     if (!e.work) {
         const size_t wb = sizeof(unsigned long long) * WORK_COUNTERS * WORK_SLOTS;
@@ -381,17 +401,17 @@ void engine_free(Engine& e)
     drop_graph(e);
     if (e.cap) (void)hipStreamDestroy(e.cap);
     e.cap = nullptr;
-    for (void* p : { e.gdev, (void*)e.first, (void*)e.tiles, (void*)e.fix_n, (void*)e.fix_list,
-                     (void*)e.work })
+    for (void* p : { e.gdev, (void*)e.first, (void*)e.tiles[0], (void*)e.tiles[1], (void*)e.fix_n,
+                     (void*)e.fix_list, (void*)e.work })
         if (p) (void)hipFree(p);
     free_tables(e.tables);
     e.gdev = nullptr;
     e.first = nullptr;
-    e.tiles = nullptr;
+    e.tiles[0] = e.tiles[1] = nullptr;
     e.fix_n = nullptr;
     e.fix_list = nullptr;
     e.work = nullptr;
-    e.gdev_cap = e.first_cap = e.tiles_cap = e.fix_cap = 0;
+    e.gdev_cap = e.first_cap = e.tiles_cap[0] = e.tiles_cap[1] = e.fix_cap = 0;
 }
 
 void free_tables(std::vector<Engine::Table>& tables)
@@ -403,9 +423,45 @@ void free_tables(std::vector<Engine::Table>& tables)
     tables.clear();
 }
 
+pi_status engine_autotune(Engine& e, int state, int tau_buf, hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_OR(hipStreamIsCapturing(s, &cs), "capture query");
+    if (cs != hipStreamCaptureStatusNone) return PI_OK;   // tuned later, outside capture
+    hipEvent_t ev[3];
+    for (int i = 0; i < 3; ++i) HIP_OR(hipEventCreate(&ev[i]), "event creation");
+    float best = 0.0f;
+    int pick = SWEEP_DEFAULT;
+    pi_status r = PI_OK;
+    for (int w = 0; w < 2 && r == PI_OK; ++w) {
+        // the second of two runs (the first warms the caches)
+        r = raytrace_any(e, state, tau_buf, w, s);
+        if (r == PI_OK && hipEventRecord(ev[0], s) != hipSuccess) r = fail(PI_EDEVICE, "event record");
+        if (r == PI_OK) r = raytrace_any(e, state, tau_buf, w, s);
+        if (r == PI_OK && hipEventRecord(ev[1], s) != hipSuccess) r = fail(PI_EDEVICE, "event record");
+        if (r == PI_OK && hipEventSynchronize(ev[1]) != hipSuccess) r = fail(PI_EDEVICE, "event sync");
+        float ms = 0.0f;
+        if (r == PI_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess)
+            r = fail(PI_EDEVICE, "event time");
+        if (r == PI_OK && (w == 0 || ms < best)) {
+            best = ms;
+            pick = w;
+        }
+    }
+    for (int i = 0; i < 3; ++i) (void)hipEventDestroy(ev[i]);
+    if (r != PI_OK) return r;
+    e.sweep = pick;
+    drop_graph(e);   // a graph captured before tuning holds the default tiles
+    return PI_OK;
+}
+
 pi_status engine_raytrace(Engine& e, int state, int tau_buf, hipStream_t s)
 {
-    return e.fp64() ? raytrace_t<double>(e, state, tau_buf, s) : raytrace_t<float>(e, state, tau_buf, s);
+    if (e.sweep < 0) {
+        pi_status r = engine_autotune(e, state, tau_buf, s);
+        if (r != PI_OK) return r;
+    }
+    return raytrace_any(e, state, tau_buf, e.sweep >= 0 ? e.sweep : SWEEP_DEFAULT, s);
 }
 
 pi_status engine_chem(Engine& e, bool dev_dt, double h, int tau_buf, int from, int to, hipStream_t s)

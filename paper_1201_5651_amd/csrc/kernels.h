@@ -12,9 +12,11 @@
 
 namespace pi {
 
-// Edge of the cubic tile of the raytrace wavefront (octant-local cells swept by
-// one workgroup, one thread per cell).
-constexpr int SWEEP_T = 8;
+// Edges of the cubic tiles of the raytrace wavefront (octant-local cells swept
+// by one workgroup, one thread per cell); an engine uses one of them, chosen
+// by timing both on its first raytrace.
+constexpr int SWEEP_T_SMALL = 4, SWEEP_T_LARGE = 8;
+constexpr int SWEEP_TILES[2] = { SWEEP_T_SMALL, SWEEP_T_LARGE };
 // Threads per workgroup of the micro-physics kernel.
 constexpr int CHEM_BLOCK = 256;
 // Threads per workgroup and largest number of workgroups per grid of the
@@ -67,11 +69,12 @@ struct BatchDev {
     long long* fix_list;     // mixed precision: (grid << 32) | cell, for the double re-solve
 };
 
-// One tile-diagonal stage of the raytrace of every grid: tiles[first ..
-// first + count) are (grid << 3 | octant, tx, ty, tz).
+// One tile-diagonal stage of the raytrace of every grid with tiles of edge
+// `tile` (SWEEP_T_SMALL or SWEEP_T_LARGE): tiles[first .. first + count) are
+// (grid << 3 | octant, tx, ty, tz).
 template <typename R>
 hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,
-                              int first, int count, hipStream_t s);
+                              int first, int count, int tile, hipStream_t s);
 // Micro-physics of every cell of every grid from state `from` on columns
 // `tau_buf` into state `to`, over h = hscale * (st->dt if dev_dt else 1).
 // With mixed, precision-sensitive cells are listed for launch_chem_fix.

@@ -36,9 +36,20 @@ template <int T> constexpr PlaneOrder<T> make_plane_order()
             }
     return o;
 }
-static_assert(SWEEP_T < 16, "tile coordinates are packed in 4 bits");
+static_assert(SWEEP_T_SMALL < 16 && SWEEP_T_LARGE < 16, "tile coordinates are packed in 4 bits");
 
-__constant__ PlaneOrder<SWEEP_T> c_plane_order = make_plane_order<SWEEP_T>();
+__constant__ PlaneOrder<SWEEP_T_SMALL> c_plane_order_small = make_plane_order<SWEEP_T_SMALL>();
+__constant__ PlaneOrder<SWEEP_T_LARGE> c_plane_order_large = make_plane_order<SWEEP_T_LARGE>();
+
+template <int T> __device__ __forceinline__ int plane_cell(int t);
+template <> __device__ __forceinline__ int plane_cell<SWEEP_T_SMALL>(int t)
+{
+    return c_plane_order_small.cell[t];
+}
+template <> __device__ __forceinline__ int plane_cell<SWEEP_T_LARGE>(int t)
+{
+    return c_plane_order_large.cell[t];
+}
 
 // Weighted upstream average of the short-characteristics interpolation:
 // sum w_i T_i / sum w_i with w_i = g_i (Mellema: divided by max(0.6, T_i)).
@@ -86,12 +97,12 @@ __device__ __forceinline__ double sc_average<double>(bool mellema, double g00, d
 // each carries T = tau_centre + (ds_C/2) kap, its depth at C's entry face, with
 // bilinear weights divided by max(0.6, T) (Mellema weighting).  Neighbours
 // across a source plane (octant-local index -1) get weight 0.
-template <typename R>
-__global__ void __launch_bounds__(SWEEP_T * SWEEP_T * SWEEP_T)
+template <typename R, int TT>
+__global__ void __launch_bounds__(TT * TT * TT)
 k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
         const int4* __restrict__ tiles, int first)
 {
-    constexpr int TX = SWEEP_T, TY = SWEEP_T, TZ = SWEEP_T;
+    constexpr int TX = TT, TY = TT, TZ = TT;
     constexpr int HX = TX + 1, HY = TY + 1, HZ = TZ + 1, NHALO = HX * HY * HZ;
     __shared__ R s_tc[NHALO];
     __shared__ R s_kap[NHALO];
@@ -122,8 +133,9 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
             if (hx == 0 || hy == 0 || hz == 0) {
                 const R ax = R(Lx) + R(0.5), ay = R(Ly) + R(0.5), az = R(Lz) + R(0.5);
                 const R da = (az >= ax && az >= ay) ? az : (ay >= ax ? ay : ax);
-                const R ds = r_sqrt(ax * ax + ay * ay + az * az) / da;
-                tc = tau[g] + R(0.5) * ds * kap;
+                const R hds = R(0.5) * r_sqrt(ax * ax + ay * ay + az * az) / da;
+                // the centre column exactly as the cell's own tile formed it
+                tc = r_fma(hds, kap, tau[g]);
             }
         }
         s_kap[q] = kap;
@@ -131,7 +143,7 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     }
     __syncthreads();
 
-    const int cl = c_plane_order.cell[threadIdx.x];
+    const int cl = plane_cell<TT>(threadIdx.x);
     const int lx = cl & 15, ly = (cl >> 4) & 15, lz = cl >> 8;
     const int L[3] = { X0 + lx, Y0 + ly, Z0 + lz };
     const bool active = L[0] < ex && L[1] < ey && L[2] < ez;
@@ -156,7 +168,7 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     const bool mellema = p.weights == 1;
     const int diag = lx + ly + lz;
 
-    const R own = hds * s_kap[self];   // the cell's half chord, entry face to centre
+    const R kself = s_kap[self];
     R tin = R(0);
     for (int s = 0; s < TX + TY + TZ - 2; ++s) {
         if (active && diag == s) {
@@ -167,7 +179,7 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
                 const R T11 = s_tc[n11] + hds * s_kap[n11];
                 tin = sc_average<R>(mellema, g00, g10, g01, g11, T00, T10, T01, T11);
             }
-            s_tc[self] = tin + own;
+            s_tc[self] = r_fma(hds, kself, tin);   // entry face to centre
         }
         __syncthreads();
     }
@@ -465,11 +477,19 @@ k_energy(int64_t n, const R* __restrict__ nH, const R* __restrict__ x, R* __rest
 // ---------------------------------------------------------------- launchers
 template <typename R>
 hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,
-                              int first, int count, hipStream_t s)
+                              int first, int count, int tile, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_sweep<R>), dim3(count), dim3(SWEEP_T * SWEEP_T * SWEEP_T), 0, s, grids,
-                       state, tau_buf, tiles, first);
+    if (tile == SWEEP_T_SMALL)
+        hipLaunchKernelGGL((k_sweep<R, SWEEP_T_SMALL>), dim3(count),
+                           dim3(SWEEP_T_SMALL * SWEEP_T_SMALL * SWEEP_T_SMALL), 0, s, grids, state,
+                           tau_buf, tiles, first);
+    else if (tile == SWEEP_T_LARGE)
+        hipLaunchKernelGGL((k_sweep<R, SWEEP_T_LARGE>), dim3(count),
+                           dim3(SWEEP_T_LARGE * SWEEP_T_LARGE * SWEEP_T_LARGE), 0, s, grids, state,
+                           tau_buf, tiles, first);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -523,7 +543,7 @@ hipError_t launch_energy(int64_t n, const R* nH, const R* x, R* E, double T0, hi
 
 #define PI_INSTANTIATE(R)                                                                          \
     template hipError_t launch_sweep_stage<R>(const GridDev<R>*, int, int, const int4*, int, int,  \
-                                              hipStream_t);                                        \
+                                              int, hipStream_t);                                   \
     template hipError_t launch_chem<R>(const GridDev<R>*, const BatchDev&, int, int, int, int,    \
                                        bool, double, unsigned long long*, bool, hipStream_t);      \
     template hipError_t launch_dtdiag<R>(const GridDev<R>*, const BatchDev&, int, double,         \

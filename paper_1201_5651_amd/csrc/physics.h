@@ -116,6 +116,17 @@ template <> PI_HD __forceinline__ float r_rcp<float>(float v) { return __builtin
 #else
 template <> PI_HD __forceinline__ float r_rcp<float>(float v) { return 1.0f / v; }
 #endif
+// Fused multiply-add with one rounding, wherever a value must come out the
+// same from every code path that forms it.
+template <typename R> PI_HD __forceinline__ R r_fma(R a, R b, R c);
+template <> PI_HD __forceinline__ double r_fma<double>(double a, double b, double c)
+{
+    return fma(a, b, c);
+}
+template <> PI_HD __forceinline__ float r_fma<float>(float a, float b, float c)
+{
+    return fmaf(a, b, c);
+}
 template <typename R> PI_HD __forceinline__ R r_abs(R v) { return v < R(0) ? -v : v; }
 template <typename R> PI_HD __forceinline__ R r_max(R a, R b) { return a > b ? a : b; }
 template <typename R> PI_HD __forceinline__ R r_min(R a, R b) { return a < b ? a : b; }

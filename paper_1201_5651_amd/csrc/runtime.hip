@@ -280,6 +280,50 @@ pi_status pi_diagnostics(pi_grid* g, double* out, void* stream)
     return r;
 }
 
+namespace {
+pi_status set_tile(Engine& e, int edge)
+{
+    if (edge == 0) {
+        e.sweep = -1;
+    } else {
+        int w = -1;
+        for (int k = 0; k < 2; ++k)
+            if (SWEEP_TILES[k] == edge) w = k;
+        if (w < 0) return fail(PI_EINVAL, "raytrace tile edge must be 0, 4 or 8");
+        e.sweep = w;
+    }
+    engine_build(e, e.grids);   // drops a graph captured with the old tiles
+    return PI_OK;
+}
+int get_tile(const Engine& e) { return e.sweep >= 0 ? SWEEP_TILES[e.sweep] : 0; }
+}  // namespace
+
+pi_status pi_set_raytrace_tile(pi_grid* g, int edge)
+{
+    if (!g) return fail(PI_EINVAL, "null grid");
+    return set_tile(g->e, edge);
+}
+
+pi_status pi_get_raytrace_tile(pi_grid* g, int* edge)
+{
+    if (!g || !edge) return fail(PI_EINVAL, "null argument");
+    *edge = get_tile(g->e);
+    return PI_OK;
+}
+
+pi_status pi_batch_set_raytrace_tile(pi_batch* b, int edge)
+{
+    if (!b) return fail(PI_EINVAL, "null batch");
+    return set_tile(b->e, edge);
+}
+
+pi_status pi_batch_get_raytrace_tile(pi_batch* b, int* edge)
+{
+    if (!b || !edge) return fail(PI_EINVAL, "null argument");
+    *edge = get_tile(b->e);
+    return PI_OK;
+}
+
 // ------------------------------------------------------------------ batch
 pi_status pi_batch_create(int ngrids, const pi_grid_desc* descs, const pi_fields* fields,
                           pi_batch** out)

@@ -183,6 +183,7 @@ pi_status pi_server::start(Request& r)
     Engine one;
     one.precision = d.precision;
     one.table_cache = &tables;
+    one.sweep = engine.sweep >= 0 ? engine.sweep : 1;   // no tuning for a one-off raytrace
     s = engine_build(one, { &r.grid });
     if (s == PI_OK) s = engine_init_energy(one, 0, r.T0, PI_BUF_N, stream);
     if (s == PI_OK) s = engine_raytrace(one, PI_BUF_N, PI_BUF_N, stream);
@@ -295,6 +296,8 @@ void pi_server::run()
         if (changed || engine.ngrids() != (int)grids.size()) {
             s = engine_build(engine, grids);
             rebuilds++;
+            // first batch: choose the raytrace tiles (recomputes the current columns)
+            if (s == PI_OK && engine.sweep < 0) s = engine_autotune(engine, PI_BUF_N, PI_BUF_N, stream);
         }
         int64_t cells = 0;
         for (GridHost* g : grids) cells += g->ncell;

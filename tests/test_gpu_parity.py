@@ -53,6 +53,28 @@ def test_raytrace_parity_fp64(oracle_lib, shape, src, weights):
     g.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_raytrace_tile_edges_give_identical_columns(precision):
+    """Tiling changes the order of the sweep, not the arithmetic of any cell:
+    4^3 and 8^3 tiles give bitwise equal columns, and tuning settles on one."""
+    spec = _spec((19, 22, 17), (7, 15, 9))
+    rng = np.random.default_rng(21)
+    g = binding.Grid(spec, precision=precision)
+    assert g.raytrace_tile == 0
+    g.load(rng.uniform(0.2, 5.0, spec.shape), rng.uniform(0.0, 1.0, spec.shape))
+    assert g.raytrace_tile in (4, 8)
+    cols = {}
+    for edge in (4, 8):
+        g.raytrace_tile = edge
+        g.tau.zero_()
+        g.raytrace()
+        cols[edge] = to_np(g.tau)
+    assert np.array_equal(cols[4], cols[8])
+    with pytest.raises(binding.PiError):
+        g.raytrace_tile = 5
+    g.close()
+
+
 @pytest.mark.parametrize("shape,src", SHAPES[:4])
 def test_raytrace_parity_fp32(oracle_lib, shape, src):
     rng = np.random.default_rng(7)
