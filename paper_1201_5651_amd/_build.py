@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpi.so")
 SOURCES = ["kernels.hip", "engine.hip", "runtime.hip", "server.hip"]
-HEADERS = ["physics.h", "kernels.h", "engine.h"]
+HEADERS = ["physics.h", "kernels.h", "engine.h", "arena.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

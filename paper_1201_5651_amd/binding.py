@@ -263,6 +263,9 @@ class Grid:
     def raytrace(self, state=PI_BUF_N, tau_buf=PI_BUF_N):
         check(lib().pi_raytrace(self._h, state, tau_buf, self._stream()))
 
+    def set_time(self, t: float, nsteps: int = 0):
+        check(lib().pi_set_time(self._h, float(t), int(nsteps), self._stream()))
+
     def chem_step(self, h: float, tau_buf=PI_BUF_N, from_state=PI_BUF_N, to_state=PI_BUF_N,
                   use_device_dt: bool = False):
         check(lib().pi_chem_step(self._h, int(use_device_dt), float(h), tau_buf, from_state,
@@ -399,9 +402,11 @@ class Batch:
         check(lib().pi_batch_state(self._h, t, k, dt, self._stream()))
         return list(t), list(k), list(dt)
 
-    def diagnostics(self):
+    def diagnostics(self, raise_on_nan: bool = True):
         out = (C.c_double * (PI_NDIAG * self.n))()
-        check(lib().pi_batch_diagnostics(self._h, out, self._stream()))
+        st = lib().pi_batch_diagnostics(self._h, out, self._stream())
+        if st != PI_OK and (raise_on_nan or st != PI_ENAN):
+            check(st)
         keys = ("n_ion", "v_ion", "r_ion", "photo_rate", "recomb_rate", "nonfinite", "octants", "t")
         return [dict(zip(keys, list(out)[i * PI_NDIAG:(i + 1) * PI_NDIAG])) for i in range(self.n)]
 

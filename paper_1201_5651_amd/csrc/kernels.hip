@@ -259,17 +259,24 @@ __device__ __forceinline__ Params<R> table_to_lds(const Params<R>& p, DevTable<R
     return pl;
 }
 
-// Micro-integration of cell q in arithmetic C from storage S.
+// Micro-integration of cell q in arithmetic C from storage S.  A non-finite
+// input stays non-finite (the bound projections of the solver would otherwise
+// turn it into a valid-looking state), so the grid's diagnostics report it.
 template <typename C, typename S>
 __device__ __forceinline__ void chem_cell(const Params<C>& p, int q, const S* __restrict__ nH,
                                           const S* x0, const S* E0, const S* __restrict__ tau,
                                           double hd, C& x, C& E, Work& w)
 {
-    const int i = q % p.nx, j = (q / p.nx) % p.ny, k = q / (p.nx * p.ny);
-    const CellGeom<C> cg = cell_geom(p, i, j, k);
-    const Env<C> e = make_env(p, C(nH[q]), cg, C(tau[q]));
     x = C(x0[q]);
     E = E0 ? C(E0[q]) : C(0);
+    const C n = C(nH[q]), tq = C(tau[q]);
+    if (!(isfinite(x) && isfinite(E) && isfinite(n) && isfinite(tq))) {
+        x = E = C(__builtin_nan(""));
+        return;
+    }
+    const int i = q % p.nx, j = (q / p.nx) % p.ny, k = q / (p.nx * p.ny);
+    const CellGeom<C> cg = cell_geom(p, i, j, k);
+    const Env<C> e = make_env(p, n, cg, tq);
     micro(p, e, C(hd), x, E, w);
 }
 

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/pi.h"
+#include "arena.h"
 #include "engine.h"
 
 using namespace pi;
@@ -30,20 +31,18 @@ double seconds(Clock::time_point a, Clock::time_point b)
     return std::chrono::duration<double>(b - a).count();
 }
 
-// First-fit allocator over one device allocation (offsets in bytes, 256-byte
-// granules).  Host bookkeeping only; the device block is allocated once.
+// One device allocation carved by an ArenaMap.
 struct Arena {
     char* base = nullptr;
     size_t size = 0;
-    std::map<size_t, size_t> free_;   // offset -> length
-    size_t used = 0;
+    ArenaMap map;
 
-    static size_t round(size_t n) { return (n + 255) & ~size_t(255); }
+    static size_t round(size_t n) { return ArenaMap::round(n); }
     bool init(size_t bytes)
     {
-        size = bytes & ~size_t(255);
+        map.init(bytes);
+        size = map.size;
         if (size == 0 || hipMalloc(reinterpret_cast<void**>(&base), size) != hipSuccess) return false;
-        free_[0] = size;
         return true;
     }
     void release()
@@ -53,36 +52,10 @@ struct Arena {
     }
     void* alloc(size_t n)
     {
-        n = round(n);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < n) continue;
-            const size_t off = it->first, len = it->second;
-            free_.erase(it);
-            if (len > n) free_[off + n] = len - n;
-            used += n;
-            return base + off;
-        }
-        return nullptr;
+        size_t off = 0;
+        return map.alloc(n, &off) ? base + off : nullptr;
     }
-    void free(void* p, size_t n)
-    {
-        n = round(n);
-        size_t off = static_cast<char*>(p) - base;
-        used -= n;
-        auto next = free_.lower_bound(off);
-        if (next != free_.end() && off + n == next->first) {
-            n += next->second;
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == off) {
-                prev->second += n;
-                return;
-            }
-        }
-        free_[off] = n;
-    }
+    void free(void* p, size_t n) { map.release(static_cast<char*>(p) - base, n); }
 };
 
 struct Request {
@@ -100,6 +73,7 @@ struct Request {
     bool active = false;
     bool was_admitted = false;
     bool cancel = false;
+    bool nonfinite = false;
     // results
     std::vector<double> x_out, T_out;
     double t = 0;
@@ -235,7 +209,7 @@ void pi_server::retire(Request& r, bool ok, const std::string& why)
         if (!good) r.error = "result download";
         else done++;
     } else {
-        r.status = r.cancel ? PI_ECANCELLED : PI_EDEVICE;
+        r.status = r.cancel ? PI_ECANCELLED : (r.nonfinite ? PI_ENAN : PI_EDEVICE);
         r.error = why;
     }
     r.completed = Clock::now();
@@ -326,6 +300,7 @@ void pi_server::run()
             if (r.cancel) {
                 retire(r, false, "cancelled");
             } else if (st[g].diag[5] > 0) {
+                r.nonfinite = true;
                 retire(r, false, "non-finite values in the grid state");
             } else if (st[g].t >= r.t_end) {
                 retire(r, true, "");
@@ -458,7 +433,7 @@ pi_status pi_server_stats(pi_server* s, double* out)
     out[3] = (double)s->steps;
     out[4] = (double)s->active.size();
     out[5] = (double)s->queue.size();
-    out[6] = (double)s->arena.used;
+    out[6] = (double)s->arena.map.used;
     out[7] = (double)s->rebuilds;
     return PI_OK;
 }

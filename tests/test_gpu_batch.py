@@ -130,3 +130,60 @@ def test_batch_of_generated_uneven_grids_runs_and_conserves():
         assert c["nonfinite"] == 0
         assert c["v_ion"] > a["v_ion"]
     b.close()
+
+
+def test_nan_in_one_grid_stays_in_that_grid():
+    """A non-finite value planted in one grid's state is reported for that grid
+    only; the other grids of the batch advance bit for bit as they do alone."""
+    specs = _specs("fp64")
+    nHs = _densities(specs)
+    alone = {}
+    for i in (0, 2):
+        g = binding.Grid(specs[i])
+        g.load(nHs[i], 1.0, T0=specs[i].T0)
+        for _ in range(5):
+            g.step_o2(specs[i].t_end)
+        alone[i] = to_np(g.x)
+        g.close()
+    b = binding.Batch(specs)
+    b.load(nHs, T0s=[s.T0 for s in specs], t_end=[s.t_end for s in specs])
+    b.grids[1].x[3, 4, 5] = float("nan")
+    for _ in range(5):
+        b.step_o2()
+    d = b.diagnostics(raise_on_nan=False)
+    assert d[1]["nonfinite"] > 0
+    assert d[0]["nonfinite"] == 0 and d[2]["nonfinite"] == 0
+    for i in (0, 2):
+        assert np.array_equal(to_np(b.grids[i].x), alone[i])
+    with pytest.raises(binding.PiError) as e:
+        b.diagnostics()
+    assert e.value.status == binding.PI_ENAN
+    b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_checkpoint_and_resume_is_bitwise(precision):
+    """The state is the caller's fields plus the clock: copying them into a new
+    grid and setting its clock continues the run bit for bit."""
+    spec = _specs(precision)[0]
+    nH = _densities([spec])[0]
+    g = binding.Grid(spec, precision=precision)
+    g.load(nH, 1.0, T0=spec.T0)
+    for _ in range(5):
+        g.step_o2(spec.t_end)
+    t, n, _ = g.state()
+    saved = {k: getattr(g, k).clone() for k in ("nH", "x", "E", "tau")}
+    for _ in range(4):
+        g.step_o2(spec.t_end)
+    want_x, want_E, want_t = to_np(g.x), to_np(g.E), g.state()[0]
+    g.close()
+    r = binding.Grid(spec, precision=precision)
+    for k, v in saved.items():
+        getattr(r, k).copy_(v)
+    r.set_time(t, n)
+    for _ in range(4):
+        r.step_o2(spec.t_end)
+    assert r.state()[0] == want_t
+    assert np.array_equal(to_np(r.x), want_x)
+    assert np.array_equal(to_np(r.E), want_E)
+    r.close()

@@ -1,0 +1,81 @@
+"""Parity at the benchmark's full size, in the launch configuration bench.py
+times: the 256^3 clumpy medium in mixed precision, advanced on the GPU to a
+state with an ionisation front, then checked against the oracle on the same
+(float) state -- the raytrace on every cell, the timestep minimum over every
+cell, and one micro-physics update on a sample of cells the oracle integrates
+one by one."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1201_5651_amd import binding, synth
+from gpu_util import rel, rel_x, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def state256():
+    spec = synth.cfg3(n=256)
+    nH = synth.density(spec)
+    g = binding.Grid(spec, precision="mixed")
+    g.load(nH, 1.0, T0=spec.T0)
+    t_pre = 0.02 * spec.t_rec
+    g.run(t_pre, check_every=16)
+    yield spec, g, oracle.Problem.from_spec(spec)
+    g.close()
+
+
+def test_raytrace_full_size(oracle_lib, state256):
+    spec, g, pb = state256
+    g.raytrace()
+    nH, x = np.ascontiguousarray(to_np(g.nH)), np.ascontiguousarray(to_np(g.x))
+    assert (x < 0.5).sum() > 1000   # a front exists
+    want = pb.raytrace(nH, x)
+    got = to_np(g.tau)
+    assert np.all((got == 0) == (want == 0))
+    m = want > 1e-3
+    assert np.max(rel(got[m], want[m])) < 1e-4
+
+
+def test_timestep_full_size(oracle_lib, state256):
+    spec, g, pb = state256
+    g.raytrace()
+    nH, x, E, tau = (np.ascontiguousarray(to_np(a)) for a in (g.nH, g.x, g.E, g.tau))
+    want = pb.timestep(nH, x, E, tau)
+    # one A2 step computes eq. (4) on this state and records the dt it took
+    t, _, _ = g.state()
+    g.step_o1(t + 1e3 * want)
+    _, _, got = g.state()
+    assert got == pytest.approx(want, rel=1e-5)
+
+
+def test_chem_full_size_sampled(oracle_lib, state256):
+    spec, g, pb = state256
+    g.raytrace()
+    nH, x, E, tau = (np.ascontiguousarray(to_np(a)) for a in (g.nH, g.x, g.E, g.tau))
+    h = 0.5 * pb.timestep(nH, x, E, tau)
+    g.chem_step(h, binding.PI_BUF_N, binding.PI_BUF_N, binding.PI_BUF_HALF)
+    xg, Eg = to_np(g.x_half).ravel(), to_np(g.E_half).ravel()
+    rng = np.random.default_rng(256)
+    front = np.flatnonzero((x.ravel() > 1e-3) & (x.ravel() < 0.999))
+    cells = np.concatenate([rng.choice(spec.ncells, 1500, replace=False),
+                            rng.choice(front, min(1500, front.size), replace=False)])
+    errs, n_ill = [], 0
+    for c in cells:
+        geo, ell = pb.cell_env(int(c))
+        args = (nH.flat[c], geo, ell, tau.flat[c], x.flat[c], E.flat[c], h)
+        xw, Ew = pb.micro_cell(*args)
+        xp, _ = pb.micro_cell(nH.flat[c], geo, ell, tau.flat[c] * (1 + 1e-12), x.flat[c],
+                              E.flat[c], h)
+        if rel_x(np.array([xp]), np.array([xw]))[0] > 1e-10:
+            n_ill += 1
+            continue
+        Tg = 2 * Eg[c] / (3 * 1.380649e-16 * nH.flat[c] * (2 - xg[c]))
+        Tw = 2 * Ew / (3 * 1.380649e-16 * nH.flat[c] * (2 - xw))
+        errs.append(max(rel_x(np.array([xg[c]]), np.array([xw]))[0], abs(Tg / Tw - 1)))
+    errs = np.array(errs)
+    print("full-size chem: %d cells, %d ill-conditioned, max err %.3g, p99 %.3g"
+          % (cells.size, n_ill, errs.max(), np.quantile(errs, 0.99)))
+    assert n_ill < 0.05 * cells.size
+    assert errs.max() < 1e-4
