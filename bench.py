@@ -264,6 +264,8 @@ def main() -> int:
     ap.add_argument("--serve-trec", type=float, default=0.05)
     ap.add_argument("--serve-max-active", type=int, default=64)
     ap.add_argument("--serve-steps-per-tick", type=int, default=4)
+    ap.add_argument("--time-tiles", action="store_true",
+                    help="also time one raytrace with each tile edge (in config.raytrace_ms_by_tile)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (a known-size "
                          "reference for hardware traffic counters)")
@@ -348,6 +350,21 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    tiles_ms = None
+    if args.time_tiles:
+        tuned = g.raytrace_tile
+        tiles_ms = {}
+        for edge in (4, 8, 16):
+            g.raytrace_tile = edge
+            g.raytrace()
+            a, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(10):
+                g.raytrace()
+            b2.record(stream)
+            torch.cuda.synchronize()
+            tiles_ms[edge] = a.elapsed_time(b2) / 10
+        g.raytrace_tile = tuned
     diag = g.diagnostics()
     t_now, n_now, _ = g.state()
     work_phase = g.work_counters(reset=True)   # the phase-timed steps only
@@ -404,6 +421,7 @@ def main() -> int:
             "t_start_trec": t_start / spec.t_rec, "t_end_trec": t_now / spec.t_rec,
             "r_ion_cells": diag["r_ion"] / spec.dx, "n_sub": spec.n_sub,
             "raytrace_tile": g.raytrace_tile,
+            "raytrace_ms_by_tile": tiles_ms,
             "substeps_per_cell_update": (work_phase["accepted"] + work_phase["rejected"])
             / (spec.ncells * args.phase_steps),
             "rejected_frac": work_phase["rejected"]

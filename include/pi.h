@@ -280,8 +280,8 @@ pi_status pi_server_destroy(pi_server* server);
  * cross-section sigma0 (nu0/nu)^3.  Nodes: 0, then 63 log-spaced in [1e-4, 1e4]. */
 pi_status pi_table_build(double T_bb, double Q, double* out);
 
-/* Raytrace tile edge: 4 or 8 (cells of the cubic tile one workgroup sweeps),
- * or 0 to time both on the next raytrace outside graph capture and keep the
+/* Raytrace tile edge: 4, 8 or 16 (cells of the cubic tile one workgroup
+ * sweeps), or 0 to time them all on the next raytrace outside graph capture and keep the
  * faster (the default; that first raytrace then SYNCHRONISES its stream).  The
  * edge does not change any result: every cell's interpolation is the same.
  * pi_get_raytrace_tile returns 0 while untuned.  PI_EINVAL for other edges. */

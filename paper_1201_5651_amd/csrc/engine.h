@@ -35,7 +35,7 @@ struct GridHost {
     double cell_vol = 0.0;
     int64_t ncell = 0;
     // per tile edge (SWEEP_TILES), per tile diagonal: (octant, tx, ty, tz)
-    std::vector<std::vector<int4>> tiles[2];
+    std::vector<std::vector<int4>> tiles[NSWEEP];
 };
 
 pi_status grid_host_init(GridHost& h, const pi_grid_desc& d, const pi_fields& f);
@@ -50,9 +50,9 @@ struct Engine {
     size_t first_cap = 0;
     int chem_blocks = 0, dt_blocks = 0;
     // raytrace schedules, one per tile edge of SWEEP_TILES
-    int4* tiles[2] = { nullptr, nullptr };
-    size_t tiles_cap[2] = { 0, 0 };
-    std::vector<int> stage_first[2], stage_count[2];
+    int4* tiles[NSWEEP] = {};
+    size_t tiles_cap[NSWEEP] = {};
+    std::vector<int> stage_first[NSWEEP], stage_count[NSWEEP];
     int sweep = -1;                  // index into SWEEP_TILES; -1 until tuned
     unsigned int* fix_n = nullptr;
     long long* fix_list = nullptr;

@@ -288,7 +288,7 @@ pi_status grid_host_init(GridHost& h, const pi_grid_desc& d, const pi_fields& f)
         return fail(PI_ENOMEM, "partials allocation");
     }
     // tile schedules: every octant's tiles, grouped by tile diagonal tx+ty+tz
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < NSWEEP; ++w) {
         const int T = SWEEP_TILES[w];
         h.tiles[w].clear();
         for (int o = 0; o < 8; ++o) {
@@ -346,7 +346,7 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
     }
     HIP_OR(hipMemcpy(e.first, first.data(), fb, hipMemcpyHostToDevice), "launch table upload");
     // combined tile schedules: stage k holds tile diagonal k of every grid
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < NSWEEP; ++w) {
         e.stage_first[w].clear();
         e.stage_count[w].clear();
         std::vector<int4> flat;
@@ -401,17 +401,20 @@ void engine_free(Engine& e)
     drop_graph(e);
     if (e.cap) (void)hipStreamDestroy(e.cap);
     e.cap = nullptr;
-    for (void* p : { e.gdev, (void*)e.first, (void*)e.tiles[0], (void*)e.tiles[1], (void*)e.fix_n,
-                     (void*)e.fix_list, (void*)e.work })
+    for (void* p : { e.gdev, (void*)e.first, (void*)e.fix_n, (void*)e.fix_list, (void*)e.work })
         if (p) (void)hipFree(p);
+    for (int w = 0; w < NSWEEP; ++w) {
+        if (e.tiles[w]) (void)hipFree(e.tiles[w]);
+        e.tiles[w] = nullptr;
+        e.tiles_cap[w] = 0;
+    }
     free_tables(e.tables);
     e.gdev = nullptr;
     e.first = nullptr;
-    e.tiles[0] = e.tiles[1] = nullptr;
     e.fix_n = nullptr;
     e.fix_list = nullptr;
     e.work = nullptr;
-    e.gdev_cap = e.first_cap = e.tiles_cap[0] = e.tiles_cap[1] = e.fix_cap = 0;
+    e.gdev_cap = e.first_cap = e.fix_cap = 0;
 }
 
 void free_tables(std::vector<Engine::Table>& tables)
@@ -433,7 +436,7 @@ pi_status engine_autotune(Engine& e, int state, int tau_buf, hipStream_t s)
     float best = 0.0f;
     int pick = SWEEP_DEFAULT;
     pi_status r = PI_OK;
-    for (int w = 0; w < 2 && r == PI_OK; ++w) {
+    for (int w = 0; w < NSWEEP && r == PI_OK; ++w) {
         // the second of two runs (the first warms the caches)
         r = raytrace_any(e, state, tau_buf, w, s);
         if (r == PI_OK && hipEventRecord(ev[0], s) != hipSuccess) r = fail(PI_EDEVICE, "event record");

@@ -13,10 +13,11 @@
 namespace pi {
 
 // Edges of the cubic tiles of the raytrace wavefront (octant-local cells swept
-// by one workgroup, one thread per cell); an engine uses one of them, chosen
-// by timing both on its first raytrace.
-constexpr int SWEEP_T_SMALL = 4, SWEEP_T_LARGE = 8;
-constexpr int SWEEP_TILES[2] = { SWEEP_T_SMALL, SWEEP_T_LARGE };
+// by one workgroup); an engine uses one of them, chosen by timing them all on
+// its first raytrace.
+constexpr int NSWEEP = 3;
+constexpr int SWEEP_TILES[NSWEEP] = { 4, 8, 16 };
+constexpr int SWEEP_T_LARGEST = 16;
 // Threads per workgroup of the micro-physics kernel.
 constexpr int CHEM_BLOCK = 256;
 // Threads per workgroup and largest number of workgroups per grid of the
@@ -70,7 +71,7 @@ struct BatchDev {
 };
 
 // One tile-diagonal stage of the raytrace of every grid with tiles of edge
-// `tile` (SWEEP_T_SMALL or SWEEP_T_LARGE): tiles[first .. first + count) are
+// `tile` (one of SWEEP_TILES): tiles[first .. first + count) are
 // (grid << 3 | octant, tx, ty, tz).
 template <typename R>
 hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,

@@ -19,7 +19,7 @@ namespace pi {
 // Thread -> cell map of a T^3 tile in diagonal-plane order (lx + ly + lz
 // ascending), built at compile time: the cells of one plane are consecutive
 // threads, so a plane occupies one or two wavefronts instead of one lane in
-// each of T wavefronts.  Packed as lx | ly << 4 | lz << 8.
+// each of T wavefronts.  Packed as lx | ly << 5 | lz << 10.
 template <int T> struct PlaneOrder {
     unsigned short cell[T * T * T];
 };
@@ -32,23 +32,28 @@ template <int T> constexpr PlaneOrder<T> make_plane_order()
         for (int lz = 0; lz < T; ++lz)
             for (int ly = 0; ly < T; ++ly) {
                 const int lx = s - ly - lz;
-                if (lx >= 0 && lx < T) o.cell[q++] = (unsigned short)(lx | ly << 4 | lz << 8);
+                if (lx >= 0 && lx < T) o.cell[q++] = (unsigned short)(lx | ly << 5 | lz << 10);
             }
     return o;
 }
-static_assert(SWEEP_T_SMALL < 16 && SWEEP_T_LARGE < 16, "tile coordinates are packed in 4 bits");
+static_assert(SWEEP_T_LARGEST <= 32, "tile coordinates are packed in 5 bits");
 
-__constant__ PlaneOrder<SWEEP_T_SMALL> c_plane_order_small = make_plane_order<SWEEP_T_SMALL>();
-__constant__ PlaneOrder<SWEEP_T_LARGE> c_plane_order_large = make_plane_order<SWEEP_T_LARGE>();
+__constant__ PlaneOrder<SWEEP_TILES[0]> c_plane_order_0 = make_plane_order<SWEEP_TILES[0]>();
+__constant__ PlaneOrder<SWEEP_TILES[1]> c_plane_order_1 = make_plane_order<SWEEP_TILES[1]>();
+__constant__ PlaneOrder<SWEEP_TILES[2]> c_plane_order_2 = make_plane_order<SWEEP_TILES[2]>();
 
 template <int T> __device__ __forceinline__ int plane_cell(int t);
-template <> __device__ __forceinline__ int plane_cell<SWEEP_T_SMALL>(int t)
+template <> __device__ __forceinline__ int plane_cell<SWEEP_TILES[0]>(int t)
 {
-    return c_plane_order_small.cell[t];
+    return c_plane_order_0.cell[t];
 }
-template <> __device__ __forceinline__ int plane_cell<SWEEP_T_LARGE>(int t)
+template <> __device__ __forceinline__ int plane_cell<SWEEP_TILES[1]>(int t)
 {
-    return c_plane_order_large.cell[t];
+    return c_plane_order_1.cell[t];
+}
+template <> __device__ __forceinline__ int plane_cell<SWEEP_TILES[2]>(int t)
+{
+    return c_plane_order_2.cell[t];
 }
 
 // Weighted upstream average of the short-characteristics interpolation:
@@ -97,13 +102,25 @@ __device__ __forceinline__ double sc_average<double>(bool mellema, double g00, d
 // each carries T = tau_centre + (ds_C/2) kap, its depth at C's entry face, with
 // bilinear weights divided by max(0.6, T) (Mellema weighting).  Neighbours
 // across a source plane (octant-local index -1) get weight 0.
+// Threads of the sweep workgroup for tile edge TT: one per cell up to 1024,
+// then several cells per thread (consecutive planes are whole thread ranges,
+// and a plane never exceeds the thread count, so a thread owns at most one
+// cell of any plane).
+template <int TT> struct SweepShape {
+    static constexpr int CELLS = TT * TT * TT;
+    static constexpr int THREADS = CELLS < 1024 ? CELLS : 1024;
+    static constexpr int CPT = CELLS / THREADS;
+};
+
 template <typename R, int TT>
-__global__ void __launch_bounds__(TT * TT * TT)
+__global__ void __launch_bounds__(SweepShape<TT>::THREADS)
 k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
         const int4* __restrict__ tiles, int first)
 {
     constexpr int TX = TT, TY = TT, TZ = TT;
+    constexpr int NT = SweepShape<TT>::THREADS, CPT = SweepShape<TT>::CPT;
     constexpr int HX = TX + 1, HY = TY + 1, HZ = TZ + 1, NHALO = HX * HY * HZ;
+    static_assert(NHALO >= TX * TY * TZ, "the output reuses the halo buffer");
     __shared__ R s_tc[NHALO];
     __shared__ R s_kap[NHALO];
 
@@ -120,7 +137,7 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     const int ez = pz ? p.nz - p.sz : p.sz;
     const int X0 = tl.y * TX, Y0 = tl.z * TY, Z0 = tl.w * TZ;
 
-    for (int q = threadIdx.x; q < NHALO; q += TX * TY * TZ) {
+    for (int q = threadIdx.x; q < NHALO; q += NT) {
         const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
         const int Lx = X0 + hx - 1, Ly = Y0 + hy - 1, Lz = Z0 + hz - 1;
         R kap = R(0), tc = R(0);
@@ -143,52 +160,66 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     }
     __syncthreads();
 
-    const int cl = plane_cell<TT>(threadIdx.x);
-    const int lx = cl & 15, ly = (cl >> 4) & 15, lz = cl >> 8;
-    const int L[3] = { X0 + lx, Y0 + ly, Z0 + lz };
-    const bool active = L[0] < ex && L[1] < ey && L[2] < ez;
-    const R ad[3] = { R(L[0]) + R(0.5), R(L[1]) + R(0.5), R(L[2]) + R(0.5) };
-    const int a = (ad[2] >= ad[0] && ad[2] >= ad[1]) ? 2 : (ad[1] >= ad[0] ? 1 : 0);
-    const int b = a == 2 ? 0 : a + 1;
-    const int c = a == 0 ? 2 : a - 1;
-    const int st[3] = { 1, HX, HX * HY };
-    const int self = (lz + 1) * HX * HY + (ly + 1) * HX + (lx + 1);
-    const int n00 = self - st[a];
-    const int n10 = n00 - st[b];
-    const int n01 = n00 - st[c];
-    const int n11 = n10 - st[c];
-    const R fb = ad[b] / ad[a], fc = ad[c] / ad[a];
-    const bool vb = L[b] >= 1, vc = L[c] >= 1;
-    const R g00 = (R(1) - fb) * (R(1) - fc);
-    const R g10 = vb ? fb * (R(1) - fc) : R(0);
-    const R g01 = vc ? (R(1) - fb) * fc : R(0);
-    const R g11 = (vb && vc) ? fb * fc : R(0);
-    const R hds = R(0.5) * r_sqrt(ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2]) / ad[a];
-    const bool corner = L[a] == 0;
+    // geometry of the thread's cells (cell k: plane-order index threadIdx.x + k NT)
     const bool mellema = p.weights == 1;
-    const int diag = lx + ly + lz;
+    int self[CPT], n00[CPT], n10[CPT], n01[CPT], n11[CPT], diag[CPT], nat[CPT];
+    bool active[CPT], corner[CPT];
+    R g00[CPT], g10[CPT], g01[CPT], g11[CPT], hds[CPT], kself[CPT], tin[CPT];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+        const int cl = plane_cell<TT>(threadIdx.x + k * NT);
+        const int lx = cl & 31, ly = (cl >> 5) & 31, lz = cl >> 10;
+        const int L[3] = { X0 + lx, Y0 + ly, Z0 + lz };
+        active[k] = L[0] < ex && L[1] < ey && L[2] < ez;
+        const R ad[3] = { R(L[0]) + R(0.5), R(L[1]) + R(0.5), R(L[2]) + R(0.5) };
+        const int a = (ad[2] >= ad[0] && ad[2] >= ad[1]) ? 2 : (ad[1] >= ad[0] ? 1 : 0);
+        const int b = a == 2 ? 0 : a + 1;
+        const int c = a == 0 ? 2 : a - 1;
+        const int st[3] = { 1, HX, HX * HY };
+        self[k] = (lz + 1) * HX * HY + (ly + 1) * HX + (lx + 1);
+        n00[k] = self[k] - st[a];
+        n10[k] = n00[k] - st[b];
+        n01[k] = n00[k] - st[c];
+        n11[k] = n10[k] - st[c];
+        // exact quotients: a tie of axes gives exactly 1 (zero weights stay zero)
+        const R fb = ad[b] / ad[a], fc = ad[c] / ad[a];
+        const bool vb = L[b] >= 1, vc = L[c] >= 1;
+        g00[k] = (R(1) - fb) * (R(1) - fc);
+        g10[k] = vb ? fb * (R(1) - fc) : R(0);
+        g01[k] = vc ? (R(1) - fb) * fc : R(0);
+        g11[k] = (vb && vc) ? fb * fc : R(0);
+        hds[k] = R(0.5) * r_sqrt(ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2]) / ad[a];
+        corner[k] = L[a] == 0;
+        diag[k] = lx + ly + lz;
+        nat[k] = lx + TX * (ly + TY * lz);
+        kself[k] = s_kap[self[k]];
+        tin[k] = R(0);
+    }
 
-    const R kself = s_kap[self];
-    R tin = R(0);
     for (int s = 0; s < TX + TY + TZ - 2; ++s) {
-        if (active && diag == s) {
-            if (!corner) {
-                const R T00 = s_tc[n00] + hds * s_kap[n00];
-                const R T10 = s_tc[n10] + hds * s_kap[n10];
-                const R T01 = s_tc[n01] + hds * s_kap[n01];
-                const R T11 = s_tc[n11] + hds * s_kap[n11];
-                tin = sc_average<R>(mellema, g00, g10, g01, g11, T00, T10, T01, T11);
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            if (active[k] && diag[k] == s) {
+                if (!corner[k]) {
+                    const R T00 = s_tc[n00[k]] + hds[k] * s_kap[n00[k]];
+                    const R T10 = s_tc[n10[k]] + hds[k] * s_kap[n10[k]];
+                    const R T01 = s_tc[n01[k]] + hds[k] * s_kap[n01[k]];
+                    const R T11 = s_tc[n11[k]] + hds[k] * s_kap[n11[k]];
+                    tin[k] = sc_average<R>(mellema, g00[k], g10[k], g01[k], g11[k], T00, T10,
+                                           T01, T11);
+                }
+                s_tc[self[k]] = r_fma(hds[k], kself[k], tin[k]);   // entry face to centre
             }
-            s_tc[self] = r_fma(hds, kself, tin);   // entry face to centre
         }
         __syncthreads();
     }
-    // entering columns back to natural order for a coalesced store
-    __shared__ R s_out[TX * TY * TZ];
-    s_out[lx + TX * (ly + TY * lz)] = tin;
+    // entering columns back to natural order (in the halo buffer, no longer
+    // read) for a coalesced store
+    R* s_out = s_kap;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) s_out[nat[k]] = tin[k];
     __syncthreads();
-    {
-        const int t = threadIdx.x;
+    for (int t = threadIdx.x; t < TX * TY * TZ; t += NT) {
         const int ox = t % TX, oy = (t / TX) % TY, oz = t / (TX * TY);
         const int Lx = X0 + ox, Ly = Y0 + oy, Lz = Z0 + oz;
         if (Lx < ex && Ly < ey && Lz < ez) {
@@ -482,19 +513,25 @@ k_energy(int64_t n, const R* __restrict__ nH, const R* __restrict__ x, R* __rest
 }
 
 // ---------------------------------------------------------------- launchers
+template <typename R, int TT>
+void launch_sweep_t(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles, int first,
+                    int count, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_sweep<R, TT>), dim3(count), dim3(SweepShape<TT>::THREADS), 0, s, grids,
+                       state, tau_buf, tiles, first);
+}
+
 template <typename R>
 hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,
                               int first, int count, int tile, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    if (tile == SWEEP_T_SMALL)
-        hipLaunchKernelGGL((k_sweep<R, SWEEP_T_SMALL>), dim3(count),
-                           dim3(SWEEP_T_SMALL * SWEEP_T_SMALL * SWEEP_T_SMALL), 0, s, grids, state,
-                           tau_buf, tiles, first);
-    else if (tile == SWEEP_T_LARGE)
-        hipLaunchKernelGGL((k_sweep<R, SWEEP_T_LARGE>), dim3(count),
-                           dim3(SWEEP_T_LARGE * SWEEP_T_LARGE * SWEEP_T_LARGE), 0, s, grids, state,
-                           tau_buf, tiles, first);
+    if (tile == SWEEP_TILES[0])
+        launch_sweep_t<R, SWEEP_TILES[0]>(grids, state, tau_buf, tiles, first, count, s);
+    else if (tile == SWEEP_TILES[1])
+        launch_sweep_t<R, SWEEP_TILES[1]>(grids, state, tau_buf, tiles, first, count, s);
+    else if (tile == SWEEP_TILES[2])
+        launch_sweep_t<R, SWEEP_TILES[2]>(grids, state, tau_buf, tiles, first, count, s);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -287,9 +287,9 @@ pi_status set_tile(Engine& e, int edge)
         e.sweep = -1;
     } else {
         int w = -1;
-        for (int k = 0; k < 2; ++k)
+        for (int k = 0; k < NSWEEP; ++k)
             if (SWEEP_TILES[k] == edge) w = k;
-        if (w < 0) return fail(PI_EINVAL, "raytrace tile edge must be 0, 4 or 8");
+        if (w < 0) return fail(PI_EINVAL, "raytrace tile edge must be 0, 4, 8 or 16");
         e.sweep = w;
     }
     engine_build(e, e.grids);   // drops a graph captured with the old tiles
