@@ -247,6 +247,8 @@ def main() -> int:
     ap.add_argument("--pre-trec", type=float, default=0.1,
                     help="untimed evolution before timing, in units of t_rec")
     ap.add_argument("--pre-steps-max", type=int, default=400)
+    ap.add_argument("--phase-reps", type=int, default=4,
+                    help="back-to-back launches per phase in the phase timing")
     ap.add_argument("--phase-steps", type=int, default=3,
                     help="extra steps timed phase by phase after the timed region")
     ap.add_argument("--cpu-sample-n", type=int, default=32)
@@ -324,25 +326,42 @@ def main() -> int:
 
     work = g.work_counters(reset=True)   # over pre-evolution + warm-up + timed steps
 
-    # phase-by-phase timing of the same kernels (same stream, HIP events)
+    # phase-by-phase timing of the same kernels (same stream, HIP events): each
+    # phase is launched `phase_reps` times back to back between two events on
+    # inputs it does not modify, so that the per-launch figure carries no event
+    # overhead; the corrector's repetitions write its result to the half-step
+    # buffer, and one untimed corrector then moves state n on as in a step
     phases = {"timestep": 0.0, "chem_predictor": 0.0, "raytrace_half": 0.0,
               "chem_corrector": 0.0, "raytrace": 0.0}
+    R = args.phase_reps
+    P_N, P_H = binding.PI_BUF_N, binding.PI_BUF_HALF
+    timed = {
+        "timestep": lambda: g.timestep(t_end),
+        "chem_predictor": lambda: g.chem_step(0.5, P_N, P_N, P_H, use_device_dt=True),
+        "raytrace_half": lambda: g.raytrace(P_H, P_H),
+        "chem_corrector": lambda: g.chem_step(1.0, P_H, P_N, P_H, use_device_dt=True),
+        "raytrace": lambda: g.raytrace(P_N, P_N),
+    }
+    g.work_counters(reset=True)
+    work_phase = {}
     for _ in range(args.phase_steps):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-        ev[0].record(stream)
-        g.timestep(t_end)
-        ev[1].record(stream)
-        g.chem_step(0.5, binding.PI_BUF_N, binding.PI_BUF_N, binding.PI_BUF_HALF, use_device_dt=True)
-        ev[2].record(stream)
-        g.raytrace(binding.PI_BUF_HALF, binding.PI_BUF_HALF)
-        ev[3].record(stream)
-        g.chem_step(1.0, binding.PI_BUF_HALF, binding.PI_BUF_N, binding.PI_BUF_N, use_device_dt=True)
-        ev[4].record(stream)
-        g.raytrace(binding.PI_BUF_N, binding.PI_BUF_N)
-        ev[5].record(stream)
-        torch.cuda.synchronize()
-        for i, k in enumerate(phases):
-            phases[k] += ev[i].elapsed_time(ev[i + 1]) / args.phase_steps
+        for k, fn in timed.items():
+            if k == "raytrace":
+                # the step's own corrector (untimed, counters excluded)
+                w = g.work_counters(reset=True)
+                for c, v in w.items():
+                    work_phase[c] = work_phase.get(c, 0) + v
+                g.chem_step(1.0, P_H, P_N, P_N, use_device_dt=True)
+                torch.cuda.synchronize()
+                g.work_counters(reset=True)
+            a, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(R):
+                fn()
+            b2.record(stream)
+            torch.cuda.synchronize()
+            phases[k] += a.elapsed_time(b2) / (R * args.phase_steps)
+    chem_launches = 2 * R * args.phase_steps
     if args.calib_copy_mib > 0:
         nel = args.calib_copy_mib * 2**20 // 4
         src = torch.ones(nel, dtype=torch.float32, device="cuda")
@@ -367,11 +386,10 @@ def main() -> int:
         g.raytrace_tile = tuned
     diag = g.diagnostics()
     t_now, n_now, _ = g.state()
-    work_phase = g.work_counters(reset=True)   # the phase-timed steps only
 
     W = word_bytes(args.precision)
     N = spec.ncells
-    newton_per_launch = work_phase["newton"] / (2 * args.phase_steps)
+    newton_per_launch = work_phase["newton"] / chem_launches
     # algorithmic bytes per launch: chemistry reads n_H, x, E, tau and writes
     # x, E (6 words per cell); a raytrace reads n_H, x and writes tau (3 words);
     # the timestep reads n_H, x, E, tau (4 words)
@@ -423,12 +441,12 @@ def main() -> int:
             "raytrace_tile": g.raytrace_tile,
             "raytrace_ms_by_tile": tiles_ms,
             "substeps_per_cell_update": (work_phase["accepted"] + work_phase["rejected"])
-            / (spec.ncells * args.phase_steps),
+            / (spec.ncells * chem_launches / 2),
             "rejected_frac": work_phase["rejected"]
             / max(1, work_phase["accepted"] + work_phase["rejected"]),
-            "fallbacks_per_cell_update": work_phase["fallbacks"] / (spec.ncells * args.phase_steps),
-            "newton_per_cell_update": work_phase["newton"] / (spec.ncells * args.phase_steps),
-            "fp64_resolved_frac": work_phase["resolved_fp64"] / (2 * spec.ncells * args.phase_steps),
+            "fallbacks_per_cell_update": work_phase["fallbacks"] / (spec.ncells * chem_launches / 2),
+            "newton_per_cell_update": work_phase["newton"] / (spec.ncells * chem_launches / 2),
+            "fp64_resolved_frac": work_phase["resolved_fp64"] / (spec.ncells * chem_launches),
         },
         "roofline": roofline,
     }

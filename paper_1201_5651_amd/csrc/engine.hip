@@ -266,6 +266,7 @@ BatchDev Engine::bd() const
     b.dt_first = first ? first + ngrids() + 1 : nullptr;
     b.fix_n = fix_n;
     b.fix_list = fix_list;
+    b.fix_cap = (unsigned int)fix_cap;
     return b;
 }
 
@@ -382,7 +383,10 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
     }
     // mixed precision: re-solve list for every cell of the batch
     if (e.mixed()) {
-        if (!e.fix_n) HIP_OR(hipMalloc(&e.fix_n, sizeof(unsigned int)), "re-solve count allocation");
+        if (!e.fix_n) {
+            HIP_OR(hipMalloc(&e.fix_n, 2 * sizeof(unsigned int)), "re-solve count allocation");
+            HIP_OR(hipMemset(e.fix_n, 0, 2 * sizeof(unsigned int)), "re-solve count clear");
+        }
         if ((size_t)cells > e.fix_cap) {
             if (e.fix_list) (void)hipFree(e.fix_list);
             e.fix_list = nullptr;
@@ -391,7 +395,9 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
                    "re-solve list allocation");
             e.fix_cap = (size_t)cells;
         }
-        e.fix_blocks = (int)std::min<int64_t>((cells + 255) / 256, 2048);
+        // 512 workgroups of four waves fill every SIMD at the two waves the
+        // double kernel's registers allow
+        e.fix_blocks = (int)std::min<int64_t>((cells + 255) / 256, 512);
     }
     return e.fp64() ? upload_grids<double>(e) : upload_grids<float>(e);
 }

@@ -66,8 +66,11 @@ struct BatchDev {
     int ngrids;
     const int* chem_first;   // micro-physics workgroups (CHEM_BLOCK cells each)
     const int* dt_first;     // timestep workgroups
-    unsigned int* fix_n;     // mixed precision: length of fix_list
-    long long* fix_list;     // mixed precision: (grid << 32) | cell, for the double re-solve
+    // Mixed precision: fix_n[0] is the length of fix_list, fix_n[1] counts the
+    // finished workgroups of launch_chem_fix (both zero between launches).
+    unsigned int* fix_n;
+    long long* fix_list;     // (grid << 32) | cell, for the double re-solve
+    unsigned int fix_cap;    // entries fix_list holds
 };
 
 // One tile-diagonal stage of the raytrace of every grid with tiles of edge
@@ -84,7 +87,8 @@ hipError_t launch_chem(const GridDev<R>* grids, const BatchDev& b, int nblocks, 
                        int tau_buf, bool dev_dt, double hscale, unsigned long long* ctr,
                        bool mixed, hipStream_t s);
 // Mixed precision: double re-solve of the cells listed by launch_chem, from the
-// unmodified float inputs.
+// unmodified float inputs; its last workgroup empties the list, so every
+// launch_chem with mixed must be followed by one launch_chem_fix.
 hipError_t launch_chem_fix(const GridDev<float>* grids, const BatchDev& b, int nblk, int from,
                            int to, int tau_buf, bool dev_dt, double hscale,
                            unsigned long long* ctr, hipStream_t s);

@@ -345,39 +345,48 @@ k_chem(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int 
             unsigned base = 0;
             if (lane == lead) base = atomicAdd(bd.fix_n, (unsigned)__popcll(m));
             base = __shfl(base, lead, 64);
-            if (flag)
-                bd.fix_list[base + __popcll(m & ((1ull << lane) - 1ull))] =
-                    ((long long)g << 32) | (long long)q;
+            const unsigned slot = base + __popcll(m & ((1ull << lane) - 1ull));
+            if (flag && slot < bd.fix_cap)
+                bd.fix_list[slot] = ((long long)g << 32) | (long long)q;
         }
     }
     add_work(ctr, w);
 }
 
-__global__ void k_fix_reset(unsigned int* fix_n)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) *fix_n = 0u;
-}
-
 // Double re-solve of the listed cells (mixed precision): each entry names its
-// grid, so the rate table is read from global memory here.
+// grid, so the rate table is read from global memory here.  Workgroups beyond
+// the list return at once; the last workgroup to finish clears the list length
+// and the finish count for the next micro-physics launch.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ChemWaves<double>::value)))
 k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int to, int tau_buf,
            int dev_dt, double hscale, unsigned long long* ctr)
 {
-    const unsigned n = *bd.fix_n;
-    Work w{};
-    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const long long e = bd.fix_list[i];
-        const GridDev<float>& G = grids[(int)(e >> 32)];
-        const int q = (int)(e & 0xffffffffll);
-        const double hd = dev_dt ? hscale * G.st->dt : hscale;
-        double x, E;
-        chem_cell<double, float>(G.pd, q, G.nH, G.x[from], G.E[from], G.tau[tau_buf], hd, x, E, w);
-        G.x[to][q] = (float)x;
-        if (G.E[to]) G.E[to][q] = (float)E;
-        ++w.fixed;
+    const unsigned n = min(bd.fix_n[0], bd.fix_cap);
+    if (blockIdx.x * blockDim.x < n) {   // uniform over the workgroup
+        Work w{};
+        for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+            const long long e = bd.fix_list[i];
+            const GridDev<float>& G = grids[(int)(e >> 32)];
+            const int q = (int)(e & 0xffffffffll);
+            const double hd = dev_dt ? hscale * G.st->dt : hscale;
+            double x, E;
+            chem_cell<double, float>(G.pd, q, G.nH, G.x[from], G.E[from], G.tau[tau_buf], hd, x, E, w);
+            G.x[to][q] = (float)x;
+            if (G.E[to]) G.E[to][q] = (float)E;
+            ++w.fixed;
+        }
+        add_work(ctr, w);
     }
-    add_work(ctr, w);
+    // Every wave has its value of the list length (its branch above waited for
+    // the load), so once all workgroups have counted themselves no read of the
+    // length is outstanding and the last one may clear it; no fence is needed.
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (atomicAdd(&bd.fix_n[1], 1u) == gridDim.x - 1) {
+            bd.fix_n[0] = 0u;
+            bd.fix_n[1] = 0u;
+        }
+    }
 }
 
 // ------------------------------------------------------ timestep + diagnostics
@@ -543,7 +552,6 @@ hipError_t launch_chem(const GridDev<R>* grids, const BatchDev& b, int nblocks, 
                        bool mixed, hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
-    if (mixed) hipLaunchKernelGGL(k_fix_reset, dim3(1), dim3(64), 0, s, b.fix_n);
     hipLaunchKernelGGL((k_chem<R>), dim3(nblocks), dim3(CHEM_BLOCK), 0, s, grids, b, from, to,
                        tau_buf, (int)dev_dt, hscale, ctr, (int)mixed);
     return hipGetLastError();
