@@ -47,11 +47,18 @@ template <> struct Tol<double> {
     static constexpr double half_ulp1 = 5.551115123125783e-17;   // half the spacing below 1
     static constexpr double rtol = 1e-13;   // Newton converged
     static constexpr double stall = 1e-11;  // correction stopped shrinking: rounding floor
+    static constexpr double one_step = 0.0; // double always confirms convergence
 };
 template <> struct Tol<float> {
     static constexpr float half_ulp1 = 2.98023224e-8f;
     static constexpr float rtol = 4e-7f;
     static constexpr float stall = 1e-4f;
+    // A first Newton step of relative size d from the stage's starting guess
+    // leaves an error of order d^2 (quadratic convergence): when it is a plain
+    // Newton step (no projection onto [0,1], no halving of E) and d is below
+    // the square root of rtol, its result is accepted without one more
+    // residual evaluation to confirm it.
+    static constexpr float one_step = 3e-4f;
 };
 
 // Rate table as the kernels use it: values normalised by Q, and the log-Hermite
@@ -526,7 +533,8 @@ PI_HD void fallback_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg,
 // Stage solve Y = base + hg f(Y); counts Newton iterations and fallbacks in w.
 // T fixed: the scalar bracketed Newton.  T evolving: Newton on (x, E) with x
 // projected onto [0,1] (E then takes the step of the linearisation with x on
-// the bound) and E kept positive, at most NEWTON_2D_MAXIT iterations;
+// the bound) and E kept positive, at most NEWTON_2D_MAXIT iterations (in float,
+// a small plain first step is accepted at once, see Tol<float>::one_step);
 // if it has not settled, a nested bracketed solve in (x, T): x at fixed T by the
 // scalar solve, and the energy residual bracketed in ln T from the floor
 // upwards and solved by the Illinois variant of regula falsi.
@@ -561,13 +569,18 @@ PI_HD void stage_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg, R&
         const R idet = r_rcp(a11 * a22 - a12 * a21);
         R xn = x - (a22 * Rx - a12 * RE) * idet;
         R En = E - (a11 * RE - a21 * Rx) * idet;
+        bool plain = true;   // an unmodified Newton step
         if (!(xn >= R(0)) || xn > R(1)) {
+            plain = false;
             // x held on the bound; E takes the step of the linearisation there
             const R xbnd = xn > R(1) ? R(1) : R(0);
             En = E - (RE + a21 * (xbnd - x)) * r_rcp(a22);
             xn = xbnd;
         }
-        if (!(En > R(0))) En = R(0.5) * E;
+        if (!(En > R(0))) {
+            En = R(0.5) * E;
+            plain = false;
+        }
         const R err = r_max(r_abs(xn - x) * r_rcp(r_max(xn, R(1e-12))), r_abs(En - E) * r_rcp(En));
         // x held on a bound while the residual puts the root inside [0, 1]
         // (a negative slope of the x-residual): not a solution -- unless at 1
@@ -576,7 +589,8 @@ PI_HD void stage_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg, R&
                            (xn <= R(0) && Rx < R(0));
         x = xn;
         E = En;
-        if (!stuck && (err <= Tol<R>::rtol || (err >= eprev && err <= Tol<R>::stall))) {
+        if (!stuck && (err <= Tol<R>::rtol || (err >= eprev && err <= Tol<R>::stall) ||
+                       (plain && it == 0 && err <= Tol<R>::one_step))) {
             // x = 1 held although it is an unstable equilibrium (a11 < 0) and
             // the residual pushes x inside: the precision cannot resolve the
             // seed that would start the runaway
@@ -594,10 +608,13 @@ PI_HD void stage_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg, R&
 // that at the initial rate no substep moves x by more than SUB_DX; at most
 // SUB_MAX.
 template <typename R>
-PI_HD __forceinline__ int substeps(const Params<R>& p, const Env<R>& e, R x0, R E0, R h, Work& w)
+PI_HD __forceinline__ int substeps(const Params<R>& p, const Env<R>& e, R x0, R E0, R h, Work& w,
+                                  R& fx0, R& fE0)
 {
     Rhs<R> r;
     rhs_full(p, e, x0, E0, r);
+    fx0 = r.fx;
+    fE0 = r.fE;
     const double s = (double)h * (double)r_abs(r.fx) / SUB_DX;
     int ns = p.n_sub > 0 ? p.n_sub : 1;
     if (s > (double)ns * (1.0 - MIX_MARGIN) && s < (double)SUB_MAX * (1.0 + MIX_MARGIN)) {
@@ -608,20 +625,44 @@ PI_HD __forceinline__ int substeps(const Params<R>& p, const Env<R>& e, R x0, R 
     return ns;
 }
 
+// Starting guess of a stage solve: the stage's base advanced by hg times an
+// estimate of the rate, unless that takes x out of [0, 1] or changes E by more
+// than PRED_MAX of itself (a stiff component, for which the explicit estimate
+// overshoots); then the base itself.  The guess only changes where Newton
+// starts, not the root it converges to.
+constexpr double PRED_MAX = 0.5;
+template <typename R>
+PI_HD __forceinline__ void stage_guess(R xb, R Eb, R hg, R fx, R fE, R& xg, R& Eg)
+{
+    const R dx = hg * fx, dE = hg * fE;
+    const bool ok = xb + dx >= R(0) && xb + dx <= R(1) && r_abs(dE) <= R(PRED_MAX) * Eb;
+    xg = ok ? xb + dx : xb;
+    Eg = ok ? Eb + dE : Eb;
+}
+
 // One step of the two-stage, L-stable, stiffly accurate SDIRK method
 // (gamma = 1 - 1/sqrt 2); the second stage starts from y + ((1-gamma)/gamma)(Y1 - y).
+// (fx, fE) is the rate at (x, E) on entry and at the new (x, E) on return: a
+// solved stage equation Y = base + hg f(Y) gives f(Y) = (Y - base)/hg without
+// another evaluation.  Stage 1 starts from y + hg f(y), stage 2 from its base
+// + hg f(Y1).
 template <typename R>
 PI_HD __forceinline__ void sdirk_step(const Params<R>& p, const Env<R>& e, R hs, R& x, R& E,
-                                      Work& w)
+                                      R& fx, R& fE, Work& w)
 {
     const R gam = R(0.29289321881345247560);          // 1 - 1/sqrt(2)
     const R cst = R(2.41421356237309504880);          // (1 - gamma)/gamma
-    R X1 = x, F1 = E;
-    stage_solve(p, e, x, E, gam * hs, X1, F1, w);
+    const R hg = gam * hs;
+    R X1, F1;
+    stage_guess(x, E, hg, fx, fE, X1, F1);
+    stage_solve(p, e, x, E, hg, X1, F1, w);
     const R xb = x + cst * (X1 - x);
     const R Eb = E + cst * (F1 - E);
-    R X2 = X1, F2 = F1;
-    stage_solve(p, e, xb, Eb, gam * hs, X2, F2, w);
+    R X2, F2;
+    stage_guess(xb, Eb, R(1), X1 - x, F1 - E, X2, F2);   // hg f(Y1) = Y1 - y
+    stage_solve(p, e, xb, Eb, hg, X2, F2, w);
+    fx = (X2 - xb) / hg;
+    fE = (F2 - Eb) / hg;
     x = X2;
     E = F2;
 }
@@ -638,14 +679,15 @@ PI_HD void micro(const Params<R>& p, const Env<R>& e, R h, R& x, R& E, Work& w)
     if (!(h > R(0))) return;
     const bool evolve = p.thermal == 1;
     if (evolve && E < e_floor(e.n, x)) E = e_floor(e.n, x);
-    const int ns = substeps(p, e, x, E, h, w);
+    R fx, fE;
+    const int ns = substeps(p, e, x, E, h, w, fx, fE);
     const int top = 1 << SUB_LEVELS;
     const int U = ns * top;
     int pos = 0, s = top;
     while (pos < U) {
         const R hs = R((double)h * (double)s / (double)U);
-        R xn = x, En = E;
-        sdirk_step(p, e, hs, xn, En, w);
+        R xn = x, En = E, fxn = fx, fEn = fE;
+        sdirk_step(p, e, hs, xn, En, fxn, fEn, w);
         const R dx = r_abs(xn - x);
         const bool bad = dx > R(REJ_DX) || (evolve && (En > R(REJ_E) * E || En * R(REJ_E) < E));
         if (r_abs(dx - R(REJ_DX)) < R(MIX_MARGIN * REJ_DX) ||
@@ -660,6 +702,8 @@ PI_HD void micro(const Params<R>& p, const Env<R>& e, R h, R& x, R& E, Work& w)
         ++w.accepted;
         x = xn;
         E = En;
+        fx = fxn;
+        fE = fEn;
         if (evolve && E < e_floor(e.n, x)) E = e_floor(e.n, x);
         pos += s;
         if (s < top && pos % (2 * s) == 0) s <<= 1;
