@@ -329,7 +329,8 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
     int64_t cells = 0;
     for (int g = 0; g < G; ++g) {
         const int64_t n = e.grids[g]->ncell;
-        const int64_t cb = (n + CHEM_BLOCK - 1) / CHEM_BLOCK;
+        const pi_grid_desc& d = e.grids[g]->d;
+        const int64_t cb = chem_workgroups(d.n[0], d.n[1], d.n[2]);
         if ((int64_t)first[g] + cb > 2147483647LL) return fail(PI_EINVAL, "batch too large");
         first[g + 1] = first[g] + (int)cb;
         first[G + 1 + g + 1] = first[G + 1 + g] + e.grids[g]->nblk_dt;

@@ -18,8 +18,22 @@ namespace pi {
 constexpr int NSWEEP = 3;
 constexpr int SWEEP_TILES[NSWEEP] = { 4, 8, 16 };
 constexpr int SWEEP_T_LARGEST = 16;
-// Threads per workgroup of the micro-physics kernel.
-constexpr int CHEM_BLOCK = 256;
+// Threads per workgroup of the micro-physics kernel.  Each wavefront
+// integrates one brick of CHEM_BRICK^3 = 64 neighbouring cells (bricks in x,
+// then y, then z order; bricks that overhang the grid leave lanes idle): cells
+// that need many Newton iterations cluster in space, so a compact brick wastes
+// fewer lanes than a 64-cell row.
+constexpr int CHEM_BLOCK = 256, CHEM_BRICK = 4;
+// Bricks of a grid and micro-physics workgroups that cover them.
+__host__ __device__ constexpr int64_t chem_bricks(int nx, int ny, int nz)
+{
+    return (int64_t)((nx + CHEM_BRICK - 1) / CHEM_BRICK) * ((ny + CHEM_BRICK - 1) / CHEM_BRICK) *
+           ((nz + CHEM_BRICK - 1) / CHEM_BRICK);
+}
+__host__ __device__ constexpr int64_t chem_workgroups(int nx, int ny, int nz)
+{
+    return (chem_bricks(nx, ny, nz) + CHEM_BLOCK / 64 - 1) / (CHEM_BLOCK / 64);
+}
 // Threads per workgroup and largest number of workgroups per grid of the
 // timestep/diagnostics reduction.
 constexpr int DT_BLOCK = 256, DT_MAX_BLOCKS = 1024;
@@ -64,7 +78,7 @@ template <typename R> struct GridDev {
 // of a launch over all grids.
 struct BatchDev {
     int ngrids;
-    const int* chem_first;   // micro-physics workgroups (CHEM_BLOCK cells each)
+    const int* chem_first;   // micro-physics workgroups (CHEM_BLOCK / 64 bricks each)
     const int* dt_first;     // timestep workgroups
     // Mixed precision: fix_n[0] is the length of fix_list, fix_n[1] counts the
     // finished workgroups of launch_chem_fix (both zero between launches).

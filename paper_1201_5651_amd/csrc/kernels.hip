@@ -323,10 +323,18 @@ k_chem(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int 
     const int g = find_grid(bd.chem_first, bd.ngrids, blockIdx.x);
     const GridDev<R>& G = grids[g];
     const Params<R> pl = table_to_lds(G.p, s_tab);
-    const int q = (blockIdx.x - bd.chem_first[g]) * CHEM_BLOCK + threadIdx.x;
+    const int brick = (blockIdx.x - bd.chem_first[g]) * (CHEM_BLOCK / 64) + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int nbx = (pl.nx + CHEM_BRICK - 1) / CHEM_BRICK, nby = (pl.ny + CHEM_BRICK - 1) / CHEM_BRICK;
+    const int i = CHEM_BRICK * (brick % nbx) + (lane & 3);
+    const int j = CHEM_BRICK * ((brick / nbx) % nby) + ((lane >> 2) & 3);
+    const int k = CHEM_BRICK * (brick / (nbx * nby)) + (lane >> 4);
+    const bool inside = i < pl.nx && j < pl.ny && k < pl.nz;
+    const int q = inside ? i + pl.nx * (j + pl.ny * k) : 0;
+    static_assert(CHEM_BRICK == 4 && CHEM_BLOCK % 64 == 0, "lane -> cell map assumes 4^3 bricks");
     Work w{};
     bool flag = false;
-    if (q < pl.ncell) {
+    if (inside) {
         const double hd = dev_dt ? hscale * G.st->dt : hscale;
         R x, E;
         chem_cell<R, R>(pl, q, G.nH, G.x[from], G.E[from], G.tau[tau_buf], hd, x, E, w);
