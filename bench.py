@@ -177,6 +177,71 @@ def bench_batch(args, torch, binding, synth) -> dict:
     }
 
 
+def bench_hardening(args, torch, binding, synth) -> dict:
+    """Spectral-hardening runs of Sect. 4 (37 500 K blackbody; cell optical
+    depth 1, 3, 10, 30 with n_H = 10, 100, 1000): the twelve grids advanced as
+    one batch, timed over K steps from the neutral start; then each run is
+    taken to 0.1 t_rec with dt02 and, in a second batch, with four times
+    smaller steps (K4 = 1/16), and the front radii are compared."""
+    INF = synth.INF
+    specs = synth.hardening_specs(args.precision)
+    nHs = [synth.density(s) for s in specs]
+    stream = torch.cuda.current_stream()
+
+    def make(K):
+        sp = [s.with_(K=K, t_end=args.hardening_trec * s.t_rec) for s in specs]
+        b = binding.Batch(sp, precision=args.precision)
+        b.load(nHs, T0s=[s.T0 for s in sp], t_end=[s.t_end for s in sp])
+        return b
+
+    bt = make(synth.EXPLICIT_CRITERIA["dt02"])
+    for _ in range(args.warmup):
+        bt.step_o2()
+    torch.cuda.synchronize()
+    _, n0, _ = bt.state()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        bt.step_o2()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    _, n1, _ = bt.state()
+    cells = sum(s.ncells * (b - a) for s, a, b in zip(specs, n0, n1))
+    value = cells / (ms * 1e-3)
+    tick = time.time()
+    bt.run()
+    _, steps_dt02, _ = bt.state()
+    r_dt02 = [d["r_ion"] for d in bt.diagnostics()]
+    print(f"# hardening: dt02 runs to {args.hardening_trec} t_rec in {time.time() - tick:.1f} s",
+          file=sys.stderr, flush=True)
+    bt.close()
+    tick = time.time()
+    ref = make((INF, INF, INF, 1.0 / 16))
+    ref.run()
+    r_ref = [d["r_ion"] for d in ref.diagnostics()]
+    print(f"# hardening: reference runs in {time.time() - tick:.1f} s", file=sys.stderr, flush=True)
+    ref.close()
+    runs = []
+    for s, a, b2, k in zip(specs, r_dt02, r_ref, steps_dt02):
+        RS = 150.0 / (s.nH_mean * synth.SIGMA0)
+        runs.append({"dtau0": round(s.dx * s.nH_mean * synth.SIGMA0, 6), "nH": s.nH_mean,
+                     "n": s.n[0], "steps_dt02": int(k), "r_ion_over_RS": a / RS,
+                     "rel_err_vs_K4_1_16": a / b2 - 1})
+    return {
+        "metric": "cell-updates/s of the batched A3 step, spectral-hardening runs",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype_name(args.precision),
+        "data": "synthetic",
+        "config": {"workload": "12 grids: 37500 K blackbody table, cell optical depth 1, 3, 10, 30 "
+                               "x n_H 10, 100, 1000 (tau_S 150, Q ~ 1/n_H), corner source, T "
+                               "evolving from 50 K, A3-dt02, from a neutral start",
+                   "cells": sum(s.ncells for s in specs), "precision": args.precision,
+                   "runs_to_trec": args.hardening_trec, "runs": runs},
+    }
+
+
 def bench_serve(args, torch, binding, synth) -> dict:
     """Served form: Poisson arrivals of single-grid requests submitted to the
     library's server at their arrival times; latency from submission to
@@ -254,9 +319,11 @@ def main() -> int:
     ap.add_argument("--cpu-sample-n", type=int, default=32)
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="cfg3", choices=["cfg3", "batch", "serve"],
+    ap.add_argument("--workload", default="cfg3", choices=["cfg3", "batch", "serve", "hardening"],
                     help="cfg3: the 256^3 single grid (default); batch / serve: the batched and "
                          "served forms (their own JSON line)")
+    ap.add_argument("--hardening-trec", type=float, default=1.0,
+                    help="hardening workload: accuracy runs end at this many t_rec")
     ap.add_argument("--batch-grids", type=int, default=64)
     ap.add_argument("--batch-fp64-sample", type=int, default=8)
     ap.add_argument("--serve-requests", type=int, default=200)
@@ -274,8 +341,9 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (grids "
+              "and octants would shard across GPUs with no exchange but two FP64 scalars "
+              "per step); run with --gpus 1", file=sys.stderr)
         return 2
 
     import torch
@@ -284,7 +352,7 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     if args.workload != "cfg3":
-        fn = bench_batch if args.workload == "batch" else bench_serve
+        fn = {"batch": bench_batch, "serve": bench_serve, "hardening": bench_hardening}[args.workload]
         print(json.dumps(fn(args, torch, binding, synth)))
         return 0
     spec = synth.cfg3(n=args.n)

@@ -154,6 +154,39 @@ def cfg3(n: int = 256, **kw) -> GridSpec:
     return s.with_(**kw) if kw else s
 
 
+HARDENING_DTAU0 = (1.0, 3.0, 10.0, 30.0)
+HARDENING_NH = (10.0, 100.0, 1000.0)
+
+
+def hardening(dtau0: float, nH: float = 100.0, tau_S: float = 150.0, **kw) -> GridSpec:
+    """Spectral-hardening set-up of Sect. 4: a 37 500 K blackbody source in a
+    uniform medium, temperature evolved from 50 K with a temperature-dependent
+    recombination rate, resolved with cell optical depth dtau0 = n_H sigma0 dx
+    at threshold.
+
+    The 3D grid is one octant around a corner source, of side 1.37 R_S (the
+    paper's 1D grid spans 1.94 pc for R_S = 1.42 pc).  The optical depth of
+    R_S at threshold, tau_S = n_H sigma0 R_S, is held at tau_S (the paper's 1D
+    problem has ~2800, which no 3D grid resolves at dtau0 = 1), so the grid
+    has about 1.37 tau_S / dtau0 cells a side.  Changing n_H at fixed tau_S
+    and dtau0 scales R_S and t_rec both as 1/n_H (Q as 1/n_H), so the front
+    expands at the same speed for every density, as the paper arranges."""
+    RS = tau_S / (nH * SIGMA0)
+    Q = 4.0 * math.pi / 3.0 * ALPHA_B_1E4 * nH * nH * RS ** 3
+    tr = recombination_time(nH)
+    dx = dtau0 / (nH * SIGMA0)
+    n = int(math.ceil(1.37 * RS / dx))
+    s = GridSpec(name=f"hard_dtau{dtau0:g}_n{nH:g}", n=(n, n, n), src=(0, 0, 0), dx=dx, Q=Q,
+                 nH_mean=nH, spectrum="table", T_bb=37500.0, thermal="evolve", recomb="power",
+                 collisional=True, t_end=2.0 * tr, t_rec=tr)
+    return s.with_(**kw) if kw else s
+
+
+def hardening_specs(precision: str = "mixed", dtau0s=HARDENING_DTAU0, nHs=HARDENING_NH) -> list:
+    """The grid of Sect. 4: every cell optical depth with every density."""
+    return [hardening(d, nH, precision=precision) for d in dtau0s for nH in nHs]
+
+
 def batch_specs(count: int = 64, seed: int = 0, nmin: int = 32, nmax: int = 160,
                 precision: str = "mixed") -> list:
     """Independent grids for the batched form: n ~ U{nmin..nmax}, uniform or

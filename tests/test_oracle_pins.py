@@ -390,35 +390,69 @@ def _bose_series(m, u0, kmax=200):
     return tot
 
 
-def test_table_nodes_match_independent_quadrature(oracle_lib):
+@pytest.mark.parametrize("T_bb", [1e5, 37500.0])
+def test_table_nodes_match_independent_quadrature(oracle_lib, T_bb):
     """Sect. 2 (rates tabulated against optical depth): node values of P, P1,
-    H, H1 for the 1e5 K blackbody with sigma ~ nu^-3 agree with scipy quadrature
-    to 1e-9; P(0) = Q."""
-    tab = oracle.table_build(1e5, 1e48)
-    u0 = 13.6 * EV / (KB * 1e5)
+    H, H1 for the 1e5 K blackbody, and for the 37 500 K source of the
+    spectral-hardening runs (Sect. 4), with sigma ~ nu^-3 agree with scipy
+    quadrature to 1e-9; P(0) = Q."""
+    tab = oracle.table_build(T_bb, 1e48)
+    u0 = 13.6 * EV / (KB * T_bb)
     norm = _bb_integral(0, u0)
     assert tab[1, 0] == pytest.approx(1e48, rel=1e-12)
     for j in (0, 1, 17, 33, 50, 63):
         tau = tab[0, j]
         assert tab[1, j] == pytest.approx(1e48 * _bb_integral(0, u0, tau=tau) / norm, rel=1e-9)
         assert tab[2, j] == pytest.approx(1e48 * _bb_integral(0, u0, s=1, tau=tau) / norm, rel=1e-9)
-        kT = KB * 1e5
+        kT = KB * T_bb
         assert tab[3, j] == pytest.approx(1e48 * kT * _bb_integral(1, u0, tau=tau) / norm, rel=1e-9)
         assert tab[4, j] == pytest.approx(1e48 * kT * _bb_integral(1, u0, s=1, tau=tau) / norm,
                                           rel=1e-9)
 
 
-def test_table_mean_excess_energy_closed_form(oracle_lib):
-    """Mean excess energy per photon of a 1e5 K blackbody above 13.6 eV from the
-    Bose series closed form: H(0)/P(0) = kT (I3 - u0 I2)/I2 = 16.01 eV."""
-    tab = oracle.table_build(1e5, 1e48)
-    kT = KB * 1e5
+@pytest.mark.parametrize("T_bb", [1e5, 37500.0])
+def test_table_mean_excess_energy_closed_form(oracle_lib, T_bb):
+    """Mean excess energy per photon of a blackbody above 13.6 eV from the
+    Bose series closed form: H(0)/P(0) = kT (I3 - u0 I2)/I2 (16.01 eV at
+    1e5 K); and per photoionisation with sigma ~ nu^-3:
+    kT (I0 - u0 I_-1)/I_-1 with I_m = int u^m/(e^u - 1) du over u > u0."""
+    tab = oracle.table_build(T_bb, 1e48)
+    kT = KB * T_bb
     u0 = 13.6 * EV / kT
     I2, I3 = _bose_series(2, u0), _bose_series(3, u0)
     expect = kT * (I3 - u0 * I2) / I2
     assert tab[3, 0] / tab[1, 0] == pytest.approx(expect, rel=1e-10)
-    assert expect / EV == pytest.approx(16.01, abs=0.01)
-    assert tab[4, 0] / tab[2, 0] / EV == pytest.approx(5.985, abs=0.002)
+    # sigma-weighted: u^2 (u0/u)^3 = u0^3/u, so the weights are 1/u and 1
+    f = lambda m: integrate.quad(lambda u: u ** m / math.expm1(u), u0, 400.0, epsabs=0,
+                                 epsrel=1e-13, limit=500)[0]
+    Im1, I0 = f(-1), f(0)
+    assert tab[4, 0] / tab[2, 0] == pytest.approx(kT * (I0 - u0 * Im1) / Im1, rel=1e-9)
+    if T_bb == 1e5:
+        assert expect / EV == pytest.approx(16.01, abs=0.01)
+        assert tab[4, 0] / tab[2, 0] / EV == pytest.approx(5.985, abs=0.002)
+
+
+def test_table_spectral_hardening_37500K(oracle_lib):
+    """Sect. 4: with sigma ~ nu^-3 the radiation hardens with depth, so the
+    mean excess energy of the photons absorbed at depth tau, H1/P1, rises
+    monotonically from its tau = 0 value.  Deep in, the absorbed spectrum is
+    set by the Wien tail e^-u against the attenuation e^-(tau u0^3/u^3); their
+    product peaks at u* = (3 tau u0^3)^(1/4) (Laplace's method), and the mean
+    absorbed photon energy approaches u* kT from above as tau grows."""
+    T_bb = 37500.0
+    tab = oracle.table_build(T_bb, 1e48)
+    ratio = tab[4, 1:] / tab[2, 1:]
+    assert np.all(np.diff(ratio) > 0)
+    assert ratio[0] == pytest.approx(tab[4, 0] / tab[2, 0], rel=1e-3)
+    kT = KB * T_bb
+    u0 = 13.6 * EV / kT
+    dev = []
+    for tau in (1e2, 1e3, 3e3):
+        _, dP = oracle.table_eval(tab, 0, tau)
+        _, dH = oracle.table_eval(tab, 1, tau)
+        mean_u = (dH / dP + 13.6 * EV) / kT
+        dev.append(mean_u / (3 * tau * u0 ** 3) ** 0.25 - 1)
+    assert 0 < dev[0] < 0.04 and dev[1] < dev[0] and dev[2] < dev[1]
 
 
 def test_table_interpolation_accuracy(oracle_lib):
@@ -496,3 +530,42 @@ def test_front_locator_eq5(oracle_lib):
     r = np.arange(200)
     x = 0.5 * (1 + np.tanh((r - 123.4) / 3.0))
     assert oracle.front_index_1d(x) == 123
+
+
+# ------------------------------------------------------- spectral hardening
+def _hardening_run(dtau0, nH, times, **kw):
+    spec = synth.hardening(dtau0, nH, **kw)
+    pb = oracle.Problem.from_spec(spec)
+    st = pb.initial_state(synth.density(spec), T0=spec.T0)
+    RS = 150.0 / (nH * synth.SIGMA0)
+    out = []
+    for tt in times:
+        pb.run(st, tt * spec.t_rec)
+        out.append((pb.diagnostics(st)["r_ion"] / RS, pb.temperature(st["nH"], st["x"], st["E"])))
+    return out
+
+
+def test_hardening_is_self_similar_in_density(oracle_lib):
+    """Sect. 4 varies n_H with the luminosity changed to keep the front speed.
+    At fixed cell optical depth and tau_S every rate per particle scales as
+    n_H and t_rec as 1/n_H, so in units of R_S and t_rec the runs at n_H = 10,
+    100 and 1000 are the same problem: front radius and temperatures agree to
+    rounding (a dropped or doubled density factor anywhere breaks this)."""
+    runs = [_hardening_run(30.0, nH, (0.1, 0.5, 1.0)) for nH in (10.0, 100.0, 1000.0)]
+    for other in runs[1:]:
+        for (ra, Ta), (rb, Tb) in zip(runs[0], other):
+            assert rb == pytest.approx(ra, rel=1e-9)
+            assert np.max(np.abs(Tb / Ta - 1)) < 1e-9
+
+
+def test_hardening_dt02_matches_a_fine_timestep(oracle_lib):
+    """Sect. 4: A3 with dt02 gives a good solution at every cell optical
+    depth; on the coarsest grid (dtau0 = 30) the front radius stays within
+    0.5% of a run with 16 times smaller steps (K4 = 1/64) up to t_rec, and the
+    front is resolved and moving (R_I/R_S 0.45 at 0.1 t_rec, 0.89 at t_rec)."""
+    INF = synth.INF
+    a = _hardening_run(30.0, 100.0, (0.1, 0.5, 1.0))
+    b = _hardening_run(30.0, 100.0, (0.1, 0.5, 1.0), K=(INF, INF, INF, 1 / 64))
+    for (ra, _), (rb, _) in zip(a, b):
+        assert ra == pytest.approx(rb, rel=5e-3)
+    assert 0.4 < a[0][0] < 0.5 and 0.85 < a[2][0] < 0.95
