@@ -25,7 +25,7 @@ KB = 1.380649e-16
 EV = 1.602176634e-12
 NTAB = 64
 
-GEOM_3D, GEOM_SPHERICAL_1D, GEOM_PLANAR_1D = 0, 1, 2
+GEOM_3D, GEOM_SPHERICAL_1D, GEOM_PLANAR_1D, GEOM_PLANE_3D = 0, 1, 2, 3
 SPEC_MONO, SPEC_TABLE = 0, 1
 T_FIXED, T_EVOLVE = 0, 1
 ALPHA_CONST, ALPHA_POWER = 0, 1
@@ -165,7 +165,7 @@ class Problem:
         d.n_sub = n_sub
         d.K[:] = K
         self.desc = d
-        self.shape = (n3[2], n3[1], n3[0]) if geometry == GEOM_3D else (n3[0],)
+        self.shape = (n3[2], n3[1], n3[0]) if geometry in (GEOM_3D, GEOM_PLANE_3D) else (n3[0],)
 
     @property
     def ncells(self):
@@ -258,7 +258,8 @@ class Problem:
     @classmethod
     def from_spec(cls, spec, **over):
         """Oracle problem for a ``synth.GridSpec`` (input description only)."""
-        kw = dict(geometry=GEOM_3D, n=tuple(spec.n), src=tuple(spec.src), dx=spec.dx, Q=spec.Q,
+        kw = dict(geometry=GEOM_PLANE_3D if getattr(spec, "source", "point") == "plane" else GEOM_3D,
+                  n=tuple(spec.n), src=tuple(spec.src), dx=spec.dx, Q=spec.Q,
                   sigma0=6.3e-18, spectrum=SPEC_TABLE if spec.spectrum == "table" else SPEC_MONO,
                   e_excess=spec.e_excess, T_bb=spec.T_bb,
                   thermal=T_EVOLVE if spec.thermal == "evolve" else T_FIXED,

@@ -278,15 +278,26 @@ static void env_1d(const orc_desc* g, int i, double* geo, double* ell)
     *ell = dr;
 }
 
+static int is_3d(const orc_desc* g)
+{
+    return g->geometry == ORC_GEOM_3D || g->geometry == ORC_GEOM_PLANE_3D;
+}
+
 static int64_t ncells(const orc_desc* g)
 {
-    if (g->geometry == ORC_GEOM_3D) return (int64_t)g->n[0] * g->n[1] * g->n[2];
+    if (is_3d(g)) return (int64_t)g->n[0] * g->n[1] * g->n[2];
     return g->n[0];
 }
 
 int orc_cell_env(const orc_desc* g, int64_t cell, double* geo, double* ell)
 {
     if (cell < 0 || cell >= ncells(g)) return -1;
+    if (g->geometry == ORC_GEOM_PLANE_3D) {
+        /* every cell is a slab cell of its row: flux Q over depth dx */
+        *geo = 1.0 / g->dx;
+        *ell = g->dx;
+        return 0;
+    }
     if (g->geometry != ORC_GEOM_3D) {
         env_1d(g, (int)cell, geo, ell);
         return 0;
@@ -391,6 +402,18 @@ int orc_raytrace_sc(const orc_desc* g, const double* nH, const double* x, double
 {
     if (!g || !nH || !x || !tau_in) return -1;
     if (g->geometry == ORC_GEOM_3D) return raytrace_sc_3d(g, nH, x, tau_in);
+    if (g->geometry == ORC_GEOM_PLANE_3D) {
+        /* each row along x is a slab: the column from the lit face x = 0 */
+        const int64_t nx = g->n[0], rows = (int64_t)g->n[1] * g->n[2];
+        for (int64_t r = 0; r < rows; ++r) {
+            double N = 0.0;
+            for (int64_t i = 0; i < nx; ++i) {
+                tau_in[r * nx + i] = g->sigma0 * N;
+                N += nH[r * nx + i] * x[r * nx + i] * g->dx;
+            }
+        }
+        return 0;
+    }
     return raytrace_1d(g, nH, x, tau_in);
 }
 
@@ -990,7 +1013,7 @@ int orc_diagnostics(const orc_desc* g, const double* nH, const double* x, const 
     for (int64_t i = 0; i < N; ++i) {
         double geo, ell, vol;
         env_of(g, i, &geo, &ell);
-        if (g->geometry == ORC_GEOM_3D) vol = g->dx * g->dx * g->dx;
+        if (is_3d(g)) vol = g->dx * g->dx * g->dx;
         else if (g->geometry == ORC_GEOM_SPHERICAL_1D) vol = 1.0 / geo;
         else vol = g->dx;
         cellenv c;
@@ -1018,6 +1041,8 @@ int orc_diagnostics(const orc_desc* g, const double* nH, const double* x, const 
             noct += ok;
         }
         out->r_ion = cbrt(3.0 * vion * 8.0 / (4.0 * M_PI * noct));
+    } else if (g->geometry == ORC_GEOM_PLANE_3D) {
+        out->r_ion = vion / ((double)g->n[1] * g->n[2] * g->dx * g->dx);
     } else if (g->geometry == ORC_GEOM_SPHERICAL_1D) {
         out->r_ion = cbrt(3.0 * vion / (4.0 * M_PI));
     } else {

@@ -17,7 +17,10 @@
 
 #define ORC_NTAB 64
 
-enum { ORC_GEOM_3D = 0, ORC_GEOM_SPHERICAL_1D = 1, ORC_GEOM_PLANAR_1D = 2 };
+/* ORC_GEOM_PLANE_3D: a 3D grid lit by a plane-parallel source at x = -infinity
+ * (the slab test of Sect. 3.1 extended to three dimensions): every row of
+ * cells along x is traced from the x = 0 face and Q is the photon flux. */
+enum { ORC_GEOM_3D = 0, ORC_GEOM_SPHERICAL_1D = 1, ORC_GEOM_PLANAR_1D = 2, ORC_GEOM_PLANE_3D = 3 };
 enum { ORC_SPEC_MONO = 0, ORC_SPEC_TABLE = 1 };
 enum { ORC_T_FIXED = 0, ORC_T_EVOLVE = 1 };
 enum { ORC_ALPHA_CONST = 0, ORC_ALPHA_POWER = 1 };
@@ -26,9 +29,9 @@ enum { ORC_W_GEOMETRIC = 0, ORC_W_MELLEMA = 1 };
 typedef struct {
     int32_t geometry;        /* ORC_GEOM_*                                        */
     int32_t n[3];            /* cells per axis (1D modes use n[0] only)           */
-    int32_t src[3];          /* source vertex, 0..n[d] (3D only)                  */
+    int32_t src[3];          /* source vertex, 0..n[d] (3D point source only)     */
     double  dx;              /* cell size [cm]                                    */
-    double  Q;               /* photons/s into 4 pi (3D, spherical); flux (planar) */
+    double  Q;               /* photons/s into 4 pi (3D, spherical); flux (planar, plane 3D) */
     double  sigma0;          /* cross-section at threshold [cm^2]                 */
     int32_t spectrum;        /* ORC_SPEC_*                                        */
     double  e_excess;        /* heating per photoionisation [erg] (mono only)     */
@@ -49,7 +52,8 @@ typedef struct {
 typedef struct {
     double n_ion;        /* sum n_H (1-x) V                                 */
     double v_ion;        /* sum (1-x) V                                     */
-    double r_ion;        /* volume-equivalent ionised radius                */
+    double r_ion;        /* volume-equivalent ionised radius; plane-parallel:
+                            ionised depth, v_ion over the lit face's area     */
     double photo_rate;   /* sum V * photoionisations per volume per second  */
     double recomb_rate;  /* sum V * alpha n_H^2 (1-x)^2                     */
     int64_t newton_fail; /* stage solves that did not converge              */

@@ -47,9 +47,9 @@ class GridSpec:
     """One photoionisation problem on a uniform Cartesian grid (CGS)."""
     name: str
     n: tuple                      # (nx, ny, nz)
-    src: tuple                    # source vertex, 0..n[d]
+    src: tuple                    # source vertex, 0..n[d] (point source)
     dx: float                     # cell size [cm]
-    Q: float                      # ionising photons / s
+    Q: float                      # ionising photons / s (point); photons / cm^2 / s (plane)
     nH_mean: float                # mean hydrogen density [cm^-3]
     density: str = "uniform"      # "uniform" | "lognormal"
     sigma_ln: float = 1.0
@@ -71,6 +71,7 @@ class GridSpec:
     t_end: float = 0.0            # [s]
     t_rec: float = 0.0            # reference recombination time [s]
     precision: str = "fp64"       # "fp64" | "fp32" | "mixed"
+    source: str = "point"         # "point" (at vertex src) | "plane" (from x = -inf)
 
     @property
     def ncells(self) -> int:
@@ -151,6 +152,23 @@ def cfg3(n: int = 256, **kw) -> GridSpec:
                  density="lognormal", sigma_ln=1.0, seed=1201, spectrum="table",
                  thermal="evolve", recomb="power", collisional=True, t_end=0.3 * tr,
                  t_rec=tr, precision="mixed")
+    return s.with_(**kw) if kw else s
+
+
+def plane(n=(100, 16, 16), density: str = "uniform", **kw) -> GridSpec:
+    """Plane-parallel source at x = -infinity (Sect. 3.1's slab test on a 3D
+    grid): monochromatic flux 1e9 photons/cm^2/s into n_H = 100 over 0.51 pc
+    along x (cell optical depth ~10 at 100 cells), T fixed at 1e4 K, no
+    recombinations or collisions, dt02; with a lognormal density (sigma_ln 1,
+    seed 5) the rows differ and the front is corrugated.  The ions per unit
+    area equal F t for a perfect integration; t_end is when they would fill
+    the grid."""
+    L, nH, F = 0.51 * PC, 100.0, 1e9
+    dx = L / n[0]
+    t_fill = L * nH / F
+    s = GridSpec(name="plane", n=tuple(n), src=(0, 0, 0), dx=dx, Q=F, nH_mean=nH,
+                 density=density, sigma_ln=1.0, seed=5, alpha_B=0.0, source="plane",
+                 t_end=0.8 * t_fill, t_rec=t_fill)
     return s.with_(**kw) if kw else s
 
 
