@@ -59,6 +59,11 @@ enum { PI_SPEC_MONO = 0, PI_SPEC_TABLE = 1 };
 enum { PI_T_FIXED = 0, PI_T_EVOLVE = 1 };
 enum { PI_ALPHA_CONST = 0, PI_ALPHA_POWER = 1 };
 enum { PI_W_GEOMETRIC = 0, PI_W_MELLEMA = 1 };
+/* PI_SRC_POINT: point source at the vertex src (Sect. 2, Sect. 5);
+ * PI_SRC_PLANE: plane-parallel source at x = -infinity (the slab test of
+ * Sect. 3.1 on a 3D grid): each row of cells along x is traced from the x = 0
+ * face, and Q is the photon flux entering that face. */
+enum { PI_SRC_POINT = 0, PI_SRC_PLANE = 1 };
 /* which state / column buffer an operation reads or writes */
 enum { PI_BUF_N = 0, PI_BUF_HALF = 1 };
 /* number of FP64 diagnostics returned by pi_diagnostics */
@@ -71,9 +76,11 @@ enum { PI_BUF_N = 0, PI_BUF_HALF = 1 };
 typedef struct {
     int32_t n[3];             /* cells per axis, each >= 1                            */
     int32_t src[3];           /* source vertex, 0 <= src[d] <= n[d] (Sect. 5: the     */
-                              /* source sits on the nearest cell vertex)              */
+                              /* source sits on the nearest cell vertex); unused for  */
+                              /* PI_SRC_PLANE                                         */
     double  dx;               /* cell size [cm], > 0                                  */
-    double  Q;                /* ionising photons per second, >= 0                    */
+    double  Q;                /* ionising photons per second, >= 0; PI_SRC_PLANE:     */
+                              /* photons per cm^2 per second into the x = 0 face      */
     double  sigma0;           /* photoionisation cross-section at 13.6 eV [cm^2] > 0  */
     int32_t spectrum;         /* PI_SPEC_MONO, or PI_SPEC_TABLE: blackbody of T_bb    */
                               /* with rates tabulated against optical depth (Sect. 2) */
@@ -92,6 +99,7 @@ typedef struct {
     double  K[4];             /* eq. (4) factors K1..K4; +inf disables a criterion    */
                               /* (dt02 of Table 1: {inf, inf, inf, 0.25})             */
     int32_t precision;        /* pi_precision                                         */
+    int32_t source;           /* PI_SRC_POINT or PI_SRC_PLANE                         */
 } pi_grid_desc;
 
 /* Caller-owned device fields (see Conventions).  E and E_half may be NULL when
@@ -167,9 +175,11 @@ pi_status pi_grid_state(pi_grid* grid, double* t, int64_t* nsteps, double* last_
 
 /* FP64 diagnostics of state PI_BUF_N with columns tau (SYNCHRONISES):
  * out[0] ions sum n_H (1-x) V, out[1] ionised volume sum (1-x) V,
- * out[2] volume-equivalent ionised radius (3 V_ion 8 / (4 pi n_octants))^1/3,
+ * out[2] volume-equivalent ionised radius (3 V_ion 8 / (4 pi n_octants))^1/3
+ * (PI_SRC_PLANE: ionised depth, V_ion over the area of the lit face),
  * out[3] photoionisations per second, out[4] recombinations per second,
- * out[5] number of non-finite cells, out[6] number of octants, out[7] time t. */
+ * out[5] number of non-finite cells, out[6] number of octants (0 for
+ * PI_SRC_PLANE), out[7] time t. */
 pi_status pi_diagnostics(pi_grid* grid, double* out, void* stream);
 
 /* Work of the micro-physics updates since the last reset (SYNCHRONISES):
@@ -295,7 +305,7 @@ const char* pi_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns the
  * value it was built with. */
-#define PI_ABI_VERSION 104
+#define PI_ABI_VERSION 105
 int pi_abi_version(void);
 
 #ifdef __cplusplus

@@ -22,6 +22,7 @@ PI_SPEC_MONO, PI_SPEC_TABLE = 0, 1
 PI_T_FIXED, PI_T_EVOLVE = 0, 1
 PI_ALPHA_CONST, PI_ALPHA_POWER = 0, 1
 PI_W_GEOMETRIC, PI_W_MELLEMA = 0, 1
+PI_SRC_POINT, PI_SRC_PLANE = 0, 1
 PI_BUF_N, PI_BUF_HALF = 0, 1
 PI_NDIAG = 8
 PI_NWORK = 5
@@ -68,6 +69,7 @@ class GridDesc(C.Structure):
         ("n_sub", C.c_int32),
         ("K", C.c_double * 4),
         ("precision", C.c_int32),
+        ("source", C.c_int32),
     ]
 
 
@@ -181,6 +183,7 @@ def desc_from_spec(spec, precision: Optional[str] = None, sigma0: float = 6.3e-1
     d.K[:] = tuple(float(k) for k in spec.K)
     prec = precision or spec.precision
     d.precision = {"fp64": PI_FP64, "fp32": PI_FP32, "mixed": PI_MIXED}[prec]
+    d.source = PI_SRC_PLANE if getattr(spec, "source", "point") == "plane" else PI_SRC_POINT
     return d
 
 

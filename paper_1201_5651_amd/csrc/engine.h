@@ -49,6 +49,7 @@ struct Engine {
     int* first = nullptr;            // chem_first[ngrids+1], then dt_first[ngrids+1]
     size_t first_cap = 0;
     int chem_blocks = 0, dt_blocks = 0;
+    int plane_rows = 0;   // rows along x of the plane-parallel grids
     // raytrace schedules, one per tile edge of SWEEP_TILES
     int4* tiles[NSWEEP] = {};
     size_t tiles_cap[NSWEEP] = {};

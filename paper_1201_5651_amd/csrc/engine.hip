@@ -23,6 +23,7 @@ namespace {
 
 int octant_count(const pi_grid_desc& d)
 {
+    if (d.source == PI_SRC_PLANE) return 0;
     int noct = 0;
     for (int o = 0; o < 8; ++o) {
         bool ok = true;
@@ -78,7 +79,9 @@ template <typename R> Params<R> make_params(const pi_grid_desc& d)
     p.sy = d.src[1];
     p.sz = d.src[2];
     p.ncell = (int64_t)d.n[0] * d.n[1] * d.n[2];
-    p.QV = R(d.Q / (d.dx * d.dx * d.dx));
+    const bool plane = d.source == PI_SRC_PLANE;
+    p.QV = R(plane ? d.Q / d.dx : d.Q / (d.dx * d.dx * d.dx));
+    p.plane = plane ? 1 : 0;
     p.sdx = R(d.sigma0 * d.dx);
     p.eps = R(d.e_excess);
     p.T_fixed = R(d.T_fixed);
@@ -169,6 +172,7 @@ template <typename R> pi_status upload_grids(Engine& e)
         D.st = G.st;
         D.part = G.part;
         D.cell_vol = G.cell_vol;
+        D.face_area = G.d.source == PI_SRC_PLANE ? (double)G.d.n[1] * G.d.n[2] * G.d.dx * G.d.dx : 0.0;
         D.noct = G.noct;
     }
     const size_t bytes = sizeof(GridDev<R>) * std::max<size_t>(1, h.size());
@@ -201,6 +205,8 @@ template <typename R> const GridDev<R>* gd(const Engine& e)
 template <typename R>
 pi_status raytrace_t(Engine& e, int state, int tau_buf, int which, hipStream_t s)
 {
+    HIP_OR(launch_plane_scan<R>(gd<R>(e), e.bd(), e.plane_rows, state, tau_buf, s),
+           "plane-parallel raytrace launch");
     for (size_t k = 0; k < e.stage_first[which].size(); ++k)
         HIP_OR(launch_sweep_stage<R>(gd<R>(e), state, tau_buf, e.tiles[which],
                                      e.stage_first[which][k], e.stage_count[which][k],
@@ -264,6 +270,7 @@ BatchDev Engine::bd() const
     b.ngrids = ngrids();
     b.chem_first = first;
     b.dt_first = first ? first + ngrids() + 1 : nullptr;
+    b.row_first = first ? first + 2 * (ngrids() + 1) : nullptr;
     b.fix_n = fix_n;
     b.fix_list = fix_list;
     b.fix_cap = (unsigned int)fix_cap;
@@ -289,9 +296,11 @@ pi_status grid_host_init(GridHost& h, const pi_grid_desc& d, const pi_fields& f)
         return fail(PI_ENOMEM, "partials allocation");
     }
     // tile schedules: every octant's tiles, grouped by tile diagonal tx+ty+tz
+    // (none for a plane-parallel source, which is traced row by row)
     for (int w = 0; w < NSWEEP; ++w) {
         const int T = SWEEP_TILES[w];
         h.tiles[w].clear();
+        if (d.source == PI_SRC_PLANE) continue;
         for (int o = 0; o < 8; ++o) {
             int ext[3];
             for (int a = 0; a < 3; ++a) ext[a] = ((o >> a) & 1) ? d.n[a] - d.src[a] : d.src[a];
@@ -325,19 +334,26 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
     e.grids = grids;
     const int G = e.ngrids();
     // launch geometry
-    std::vector<int> first(2 * (G + 1), 0);
+    // three prefix tables of G + 1 entries: micro-physics workgroups,
+    // timestep workgroups, rows of plane-parallel grids
+    std::vector<int> first(3 * (G + 1), 0);
     int64_t cells = 0;
+    int* rowf = first.data() + 2 * (G + 1);
     for (int g = 0; g < G; ++g) {
         const int64_t n = e.grids[g]->ncell;
         const pi_grid_desc& d = e.grids[g]->d;
         const int64_t cb = chem_workgroups(d.n[0], d.n[1], d.n[2]);
-        if ((int64_t)first[g] + cb > 2147483647LL) return fail(PI_EINVAL, "batch too large");
+        const int64_t rows = d.source == PI_SRC_PLANE ? (int64_t)d.n[1] * d.n[2] : 0;
+        if ((int64_t)first[g] + cb > 2147483647LL || (int64_t)rowf[g] + rows > 2147483647LL)
+            return fail(PI_EINVAL, "batch too large");
         first[g + 1] = first[g] + (int)cb;
         first[G + 1 + g + 1] = first[G + 1 + g] + e.grids[g]->nblk_dt;
+        rowf[g + 1] = rowf[g] + (int)rows;
         cells += n;
     }
     e.chem_blocks = first[G];
     e.dt_blocks = first[2 * G + 1];
+    e.plane_rows = rowf[G];
     const size_t fb = sizeof(int) * first.size();
     if (fb > e.first_cap) {
         if (e.first) (void)hipFree(e.first);

@@ -71,6 +71,7 @@ template <typename R> struct GridDev {
     DevState* st;
     double* part;         // timestep partials of the grid's blocks
     double cell_vol;
+    double face_area;     // plane-parallel source: area of the lit face [cm^2]; else 0
     int noct;
 };
 
@@ -80,6 +81,7 @@ struct BatchDev {
     int ngrids;
     const int* chem_first;   // micro-physics workgroups (CHEM_BLOCK / 64 bricks each)
     const int* dt_first;     // timestep workgroups
+    const int* row_first;    // rows along x of plane-parallel grids (0 for point sources)
     // Mixed precision: fix_n[0] is the length of fix_list, fix_n[1] counts the
     // finished workgroups of launch_chem_fix (both zero between launches).
     unsigned int* fix_n;
@@ -96,6 +98,11 @@ hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, c
 // Micro-physics of every cell of every grid from state `from` on columns
 // `tau_buf` into state `to`, over h = hscale * (st->dt if dev_dt else 1).
 // With mixed, precision-sensitive cells are listed for launch_chem_fix.
+// Raytrace of the plane-parallel grids: one wavefront per row along x of
+// every such grid (`rows` in all), a running column from the x = 0 face.
+template <typename R>
+hipError_t launch_plane_scan(const GridDev<R>* grids, const BatchDev& b, int rows, int state,
+                             int tau_buf, hipStream_t s);
 template <typename R>
 hipError_t launch_chem(const GridDev<R>* grids, const BatchDev& b, int nblocks, int from, int to,
                        int tau_buf, bool dev_dt, double hscale, unsigned long long* ctr,

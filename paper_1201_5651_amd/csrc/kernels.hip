@@ -397,6 +397,42 @@ k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int 
     }
 }
 
+// ---------------------------------------------------- plane-parallel raytrace
+// One wavefront per row: the cells' optical depths sigma0 n_H x dx are summed
+// along x in chunks of 64 (a shuffle scan within the wavefront plus the carry
+// of the chunks before), and each cell gets the column before it.  No barrier:
+// a wavefront past the last row returns whole.
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_plane_scan(const GridDev<R>* __restrict__ grids, BatchDev bd, int rows, int state, int tau_buf)
+{
+    const int row = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (row >= rows) return;
+    const int lane = threadIdx.x & 63;
+    const int g = find_grid(bd.row_first, bd.ngrids, row);
+    const GridDev<R>& G = grids[g];
+    const int nx = G.p.nx;
+    const int64_t base = (int64_t)(row - bd.row_first[g]) * nx;
+    const R* __restrict__ nH = G.nH + base;
+    const R* __restrict__ x = G.x[state] + base;
+    R* __restrict__ tau = G.tau[tau_buf] + base;
+    const R sdx = G.p.sdx;
+    R carry = R(0);
+    for (int i0 = 0; i0 < nx; i0 += 64) {
+        const int i = i0 + lane;
+        const R d = i < nx ? sdx * nH[i] * x[i] : R(0);
+        R v = d;   // inclusive scan over the wavefront
+        for (int o = 1; o < 64; o <<= 1) {
+            const R u = __shfl_up(v, o, 64);
+            if (lane >= o) v += u;
+        }
+        R before = __shfl_up(v, 1, 64);
+        if (lane == 0) before = R(0);
+        if (i < nx) tau[i] = carry + before;
+        carry += __shfl(v, 63, 64);
+    }
+}
+
 // ------------------------------------------------------ timestep + diagnostics
 template <typename T> __device__ __forceinline__ T wave_sum(T v)
 {
@@ -497,7 +533,9 @@ k_finalize(const GridDev<R>* __restrict__ grids, BatchDev bd, double t_end_arg)
         st->t_end = t_end;
         st->diag[0] = sm[1][0] * cv;
         st->diag[1] = sm[2][0] * cv;
-        st->diag[2] = cbrt(3.0 * sm[2][0] * cv * 8.0 / (4.0 * 3.14159265358979323846 * G.noct));
+        st->diag[2] = G.face_area > 0.0
+                          ? sm[2][0] * cv / G.face_area
+                          : cbrt(3.0 * sm[2][0] * cv * 8.0 / (4.0 * 3.14159265358979323846 * G.noct));
         st->diag[3] = sm[3][0] * cv;
         st->diag[4] = sm[4][0] * cv;
         st->diag[5] = sm[5][0];
@@ -551,6 +589,16 @@ hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, c
         launch_sweep_t<R, SWEEP_TILES[2]>(grids, state, tau_buf, tiles, first, count, s);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_plane_scan(const GridDev<R>* grids, const BatchDev& b, int rows, int state,
+                             int tau_buf, hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_plane_scan<R>), dim3((rows + 3) / 4), dim3(256), 0, s, grids, b, rows,
+                       state, tau_buf);
     return hipGetLastError();
 }
 
@@ -609,6 +657,8 @@ hipError_t launch_energy(int64_t n, const R* nH, const R* x, R* E, double T0, hi
     template hipError_t launch_dtdiag<R>(const GridDev<R>*, const BatchDev&, int, double,         \
                                          hipStream_t);                                             \
     template hipError_t launch_advance<R>(const GridDev<R>*, int, hipStream_t);                   \
+    template hipError_t launch_plane_scan<R>(const GridDev<R>*, const BatchDev&, int, int, int,   \
+                                             hipStream_t);                                         \
     template hipError_t launch_energy<R>(int64_t, const R*, const R*, R*, double, hipStream_t);
 PI_INSTANTIATE(double)
 PI_INSTANTIATE(float)

@@ -76,12 +76,13 @@ template <typename R> struct Params {
     int nx, ny, nz;
     int sx, sy, sz;
     int64_t ncell;
-    R QV;        // Q / dx^3                  [photons s^-1 cm^-3]
+    R QV;        // Q / dx^3 [photons s^-1 cm^-3]; plane-parallel source: flux / dx
     R sdx;       // sigma0 * dx               [cm^3] (times n_H x: optical depth per cell length)
     R eps;       // mono: heating per photoionisation [erg]
     R T_fixed, alpha_B;
     R K[4];
     int spectrum, thermal, recomb, collisional, cooling, weights, src_rule, n_sub;
+    int plane;   // 1: plane-parallel source at x = -inf
     const DevTable<R>* tab;
 };
 
@@ -153,6 +154,13 @@ template <typename R> struct CellGeom {
 template <typename R>
 PI_HD __forceinline__ CellGeom<R> cell_geom(const Params<R>& p, int i, int j, int k)
 {
+    if (p.plane) {
+        // slab cell of its row: the flux (in QV) over one cell length
+        CellGeom<R> c;
+        c.g = R(1);
+        c.ell = R(1);
+        return c;
+    }
     // exact half-integers: (2i + 1 - 2s) / 2
     const R ax = r_abs(R(2 * (i - p.sx) + 1)) * R(0.5);
     const R ay = r_abs(R(2 * (j - p.sy) + 1)) * R(0.5);

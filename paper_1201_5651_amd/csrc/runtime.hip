@@ -33,9 +33,11 @@ const std::string& last_error() { return g_err; }
 pi_status validate_desc(const pi_grid_desc* d)
 {
     if (!d) return fail(PI_EINVAL, "null descriptor");
+    if (d->source != PI_SRC_POINT && d->source != PI_SRC_PLANE) return fail(PI_EINVAL, "source");
     for (int a = 0; a < 3; ++a) {
         if (d->n[a] < 1) return fail(PI_EINVAL, "n[d] must be >= 1");
-        if (d->src[a] < 0 || d->src[a] > d->n[a]) return fail(PI_EINVAL, "source vertex outside [0, n]");
+        if (d->source == PI_SRC_POINT && (d->src[a] < 0 || d->src[a] > d->n[a]))
+            return fail(PI_EINVAL, "source vertex outside [0, n]");
     }
     const double N = (double)d->n[0] * d->n[1] * d->n[2];
     if (N >= 2147483647.0) return fail(PI_EINVAL, "grid larger than 2^31 - 1 cells");

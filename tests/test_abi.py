@@ -31,6 +31,18 @@ def test_library_loads_and_exports_every_declared_symbol():
     # the binding's constants mirror the header's
     for name in ("PI_NDIAG", "PI_NWORK", "PI_NTAB"):
         assert getattr(binding, name) == int(re.search(r"#define %s (\d+)" % name, header).group(1))
+    m = re.search(r"enum \{ PI_SRC_POINT = (\d+), PI_SRC_PLANE = (\d+) \}", header)
+    assert (binding.PI_SRC_POINT, binding.PI_SRC_PLANE) == (int(m.group(1)), int(m.group(2)))
+    # the descriptor's field order and types as the header declares them
+    body = re.search(r"typedef struct \{(.*?)\} pi_grid_desc;", header, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    decl = re.findall(r"(int32_t|double)\s+(\w+)(?:\[(\d)\])?;", body)
+    ctype = {"int32_t": C.c_int32, "double": C.c_double}
+    want = [(n, ctype[t] * int(k) if k else ctype[t]) for t, n, k in decl]
+    got = [(n, t) for n, t in binding.GridDesc._fields_]
+    assert [n for n, _ in want] == [n for n, _ in got]
+    for (n, a), (_, b) in zip(want, got):
+        assert C.sizeof(a) == C.sizeof(b) and getattr(a, "_type_", a) == getattr(b, "_type_", b), n
 
 
 def test_descriptor_validation_rejects_bad_input():
@@ -53,6 +65,9 @@ def test_descriptor_validation_rejects_bad_input():
     cases.append(d)
     d = binding.desc_from_spec(spec)
     d.K[3] = -1.0
+    cases.append(d)
+    d = binding.desc_from_spec(spec)
+    d.source = 2
     cases.append(d)
     for d in cases:
         h = C.c_void_p()
