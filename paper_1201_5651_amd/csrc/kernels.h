@@ -19,16 +19,33 @@ constexpr int NSWEEP = 3;
 constexpr int SWEEP_TILES[NSWEEP] = { 4, 8, 16 };
 constexpr int SWEEP_T_LARGEST = 16;
 // Threads per workgroup of the micro-physics kernel.  Each wavefront
-// integrates one brick of CHEM_BRICK^3 = 64 neighbouring cells (bricks in x,
-// then y, then z order; bricks that overhang the grid leave lanes idle): cells
-// that need many Newton iterations cluster in space, so a compact brick wastes
-// fewer lanes than a 64-cell row.
-constexpr int CHEM_BLOCK = 256, CHEM_BRICK = 4;
+// integrates one brick of CHEM_BX x CHEM_BY x CHEM_BZ = 64 neighbouring cells
+// (bricks in x, then y, then z order; bricks that overhang the grid leave
+// lanes idle): cells that need many Newton iterations cluster in space, so a
+// compact brick wastes fewer lanes than a 64-cell row.  The four bricks of a
+// workgroup lie side by side along x (16 cells); pairs of consecutive
+// workgroups, which share 128-byte lines, are kept on one XCD (xcd_block).
+constexpr int CHEM_BLOCK = 256, CHEM_BX = 4, CHEM_BY = 4, CHEM_BZ = 4;
+// XCDs of the device: the hardware hands workgroup ids to them in turn.
+constexpr int NXCD = 8;
+// Logical block of hardware workgroup id w in a launch of n workgroups: the two
+// logical blocks 2m and 2m + 1, which share 128-byte lines, go to the same XCD
+// (m % NXCD), and successive pairs go round the XCDs so that every XCD still
+// samples the whole grid (work per cell varies in space).  A bijection of
+// [0, n): the last n % (2 NXCD) blocks keep their ids.
+__host__ __device__ constexpr int xcd_block(int w, int n)
+{
+    const int full = n - n % (2 * NXCD);
+    if (w >= full) return w;
+    const int x = w % NXCD, slot = w / NXCD;
+    return 2 * NXCD * (slot / 2) + 2 * x + slot % 2;
+}
+static_assert(CHEM_BX * CHEM_BY * CHEM_BZ == 64, "one brick per wavefront");
 // Bricks of a grid and micro-physics workgroups that cover them.
 __host__ __device__ constexpr int64_t chem_bricks(int nx, int ny, int nz)
 {
-    return (int64_t)((nx + CHEM_BRICK - 1) / CHEM_BRICK) * ((ny + CHEM_BRICK - 1) / CHEM_BRICK) *
-           ((nz + CHEM_BRICK - 1) / CHEM_BRICK);
+    return (int64_t)((nx + CHEM_BX - 1) / CHEM_BX) * ((ny + CHEM_BY - 1) / CHEM_BY) *
+           ((nz + CHEM_BZ - 1) / CHEM_BZ);
 }
 __host__ __device__ constexpr int64_t chem_workgroups(int nx, int ny, int nz)
 {

@@ -320,18 +320,20 @@ k_chem(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int 
        int dev_dt, double hscale, unsigned long long* ctr, int mixed)
 {
     __shared__ DevTable<R> s_tab;
-    const int g = find_grid(bd.chem_first, bd.ngrids, blockIdx.x);
+    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int g = find_grid(bd.chem_first, bd.ngrids, lb);
     const GridDev<R>& G = grids[g];
     const Params<R> pl = table_to_lds(G.p, s_tab);
-    const int brick = (blockIdx.x - bd.chem_first[g]) * (CHEM_BLOCK / 64) + (int)(threadIdx.x >> 6);
+    const int brick = (lb - bd.chem_first[g]) * (CHEM_BLOCK / 64) + (int)(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int nbx = (pl.nx + CHEM_BRICK - 1) / CHEM_BRICK, nby = (pl.ny + CHEM_BRICK - 1) / CHEM_BRICK;
-    const int i = CHEM_BRICK * (brick % nbx) + (lane & 3);
-    const int j = CHEM_BRICK * ((brick / nbx) % nby) + ((lane >> 2) & 3);
-    const int k = CHEM_BRICK * (brick / (nbx * nby)) + (lane >> 4);
+    const int nbx = (pl.nx + CHEM_BX - 1) / CHEM_BX, nby = (pl.ny + CHEM_BY - 1) / CHEM_BY;
+    const int i = CHEM_BX * (brick % nbx) + (lane & 3);
+    const int j = CHEM_BY * ((brick / nbx) % nby) + ((lane >> 2) & 3);
+    const int k = CHEM_BZ * (brick / (nbx * nby)) + (lane >> 4);
     const bool inside = i < pl.nx && j < pl.ny && k < pl.nz;
     const int q = inside ? i + pl.nx * (j + pl.ny * k) : 0;
-    static_assert(CHEM_BRICK == 4 && CHEM_BLOCK % 64 == 0, "lane -> cell map assumes 4^3 bricks");
+    static_assert(CHEM_BX == 4 && CHEM_BY == 4 && CHEM_BZ == 4 && CHEM_BLOCK % 64 == 0,
+                  "lane -> cell map assumes 4^3 bricks");
     Work w{};
     bool flag = false;
     if (inside) {
