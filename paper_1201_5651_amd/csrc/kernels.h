@@ -53,7 +53,7 @@ __host__ __device__ constexpr int64_t chem_workgroups(int nx, int ny, int nz)
 }
 // Threads per workgroup and largest number of workgroups per grid of the
 // timestep/diagnostics reduction.
-constexpr int DT_BLOCK = 256, DT_MAX_BLOCKS = 1024;
+constexpr int DT_BLOCK = 256, DT_MAX_BLOCKS = 4096;
 // Per-block partials of the timestep/diagnostics reduction:
 // [0] min dt limit, [1] sum n(1-x), [2] sum (1-x), [3] sum A, [4] sum recomb, [5] non-finite cells
 constexpr int NPART = 6;
