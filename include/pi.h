@@ -114,6 +114,10 @@ typedef struct {
     void* x_half;
     void* E_half;
     void* tau_half;
+    void* nH_half;   /* optional, may be NULL: the density at t + dt/2 that the */
+                     /* raytrace of the half-step state uses (Sect. 2.2: the    */
+                     /* time-centred density of a hydrodynamics code); NULL:    */
+                     /* nH.  Read at every raytrace of PI_BUF_HALF.             */
 } pi_fields;
 
 typedef struct pi_grid pi_grid;
@@ -305,7 +309,7 @@ const char* pi_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns the
  * value it was built with. */
-#define PI_ABI_VERSION 105
+#define PI_ABI_VERSION 106
 int pi_abi_version(void);
 
 #ifdef __cplusplus

@@ -100,6 +100,7 @@ def lib():
         L.orc_timestep.argtypes = [pd, dp, dp, dp, dp, dp]
         L.orc_chem.argtypes = [pd, dp, dp, dp, dp, C.c_double, dp, dp]
         L.orc_step.argtypes = [pd, dp, dp, dp, dp, dp, C.c_double, C.c_int, dp]
+        L.orc_step_tc.argtypes = [pd, dp, dp, dp, dp, dp, dp, C.c_double, C.c_int, dp]
         L.orc_diagnostics.argtypes = [pd, dp, dp, dp, dp, C.POINTER(Diag)]
         L.orc_newton_failures.restype = C.c_int64
         L.orc_front_index_1d.argtypes = [C.c_int, dp]
@@ -219,13 +220,15 @@ class Problem:
         lib().orc_chem(C.byref(self.desc), _p(nH), _p(x0), _p(E0), _p(tau), h, _p(x1), _p(E1))
         return x1, E1
 
-    def step(self, state, t_end, algo=3):
-        """Advance ``state`` (dict nH, x, E or None, tau, t) by one step in place."""
+    def step(self, state, t_end, algo=3, nH_half=None):
+        """Advance ``state`` (dict nH, x, E or None, tau, t) by one step in place;
+        ``nH_half``: time-centred density for the half-step raytrace."""
         t = C.c_double(state["t"])
         dt = C.c_double()
-        rc = lib().orc_step(C.byref(self.desc), _p(state["nH"]), _p(state["x"]),
-                            _p(state["E"]), _p(state["tau"]), C.byref(t), t_end, algo,
-                            C.byref(dt))
+        nh = None if nH_half is None else np.ascontiguousarray(nH_half, dtype=np.float64)
+        rc = lib().orc_step_tc(C.byref(self.desc), _p(state["nH"]), _p(nh), _p(state["x"]),
+                               _p(state["E"]), _p(state["tau"]), C.byref(t), t_end, algo,
+                               C.byref(dt))
         state["t"] = t.value
         return rc, dt.value
 

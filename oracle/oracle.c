@@ -976,6 +976,16 @@ int orc_chem(const orc_desc* g, const double* nH, const double* x0, const double
 int orc_step(const orc_desc* g, const double* nH, double* x, double* E, double* tau,
              double* t, double t_end, int algo, double* dt_out)
 {
+    return orc_step_tc(g, nH, NULL, x, E, tau, t, t_end, algo, dt_out);
+}
+
+/* The same step with a time-centred density for the raytrace of the half-step
+ * state (Sect. 2.2: the second raytrace uses the density and ion fraction of
+ * the half step; a hydrodynamics code supplies the density at t + dt/2).  The
+ * micro-physics and the other raytraces use nH.  nH_half NULL: nH. */
+int orc_step_tc(const orc_desc* g, const double* nH, const double* nH_half, double* x, double* E,
+                double* tau, double* t, double t_end, int algo, double* dt_out)
+{
     const int64_t N = ncells(g);
     double dt;
     orc_timestep(g, nH, x, E, tau, &dt);
@@ -988,7 +998,7 @@ int orc_step(const orc_desc* g, const double* nH, double* x, double* E, double* 
         double* Es = E ? (double*)malloc(sizeof(double) * (size_t)N) : NULL;
         double* ts = (double*)malloc(sizeof(double) * (size_t)N);
         orc_chem(g, nH, x, E, tau, 0.5 * dt, xs, Es);
-        orc_raytrace_sc(g, nH, xs, ts);
+        orc_raytrace_sc(g, nH_half ? nH_half : nH, xs, ts);
         orc_chem(g, nH, x, E, ts, dt, x, E);
         free(xs);
         free(Es);

@@ -79,6 +79,8 @@ int    orc_chem(const orc_desc* g, const double* nH, const double* x0, const dou
                 const double* tau, double h, double* x1, double* E1);
 int    orc_step(const orc_desc* g, const double* nH, double* x, double* E, double* tau,
                 double* t, double t_end, int algo, double* dt_out);
+int    orc_step_tc(const orc_desc* g, const double* nH, const double* nH_half, double* x,
+                   double* E, double* tau, double* t, double t_end, int algo, double* dt_out);
 int    orc_diagnostics(const orc_desc* g, const double* nH, const double* x, const double* E,
                        const double* tau, orc_diag* out);
 int64_t orc_newton_failures(void);

@@ -74,7 +74,8 @@ class GridDesc(C.Structure):
 
 
 class Fields(C.Structure):
-    _fields_ = [(k, C.c_void_p) for k in ("nH", "x", "E", "tau", "x_half", "E_half", "tau_half")]
+    _fields_ = [(k, C.c_void_p) for k in ("nH", "x", "E", "tau", "x_half", "E_half", "tau_half",
+                                          "nH_half")]
 
 
 class ServerDesc(C.Structure):
@@ -187,13 +188,13 @@ def desc_from_spec(spec, precision: Optional[str] = None, sigma0: float = 6.3e-1
     return d
 
 
-FIELD_NAMES = ("nH", "x", "E", "tau", "x_half", "E_half", "tau_half")
+FIELD_NAMES = ("nH", "x", "E", "tau", "x_half", "E_half", "tau_half", "nH_half")
 
 
 class GridFields:
     """Device field tensors of one grid (torch, caller-owned memory of the ABI)."""
 
-    def __init__(self, spec, precision: str, device):
+    def __init__(self, spec, precision: str, device, time_centred_density: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the photoionisation library needs a GPU (no CPU fallback)")
@@ -207,6 +208,8 @@ class GridFields:
         evolve = spec.thermal == "evolve"
         self.E = z() if evolve else None
         self.E_half = z() if evolve else None
+        # time-centred density for the half-step raytrace (None: nH)
+        self.nH_half = z() if time_centred_density else None
 
     def abi_fields(self) -> Fields:
         f = Fields()
@@ -231,10 +234,11 @@ class Grid:
     Methods map one-to-one onto the ABI calls, on torch's current stream.
     """
 
-    def __init__(self, spec, device: str = "cuda:0", precision: Optional[str] = None):
+    def __init__(self, spec, device: str = "cuda:0", precision: Optional[str] = None,
+                 time_centred_density: bool = False):
         self.spec = spec
         self.precision = precision or spec.precision
-        self._fl = GridFields(spec, self.precision, device)
+        self._fl = GridFields(spec, self.precision, device, time_centred_density)
         self.dtype, self.device = self._fl.dtype, self._fl.device
         for k in FIELD_NAMES:
             setattr(self, k, getattr(self._fl, k))
@@ -343,10 +347,15 @@ class Batch:
     each step replayed from a captured HIP graph).  ``grids[i]`` holds the
     field tensors of grid i; every grid keeps its own clock and t_end."""
 
-    def __init__(self, specs, device: str = "cuda:0", precision: Optional[str] = None):
+    def __init__(self, specs, device: str = "cuda:0", precision: Optional[str] = None,
+                 time_centred_density=False):
+        """``time_centred_density``: a bool for every grid, or one per grid,
+        giving the grid an ``nH_half`` field for its half-step raytraces."""
         self.specs = list(specs)
         self.precision = precision or self.specs[0].precision
-        self.grids = [GridFields(s, self.precision, device) for s in self.specs]
+        tc = (list(time_centred_density) if isinstance(time_centred_density, (list, tuple))
+              else [bool(time_centred_density)] * len(self.specs))
+        self.grids = [GridFields(s, self.precision, device, c) for s, c in zip(self.specs, tc)]
         n = len(self.specs)
         self._descs = (GridDesc * n)(*[desc_from_spec(s, self.precision) for s in self.specs])
         self._fields = (Fields * n)(*[g.abi_fields() for g in self.grids])

@@ -162,6 +162,8 @@ template <typename R> pi_status upload_grids(Engine& e)
         D.pd.tab = static_cast<const DevTable<double>*>(td);
         D.p.tab = static_cast<const DevTable<R>*>(sizeof(R) == sizeof(double) ? td : tf);
         D.nH = fld<R>(G.f.nH);
+        D.nHr[0] = D.nH;
+        D.nHr[1] = G.f.nH_half ? fld<R>(G.f.nH_half) : D.nH;
         D.x[0] = fld<R>(G.f.x);
         D.x[1] = fld<R>(G.f.x_half);
         const bool ev = G.d.thermal == PI_T_EVOLVE;

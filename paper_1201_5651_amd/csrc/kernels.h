@@ -82,6 +82,7 @@ template <typename R> struct GridDev {
     Params<R> p;          // parameters in the grid's arithmetic
     Params<double> pd;    // double parameters (mixed-precision re-solve)
     const R* nH;
+    const R* nHr[2];      // density a raytrace of state 0 / 1 uses (1: time-centred, or nH)
     R* x[2];
     R* E[2];              // null when the temperature is fixed
     R* tau[2];

@@ -127,7 +127,7 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     const int4 tl = tiles[first + blockIdx.x];
     const GridDev<R>& G = grids[tl.x >> 3];
     const Params<R> p = G.p;
-    const R* __restrict__ nH = G.nH;
+    const R* __restrict__ nH = G.nHr[state];
     const R* __restrict__ xs = G.x[state];
     R* __restrict__ tau = G.tau[tau_buf];
     const int oct = tl.x & 7;
@@ -415,7 +415,7 @@ k_plane_scan(const GridDev<R>* __restrict__ grids, BatchDev bd, int rows, int st
     const GridDev<R>& G = grids[g];
     const int nx = G.p.nx;
     const int64_t base = (int64_t)(row - bd.row_first[g]) * nx;
-    const R* __restrict__ nH = G.nH + base;
+    const R* __restrict__ nH = G.nHr[state] + base;
     const R* __restrict__ x = G.x[state] + base;
     R* __restrict__ tau = G.tau[tau_buf] + base;
     const R sdx = G.p.sdx;
