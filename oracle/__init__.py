@@ -94,6 +94,7 @@ def lib():
             f.argtypes = [pd, dp, dp, dp]
         L.orc_cell_env.argtypes = [pd, C.c_int64, dp, dp]
         L.orc_micro_cell.argtypes = [pd] + [C.c_double] * 7 + [dp, dp]
+        L.orc_micro_cell_avg.argtypes = [pd] + [C.c_double] * 7 + [dp, dp, dp]
         L.orc_rhs_cell.argtypes = [pd] + [C.c_double] * 6 + [dp, dp]
         L.orc_cell_dt.argtypes = [pd] + [C.c_double] * 6
         L.orc_cell_dt.restype = C.c_double
@@ -101,6 +102,7 @@ def lib():
         L.orc_chem.argtypes = [pd, dp, dp, dp, dp, C.c_double, dp, dp]
         L.orc_step.argtypes = [pd, dp, dp, dp, dp, dp, C.c_double, C.c_int, dp]
         L.orc_step_tc.argtypes = [pd, dp, dp, dp, dp, dp, dp, C.c_double, C.c_int, dp]
+        L.orc_a1_pass.argtypes = [pd, dp, dp, dp, C.c_double, dp, dp]
         L.orc_diagnostics.argtypes = [pd, dp, dp, dp, dp, C.POINTER(Diag)]
         L.orc_newton_failures.restype = C.c_int64
         L.orc_front_index_1d.argtypes = [C.c_int, dp]
@@ -200,6 +202,14 @@ class Problem:
                              C.byref(x1), C.byref(E1))
         return x1.value, E1.value
 
+    def micro_cell_avg(self, nH, geo, ell, tau_in, x0, E0, h):
+        """(x1, E1, tau_avg): the micro-integration and the cell's time-averaged
+        optical depth -ln <exp(-n sigma0 ell x(t))> over h."""
+        x1, E1, ta = C.c_double(), C.c_double(), C.c_double()
+        lib().orc_micro_cell_avg(C.byref(self.desc), nH, geo, ell, tau_in, x0, E0, h,
+                                 C.byref(x1), C.byref(E1), C.byref(ta))
+        return x1.value, E1.value, ta.value
+
     def rhs_cell(self, nH, geo, ell, tau_in, x, E):
         fx, fE = C.c_double(), C.c_double()
         lib().orc_rhs_cell(C.byref(self.desc), nH, geo, ell, tau_in, x, E, C.byref(fx),
@@ -231,6 +241,19 @@ class Problem:
                                C.byref(dt))
         state["t"] = t.value
         return rc, dt.value
+
+    def a1_pass(self, nH, x, E, dt):
+        """Algorithm 1's combined pass over dt: returns (x, E, tau_avg, kbar)
+        without touching the inputs."""
+        x1 = np.ascontiguousarray(x, dtype=np.float64).copy()
+        E1 = None if E is None else np.ascontiguousarray(E, dtype=np.float64).copy()
+        ta = np.zeros_like(x1)
+        kb = np.zeros_like(x1)
+        rc = lib().orc_a1_pass(C.byref(self.desc), _p(np.ascontiguousarray(nH, dtype=np.float64)),
+                               _p(x1), _p(E1), dt, _p(ta), _p(kb))
+        if rc != 0:
+            raise RuntimeError(f"orc_a1_pass failed ({rc})")
+        return x1, E1, ta, kb
 
     def diagnostics(self, state):
         d = Diag()

@@ -24,6 +24,8 @@
  *     on the instantaneous columns; raytrace of the half-step state; microphysics
  *     over dt from the initial state on the time-centred columns   -> orc_step
  *   - algorithm 2 (Sect. 2.2), the first-order variant, for order tests only
+ *   - algorithm 1 (Sect. 2.1): one pass in raytrace order integrating every
+ *     cell on its time-averaged entering column                -> orc_a1_pass
  *   - 1D spherical and plane-parallel modes of Sect. 3 (tests only)
  *   - front locator (eq. 5)
  *
@@ -188,7 +190,7 @@ double orc_table_eval(const double* table, int which, double tau, double* dvdtau
         if (dvdtau) *dvdtau = -V1[0];
         return V[0] - V1[0] * tau;
     }
-    if (tau >= tn[ORC_NTAB - 1]) {
+    if (tau >= tn[ORC_NTAB - 1] || !(V[0] > 0.0)) {   /* beyond the table, or no source */
         if (dvdtau) *dvdtau = 0.0;
         return 0.0;
     }
@@ -818,7 +820,8 @@ static int substeps(const orc_desc* g, const cellenv* c, double x0, double E0, d
 /* One step of the two-stage, L-stable, stiffly accurate SDIRK method
  * (gamma = 1 - 1/sqrt 2) of size hs; the second stage starts from
  * y + ((1-gamma)/gamma)(Y1 - y).  Returns 1 if a stage needed the fallback. */
-static int sdirk_step(const orc_desc* g, const cellenv* c, double hs, double* x, double* E)
+static int sdirk_step(const orc_desc* g, const cellenv* c, double hs, double* x, double* E,
+                      double* x_stage1)
 {
     const double gam = 1.0 - sqrt(0.5);
     const double cst = (1.0 - gam) / gam;
@@ -830,7 +833,27 @@ static int sdirk_step(const orc_desc* g, const cellenv* c, double hs, double* x,
     fb |= stage_solve(g, c, xb, Eb, gam * hs, &X2, &F2);
     *x = X2;
     *E = F2;
+    if (x_stage1) *x_stage1 = X1;
     return fb;
+}
+
+/* Integral of exp(-tau(t)) over an interval, held as S exp(-m) so that very
+ * thick cells do not underflow: add(w, tau) adds the term w exp(-tau). */
+typedef struct {
+    double m, S;
+} lse_acc;
+
+static void lse_add(lse_acc* a, double w, double tau)
+{
+    if (a->S == 0.0) {
+        a->m = tau;
+        a->S = w;
+    } else if (tau >= a->m) {
+        a->S += w * exp(-(tau - a->m));
+    } else {
+        a->S = a->S * exp(-(a->m - tau)) + w;
+        a->m = tau;
+    }
 }
 
 /* Micro-integration M(x0, E0; tau_in, h): eq.(2) over h with the entering
@@ -842,9 +865,26 @@ static int sdirk_step(const orc_desc* g, const cellenv* c, double hs, double* x,
  * a factor REJ_E (while s > 1), and an accepted substep is doubled again when
  * the position allows.  E is held at
  * or above the temperature floor between substeps. */
+static void micro_avg(const orc_desc* g, const cellenv* c, double x0, double E0, double h,
+                      double* x1, double* E1, double* tau_avg);
+
 static void micro(const orc_desc* g, const cellenv* c, double x0, double E0, double h,
                   double* x1, double* E1)
 {
+    micro_avg(g, c, x0, E0, h, x1, E1, NULL);
+}
+
+/* The micro-integration, and (tau_avg not NULL) the cell's time-averaged
+ * optical depth -ln <exp(-n_H sigma0 ell x(t))> over the interval (A1,
+ * Sect. 2.1): the attenuation is integrated with the same SDIRK stages as
+ * (x, E), i.e. weights (1 - gamma, gamma) at the two stage values of x of
+ * every accepted substep (reading: the paper integrates it with CVODE). */
+static void micro_avg(const orc_desc* g, const cellenv* c, double x0, double E0, double h,
+                      double* x1, double* E1, double* tau_avg)
+{
+    const double gam = 1.0 - sqrt(0.5);
+    const double k = c->nH * g->sigma0 * c->ell;   /* own optical depth per unit x */
+    lse_acc acc = { 0.0, 0.0 };
     double x = x0, E = E0;
     if (h > 0.0) {
         if (g->thermal == ORC_T_EVOLVE && E < e_floor(g, c->nH, x)) E = e_floor(g, c->nH, x);
@@ -854,13 +894,17 @@ static void micro(const orc_desc* g, const cellenv* c, double x0, double E0, dou
         long p = 0, s = top;
         while (p < U) {
             const double hs = h * (double)s / (double)U;
-            double xn = x, En = E;
-            sdirk_step(g, c, hs, &xn, &En);
+            double xn = x, En = E, X1;
+            sdirk_step(g, c, hs, &xn, &En, &X1);
             int bad = fabs(xn - x) > REJ_DX ||
                       (g->thermal == ORC_T_EVOLVE && (En > REJ_E * E || En * REJ_E < E));
             if (bad && s > 1) {
                 s >>= 1;
                 continue;
+            }
+            if (tau_avg) {
+                lse_add(&acc, hs * (1.0 - gam), k * X1);
+                lse_add(&acc, hs * gam, k * xn);
             }
             x = xn;
             E = En;
@@ -871,6 +915,7 @@ static void micro(const orc_desc* g, const cellenv* c, double x0, double E0, dou
     }
     *x1 = x;
     *E1 = E;
+    if (tau_avg) *tau_avg = h > 0.0 ? acc.m - log(acc.S / h) : k * x0;
 }
 
 int orc_micro_cell(const orc_desc* g, double nH, double geo, double ell, double tau_in,
@@ -880,6 +925,16 @@ int orc_micro_cell(const orc_desc* g, double nH, double geo, double ell, double 
     make_env(g, nH, geo, ell, tau_in, &c);
     double e;
     micro(g, &c, x0, E0, h, x1, E1 ? E1 : &e);
+    return 0;
+}
+
+int orc_micro_cell_avg(const orc_desc* g, double nH, double geo, double ell, double tau_in,
+                       double x0, double E0, double h, double* x1, double* E1, double* tau_avg)
+{
+    cellenv c;
+    make_env(g, nH, geo, ell, tau_in, &c);
+    double e;
+    micro_avg(g, &c, x0, E0, h, x1, E1 ? E1 : &e, tau_avg);
     return 0;
 }
 
@@ -962,7 +1017,9 @@ int orc_chem(const orc_desc* g, const double* nH, const double* x0, const double
     return 0;
 }
 
-/* One step of algorithm 3 (algo = 3) or algorithm 2 (algo = 2), Sect. 2.2.
+/* One step of algorithm 3 (algo = 3), algorithm 2 (algo = 2), Sect. 2.2, or
+ * algorithm 1 (algo = 1), Sect. 2.1 (orc_a1_pass between the timestep and the
+ * raytrace of the new state).
  * On entry tau holds the columns of the current state (from the raytrace that
  * ended the previous step, or the initial raytrace); on exit it holds the
  * columns of the new state, ready for the next step.
@@ -973,6 +1030,104 @@ int orc_chem(const orc_desc* g, const double* nH, const double* x0, const double
  *      the state at t_n on those time-centred columns.
  *      A2: micro-integrate over dt on the columns of t_n.
  *   3. raytrace the new state. */
+/* Algorithm 1 (Sect. 2.1): one pass over the cells in the order of the
+ * raytrace, in which every cell is integrated over dt on the time-averaged
+ * column entering it, and passes on its own time-averaged optical depth.
+ * Reading: the short-characteristics interpolation of raytrace_sc_3d with each
+ * cell's n_H x replaced by kbar = tau_own / (sigma0 ell), where tau_own =
+ * -ln <exp(-n_H sigma0 ell x(t))> over the step (micro_avg) and ell the chord of
+ * the cell's rate: a cell whose x does not change passes on exactly n_H x.
+ * Outputs: x, E advanced in place; tau_avg = sigma0 times the time-averaged
+ * column to each cell's entry face; kbar per cell [cm^-3].  Point sources in
+ * 3D, and slabs (1D and plane-parallel 3D rows). */
+int orc_a1_pass(const orc_desc* g, const double* nH, double* x, double* E, double dt,
+                double* tau_avg, double* kbar)
+{
+    if (!g || !nH || !x || !tau_avg || !kbar) return -1;
+    if (g->geometry == ORC_GEOM_SPHERICAL_1D) return -1;
+    const int64_t N = ncells(g);
+    if (g->geometry != ORC_GEOM_3D) {
+        /* slabs: every row from its lit face */
+        const int64_t nx = g->n[0], rows = g->geometry == ORC_GEOM_PLANE_3D
+                                                ? (int64_t)g->n[1] * g->n[2] : 1;
+        for (int64_t r = 0; r < rows; ++r) {
+            double Ncol = 0.0;
+            for (int64_t i = 0; i < nx; ++i) {
+                const int64_t q = r * nx + i;
+                double geo, ell, tb, e1, Eq = E ? E[q] : 0.0;
+                orc_cell_env(g, q, &geo, &ell);
+                cellenv c;
+                make_env(g, nH[q], geo, ell, g->sigma0 * Ncol, &c);
+                tau_avg[q] = g->sigma0 * Ncol;
+                micro_avg(g, &c, x[q], Eq, dt, &x[q], &e1, &tb);
+                if (E) E[q] = e1;
+                kbar[q] = tb / (g->sigma0 * ell);
+                Ncol += kbar[q] * g->dx;
+            }
+        }
+        return 0;
+    }
+    const int nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    double* Nc = (double*)malloc(sizeof(double) * (size_t)N);
+    if (!Nc) return -2;
+    for (int oz = -1; oz <= 1; oz += 2)
+    for (int oy = -1; oy <= 1; oy += 2)
+    for (int ox = -1; ox <= 1; ox += 2) {
+        int o[3] = { ox, oy, oz };
+        int ext[3];
+        for (int d = 0; d < 3; ++d) ext[d] = o[d] > 0 ? g->n[d] - g->src[d] : g->src[d];
+        if (ext[0] <= 0 || ext[1] <= 0 || ext[2] <= 0) continue;
+        for (int lz = 0; lz < ext[2]; ++lz)
+        for (int ly = 0; ly < ext[1]; ++ly)
+        for (int lx = 0; lx < ext[0]; ++lx) {
+            int l[3] = { lx, ly, lz };
+            int gi[3];
+            for (int d = 0; d < 3; ++d) gi[d] = o[d] > 0 ? g->src[d] + l[d] : g->src[d] - 1 - l[d];
+            int64_t idx = gi[0] + (int64_t)nx * (gi[1] + (int64_t)ny * gi[2]);
+            cellpos c;
+            cell_pos(g, gi[0], gi[1], gi[2], &c);
+            const int a = c.a;
+            const double norm = sqrt(c.ad[0] * c.ad[0] + c.ad[1] * c.ad[1] + c.ad[2] * c.ad[2]);
+            const double ds = g->dx * norm / c.ad[a];
+            double Nin = 0.0;
+            if (l[a] > 0) {
+                int b = (a + 1) % 3, cc = (a + 2) % 3;
+                double db = c.ad[b] / c.ad[a];
+                double dc = c.ad[cc] / c.ad[a];
+                double sw = 0.0, sum = 0.0;
+                for (int mb = 0; mb <= 1; ++mb)
+                for (int mc = 0; mc <= 1; ++mc) {
+                    int ln[3];
+                    ln[a] = l[a] - 1;
+                    ln[b] = l[b] - mb;
+                    ln[cc] = l[cc] - mc;
+                    if (ln[b] < 0 || ln[cc] < 0) continue;
+                    int gn[3];
+                    for (int d = 0; d < 3; ++d) gn[d] = o[d] > 0 ? g->src[d] + ln[d] : g->src[d] - 1 - ln[d];
+                    int64_t nidx = gn[0] + (int64_t)nx * (gn[1] + (int64_t)ny * gn[2]);
+                    double w = (mb ? db : 1.0 - db) * (mc ? dc : 1.0 - dc);
+                    double T = Nc[nidx] + 0.5 * ds * kbar[nidx];
+                    if (g->weights == ORC_W_MELLEMA) w = w / fmax(TAU0_MELLEMA, g->sigma0 * T);
+                    sum += w * T;
+                    sw += w;
+                }
+                Nin = sum / sw;
+            }
+            double geo, ell, tb, e1, Eq = E ? E[idx] : 0.0;
+            env_3d(g, &c, &geo, &ell);
+            cellenv ce;
+            make_env(g, nH[idx], geo, ell, g->sigma0 * Nin, &ce);
+            tau_avg[idx] = g->sigma0 * Nin;
+            micro_avg(g, &ce, x[idx], Eq, dt, &x[idx], &e1, &tb);
+            if (E) E[idx] = e1;
+            kbar[idx] = tb / (g->sigma0 * ell);
+            Nc[idx] = Nin + 0.5 * ds * kbar[idx];
+        }
+    }
+    free(Nc);
+    return 0;
+}
+
 int orc_step(const orc_desc* g, const double* nH, double* x, double* E, double* tau,
              double* t, double t_end, int algo, double* dt_out)
 {
@@ -993,7 +1148,14 @@ int orc_step_tc(const orc_desc* g, const double* nH, const double* nH_half, doub
     if (!(rem > 0.0)) { if (dt_out) *dt_out = 0.0; return 1; }
     if (dt > rem) dt = rem;
     if (rem - dt <= 1e-12 * t_end) dt = rem;
-    if (algo == 3) {
+    if (algo == 1) {
+        double* ta = (double*)malloc(sizeof(double) * (size_t)N);
+        double* kb = (double*)malloc(sizeof(double) * (size_t)N);
+        int rc = orc_a1_pass(g, nH, x, E, dt, ta, kb);
+        free(ta);
+        free(kb);
+        if (rc != 0) return rc;
+    } else if (algo == 3) {
         double* xs = (double*)malloc(sizeof(double) * (size_t)N);
         double* Es = E ? (double*)malloc(sizeof(double) * (size_t)N) : NULL;
         double* ts = (double*)malloc(sizeof(double) * (size_t)N);

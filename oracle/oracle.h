@@ -68,6 +68,9 @@ int    orc_raytrace_lc(const orc_desc* g, const double* nH, const double* x, dou
 int    orc_cell_env(const orc_desc* g, int64_t cell, double* geo, double* ell);
 int    orc_micro_cell(const orc_desc* g, double nH, double geo, double ell, double tau_in,
                       double x0, double E0, double h, double* x1, double* E1);
+/* orc_micro_cell plus the cell's time-averaged optical depth over h (A1) */
+int    orc_micro_cell_avg(const orc_desc* g, double nH, double geo, double ell, double tau_in,
+                          double x0, double E0, double h, double* x1, double* E1, double* tau_avg);
 int    orc_rhs_cell(const orc_desc* g, double nH, double geo, double ell, double tau_in,
                     double x, double E, double* fx, double* fE);
 double orc_cell_dt(const orc_desc* g, double nH, double geo, double ell, double tau_in,
@@ -81,6 +84,11 @@ int    orc_step(const orc_desc* g, const double* nH, double* x, double* E, doubl
                 double* t, double t_end, int algo, double* dt_out);
 int    orc_step_tc(const orc_desc* g, const double* nH, const double* nH_half, double* x,
                    double* E, double* tau, double* t, double t_end, int algo, double* dt_out);
+/* Algorithm 1's combined raytrace and micro-physics pass over dt (Sect. 2.1);
+ * orc_step with algo = 1 is the timestep, this pass and a raytrace of the new
+ * state. */
+int    orc_a1_pass(const orc_desc* g, const double* nH, double* x, double* E, double dt,
+                   double* tau_avg, double* kbar);
 int    orc_diagnostics(const orc_desc* g, const double* nH, const double* x, const double* E,
                        const double* tau, orc_diag* out);
 int64_t orc_newton_failures(void);

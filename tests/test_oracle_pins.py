@@ -641,3 +641,78 @@ def test_time_centred_density_for_the_half_step_raytrace(oracle_lib):
     pb.step(c, spec.t_end, nH_half=0.7 * nH)
     assert np.all(c["x"] <= d["x"] * (1 + 1e-12))
     assert (1 - c["x"]).sum() > (1 - d["x"]).sum()
+
+
+# ------------------------------------------------------- algorithm 1 (Sect. 2.1)
+def test_a1_time_averaged_attenuation_closed_form(oracle_lib):
+    """A1 integrates the attenuation exp(-Delta tau(t)) of a cell with its
+    (x, E).  With photoionisation alone, u = n sigma ell x follows
+    e^u = 1 + (e^u0 - 1) e^(-a t), a = F sigma, so
+    <e^-u> = ln((e^(a h) + e^u0 - 1) / e^u0) / (a h); the integrated value
+    converges to it at second order as the substeps double."""
+    n, ell, sigma = 10.0, 1e18, 6.3e-18
+    k = n * sigma * ell
+    geo = 1.0 / (4 * math.pi * (5e18) ** 2 * ell)
+    F = 1e48 * geo * ell
+    a = F * sigma
+    errs = []
+    for u0 in (0.5, 3.0):
+        h = 0.5 / a
+        c = math.expm1(u0)
+        exact = -math.log(math.log((math.exp(a * h) + c) / (1 + c)) / (a * h))
+        e = []
+        for nsub in (2, 4, 8, 16):
+            pb = _cell_problem(Q=1e48, alpha_B=0.0, n_sub=nsub)
+            _, _, ta = pb.micro_cell_avg(n, geo, ell, 0.0, u0 / k, 0.0, h)
+            e.append(abs(ta / exact - 1.0))
+        errs.append(e)
+        assert e[0] < 1e-2, e
+        for e0, e1 in zip(e, e[1:]):
+            assert e1 < e0 / 3.0 or e1 < 1e-12, e
+
+
+def test_a1_pass_with_nothing_changing_is_the_raytrace(oracle_lib):
+    """No source and no recombination: the A1 pass leaves x alone and its
+    time-averaged columns are the instantaneous short-characteristics columns."""
+    spec = synth.cfg2(n=10)
+    pb = oracle.Problem.from_spec(spec, Q=0.0, alpha_B=0.0, collisional=0)
+    nH = synth.lognormal_density(spec.shape, 10.0, 1.0, 1)
+    x = np.random.default_rng(0).uniform(0.2, 1.0, spec.shape)
+    E = pb.energy_from_temperature(nH, x, 100.0)
+    x1, _, tau_avg, kbar = pb.a1_pass(nH, x, E, 1e9)
+    assert np.array_equal(x1, x)
+    tau = pb.raytrace(nH, x)
+    assert np.max(np.abs(tau_avg - tau) / np.maximum(tau, 1e-300)) < 1e-13
+    assert np.max(np.abs(kbar / (nH * x) - 1)) < 1e-13
+
+
+def test_a1_slab_photon_count(oracle_lib):
+    """Sect. 3.1 calls the slab a simple problem for A1: with the time-averaged
+    attenuation the ions per unit area stay within 0.5% of F t at steps of
+    K4 = 1/2 (half the A3-dt02 step count), where A3-dt02 is off by ~1.5%."""
+    L = 0.51 * PC
+    pb = oracle.Problem(geometry=oracle.GEOM_PLANAR_1D, n=(100,), dx=L / 100, Q=1e9,
+                        thermal=oracle.T_FIXED, alpha_B=0.0,
+                        K=(math.inf, math.inf, math.inf, 0.5))
+    st = pb.initial_state(100.0)
+    T = L * 100.0 / 1e9
+    errs = []
+    for f in np.linspace(0.05, 0.8, 16):
+        pb.run(st, f * T, algo=1)
+        errs.append(abs(pb.diagnostics(st)["n_ion"] / (1e9 * st["t"]) - 1.0))
+    assert max(errs) < 5e-3, max(errs)
+
+
+def test_a1_stromgren_front_with_long_steps(oracle_lib):
+    """Sect. 3.2: A1 with dt02 (K1 = 0.1, steps of a tenth of t_rec) tracks the
+    R-type front of config 1 within 2% from its first step, reaching 0.1 t_rec
+    in one step."""
+    spec = synth.cfg1()
+    pb = oracle.Problem.from_spec(spec, K=(0.1, math.inf, math.inf, math.inf))
+    st = pb.initial_state(np.full(spec.shape, 1.0))
+    RS = synth.stromgren_radius(spec.Q, 1.0)
+    assert pb.run(st, 0.1 * spec.t_rec, algo=1) == 1
+    for c in (0.1, 0.3, 1.0, 4.0):
+        pb.run(st, c * spec.t_rec, algo=1)
+        Ra = RS * (1 - math.exp(-st["t"] / spec.t_rec)) ** (1 / 3)
+        assert abs(pb.diagnostics(st)["r_ion"] / Ra - 1) < 0.02, c
