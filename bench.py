@@ -242,6 +242,47 @@ def bench_hardening(args, torch, binding, synth) -> dict:
     }
 
 
+def bench_a1(args, torch, binding, synth) -> dict:
+    """Algorithm 1 (implicit, time-averaged attenuation) on the same 256^3
+    clumpy medium as the default workload, with Table 1's implicit dt02
+    (steps of a tenth of the recombination time), from the state the A3
+    pre-evolution reaches at 0.1 t_rec."""
+    INF = synth.INF
+    spec = synth.cfg3(n=args.n).with_(precision=args.precision)
+    g = binding.Grid(spec, precision=args.precision)
+    g.load(synth.density(spec), 1.0, T0=spec.T0)
+    g.run(args.pre_trec * spec.t_rec, check_every=16)
+    t0, n0, _ = g.state()
+    ga = binding.Grid(spec.with_(K=(0.1, INF, INF, INF)), precision=args.precision)
+    for k in ("nH", "x", "E", "tau"):
+        getattr(ga, k).copy_(getattr(g, k))
+    ga.set_time(t0, n0)
+    g.close()
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        ga.step_a1(1e30)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        ga.step_a1(1e30)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    _, _, dt = ga.state()
+    ga.close()
+    return {
+        "metric": "cell-updates/s of algorithm 1 steps at 256^3",
+        "value": spec.ncells * args.steps / (ms * 1e-3), "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype_name(args.precision), "data": "synthetic",
+        "config": {"workload": f"cfg3 clumpy medium {args.n}^3, algorithm 1 with implicit dt02 "
+                               f"(K1 = 0.1), from the A3 state at {args.pre_trec} t_rec",
+                   "precision": args.precision, "dt_over_trec": dt / spec.t_rec},
+    }
+
+
 def bench_serve(args, torch, binding, synth) -> dict:
     """Served form: Poisson arrivals of single-grid requests submitted to the
     library's server at their arrival times; latency from submission to
@@ -319,7 +360,8 @@ def main() -> int:
     ap.add_argument("--cpu-sample-n", type=int, default=32)
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="cfg3", choices=["cfg3", "batch", "serve", "hardening"],
+    ap.add_argument("--workload", default="cfg3",
+                    choices=["cfg3", "batch", "serve", "hardening", "a1"],
                     help="cfg3: the 256^3 single grid (default); batch / serve: the batched and "
                          "served forms (their own JSON line)")
     ap.add_argument("--hardening-trec", type=float, default=1.0,
@@ -352,7 +394,8 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     if args.workload != "cfg3":
-        fn = {"batch": bench_batch, "serve": bench_serve, "hardening": bench_hardening}[args.workload]
+        fn = {"batch": bench_batch, "serve": bench_serve, "hardening": bench_hardening,
+              "a1": bench_a1}[args.workload]
         print(json.dumps(fn(args, torch, binding, synth)))
         return 0
     spec = synth.cfg3(n=args.n)

@@ -166,6 +166,19 @@ pi_status pi_step_o2(pi_grid* grid, double t_end, void* stream);
  * micro-physics over dt on tau, raytrace of the new state. */
 pi_status pi_step_o1(pi_grid* grid, double t_end, void* stream);
 
+/* One step of algorithm 1 (Sect. 2.1), the implicit scheme with time-averaged
+ * attenuation: timestep (eq. 4 with the grid's K; Table 1's implicit columns
+ * limit it by K1 t_rec), then one pass over the cells in raytrace order in
+ * which each cell is integrated over dt on the time-averaged column entering
+ * it while its attenuation exp(-Delta tau) is averaged over the step; the
+ * cell's time-averaged optical depth -ln <exp(-Delta tau)> then enters the
+ * columns of the cells behind it.  Afterwards x_half holds each cell's
+ * time-averaged optical depth per cell length (sigma0 dx units), tau_half the
+ * time-averaged entering columns, and tau the columns of the new state (a
+ * raytrace, for the next timestep).  Point sources only (PI_EINVAL for
+ * PI_SRC_PLANE); the pass runs on 4^3 tiles whatever the raytrace tile. */
+pi_status pi_step_a1(pi_grid* grid, double t_end, void* stream);
+
 /* Energy density of state `state` from a uniform temperature T0 [K] for pure
  * hydrogen with gamma = 5/3 (Sect. 2): E = 3/2 n_H (2 - x) k_B T0. */
 pi_status pi_init_energy(pi_grid* grid, double T0, int state, void* stream);
@@ -223,6 +236,9 @@ pi_status pi_batch_raytrace(pi_batch* batch, int state, int tau_buf, void* strea
 /* One algorithm-3 step of every grid toward its own t_end (pi_step_o2 with the
  * t_end set by pi_batch_set_time), enqueued as one graph launch on stream. */
 pi_status pi_batch_step_o2(pi_batch* batch, void* stream);
+/* One algorithm-1 step (pi_step_a1) of every grid, each to its own t_end;
+ * launched directly (not from a captured graph). */
+pi_status pi_batch_step_a1(pi_batch* batch, void* stream);
 /* Per grid clock (host arrays of ngrids; NULL skips).  SYNCHRONISES. */
 pi_status pi_batch_state(pi_batch* batch, double* t, int64_t* nsteps, double* last_dt,
                          void* stream);
@@ -309,7 +325,7 @@ const char* pi_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns the
  * value it was built with. */
-#define PI_ABI_VERSION 106
+#define PI_ABI_VERSION 107
 int pi_abi_version(void);
 
 #ifdef __cplusplus

@@ -39,6 +39,8 @@ ABI_SYMBOLS = (
     "pi_server_create", "pi_submit", "pi_poll", "pi_cancel", "pi_server_stats", "pi_server_destroy",
     "pi_set_raytrace_tile", "pi_get_raytrace_tile", "pi_batch_set_raytrace_tile",
     "pi_batch_get_raytrace_tile",
+    "pi_step_a1",
+    "pi_batch_step_a1",
 )
 
 
@@ -112,6 +114,7 @@ def lib() -> C.CDLL:
         L.pi_timestep.argtypes = [vp, d, vp]
         L.pi_step_o2.argtypes = [vp, d, vp]
         L.pi_step_o1.argtypes = [vp, d, vp]
+        L.pi_step_a1.argtypes = [vp, d, vp]
         L.pi_init_energy.argtypes = [vp, d, i32, vp]
         L.pi_set_time.argtypes = [vp, d, i64, vp]
         L.pi_grid_state.argtypes = [vp, dp, C.POINTER(C.c_int64), dp, vp]
@@ -125,6 +128,7 @@ def lib() -> C.CDLL:
         L.pi_batch_init_energy.argtypes = [vp, dp, i32, vp]
         L.pi_batch_raytrace.argtypes = [vp, i32, i32, vp]
         L.pi_batch_step_o2.argtypes = [vp, vp]
+        L.pi_batch_step_a1.argtypes = [vp, vp]
         L.pi_batch_state.argtypes = [vp, dp, i64p, dp, vp]
         L.pi_batch_diagnostics.argtypes = [vp, dp, vp]
         L.pi_batch_work_counters.argtypes = [vp, i64p, i32, vp]
@@ -287,6 +291,12 @@ class Grid:
     def step_o1(self, t_end: float):
         check(lib().pi_step_o1(self._h, float(t_end), self._stream()))
 
+    def step_a1(self, t_end: float):
+        """One step of algorithm 1 (the implicit scheme with time-averaged
+        attenuation); afterwards x_half holds the time-averaged optical depth
+        per cell length and tau_half the time-averaged entering columns."""
+        check(lib().pi_step_a1(self._h, float(t_end), self._stream()))
+
     def state(self):
         t, dt = C.c_double(), C.c_double()
         n = C.c_int64()
@@ -397,6 +407,9 @@ class Batch:
 
     def step_o2(self):
         check(lib().pi_batch_step_o2(self._h, self._stream()))
+
+    def step_a1(self):
+        check(lib().pi_batch_step_a1(self._h, self._stream()))
 
     @property
     def raytrace_tile(self) -> int:

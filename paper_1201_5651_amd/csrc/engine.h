@@ -97,6 +97,8 @@ pi_status engine_chem(Engine& e, bool dev_dt, double h, int tau_buf, int from, i
 // t_end_arg finite: the common t_end, else each grid's stored t_end.
 pi_status engine_timestep(Engine& e, double t_end_arg, hipStream_t s);
 pi_status engine_step(Engine& e, double t_end_arg, int order, hipStream_t s);
+// One step of algorithm 1 (Sect. 2.1) for every grid (point sources only).
+pi_status engine_step_a1(Engine& e, double t_end_arg, hipStream_t s);
 // One A3 step of every grid toward its stored t_end, as a captured graph
 // (captured on first use, replayed on s).
 pi_status engine_step_graph(Engine& e, hipStream_t s);

@@ -264,6 +264,25 @@ template <typename R> pi_status step_t(Engine& e, double t_end_arg, int order, h
     return PI_OK;
 }
 
+// Algorithm 1 (Sect. 2.1): timestep, the combined pass (stages of the 4^3
+// tile schedule), the raytrace of the new state for the next timestep, clock.
+template <typename R> pi_status step_a1_t(Engine& e, double t_end_arg, hipStream_t s)
+{
+    for (GridHost* h : e.grids)
+        if (h->d.source != PI_SRC_POINT)
+            return fail(PI_EINVAL, "algorithm 1 needs point-source grids");
+    pi_status r = timestep_t<R>(e, t_end_arg, s);
+    if (r != PI_OK) return r;
+    for (size_t k = 0; k < e.stage_first[0].size(); ++k)
+        HIP_OR(launch_sweep_a1<R>(gd<R>(e), e.tiles[0], e.stage_first[0][k], e.stage_count[0][k],
+                                  e.work, e.mixed(), s),
+               "algorithm 1 pass launch");
+    if ((r = raytrace_t<R>(e, PI_BUF_N, PI_BUF_N, e.sweep >= 0 ? e.sweep : SWEEP_DEFAULT, s)) != PI_OK)
+        return r;
+    HIP_OR(launch_advance<R>(gd<R>(e), e.ngrids(), s), "advance launch");
+    return PI_OK;
+}
+
 }  // namespace
 
 BatchDev Engine::bd() const
@@ -506,6 +525,11 @@ pi_status engine_timestep(Engine& e, double t_end_arg, hipStream_t s)
 pi_status engine_step(Engine& e, double t_end_arg, int order, hipStream_t s)
 {
     return e.fp64() ? step_t<double>(e, t_end_arg, order, s) : step_t<float>(e, t_end_arg, order, s);
+}
+
+pi_status engine_step_a1(Engine& e, double t_end_arg, hipStream_t s)
+{
+    return e.fp64() ? step_a1_t<double>(e, t_end_arg, s) : step_a1_t<float>(e, t_end_arg, s);
 }
 
 pi_status engine_step_graph(Engine& e, hipStream_t s)

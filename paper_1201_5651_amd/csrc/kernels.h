@@ -121,6 +121,13 @@ hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, c
 template <typename R>
 hipError_t launch_plane_scan(const GridDev<R>* grids, const BatchDev& b, int rows, int state,
                              int tau_buf, hipStream_t s);
+// Algorithm 1's pass (Sect. 2.1) over one stage of the 4^3 tile schedule
+// (tiles[first .. first + count)): state n advanced in place over st->dt,
+// time-averaged entering columns into tau[1], time-averaged optical depth per
+// cell length into x[1].
+template <typename R>
+hipError_t launch_sweep_a1(const GridDev<R>* grids, const int4* tiles, int first, int count,
+                           unsigned long long* ctr, bool mixed, hipStream_t s);
 template <typename R>
 hipError_t launch_chem(const GridDev<R>* grids, const BatchDev& b, int nblocks, int from, int to,
                        int tau_buf, bool dev_dt, double hscale, unsigned long long* ctr,

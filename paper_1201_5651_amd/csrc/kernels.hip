@@ -399,6 +399,149 @@ k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int 
     }
 }
 
+// ------------------------------------------------------------- algorithm 1
+// Algorithm 1's pass (Sect. 2.1): the raytrace of k_sweep on 4^3 tiles (one
+// wavefront each) in which every cell, when its plane comes, is integrated
+// over dt on the time-averaged column entering it and then passes on its own
+// time-averaged optical depth per cell length, kbar = tau_avg / ell, in place
+// of sigma0 n_H x dx.  The state n is advanced in place; the half-step buffers
+// receive the pass's time-averaged entering columns (tau[1]) and kbar (x[1]),
+// which the tiles of later stages read as their halo.  With mixed precision a
+// cell whose float integration took a precision-sensitive decision is
+// integrated again in double at once (later cells depend on it).
+template <typename R>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ChemWaves<R>::value)))
+k_sweep_a1(const GridDev<R>* __restrict__ grids, const int4* __restrict__ tiles, int first,
+           unsigned long long* ctr, int mixed)
+{
+    constexpr int TT = 4, TX = TT, TY = TT, TZ = TT, NC = TT * TT * TT;
+    constexpr int HX = TX + 1, HY = TY + 1, HZ = TZ + 1, NHALO = HX * HY * HZ;
+    __shared__ R s_tc[NHALO];
+    __shared__ R s_kap[NHALO];
+
+    const int4 tl = tiles[first + blockIdx.x];
+    const GridDev<R>& G = grids[tl.x >> 3];
+    const Params<R> p = G.p;
+    const R* __restrict__ kbar_in = G.x[1];
+    const R* __restrict__ tavg_in = G.tau[1];
+    const int oct = tl.x & 7;
+    const bool px = oct & 1, py = oct & 2, pz = oct & 4;
+    const int ex = px ? p.nx - p.sx : p.sx;
+    const int ey = py ? p.ny - p.sy : p.sy;
+    const int ez = pz ? p.nz - p.sz : p.sz;
+    const int X0 = tl.y * TX, Y0 = tl.z * TY, Z0 = tl.w * TZ;
+
+    // halo from the earlier stages of this pass; the tile's own cells are
+    // written when their planes come
+    for (int q = threadIdx.x; q < NHALO; q += NC) {
+        const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
+        const int Lx = X0 + hx - 1, Ly = Y0 + hy - 1, Lz = Z0 + hz - 1;
+        R kap = R(0), tc = R(0);
+        if ((hx == 0 || hy == 0 || hz == 0) && Lx >= 0 && Ly >= 0 && Lz >= 0 && Lx < ex &&
+            Ly < ey && Lz < ez) {
+            const int gi = px ? p.sx + Lx : p.sx - 1 - Lx;
+            const int gj = py ? p.sy + Ly : p.sy - 1 - Ly;
+            const int gk = pz ? p.sz + Lz : p.sz - 1 - Lz;
+            const int64_t g = gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk);
+            kap = kbar_in[g];
+            const R ax = R(Lx) + R(0.5), ay = R(Ly) + R(0.5), az = R(Lz) + R(0.5);
+            const R da = (az >= ax && az >= ay) ? az : (ay >= ax ? ay : ax);
+            const R hds = R(0.5) * r_sqrt(ax * ax + ay * ay + az * az) / da;
+            tc = r_fma(hds, kap, tavg_in[g]);
+        }
+        s_kap[q] = kap;
+        s_tc[q] = tc;
+    }
+
+    // the thread's cell (plane order) and its geometry, as in k_sweep
+    const int cl = plane_cell<TT>(threadIdx.x);
+    const int lx = cl & 31, ly = (cl >> 5) & 31, lz = cl >> 10;
+    const int L[3] = { X0 + lx, Y0 + ly, Z0 + lz };
+    const bool active = L[0] < ex && L[1] < ey && L[2] < ez;
+    const R ad[3] = { R(L[0]) + R(0.5), R(L[1]) + R(0.5), R(L[2]) + R(0.5) };
+    const int a = (ad[2] >= ad[0] && ad[2] >= ad[1]) ? 2 : (ad[1] >= ad[0] ? 1 : 0);
+    const int b = a == 2 ? 0 : a + 1;
+    const int c = a == 0 ? 2 : a - 1;
+    const int st[3] = { 1, HX, HX * HY };
+    const int self = (lz + 1) * HX * HY + (ly + 1) * HX + (lx + 1);
+    const int n00 = self - st[a], n10 = n00 - st[b], n01 = n00 - st[c], n11 = n10 - st[c];
+    const R fb = ad[b] / ad[a], fc = ad[c] / ad[a];
+    const bool vb = L[b] >= 1, vc = L[c] >= 1;
+    const R g00 = (R(1) - fb) * (R(1) - fc);
+    const R g10 = vb ? fb * (R(1) - fc) : R(0);
+    const R g01 = vc ? (R(1) - fb) * fc : R(0);
+    const R g11 = (vb && vc) ? fb * fc : R(0);
+    const R hds = R(0.5) * r_sqrt(ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2]) / ad[a];
+    const bool corner = L[a] == 0;
+    const int diag = lx + ly + lz;
+    const int gi = px ? p.sx + L[0] : p.sx - 1 - L[0];
+    const int gj = py ? p.sy + L[1] : p.sy - 1 - L[1];
+    const int gk = pz ? p.sz + L[2] : p.sz - 1 - L[2];
+    const int64_t q = active ? gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk) : 0;
+    R n = R(1), x = R(1), E = R(0);
+    if (active) {
+        n = G.nH[q];
+        x = G.x[0][q];
+        E = G.E[0] ? G.E[0][q] : R(0);
+    }
+    const double hd = G.st->dt;
+    const bool mellema = p.weights == 1;
+    Work w{};
+    R tin = R(0), kbar = R(0);
+    __syncthreads();
+
+    for (int s = 0; s < TX + TY + TZ - 2; ++s) {
+        if (active && diag == s) {
+            if (!corner) {
+                const R T00 = s_tc[n00] + hds * s_kap[n00];
+                const R T10 = s_tc[n10] + hds * s_kap[n10];
+                const R T01 = s_tc[n01] + hds * s_kap[n01];
+                const R T11 = s_tc[n11] + hds * s_kap[n11];
+                tin = sc_average<R>(mellema, g00, g10, g01, g11, T00, T10, T01, T11);
+            }
+            const CellGeom<R> cg = cell_geom(p, gi, gj, gk);
+            R xo = x, Eo = E, tb;
+            if (!(isfinite(n) && isfinite(x) && isfinite(E) && isfinite(tin))) {
+                xo = Eo = tb = R(__builtin_nan(""));
+            } else {
+                Work wc{};
+                const Env<R> env = make_env(p, n, cg, tin);
+                micro_t<R, true>(p, env, R(hd), xo, Eo, wc, &tb);
+                if (mixed && wc.close > 0) {
+                    // precision-sensitive: the same cell in double, from the same inputs
+                    const Params<double>& pd = G.pd;
+                    const CellGeom<double> cgd = cell_geom(pd, gi, gj, gk);
+                    const Env<double> ed = make_env(pd, (double)n, cgd, (double)tin);
+                    double xd = (double)x, Ed = (double)E, tbd;
+                    micro_t<double, true>(pd, ed, hd, xd, Ed, wc, &tbd);
+                    xo = R(xd);
+                    Eo = R(Ed);
+                    tb = R(tbd);
+                    ++wc.fixed;
+                }
+                w.accepted += wc.accepted;
+                w.rejected += wc.rejected;
+                w.fallbacks += wc.fallbacks;
+                w.newton += wc.newton;
+                w.fixed += wc.fixed;
+            }
+            kbar = tb / cg.ell;
+            s_kap[self] = kbar;
+            s_tc[self] = r_fma(hds, kbar, tin);   // entry face to centre
+            x = xo;
+            E = Eo;
+        }
+        __syncthreads();
+    }
+    if (active) {
+        G.x[0][q] = x;
+        if (G.E[0]) G.E[0][q] = E;
+        G.tau[1][q] = tin;
+        G.x[1][q] = kbar;
+    }
+    add_work(ctr, w);
+}
+
 // ---------------------------------------------------- plane-parallel raytrace
 // One wavefront per row: the cells' optical depths sigma0 n_H x dx are summed
 // along x in chunks of 64 (a shuffle scan within the wavefront plus the carry
@@ -595,6 +738,16 @@ hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, c
 }
 
 template <typename R>
+hipError_t launch_sweep_a1(const GridDev<R>* grids, const int4* tiles, int first, int count,
+                           unsigned long long* ctr, bool mixed, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_sweep_a1<R>), dim3(count), dim3(64), 0, s, grids, tiles, first, ctr,
+                       (int)mixed);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_plane_scan(const GridDev<R>* grids, const BatchDev& b, int rows, int state,
                              int tau_buf, hipStream_t s)
 {
@@ -661,6 +814,8 @@ hipError_t launch_energy(int64_t n, const R* nH, const R* x, R* E, double T0, hi
     template hipError_t launch_advance<R>(const GridDev<R>*, int, hipStream_t);                   \
     template hipError_t launch_plane_scan<R>(const GridDev<R>*, const BatchDev&, int, int, int,   \
                                              hipStream_t);                                         \
+    template hipError_t launch_sweep_a1<R>(const GridDev<R>*, const int4*, int, int,              \
+                                           unsigned long long*, bool, hipStream_t);                \
     template hipError_t launch_energy<R>(int64_t, const R*, const R*, R*, double, hipStream_t);
 PI_INSTANTIATE(double)
 PI_INSTANTIATE(float)

@@ -656,7 +656,7 @@ PI_HD __forceinline__ void stage_guess(R xb, R Eb, R hg, R fx, R fE, R& xg, R& E
 // + hg f(Y1).
 template <typename R>
 PI_HD __forceinline__ void sdirk_step(const Params<R>& p, const Env<R>& e, R hs, R& x, R& E,
-                                      R& fx, R& fE, Work& w)
+                                      R& fx, R& fE, Work& w, R& x_stage1)
 {
     const R gam = R(0.29289321881345247560);          // 1 - 1/sqrt(2)
     const R cst = R(2.41421356237309504880);          // (1 - gamma)/gamma
@@ -671,9 +671,28 @@ PI_HD __forceinline__ void sdirk_step(const Params<R>& p, const Env<R>& e, R hs,
     stage_solve(p, e, xb, Eb, hg, X2, F2, w);
     fx = (X2 - xb) / hg;
     fE = (F2 - Eb) / hg;
+    x_stage1 = X1;
     x = X2;
     E = F2;
 }
+
+// Integral of exp(-tau) terms held as S exp(-m), so that a very thick cell
+// does not underflow (algorithm 1's time-averaged attenuation).
+template <typename R> struct LseAcc {
+    R m = R(0), S = R(0);
+    PI_HD __forceinline__ void add(R w, R tau)
+    {
+        if (S == R(0)) {
+            m = tau;
+            S = w;
+        } else if (tau >= m) {
+            S += w * r_exp(-(tau - m));
+        } else {
+            S = S * r_exp(-(m - tau)) + w;
+            m = tau;
+        }
+    }
+};
 
 // Micro-integration M(x0, E0; tau, h) with deterministic substep control: the
 // interval is cut into U = ns 2^SUB_LEVELS units; a substep of s units is
@@ -681,10 +700,16 @@ PI_HD __forceinline__ void sdirk_step(const Params<R>& p, const Env<R>& e, R hs,
 // by more than a factor REJ_E, and doubled again after an accepted substep
 // when the position allows.  E is held at or above
 // the temperature floor between substeps.
-template <typename R>
-PI_HD void micro(const Params<R>& p, const Env<R>& e, R h, R& x, R& E, Work& w)
+// With AVG (algorithm 1, Sect. 2.1) the cell's attenuation exp(-k x(t)) is
+// integrated over h with the same SDIRK stages (weights 1 - gamma and gamma at
+// the two stage values of x of every accepted substep), and tau_avg returns
+// the time-averaged optical depth -ln <exp(-k x)>.
+template <typename R, bool AVG>
+PI_HD void micro_t(const Params<R>& p, const Env<R>& e, R h, R& x, R& E, Work& w, R* tau_avg)
 {
+    if constexpr (AVG) *tau_avg = e.k * x;
     if (!(h > R(0))) return;
+    LseAcc<R> acc;
     const bool evolve = p.thermal == 1;
     if (evolve && E < e_floor(e.n, x)) E = e_floor(e.n, x);
     R fx, fE;
@@ -694,8 +719,8 @@ PI_HD void micro(const Params<R>& p, const Env<R>& e, R h, R& x, R& E, Work& w)
     int pos = 0, s = top;
     while (pos < U) {
         const R hs = R((double)h * (double)s / (double)U);
-        R xn = x, En = E, fxn = fx, fEn = fE;
-        sdirk_step(p, e, hs, xn, En, fxn, fEn, w);
+        R xn = x, En = E, fxn = fx, fEn = fE, X1;
+        sdirk_step(p, e, hs, xn, En, fxn, fEn, w, X1);
         const R dx = r_abs(xn - x);
         const bool bad = dx > R(REJ_DX) || (evolve && (En > R(REJ_E) * E || En * R(REJ_E) < E));
         if (r_abs(dx - R(REJ_DX)) < R(MIX_MARGIN * REJ_DX) ||
@@ -708,6 +733,11 @@ PI_HD void micro(const Params<R>& p, const Env<R>& e, R h, R& x, R& E, Work& w)
             continue;
         }
         ++w.accepted;
+        if constexpr (AVG) {
+            const R gam = R(0.29289321881345247560);
+            acc.add(hs * (R(1) - gam), e.k * X1);
+            acc.add(hs * gam, e.k * xn);
+        }
         x = xn;
         E = En;
         fx = fxn;
@@ -716,6 +746,13 @@ PI_HD void micro(const Params<R>& p, const Env<R>& e, R h, R& x, R& E, Work& w)
         pos += s;
         if (s < top && pos % (2 * s) == 0) s <<= 1;
     }
+    if constexpr (AVG) *tau_avg = acc.m - r_log(acc.S / h);
+}
+
+template <typename R>
+PI_HD __forceinline__ void micro(const Params<R>& p, const Env<R>& e, R h, R& x, R& E, Work& w)
+{
+    micro_t<R, false>(p, e, h, x, E, w, nullptr);
 }
 
 // Per-cell limit of eq. (4) at (x, E) with the entering column of t_n:

@@ -232,6 +232,13 @@ pi_status pi_step_o1(pi_grid* g, double t_end, void* stream)
     return engine_step(g->e, t_end, 1, static_cast<hipStream_t>(stream));
 }
 
+pi_status pi_step_a1(pi_grid* g, double t_end, void* stream)
+{
+    if (!g) return fail(PI_EINVAL, "null grid");
+    if (!std::isfinite(t_end)) return fail(PI_EINVAL, "t_end must be finite");
+    return engine_step_a1(g->e, t_end, static_cast<hipStream_t>(stream));
+}
+
 pi_status pi_init_energy(pi_grid* g, double T0, int state, void* stream)
 {
     if (!g) return fail(PI_EINVAL, "null grid");
@@ -415,6 +422,12 @@ pi_status pi_batch_step_o2(pi_batch* b, void* stream)
 {
     if (!b) return fail(PI_EINVAL, "null batch");
     return engine_step_graph(b->e, static_cast<hipStream_t>(stream));
+}
+
+pi_status pi_batch_step_a1(pi_batch* b, void* stream)
+{
+    if (!b) return fail(PI_EINVAL, "null batch");
+    return engine_step_a1(b->e, NAN, static_cast<hipStream_t>(stream));
 }
 
 pi_status pi_batch_state(pi_batch* b, double* t, int64_t* nsteps, double* last_dt, void* stream)
