@@ -222,6 +222,14 @@ void pi_server::retire(Request& r, bool ok, const std::string& why)
 void pi_server::run()
 {
     (void)hipSetDevice(device);
+    // The batch is rebuilt once per change of the active set (at the next tick
+    // after admissions or retirements).  A HIP graph of the step costs a
+    // capture (several ms of host time while the GPU waits), so steps are
+    // launched directly until the set has been the same for two ticks, and
+    // replayed from a graph after that; the kernels and their order are the
+    // same either way.
+    bool dirty = false;
+    int stable = 0;
     for (;;) {
         std::vector<std::shared_ptr<Request>> admitted;
         {
@@ -267,9 +275,11 @@ void pi_server::run()
         }
         if (grids.empty()) continue;
         pi_status s = PI_OK;
-        if (changed || engine.ngrids() != (int)grids.size()) {
+        if (changed || dirty || engine.ngrids() != (int)grids.size()) {
             s = engine_build(engine, grids);
             rebuilds++;
+            dirty = false;
+            stable = 0;
             // first batch: choose the raytrace tiles (recomputes the current columns)
             if (s == PI_OK && engine.sweep < 0) s = engine_autotune(engine, PI_BUF_N, PI_BUF_N, stream);
         }
@@ -277,7 +287,9 @@ void pi_server::run()
         for (GridHost* g : grids) cells += g->ncell;
         std::vector<DevState> st;
         if (s == PI_OK) {
-            for (int k = 0; k < desc.steps_per_tick && s == PI_OK; ++k) s = engine_step_graph(engine, stream);
+            for (int k = 0; k < desc.steps_per_tick && s == PI_OK; ++k)
+                s = stable >= 2 ? engine_step_graph(engine, stream) : engine_step(engine, NAN, 2, stream);
+            ++stable;
             if (s == PI_OK) s = engine_read_states(engine, st, stream);
         }
         std::lock_guard<std::mutex> lk(mu);
@@ -310,10 +322,7 @@ void pi_server::run()
         }
         if (keep.size() != active.size()) {
             active = keep;
-            grids.clear();
-            for (auto& r : active) grids.push_back(&r->grid);
-            engine_build(engine, grids);
-            rebuilds++;
+            dirty = true;   // retired grids' memory is free: rebuilt before the next step
         }
     }
 }
