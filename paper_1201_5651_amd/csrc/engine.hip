@@ -268,6 +268,7 @@ template <typename R> pi_status step_t(Engine& e, double t_end_arg, int order, h
 // tile schedule), the raytrace of the new state for the next timestep, clock.
 template <typename R> pi_status step_a1_t(Engine& e, double t_end_arg, hipStream_t s)
 {
+    static_assert(SWEEP_TILES[0] == 4, "the algorithm 1 pass runs on the 4^3 tile schedule");
     for (GridHost* h : e.grids)
         if (h->d.source != PI_SRC_POINT)
             return fail(PI_EINVAL, "algorithm 1 needs point-source grids");
