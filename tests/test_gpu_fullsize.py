@@ -79,3 +79,28 @@ def test_chem_full_size_sampled(oracle_lib, state256):
           % (cells.size, n_ill, errs.max(), np.quantile(errs, 0.99)))
     assert n_ill < 0.05 * cells.size
     assert errs.max() < 1e-4
+
+
+def test_batch_full_size_matches_grids_alone():
+    """The 64-grid batch of the batched-form bench (94 M cells, mixed, one
+    graph replay per step): after a few steps, grids taken from across the
+    batch hold bit for bit what they hold when advanced alone."""
+    specs = synth.batch_specs(64, seed=0, precision="mixed")
+    nHs = [synth.density(s) for s in specs]
+    b = binding.Batch(specs, precision="mixed")
+    b.load(nHs, T0s=[s.T0 for s in specs], t_end=[s.t_end for s in specs])
+    for _ in range(3):
+        b.step_o2()
+    t, n, _ = b.state()
+    picks = (0, 21, 42, 63)
+    got = {i: (t[i], to_np(b.grids[i].x), to_np(b.grids[i].tau)) for i in picks}
+    b.close()
+    for i in picks:
+        g = binding.Grid(specs[i], precision="mixed")
+        g.load(nHs[i], 1.0, T0=specs[i].T0)
+        for _ in range(3):
+            g.step_o2(specs[i].t_end)
+        assert g.state()[0] == got[i][0]
+        assert np.array_equal(to_np(g.x), got[i][1]), i
+        assert np.array_equal(to_np(g.tau), got[i][2]), i
+        g.close()
