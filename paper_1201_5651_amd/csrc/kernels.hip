@@ -165,6 +165,9 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     int self[CPT], n00[CPT], n10[CPT], n01[CPT], n11[CPT], diag[CPT], nat[CPT];
     bool active[CPT], corner[CPT];
     R g00[CPT], g10[CPT], g01[CPT], g11[CPT], hds[CPT], kself[CPT], tin[CPT];
+    // hds * sigma0 n_H x dx of the four upstream cells: fixed while the tile is
+    // swept, so the plane loop reads only their centre columns
+    R c00[CPT], c10[CPT], c01[CPT], c11[CPT];
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
         const int cl = plane_cell<TT>(threadIdx.x + k * NT);
@@ -193,6 +196,10 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
         diag[k] = lx + ly + lz;
         nat[k] = lx + TX * (ly + TY * lz);
         kself[k] = s_kap[self[k]];
+        c00[k] = hds[k] * s_kap[n00[k]];
+        c10[k] = hds[k] * s_kap[n10[k]];
+        c01[k] = hds[k] * s_kap[n01[k]];
+        c11[k] = hds[k] * s_kap[n11[k]];
         tin[k] = R(0);
     }
 
@@ -201,10 +208,10 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
         for (int k = 0; k < CPT; ++k) {
             if (active[k] && diag[k] == s) {
                 if (!corner[k]) {
-                    const R T00 = s_tc[n00[k]] + hds[k] * s_kap[n00[k]];
-                    const R T10 = s_tc[n10[k]] + hds[k] * s_kap[n10[k]];
-                    const R T01 = s_tc[n01[k]] + hds[k] * s_kap[n01[k]];
-                    const R T11 = s_tc[n11[k]] + hds[k] * s_kap[n11[k]];
+                    const R T00 = s_tc[n00[k]] + c00[k];
+                    const R T10 = s_tc[n10[k]] + c10[k];
+                    const R T01 = s_tc[n01[k]] + c01[k];
+                    const R T11 = s_tc[n11[k]] + c11[k];
                     tin[k] = sc_average<R>(mellema, g00[k], g10[k], g01[k], g11[k], T00, T10,
                                            T01, T11);
                 }
