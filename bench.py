@@ -12,6 +12,12 @@ half-step state, corrector micro-physics, raytrace of the new state.
 Prints ONE JSON line: cell-updates/s (whole job), ms per step, the roofline
 object of the dominant kernel (measured live with HIP events on the stream the
 kernels run on) and the FP64 oracle's rate on a bounded CPU sample.
+
+Other workloads (--workload): batch (64 uneven grids advanced together, and
+the FP64 single-grid path on a sample of them), serve (Poisson requests to the
+library's server; p50/p99 latency), hardening (the 37 500 K blackbody runs of
+Sect. 4 as one batch, with A3-dt02 against smaller steps), a1 (algorithm 1
+steps on the same 256^3 medium).
 """
 from __future__ import annotations
 
