@@ -24,6 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 KB = 1.380649e-16
 EV = 1.602176634e-12
 NTAB = 64
+MAX_SRC = 4
 
 GEOM_3D, GEOM_SPHERICAL_1D, GEOM_PLANAR_1D, GEOM_PLANE_3D = 0, 1, 2, 3
 SPEC_MONO, SPEC_TABLE = 0, 1
@@ -63,6 +64,9 @@ class Desc(C.Structure):
         ("source_cell_rule", C.c_int32),
         ("n_sub", C.c_int32),
         ("K", C.c_double * 4),
+        ("nsrc", C.c_int32),
+        ("src_more", (C.c_int32 * 3) * (MAX_SRC - 1)),
+        ("Q_more", C.c_double * (MAX_SRC - 1)),
     ]
 
 
@@ -140,7 +144,7 @@ class Problem:
                  sigma0=6.3e-18, spectrum=SPEC_MONO, e_excess=0.0, T_bb=1e5, thermal=T_FIXED,
                  T_fixed=1e4, recomb=ALPHA_CONST, alpha_B=2.59e-13, collisional=0,
                  cooling=1, weights=W_MELLEMA, source_cell_rule=1, n_sub=2,
-                 K=(math.inf, math.inf, math.inf, 0.25), table=None):
+                 K=(math.inf, math.inf, math.inf, 0.25), table=None, more_sources=()):
         d = Desc()
         d.geometry = geometry
         n3 = tuple(n) + (1,) * (3 - len(tuple(n)))
@@ -167,8 +171,19 @@ class Problem:
         d.source_cell_rule = source_cell_rule
         d.n_sub = n_sub
         d.K[:] = K
+        # further point sources: ((i, j, k), Q) each; columns then carry one
+        # grid per source (tau_shape)
+        more = list(more_sources)
+        if len(more) > MAX_SRC - 1:
+            raise ValueError(f"at most {MAX_SRC} sources")
+        d.nsrc = 1 + len(more)
+        for m, (v, q) in enumerate(more):
+            d.src_more[m][:] = tuple(int(c) for c in v)
+            d.Q_more[m] = float(q)
         self.desc = d
         self.shape = (n3[2], n3[1], n3[0]) if geometry in (GEOM_3D, GEOM_PLANE_3D) else (n3[0],)
+        self.nsrc = d.nsrc
+        self.tau_shape = (self.nsrc,) + self.shape if self.nsrc > 1 else self.shape
 
     @property
     def ncells(self):
@@ -184,7 +199,7 @@ class Problem:
         return np.maximum(2.0 * E / (3.0 * KB * nH * (2.0 - x)), 10.0)
 
     def raytrace(self, nH, x, long_characteristics=False):
-        tau = np.zeros(self.shape)
+        tau = np.zeros(self.tau_shape)
         f = lib().orc_raytrace_lc if long_characteristics else lib().orc_raytrace_sc
         rc = f(C.byref(self.desc), _p(nH), _p(x), _p(tau))
         if rc != 0:

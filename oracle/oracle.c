@@ -313,6 +313,24 @@ int orc_cell_env(const orc_desc* g, int64_t cell, double* geo, double* ell)
     return 0;
 }
 
+/* number of sources of the grid, and the description of the grid as seen by
+ * source s alone (its vertex and Q in src / Q) */
+static int nsources(const orc_desc* g)
+{
+    return (g->geometry == ORC_GEOM_3D && g->nsrc > 1) ? g->nsrc : 1;
+}
+
+static orc_desc source_desc(const orc_desc* g, int s)
+{
+    orc_desc d = *g;
+    d.nsrc = 0;
+    if (s > 0) {
+        for (int a = 0; a < 3; ++a) d.src[a] = g->src_more[s - 1][a];
+        d.Q = g->Q_more[s - 1];
+    }
+    return d;
+}
+
 /* ----------------------------------------------------------------- raytrace */
 /* Short characteristics from a vertex source (Sect. 2; Sect. 5).  Per octant,
  * cells are visited in increasing octant-local (z, y, x); every upstream
@@ -403,7 +421,15 @@ static int raytrace_1d(const orc_desc* g, const double* nH, const double* x, dou
 int orc_raytrace_sc(const orc_desc* g, const double* nH, const double* x, double* tau_in)
 {
     if (!g || !nH || !x || !tau_in) return -1;
-    if (g->geometry == ORC_GEOM_3D) return raytrace_sc_3d(g, nH, x, tau_in);
+    if (g->geometry == ORC_GEOM_3D) {
+        /* every source traced on its own into its own grid of columns */
+        for (int s = 0; s < nsources(g); ++s) {
+            const orc_desc sd = source_desc(g, s);
+            int rc = raytrace_sc_3d(&sd, nH, x, tau_in + s * ncells(g));
+            if (rc != 0) return rc;
+        }
+        return 0;
+    }
     if (g->geometry == ORC_GEOM_PLANE_3D) {
         /* each row along x is a slab: the column from the lit face x = 0 */
         const int64_t nx = g->n[0], rows = (int64_t)g->n[1] * g->n[2];
@@ -430,9 +456,8 @@ static int cmp_double(const void* a, const void* b)
  * stopped on the upstream face along the dominant axis): the segment is cut at
  * every grid plane it crosses and each piece is charged n_H x of the cell that
  * holds its midpoint.  Accuracy reference for the short characteristics only. */
-int orc_raytrace_lc(const orc_desc* g, const double* nH, const double* x, double* tau_in)
+static int raytrace_lc_3d(const orc_desc* g, const double* nH, const double* x, double* tau_in)
 {
-    if (!g || g->geometry != ORC_GEOM_3D) return -1;
     const int nx = g->n[0], ny = g->n[1], nz = g->n[2];
     for (int k = 0; k < nz; ++k)
     for (int j = 0; j < ny; ++j)
@@ -468,6 +493,17 @@ int orc_raytrace_lc(const orc_desc* g, const double* nH, const double* x, double
         }
         free(ts);
         tau_in[idx] = g->sigma0 * col;
+    }
+    return 0;
+}
+
+int orc_raytrace_lc(const orc_desc* g, const double* nH, const double* x, double* tau_in)
+{
+    if (!g || g->geometry != ORC_GEOM_3D) return -1;
+    for (int s = 0; s < nsources(g); ++s) {
+        const orc_desc sd = source_desc(g, s);
+        int rc = raytrace_lc_3d(&sd, nH, x, tau_in + s * ncells(g));
+        if (rc != 0) return rc;
     }
     return 0;
 }
@@ -517,52 +553,85 @@ static void cooling_coeffs(const orc_desc* g, double T, double* cii, double* dci
     *dcin = cce * dlce + cci * dlci;
 }
 
+/* one further source's beam through a cell of a multi-source grid */
+typedef struct {
+    double geo, ell, tau_in, Pin, Hin, lin;
+    double Q;        /* mono: the source's photons per second                   */
+    double tscale;   /* table: the source's Q over the Q the table is written for */
+} beamenv;
+
 typedef struct {
     double nH, geo, ell, tau_in;
     double Pin, Hin; /* table values at tau_in */
     double lin;      /* -d ln P / d tau at tau_in: fraction absorbed per unit depth */
+    int nmore;       /* further sources (multi-source grids) */
+    beamenv more[ORC_MAX_SRC - 1];
 } cellenv;
 
-/* photon absorption per unit volume A(x) and heating per unit volume G(x) in a
- * cell whose neutral fraction is x, with the entering column tau_in frozen
- * (photon-conserving form: what enters minus what leaves). */
-static void photo(const orc_desc* g, const cellenv* c, double x, double* A, double* dA,
-                  double* G, double* dG)
+/* photon absorption per unit volume A(x) and heating per unit volume G(x) of
+ * one source's photons in a cell whose neutral fraction is x, with the
+ * entering column tau_in frozen (photon-conserving form: what enters minus
+ * what leaves).  Q: the source's photons per second (mono); ts: the source's
+ * Q over the table's (table mode). */
+static void photo_beam(const orc_desc* g, double nH, double Q, double ts, double geo,
+                       double ell, double tau_in, double Pin, double Hin, double lin, double x,
+                       double* A, double* dA, double* G, double* dG)
 {
-    const double k = c->nH * g->sigma0 * c->ell;
+    const double k = nH * g->sigma0 * ell;
     const double u = k * x;
     if (g->spectrum == ORC_SPEC_MONO) {
-        const double Fin = g->Q * exp(-c->tau_in);
-        *A = c->geo * Fin * (-expm1(-u));
-        *dA = c->geo * Fin * exp(-u) * k;
+        const double Fin = Q * exp(-tau_in);
+        *A = geo * Fin * (-expm1(-u));
+        *dA = geo * Fin * exp(-u) * k;
         *G = *A * g->e_excess;
         *dG = *dA * g->e_excess;
         return;
     }
-    if (u * c->lin < THIN_CELL) {
+    const double gs = geo * ts;
+    if (u * lin < THIN_CELL) {
         /* the cell absorbs a small fraction of what enters: P(tau) - P(tau + u)
          * as the integral of -dP/dtau over the cell, by two-point
          * Gauss-Legendre (no cancellation); the x-derivative keeps only the
          * leading term k * mean(-dP/dtau) */
         const double c2 = 0.5 / sqrt(3.0);
         double dP1, dP2, dH1, dH2;
-        orc_table_eval(g->table, 0, c->tau_in + (0.5 - c2) * u, &dP1);
-        orc_table_eval(g->table, 0, c->tau_in + (0.5 + c2) * u, &dP2);
-        orc_table_eval(g->table, 1, c->tau_in + (0.5 - c2) * u, &dH1);
-        orc_table_eval(g->table, 1, c->tau_in + (0.5 + c2) * u, &dH2);
+        orc_table_eval(g->table, 0, tau_in + (0.5 - c2) * u, &dP1);
+        orc_table_eval(g->table, 0, tau_in + (0.5 + c2) * u, &dP2);
+        orc_table_eval(g->table, 1, tau_in + (0.5 - c2) * u, &dH1);
+        orc_table_eval(g->table, 1, tau_in + (0.5 + c2) * u, &dH2);
         const double mP = -0.5 * (dP1 + dP2), mH = -0.5 * (dH1 + dH2);
-        *A = c->geo * mP * u;
-        *dA = c->geo * mP * k;
-        *G = c->geo * mH * u;
-        *dG = c->geo * mH * k;
+        *A = gs * mP * u;
+        *dA = gs * mP * k;
+        *G = gs * mH * u;
+        *dG = gs * mH * k;
     } else {
         double dP, dH;
-        double Pout = orc_table_eval(g->table, 0, c->tau_in + u, &dP);
-        double Hout = orc_table_eval(g->table, 1, c->tau_in + u, &dH);
-        *A = c->geo * (c->Pin - Pout);
-        *dA = c->geo * (-dP) * k;
-        *G = c->geo * (c->Hin - Hout);
-        *dG = c->geo * (-dH) * k;
+        double Pout = orc_table_eval(g->table, 0, tau_in + u, &dP);
+        double Hout = orc_table_eval(g->table, 1, tau_in + u, &dH);
+        *A = gs * (Pin - Pout);
+        *dA = gs * (-dP) * k;
+        *G = gs * (Hin - Hout);
+        *dG = gs * (-dH) * k;
+    }
+}
+
+/* A(x), G(x) and their x-derivatives in a cell: the sum over the sources that
+ * reach it, each beam absorbed on its own chord (several sources: each is
+ * traced separately and their rates add). */
+static void photo(const orc_desc* g, const cellenv* c, double x, double* A, double* dA,
+                  double* G, double* dG)
+{
+    photo_beam(g, c->nH, g->Q, 1.0, c->geo, c->ell, c->tau_in, c->Pin, c->Hin, c->lin, x, A, dA,
+               G, dG);
+    for (int m = 0; m < c->nmore; ++m) {
+        const beamenv* b = &c->more[m];
+        double a, da, h, dh;
+        photo_beam(g, c->nH, b->Q, b->tscale, b->geo, b->ell, b->tau_in, b->Pin, b->Hin, b->lin,
+                   x, &a, &da, &h, &dh);
+        *A += a;
+        *dA += da;
+        *G += h;
+        *dG += dh;
     }
 }
 
@@ -795,12 +864,41 @@ static void make_env(const orc_desc* g, double nH, double geo, double ell, doubl
     c->ell = ell;
     c->tau_in = tau_in;
     c->Pin = c->Hin = c->lin = 0.0;
+    c->nmore = 0;
     if (g->spectrum == ORC_SPEC_TABLE) {
         double dP;
         c->Pin = orc_table_eval(g->table, 0, tau_in, &dP);
         c->Hin = orc_table_eval(g->table, 1, tau_in, NULL);
         c->lin = c->Pin > 0.0 ? -dP / c->Pin : 0.0;
     }
+}
+
+/* environment of grid cell i: every source's geometry and entering column
+ * (tau holds one grid of columns per source) */
+static void make_env_grid(const orc_desc* g, int64_t i, double nH, const double* tau,
+                          cellenv* c)
+{
+    double geo, ell;
+    orc_cell_env(g, i, &geo, &ell);
+    make_env(g, nH, geo, ell, tau ? tau[i] : 0.0, c);
+    const int ns = nsources(g);
+    const int64_t N = ncells(g);
+    for (int s = 1; s < ns; ++s) {
+        const orc_desc d = source_desc(g, s);
+        beamenv* b = &c->more[s - 1];
+        orc_cell_env(&d, i, &b->geo, &b->ell);
+        b->tau_in = tau ? tau[s * N + i] : 0.0;
+        b->Q = d.Q;
+        b->tscale = d.Q / g->Q;
+        b->Pin = b->Hin = b->lin = 0.0;
+        if (g->spectrum == ORC_SPEC_TABLE) {
+            double dP;
+            b->Pin = orc_table_eval(g->table, 0, b->tau_in, &dP);
+            b->Hin = orc_table_eval(g->table, 1, b->tau_in, NULL);
+            b->lin = b->Pin > 0.0 ? -dP / b->Pin : 0.0;
+        }
+    }
+    c->nmore = ns - 1;
 }
 
 /* Initial substep count of one micro-integration (reading, a fixed-structure
@@ -990,10 +1088,8 @@ int orc_timestep(const orc_desc* g, const double* nH, const double* x, const dou
     const int64_t N = ncells(g);
     double dt = INFINITY;
     for (int64_t i = 0; i < N; ++i) {
-        double geo, ell;
-        env_of(g, i, &geo, &ell);
         cellenv c;
-        make_env(g, nH[i], geo, ell, tau[i], &c);
+        make_env_grid(g, i, nH[i], tau, &c);
         dt = fmin(dt, cell_dt(g, &c, x[i], E ? E[i] : 0.0));
     }
     *dt_out = dt;
@@ -1005,10 +1101,8 @@ int orc_chem(const orc_desc* g, const double* nH, const double* x0, const double
 {
     const int64_t N = ncells(g);
     for (int64_t i = 0; i < N; ++i) {
-        double geo, ell;
-        env_of(g, i, &geo, &ell);
         cellenv c;
-        make_env(g, nH[i], geo, ell, tau[i], &c);
+        make_env_grid(g, i, nH[i], tau, &c);
         double xe, Ee;
         micro(g, &c, x0[i], E0 ? E0[i] : 0.0, h, &xe, &Ee);
         x1[i] = xe;
@@ -1045,6 +1139,7 @@ int orc_a1_pass(const orc_desc* g, const double* nH, double* x, double* E, doubl
 {
     if (!g || !nH || !x || !tau_avg || !kbar) return -1;
     if (g->geometry == ORC_GEOM_SPHERICAL_1D) return -1;
+    if (nsources(g) > 1) return -1;   /* one point source */
     const int64_t N = ncells(g);
     if (g->geometry != ORC_GEOM_3D) {
         /* slabs: every row from its lit face */
@@ -1158,7 +1253,7 @@ int orc_step_tc(const orc_desc* g, const double* nH, const double* nH_half, doub
     } else if (algo == 3) {
         double* xs = (double*)malloc(sizeof(double) * (size_t)N);
         double* Es = E ? (double*)malloc(sizeof(double) * (size_t)N) : NULL;
-        double* ts = (double*)malloc(sizeof(double) * (size_t)N);
+        double* ts = (double*)malloc(sizeof(double) * (size_t)(N * nsources(g)));
         orc_chem(g, nH, x, E, tau, 0.5 * dt, xs, Es);
         orc_raytrace_sc(g, nH_half ? nH_half : nH, xs, ts);
         orc_chem(g, nH, x, E, ts, dt, x, E);
@@ -1189,7 +1284,7 @@ int orc_diagnostics(const orc_desc* g, const double* nH, const double* x, const 
         else if (g->geometry == ORC_GEOM_SPHERICAL_1D) vol = 1.0 / geo;
         else vol = g->dx;
         cellenv c;
-        make_env(g, nH[i], geo, ell, tau ? tau[i] : 0.0, &c);
+        make_env_grid(g, i, nH[i], tau, &c);
         rhsval r;
         rhs(g, &c, x[i], E ? E[i] : 0.0, &r);
         nion += nH[i] * (1.0 - x[i]) * vol;
@@ -1203,14 +1298,19 @@ int orc_diagnostics(const orc_desc* g, const double* nH, const double* x, const 
     out->recomb_rate = rr;
     out->newton_fail = g_newton_fail;
     if (g->geometry == ORC_GEOM_3D) {
+        /* several sources: octants of all of them (reading: each source's
+         * region counts as its share of one sphere) */
         int noct = 0;
-        for (int o = 0; o < 8; ++o) {
-            int ok = 1;
-            for (int d = 0; d < 3; ++d) {
-                int ext = ((o >> d) & 1) ? g->n[d] - g->src[d] : g->src[d];
-                if (ext <= 0) ok = 0;
+        for (int s = 0; s < nsources(g); ++s) {
+            const orc_desc sd = source_desc(g, s);
+            for (int o = 0; o < 8; ++o) {
+                int ok = 1;
+                for (int d = 0; d < 3; ++d) {
+                    int ext = ((o >> d) & 1) ? sd.n[d] - sd.src[d] : sd.src[d];
+                    if (ext <= 0) ok = 0;
+                }
+                noct += ok;
             }
-            noct += ok;
         }
         out->r_ion = cbrt(3.0 * vion * 8.0 / (4.0 * M_PI * noct));
     } else if (g->geometry == ORC_GEOM_PLANE_3D) {

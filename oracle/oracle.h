@@ -16,6 +16,7 @@
 #include <stdint.h>
 
 #define ORC_NTAB 64
+#define ORC_MAX_SRC 4
 
 /* ORC_GEOM_PLANE_3D: a 3D grid lit by a plane-parallel source at x = -infinity
  * (the slab test of Sect. 3.1 extended to three dimensions): every row of
@@ -46,6 +47,16 @@ typedef struct {
     int32_t source_cell_rule;/* 1: octant-corner cell takes Q/8 over mean chord   */
     int32_t n_sub;           /* SDIRK substeps per micro-integration              */
     double  K[4];            /* eq.(4) factors; +inf = criterion unused           */
+    /* Further point sources (ORC_GEOM_3D only).  nsrc 0 or 1: the source at
+     * src alone.  nsrc = m > 1: source 0 at src with Q, sources 1..m-1 at
+     * src_more[s-1] with Q_more[s-1]; all share the spectrum (table mode: the
+     * table is written for Q > 0 and scaled by Q_s / Q).  Every column array
+     * (tau, tau_in) then holds m consecutive grids of N cells, source s at
+     * offset s N, each traced on its own; the photoionisation and heating
+     * rates of the sources add in every cell. */
+    int32_t nsrc;
+    int32_t src_more[ORC_MAX_SRC - 1][3];
+    double  Q_more[ORC_MAX_SRC - 1];
 } orc_desc;
 
 /* per-step diagnostics (FP64 sums) */

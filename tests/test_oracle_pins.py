@@ -716,3 +716,82 @@ def test_a1_stromgren_front_with_long_steps(oracle_lib):
         pb.run(st, c * spec.t_rec, algo=1)
         Ra = RS * (1 - math.exp(-st["t"] / spec.t_rec)) ** (1 / 3)
         assert abs(pb.diagnostics(st)["r_ion"] / Ra - 1) < 0.02, c
+
+
+# ----------------------------------------------------------- several sources
+def _two_source_problem(spec, more, **over):
+    return oracle.Problem.from_spec(spec, more_sources=more, **over)
+
+
+@pytest.mark.parametrize("spectrum", ["mono", "table"])
+def test_sources_at_one_vertex_split_the_luminosity(oracle_lib, spectrum):
+    """Rates of several sources add in every cell (each source traced on its
+    own): sources Q_a + Q_b = Q at one vertex are the single source Q, through
+    whole A3 steps, to rounding.  A dropped or mis-scaled beam changes the
+    ionised volume by a fraction of order Q_b / Q."""
+    spec = synth.cfg2(n=10)
+    if spectrum == "mono":
+        spec = synth.cfg2(n=10, spectrum="mono", e_excess=2.0 * EV)
+    nH = synth.lognormal_density(spec.shape, 10.0, 1.0, 3)
+    one = oracle.Problem.from_spec(spec)
+    two = _two_source_problem(spec, [(spec.src, 0.35 * spec.Q)], Q=0.65 * spec.Q)
+    a = one.initial_state(nH, T0=50.0)
+    b = two.initial_state(nH, T0=50.0)
+    assert b["tau"].shape == (2,) + one.shape
+    assert np.array_equal(b["tau"][0], a["tau"]) and np.array_equal(b["tau"][1], a["tau"])
+    for _ in range(5):
+        one.step(a, spec.t_end)
+        two.step(b, spec.t_end)
+    assert b["t"] == pytest.approx(a["t"], rel=1e-12)
+    np.testing.assert_allclose(b["x"], a["x"], rtol=1e-10, atol=1e-13)
+    np.testing.assert_allclose(b["E"], a["E"], rtol=1e-10)
+    assert (1 - a["x"]).sum() > 1.0   # something happened
+
+
+def test_two_sources_columns_and_rates_superpose(oracle_lib):
+    """Each source's columns are the single-source raytrace from its vertex
+    (bit for bit), and at a fixed state the photoionisation rate of the grid
+    is the sum of the two single-source rates, each with its own columns."""
+    spec = synth.cfg2(n=12)
+    rng = np.random.default_rng(7)
+    nH = synth.lognormal_density(spec.shape, 10.0, 1.0, 4)
+    x = rng.uniform(0.05, 1.0, spec.shape)
+    va, vb = (3, 4, 5), (9, 7, 2)
+    pa = oracle.Problem.from_spec(spec, src=va, Q=0.6 * spec.Q)
+    pb_ = oracle.Problem.from_spec(spec, src=vb, Q=0.4 * spec.Q)
+    pab = oracle.Problem.from_spec(spec, src=va, Q=0.6 * spec.Q,
+                                   more_sources=[(vb, 0.4 * spec.Q)])
+    E = pa.energy_from_temperature(nH, x, 8000.0)
+    ta, tb, tab = pa.raytrace(nH, x), pb_.raytrace(nH, x), pab.raytrace(nH, x)
+    assert np.array_equal(tab[0], ta) and np.array_equal(tab[1], tb)
+    da = pa.diagnostics({"nH": nH, "x": x, "E": E, "tau": ta})
+    db = pb_.diagnostics({"nH": nH, "x": x, "E": E, "tau": tb})
+    dab = pab.diagnostics({"nH": nH, "x": x, "E": E, "tau": tab})
+    assert dab["photo_rate"] == pytest.approx(da["photo_rate"] + db["photo_rate"], rel=1e-12)
+    assert dab["recomb_rate"] == pytest.approx(da["recomb_rate"], rel=1e-14)
+    # both sources inside: 16 octants, each source's share of one sphere
+    assert dab["r_ion"] == pytest.approx(
+        (3 * dab["v_ion"] * 8 / (4 * math.pi * 16)) ** (1 / 3), rel=1e-14)
+    # the timestep sees the summed rate: no larger than either source alone
+    dt_ab = pab.timestep(nH, x, E, tab)
+    assert dt_ab <= min(pa.timestep(nH, x, E, ta), pb_.timestep(nH, x, E, tb)) * (1 + 1e-12)
+
+
+def test_mirrored_sources_give_a_mirrored_solution(oracle_lib):
+    """Two equal sources at mirror-image vertices in a density field that is
+    symmetric under the mirror: every A3 step keeps the state symmetric (a
+    beam traced or weighted from the wrong vertex breaks it)."""
+    spec = synth.cfg2(n=12)
+    n = spec.n[0]
+    nH = synth.lognormal_density(spec.shape, 10.0, 1.0, 5)
+    nH = 0.5 * (nH + nH[:, :, ::-1])                    # symmetric in x
+    va, vb = (3, 5, 6), (n - 3, 5, 6)
+    pm = oracle.Problem.from_spec(spec, src=va, Q=0.5 * spec.Q,
+                                  more_sources=[(vb, 0.5 * spec.Q)])
+    st = pm.initial_state(nH, T0=50.0)
+    np.testing.assert_allclose(st["tau"][1], st["tau"][0][:, :, ::-1], rtol=1e-14, atol=0)
+    for _ in range(6):
+        pm.step(st, spec.t_end)
+    np.testing.assert_allclose(st["x"], st["x"][:, :, ::-1], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(st["E"], st["E"][:, :, ::-1], rtol=1e-12)
+    assert (1 - st["x"]).sum() > 1.0
