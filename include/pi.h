@@ -71,6 +71,8 @@ enum { PI_BUF_N = 0, PI_BUF_HALF = 1 };
 /* number of work counters returned by pi_work_counters */
 #define PI_NWORK 5
 #define PI_NTAB 64
+/* most point sources of one grid */
+#define PI_MAX_SRC 4
 
 /* Problem description (copied by pi_grid_create). */
 typedef struct {
@@ -100,6 +102,16 @@ typedef struct {
                               /* (dt02 of Table 1: {inf, inf, inf, 0.25})             */
     int32_t precision;        /* pi_precision                                         */
     int32_t source;           /* PI_SRC_POINT or PI_SRC_PLANE                         */
+    /* Several point sources (PI_SRC_POINT, single grids: pi_grid_create only).
+     * nsrc 0 or 1: the source at src with Q alone.  nsrc = m in 2..PI_MAX_SRC:
+     * source 0 at src with Q, source s = 1..m-1 at vertex src_more[s-1] with
+     * Q_more[s-1] photons per second (>= 0); all share the spectrum.  Each
+     * source is traced on its own and the photoionisation and heating rates of
+     * the sources add in every cell.  tau and tau_half then hold m consecutive
+     * arrays of nx*ny*nz cells, source s at element offset s*nx*ny*nz. */
+    int32_t nsrc;
+    int32_t src_more[PI_MAX_SRC - 1][3];
+    double  Q_more[PI_MAX_SRC - 1];
 } pi_grid_desc;
 
 /* Caller-owned device fields (see Conventions).  E and E_half may be NULL when
@@ -110,7 +122,8 @@ typedef struct {
     void* x;         /* neutral fraction 1 - y in [0, 1] (Sect. 2.1)          */
     void* E;         /* internal energy density [erg cm^-3]                   */
     void* tau;       /* threshold optical depth from the source to each       */
-                     /* cell's entry face, for (x, E)                         */
+                     /* cell's entry face, for (x, E); nsrc > 1: one array of */
+                     /* cells per source, source after source                 */
     void* x_half;
     void* E_half;
     void* tau_half;
@@ -175,8 +188,9 @@ pi_status pi_step_o1(pi_grid* grid, double t_end, void* stream);
  * columns of the cells behind it.  Afterwards x_half holds each cell's
  * time-averaged optical depth per cell length (sigma0 dx units), tau_half the
  * time-averaged entering columns, and tau the columns of the new state (a
- * raytrace, for the next timestep).  Point sources only (PI_EINVAL for
- * PI_SRC_PLANE); the pass runs on 4^3 tiles whatever the raytrace tile. */
+ * raytrace, for the next timestep).  One point source only (PI_EINVAL for
+ * PI_SRC_PLANE or nsrc > 1); the pass runs on 4^3 tiles whatever the raytrace
+ * tile. */
 pi_status pi_step_a1(pi_grid* grid, double t_end, void* stream);
 
 /* Energy density of state `state` from a uniform temperature T0 [K] for pure
@@ -193,7 +207,8 @@ pi_status pi_grid_state(pi_grid* grid, double* t, int64_t* nsteps, double* last_
 /* FP64 diagnostics of state PI_BUF_N with columns tau (SYNCHRONISES):
  * out[0] ions sum n_H (1-x) V, out[1] ionised volume sum (1-x) V,
  * out[2] volume-equivalent ionised radius (3 V_ion 8 / (4 pi n_octants))^1/3
- * (PI_SRC_PLANE: ionised depth, V_ion over the area of the lit face),
+ * (PI_SRC_PLANE: ionised depth, V_ion over the area of the lit face; several
+ * sources: n_octants counts the octants of every source),
  * out[3] photoionisations per second, out[4] recombinations per second,
  * out[5] number of non-finite cells, out[6] number of octants (0 for
  * PI_SRC_PLANE), out[7] time t. */
@@ -220,7 +235,8 @@ typedef struct pi_batch pi_batch;
 
 /* ngrids descriptors and fields (arrays of ngrids, copied; the fields stay
  * owned by the caller and valid until pi_batch_destroy).  All descriptors
- * share one precision.  Errors as pi_grid_create, prefixed with the grid. */
+ * share one precision and have one source each (PI_EINVAL for nsrc > 1).
+ * Errors as pi_grid_create, prefixed with the grid. */
 pi_status pi_batch_create(int ngrids, const pi_grid_desc* descs, const pi_fields* fields,
                           pi_batch** out);
 /* Synchronises the device and frees the batch; NULL is accepted. */
@@ -266,7 +282,7 @@ typedef struct {
 } pi_server_desc;
 
 typedef struct {
-    pi_grid_desc  desc;       /* precision must be the server's                  */
+    pi_grid_desc  desc;       /* precision must be the server's; one source      */
     const double* nH;         /* host, n[0]*n[1]*n[2] cells, > 0 (copied)         */
     const double* x0;         /* host initial neutral fraction, or NULL: 1       */
     double        T0;         /* initial temperature [K] (T evolving)            */
@@ -325,7 +341,7 @@ const char* pi_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns the
  * value it was built with. */
-#define PI_ABI_VERSION 107
+#define PI_ABI_VERSION 108
 int pi_abi_version(void);
 
 #ifdef __cplusplus

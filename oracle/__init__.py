@@ -309,7 +309,8 @@ class Problem:
                   alpha_B=spec.alpha_B, collisional=int(spec.collisional),
                   cooling=int(spec.cooling),
                   weights=W_MELLEMA if spec.weights == "mellema" else W_GEOMETRIC,
-                  source_cell_rule=int(spec.source_cell_rule), n_sub=spec.n_sub, K=tuple(spec.K))
+                  source_cell_rule=int(spec.source_cell_rule), n_sub=spec.n_sub, K=tuple(spec.K),
+                  more_sources=tuple(getattr(spec, "more_sources", ())))
         kw.update(over)
         return cls(**kw)
 

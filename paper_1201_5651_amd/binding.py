@@ -27,6 +27,7 @@ PI_BUF_N, PI_BUF_HALF = 0, 1
 PI_NDIAG = 8
 PI_NWORK = 5
 PI_NTAB = 64
+PI_MAX_SRC = 4
 
 # every symbol include/pi.h declares
 ABI_SYMBOLS = (
@@ -72,6 +73,9 @@ class GridDesc(C.Structure):
         ("K", C.c_double * 4),
         ("precision", C.c_int32),
         ("source", C.c_int32),
+        ("nsrc", C.c_int32),
+        ("src_more", (C.c_int32 * 3) * (PI_MAX_SRC - 1)),
+        ("Q_more", C.c_double * (PI_MAX_SRC - 1)),
     ]
 
 
@@ -189,6 +193,13 @@ def desc_from_spec(spec, precision: Optional[str] = None, sigma0: float = 6.3e-1
     prec = precision or spec.precision
     d.precision = {"fp64": PI_FP64, "fp32": PI_FP32, "mixed": PI_MIXED}[prec]
     d.source = PI_SRC_PLANE if getattr(spec, "source", "point") == "plane" else PI_SRC_POINT
+    more = tuple(getattr(spec, "more_sources", ()))
+    if len(more) > PI_MAX_SRC - 1:
+        raise ValueError(f"at most {PI_MAX_SRC} sources")
+    d.nsrc = 1 + len(more)
+    for m, (v, q) in enumerate(more):
+        d.src_more[m][:] = tuple(int(c) for c in v)
+        d.Q_more[m] = float(q)
     return d
 
 
@@ -207,8 +218,12 @@ class GridFields:
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
         self.device = torch.device(device)
         z = lambda: torch.zeros(spec.shape, dtype=self.dtype, device=self.device)
-        self.nH, self.x, self.tau = z(), z(), z()
-        self.x_half, self.tau_half = z(), z()
+        # columns: one grid of cells per source
+        ns = 1 + len(tuple(getattr(spec, "more_sources", ())))
+        tshape = (ns,) + tuple(spec.shape) if ns > 1 else spec.shape
+        zt = lambda: torch.zeros(tshape, dtype=self.dtype, device=self.device)
+        self.nH, self.x, self.tau = z(), z(), zt()
+        self.x_half, self.tau_half = z(), zt()
         evolve = spec.thermal == "evolve"
         self.E = z() if evolve else None
         self.E_half = z() if evolve else None

@@ -34,8 +34,9 @@ struct GridHost {
     int noct = 0;
     double cell_vol = 0.0;
     int64_t ncell = 0;
-    // per tile edge (SWEEP_TILES), per tile diagonal: (octant, tx, ty, tz)
-    std::vector<std::vector<int4>> tiles[NSWEEP];
+    // per source, per tile edge (SWEEP_TILES), per tile diagonal:
+    // (octant, tx, ty, tz)
+    std::vector<std::vector<int4>> tiles[MAX_SRC][NSWEEP];
 };
 
 pi_status grid_host_init(GridHost& h, const pi_grid_desc& d, const pi_fields& f);
@@ -50,6 +51,10 @@ struct Engine {
     size_t first_cap = 0;
     int chem_blocks = 0, dt_blocks = 0;
     int plane_rows = 0;   // rows along x of the plane-parallel grids
+    // (grid, source) of the raytrace entries past the grids: the further
+    // sources of a grid with several; msrc is MAX_SRC when there are any
+    std::vector<int2> extra;
+    int msrc = 1;
     // raytrace schedules, one per tile edge of SWEEP_TILES
     int4* tiles[NSWEEP] = {};
     size_t tiles_cap[NSWEEP] = {};

@@ -21,17 +21,32 @@ namespace pi {
 
 namespace {
 
+// Point sources of a grid and the vertex of source s.
+int nsources(const pi_grid_desc& d)
+{
+    return (d.source == PI_SRC_POINT && d.nsrc > 1) ? d.nsrc : 1;
+}
+
+const int32_t* source_vertex(const pi_grid_desc& d, int s)
+{
+    return s == 0 ? d.src : d.src_more[s - 1];
+}
+
+// Octants around every source that hold cells.
 int octant_count(const pi_grid_desc& d)
 {
     if (d.source == PI_SRC_PLANE) return 0;
     int noct = 0;
-    for (int o = 0; o < 8; ++o) {
-        bool ok = true;
-        for (int a = 0; a < 3; ++a) {
-            const int ext = ((o >> a) & 1) ? d.n[a] - d.src[a] : d.src[a];
-            ok = ok && ext > 0;
+    for (int s = 0; s < nsources(d); ++s) {
+        const int32_t* v = source_vertex(d, s);
+        for (int o = 0; o < 8; ++o) {
+            bool ok = true;
+            for (int a = 0; a < 3; ++a) {
+                const int ext = ((o >> a) & 1) ? d.n[a] - v[a] : v[a];
+                ok = ok && ext > 0;
+            }
+            noct += ok;
         }
-        noct += ok;
     }
     return noct;
 }
@@ -96,6 +111,12 @@ template <typename R> Params<R> make_params(const pi_grid_desc& d)
     p.src_rule = d.source_cell_rule;
     p.n_sub = d.n_sub;
     p.tab = nullptr;
+    p.nsrc = nsources(d);
+    for (int s = 1; s < MAX_SRC; ++s) {
+        const bool on = s < p.nsrc;
+        for (int a = 0; a < 3; ++a) p.msrc[s - 1][a] = on ? d.src_more[s - 1][a] : 0;
+        p.mQV[s - 1] = R(on ? d.Q_more[s - 1] / (d.dx * d.dx * d.dx) : 0.0);
+    }
     return p;
 }
 
@@ -150,7 +171,7 @@ template <typename R> R* fld(void* v) { return static_cast<R*>(v); }
 
 template <typename R> pi_status upload_grids(Engine& e)
 {
-    std::vector<GridDev<R>> h(e.grids.size());
+    std::vector<GridDev<R>> h(e.grids.size() + e.extra.size());
     for (size_t g = 0; g < e.grids.size(); ++g) {
         const GridHost& G = *e.grids[g];
         void *td, *tf;
@@ -176,6 +197,20 @@ template <typename R> pi_status upload_grids(Engine& e)
         D.cell_vol = G.cell_vol;
         D.face_area = G.d.source == PI_SRC_PLANE ? (double)G.d.n[1] * G.d.n[2] * G.d.dx * G.d.dx : 0.0;
         D.noct = G.noct;
+    }
+    // the raytrace entries of further sources: the grid seen from source s,
+    // whose columns follow the grid's columns at s cells of arrays
+    for (size_t m = 0; m < e.extra.size(); ++m) {
+        const int g = e.extra[m].x, src = e.extra[m].y;
+        const GridHost& G = *e.grids[g];
+        GridDev<R>& D = h[e.grids.size() + m];
+        D = h[g];
+        const int32_t* v = source_vertex(G.d, src);
+        D.p.sx = D.pd.sx = v[0];
+        D.p.sy = D.pd.sy = v[1];
+        D.p.sz = D.pd.sz = v[2];
+        D.tau[0] += (int64_t)src * G.ncell;
+        D.tau[1] += (int64_t)src * G.ncell;
     }
     const size_t bytes = sizeof(GridDev<R>) * std::max<size_t>(1, h.size());
     if (bytes > e.gdev_cap) {
@@ -270,8 +305,8 @@ template <typename R> pi_status step_a1_t(Engine& e, double t_end_arg, hipStream
 {
     static_assert(SWEEP_TILES[0] == 4, "the algorithm 1 pass runs on the 4^3 tile schedule");
     for (GridHost* h : e.grids)
-        if (h->d.source != PI_SRC_POINT)
-            return fail(PI_EINVAL, "algorithm 1 needs point-source grids");
+        if (h->d.source != PI_SRC_POINT || nsources(h->d) > 1)
+            return fail(PI_EINVAL, "algorithm 1 needs grids with one point source");
     pi_status r = timestep_t<R>(e, t_end_arg, s);
     if (r != PI_OK) return r;
     for (size_t k = 0; k < e.stage_first[0].size(); ++k)
@@ -296,6 +331,7 @@ BatchDev Engine::bd() const
     b.fix_n = fix_n;
     b.fix_list = fix_list;
     b.fix_cap = (unsigned int)fix_cap;
+    b.msrc = msrc;
     return b;
 }
 
@@ -317,28 +353,32 @@ pi_status grid_host_init(GridHost& h, const pi_grid_desc& d, const pi_fields& f)
         grid_host_free(h);
         return fail(PI_ENOMEM, "partials allocation");
     }
-    // tile schedules: every octant's tiles, grouped by tile diagonal tx+ty+tz
-    // (none for a plane-parallel source, which is traced row by row)
-    for (int w = 0; w < NSWEEP; ++w) {
-        const int T = SWEEP_TILES[w];
-        h.tiles[w].clear();
-        if (d.source == PI_SRC_PLANE) continue;
-        for (int o = 0; o < 8; ++o) {
-            int ext[3];
-            for (int a = 0; a < 3; ++a) ext[a] = ((o >> a) & 1) ? d.n[a] - d.src[a] : d.src[a];
-            if (ext[0] <= 0 || ext[1] <= 0 || ext[2] <= 0) continue;
-            const int ntx = (ext[0] + T - 1) / T;
-            const int nty = (ext[1] + T - 1) / T;
-            const int ntz = (ext[2] + T - 1) / T;
-            for (int tz = 0; tz < ntz; ++tz)
-                for (int ty = 0; ty < nty; ++ty)
-                    for (int tx = 0; tx < ntx; ++tx) {
-                        const int D = tx + ty + tz;
-                        if ((int)h.tiles[w].size() <= D) h.tiles[w].resize(D + 1);
-                        h.tiles[w][D].push_back(make_int4(o, tx, ty, tz));
-                    }
+    // tile schedules of every source: every octant's tiles, grouped by tile
+    // diagonal tx+ty+tz (none for a plane-parallel source, which is traced row
+    // by row)
+    for (int s = 0; s < MAX_SRC; ++s)
+        for (int w = 0; w < NSWEEP; ++w) {
+            const int T = SWEEP_TILES[w];
+            std::vector<std::vector<int4>>& tl = h.tiles[s][w];
+            tl.clear();
+            if (d.source == PI_SRC_PLANE || s >= nsources(d)) continue;
+            const int32_t* v = source_vertex(d, s);
+            for (int o = 0; o < 8; ++o) {
+                int ext[3];
+                for (int a = 0; a < 3; ++a) ext[a] = ((o >> a) & 1) ? d.n[a] - v[a] : v[a];
+                if (ext[0] <= 0 || ext[1] <= 0 || ext[2] <= 0) continue;
+                const int ntx = (ext[0] + T - 1) / T;
+                const int nty = (ext[1] + T - 1) / T;
+                const int ntz = (ext[2] + T - 1) / T;
+                for (int tz = 0; tz < ntz; ++tz)
+                    for (int ty = 0; ty < nty; ++ty)
+                        for (int tx = 0; tx < ntx; ++tx) {
+                            const int D = tx + ty + tz;
+                            if ((int)tl.size() <= D) tl.resize(D + 1);
+                            tl[D].push_back(make_int4(o, tx, ty, tz));
+                        }
+            }
         }
-    }
     return PI_OK;
 }
 
@@ -355,6 +395,13 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
     drop_graph(e);
     e.grids = grids;
     const int G = e.ngrids();
+    // further sources of each grid: raytrace entries G, G + 1, ...
+    e.extra.clear();
+    for (int g = 0; g < G; ++g)
+        for (int s = 1; s < nsources(e.grids[g]->d); ++s) e.extra.push_back(make_int2(g, s));
+    e.msrc = e.extra.empty() ? 1 : MAX_SRC;
+    if (!e.extra.empty() && G > 1)
+        return fail(PI_EINVAL, "a grid with several sources is advanced on its own, not in a batch");
     // launch geometry
     // three prefix tables of G + 1 entries: micro-physics workgroups,
     // timestep workgroups, rows of plane-parallel grids
@@ -391,14 +438,18 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
         e.stage_count[w].clear();
         std::vector<int4> flat;
         size_t nst = 0;
-        for (GridHost* h : e.grids) nst = std::max(nst, h->tiles[w].size());
+        for (GridHost* h : e.grids)
+            for (int s = 0; s < MAX_SRC; ++s) nst = std::max(nst, h->tiles[s][w].size());
+        // entry r of the grid table traces grid g from source s
+        const int R = G + (int)e.extra.size();
         for (size_t k = 0; k < nst; ++k) {
             e.stage_first[w].push_back((int)flat.size());
-            for (int g = 0; g < G; ++g) {
-                const GridHost& h = *e.grids[g];
-                if (k >= h.tiles[w].size()) continue;
-                for (const int4& t : h.tiles[w][k])
-                    flat.push_back(make_int4((g << 3) | t.x, t.y, t.z, t.w));
+            for (int r = 0; r < R; ++r) {
+                const int g = r < G ? r : e.extra[r - G].x;
+                const int src = r < G ? 0 : e.extra[r - G].y;
+                const std::vector<std::vector<int4>>& tl = e.grids[g]->tiles[src][w];
+                if (k >= tl.size()) continue;
+                for (const int4& t : tl[k]) flat.push_back(make_int4((r << 3) | t.x, t.y, t.z, t.w));
             }
             e.stage_count[w].push_back((int)flat.size() - e.stage_first[w].back());
         }

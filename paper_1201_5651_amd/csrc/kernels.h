@@ -105,6 +105,8 @@ struct BatchDev {
     unsigned int* fix_n;
     long long* fix_list;     // (grid << 32) | cell, for the double re-solve
     unsigned int fix_cap;    // entries fix_list holds
+    int msrc;                // MAX_SRC when a grid has several sources (their
+                             // micro-physics and timestep kernels), else 1
 };
 
 // One tile-diagonal stage of the raytrace of every grid with tiles of edge

@@ -297,10 +297,41 @@ __device__ __forceinline__ Params<R> table_to_lds(const Params<R>& p, DevTable<R
     return pl;
 }
 
+// Environment of the kernels instantiated for MS sources: a one-source grid
+// takes Env, grids with several sources EnvM.
+template <typename C, int MS> struct EnvSel { using type = EnvM<C, MS>; };
+template <typename C> struct EnvSel<C, 1> { using type = Env<C>; };
+
+// Environment of cell q = (i, j, k) of a grid with several sources: source s
+// has its own geometry and its own columns, tau[s * ncell + q].  ok turns false
+// when one of the columns is not finite.
+template <int MS, typename C, typename S>
+__device__ __forceinline__ EnvM<C, MS> multi_env(const Params<C>& p, C n, const S* __restrict__ tau,
+                                                 int q, int i, int j, int k, C tq, bool& ok)
+{
+    EnvM<C, MS> e{};
+    e.s[0] = make_env(p, n, cell_geom(p, i, j, k), tq);
+    e.n = e.s[0].n;
+    e.inv_n = e.s[0].inv_n;
+    e.c3 = e.s[0].c3;
+    e.ns = p.nsrc;
+#pragma unroll
+    for (int s = 1; s < MS; ++s) {
+        if (s < p.nsrc) {
+            const C ts = C(tau[(int64_t)s * p.ncell + q]);
+            ok = ok && isfinite(ts);
+            const CellGeom<C> cg =
+                cell_geom_at(p, p.msrc[s - 1][0], p.msrc[s - 1][1], p.msrc[s - 1][2], i, j, k);
+            e.s[s] = make_env_q(p, p.mQV[s - 1], n, cg, ts);
+        }
+    }
+    return e;
+}
+
 // Micro-integration of cell q in arithmetic C from storage S.  A non-finite
 // input stays non-finite (the bound projections of the solver would otherwise
 // turn it into a valid-looking state), so the grid's diagnostics report it.
-template <typename C, typename S>
+template <typename C, typename S, int MS>
 __device__ __forceinline__ void chem_cell(const Params<C>& p, int q, const S* __restrict__ nH,
                                           const S* x0, const S* E0, const S* __restrict__ tau,
                                           double hd, C& x, C& E, Work& w)
@@ -313,15 +344,25 @@ __device__ __forceinline__ void chem_cell(const Params<C>& p, int q, const S* __
         return;
     }
     const int i = q % p.nx, j = (q / p.nx) % p.ny, k = q / (p.nx * p.ny);
-    const CellGeom<C> cg = cell_geom(p, i, j, k);
-    const Env<C> e = make_env(p, n, cg, tq);
-    micro(p, e, C(hd), x, E, w);
+    if constexpr (MS == 1) {
+        const CellGeom<C> cg = cell_geom(p, i, j, k);
+        const Env<C> e = make_env(p, n, cg, tq);
+        micro(p, e, C(hd), x, E, w);
+    } else {
+        bool ok = true;
+        const EnvM<C, MS> e = multi_env<MS>(p, n, tau, q, i, j, k, tq, ok);
+        if (!ok) {
+            x = E = C(__builtin_nan(""));
+            return;
+        }
+        micro(p, e, C(hd), x, E, w);
+    }
 }
 
 // Micro-physics of every cell of every grid.  With mixed precision, a cell
 // whose float integration took a precision-sensitive decision is not written;
 // it is appended to the batch's re-solve list for the double pass.
-template <typename R>
+template <typename R, int MS>
 __global__ void __launch_bounds__(CHEM_BLOCK) __attribute__((amdgpu_waves_per_eu(ChemWaves<R>::value)))
 k_chem(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int tau_buf,
        int dev_dt, double hscale, unsigned long long* ctr, int mixed)
@@ -346,7 +387,7 @@ k_chem(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int 
     if (inside) {
         const double hd = dev_dt ? hscale * G.st->dt : hscale;
         R x, E;
-        chem_cell<R, R>(pl, q, G.nH, G.x[from], G.E[from], G.tau[tau_buf], hd, x, E, w);
+        chem_cell<R, R, MS>(pl, q, G.nH, G.x[from], G.E[from], G.tau[tau_buf], hd, x, E, w);
         flag = mixed && w.close > 0;
         if (!flag) {
             G.x[to][q] = x;
@@ -374,6 +415,7 @@ k_chem(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int 
 // grid, so the rate table is read from global memory here.  Workgroups beyond
 // the list return at once; the last workgroup to finish clears the list length
 // and the finish count for the next micro-physics launch.
+template <int MS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ChemWaves<double>::value)))
 k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int to, int tau_buf,
            int dev_dt, double hscale, unsigned long long* ctr)
@@ -387,7 +429,8 @@ k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int 
             const int q = (int)(e & 0xffffffffll);
             const double hd = dev_dt ? hscale * G.st->dt : hscale;
             double x, E;
-            chem_cell<double, float>(G.pd, q, G.nH, G.x[from], G.E[from], G.tau[tau_buf], hd, x, E, w);
+            chem_cell<double, float, MS>(G.pd, q, G.nH, G.x[from], G.E[from], G.tau[tau_buf], hd,
+                                         x, E, w);
             G.x[to][q] = (float)x;
             if (G.E[to]) G.E[to][q] = (float)E;
             ++w.fixed;
@@ -599,7 +642,7 @@ template <typename T> __device__ __forceinline__ T wave_min(T v)
 
 // Per-workgroup partials of the timestep limit and diagnostics of state n; the
 // workgroups of grid g stride over its cells.
-template <typename R>
+template <typename R, int MS>
 __global__ void __launch_bounds__(DT_BLOCK)
 k_dtdiag(const GridDev<R>* __restrict__ grids, BatchDev bd)
 {
@@ -617,15 +660,21 @@ k_dtdiag(const GridDev<R>* __restrict__ grids, BatchDev bd)
         const CellGeom<R> cg = cell_geom(p, i, j, k);
         const R n = nH[q], xq = x[q], tq = tau[q];
         const R Eq = E ? E[q] : R(0);
-        const Env<R> e = make_env(p, n, cg, tq);
         Rhs<R> r;
-        rhs_full(p, e, xq, Eq, r);
+        bool ok = true;
+        if constexpr (MS == 1) {
+            const Env<R> e = make_env(p, n, cg, tq);
+            rhs_full(p, e, xq, Eq, r);
+        } else {
+            const EnvM<R, MS> e = multi_env<MS>(p, n, tau, q, i, j, k, tq, ok);
+            rhs_full(p, e, xq, Eq, r);
+        }
         v[0] = fmin(v[0], cell_dt(p, r, n, xq, Eq));
         v[1] += (double)n * (1.0 - (double)xq);
         v[2] += 1.0 - (double)xq;
         v[3] += (double)r.A;
         v[4] += (double)r.rec;
-        const bool bad = !isfinite((double)xq) || !isfinite((double)tq) ||
+        const bool bad = !isfinite((double)xq) || !isfinite((double)tq) || !ok ||
                          (E && !isfinite((double)Eq));
         v[5] += bad ? 1.0 : 0.0;
     }
@@ -770,8 +819,12 @@ hipError_t launch_chem(const GridDev<R>* grids, const BatchDev& b, int nblocks, 
                        bool mixed, hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_chem<R>), dim3(nblocks), dim3(CHEM_BLOCK), 0, s, grids, b, from, to,
-                       tau_buf, (int)dev_dt, hscale, ctr, (int)mixed);
+    if (b.msrc > 1)
+        hipLaunchKernelGGL((k_chem<R, MAX_SRC>), dim3(nblocks), dim3(CHEM_BLOCK), 0, s, grids, b,
+                           from, to, tau_buf, (int)dev_dt, hscale, ctr, (int)mixed);
+    else
+        hipLaunchKernelGGL((k_chem<R, 1>), dim3(nblocks), dim3(CHEM_BLOCK), 0, s, grids, b, from,
+                           to, tau_buf, (int)dev_dt, hscale, ctr, (int)mixed);
     return hipGetLastError();
 }
 
@@ -780,8 +833,12 @@ hipError_t launch_chem_fix(const GridDev<float>* grids, const BatchDev& b, int n
                            unsigned long long* ctr, hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_chem_fix, dim3(nblk), dim3(256), 0, s, grids, b, from, to, tau_buf,
-                       (int)dev_dt, hscale, ctr);
+    if (b.msrc > 1)
+        hipLaunchKernelGGL(k_chem_fix<MAX_SRC>, dim3(nblk), dim3(256), 0, s, grids, b, from, to,
+                           tau_buf, (int)dev_dt, hscale, ctr);
+    else
+        hipLaunchKernelGGL(k_chem_fix<1>, dim3(nblk), dim3(256), 0, s, grids, b, from, to,
+                           tau_buf, (int)dev_dt, hscale, ctr);
     return hipGetLastError();
 }
 
@@ -790,7 +847,10 @@ hipError_t launch_dtdiag(const GridDev<R>* grids, const BatchDev& b, int nblocks
                          hipStream_t s)
 {
     if (nblocks <= 0 || b.ngrids <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_dtdiag<R>), dim3(nblocks), dim3(DT_BLOCK), 0, s, grids, b);
+    if (b.msrc > 1)
+        hipLaunchKernelGGL((k_dtdiag<R, MAX_SRC>), dim3(nblocks), dim3(DT_BLOCK), 0, s, grids, b);
+    else
+        hipLaunchKernelGGL((k_dtdiag<R, 1>), dim3(nblocks), dim3(DT_BLOCK), 0, s, grids, b);
     hipLaunchKernelGGL((k_finalize<R>), dim3(b.ngrids), dim3(256), 0, s, grids, b, t_end_arg);
     return hipGetLastError();
 }

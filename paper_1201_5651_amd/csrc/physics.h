@@ -28,6 +28,7 @@ constexpr double W_FLOOR = 0.6;               // Mellema weights: 1 / max(0.6, t
 // optically thin and the optically thick limit.
 constexpr double CORNER_CHORD = 1.2213748039031678;
 constexpr int NTAB = 64;
+constexpr int MAX_SRC = 4;        // point sources of one grid
 constexpr int NEWTON_MAXIT = 60;
 constexpr int NEWTON_2D_MAXIT = 20;
 constexpr int FALLBACK_MAXIT = 200;
@@ -83,6 +84,11 @@ template <typename R> struct Params {
     R K[4];
     int spectrum, thermal, recomb, collisional, cooling, weights, src_rule, n_sub;
     int plane;   // 1: plane-parallel source at x = -inf
+    // point sources of the grid: source 0 at (sx, sy, sz) with QV, source
+    // q >= 1 at msrc[q - 1] with mQV[q - 1]
+    int nsrc;
+    int msrc[MAX_SRC - 1][3];
+    R mQV[MAX_SRC - 1];
     const DevTable<R>* tab;
 };
 
@@ -152,7 +158,8 @@ template <typename R> struct CellGeom {
 };
 
 template <typename R>
-PI_HD __forceinline__ CellGeom<R> cell_geom(const Params<R>& p, int i, int j, int k)
+PI_HD __forceinline__ CellGeom<R> cell_geom_at(const Params<R>& p, int sx, int sy, int sz, int i,
+                                               int j, int k)
 {
     if (p.plane) {
         // slab cell of its row: the flux (in QV) over one cell length
@@ -162,9 +169,9 @@ PI_HD __forceinline__ CellGeom<R> cell_geom(const Params<R>& p, int i, int j, in
         return c;
     }
     // exact half-integers: (2i + 1 - 2s) / 2
-    const R ax = r_abs(R(2 * (i - p.sx) + 1)) * R(0.5);
-    const R ay = r_abs(R(2 * (j - p.sy) + 1)) * R(0.5);
-    const R az = r_abs(R(2 * (k - p.sz) + 1)) * R(0.5);
+    const R ax = r_abs(R(2 * (i - sx) + 1)) * R(0.5);
+    const R ay = r_abs(R(2 * (j - sy) + 1)) * R(0.5);
+    const R az = r_abs(R(2 * (k - sz) + 1)) * R(0.5);
     const R rr = ax * ax + ay * ay + az * az;
     const R da = (az >= ax && az >= ay) ? az : (ay >= ax ? ay : ax);
     CellGeom<R> c;
@@ -177,6 +184,13 @@ PI_HD __forceinline__ CellGeom<R> cell_geom(const Params<R>& p, int i, int j, in
         c.ell = ds;
     }
     return c;
+}
+
+// Geometry of cell (i,j,k) seen from source 0.
+template <typename R>
+PI_HD __forceinline__ CellGeom<R> cell_geom(const Params<R>& p, int i, int j, int k)
+{
+    return cell_geom_at(p, p.sx, p.sy, p.sz, i, j, k);
 }
 
 // -------------------------------------------------------------------- table
@@ -242,14 +256,16 @@ template <typename R> struct Env {
     R lin;      // table: -d ln P / d tau at tau (fraction absorbed per unit depth)
 };
 
+// Environment of a cell lit by a source of QV photons per second per cell
+// volume.
 template <typename R>
-PI_HD __forceinline__ Env<R> make_env(const Params<R>& p, R n, CellGeom<R> c, R tau)
+PI_HD __forceinline__ Env<R> make_env_q(const Params<R>& p, R QV, R n, CellGeom<R> c, R tau)
 {
     Env<R> e;
     e.n = n;
     e.inv_n = R(1) / n;
     e.c3 = R(1) / (R(3.0 * KB) * n);
-    e.Qg = p.QV * c.g;
+    e.Qg = QV * c.g;
     e.k = n * p.sdx * c.ell;
     e.tau = tau;
     e.att = R(0);
@@ -262,6 +278,12 @@ PI_HD __forceinline__ Env<R> make_env(const Params<R>& p, R n, CellGeom<R> c, R 
         e.lin = e.Pin > R(0) ? -dP / e.Pin : R(0);
     }
     return e;
+}
+
+template <typename R>
+PI_HD __forceinline__ Env<R> make_env(const Params<R>& p, R n, CellGeom<R> c, R tau)
+{
+    return make_env_q(p, p.QV, n, c, tau);
 }
 
 // Photoionisations A and photoheating G per unit volume and time, and their
@@ -301,6 +323,33 @@ PI_HD __forceinline__ void photo(const Params<R>& p, const Env<R>& e, R x, R& A,
         dA = -e.Qg * dP * e.k;
         G = e.Qg * (e.Hin - H);
         dG = -e.Qg * dH * e.k;
+    }
+}
+
+// Cell lit by up to MS point sources (a grid with several sources): one Env
+// per source (its own geometry and entering column, common n_H); the rates of
+// the ns sources add.  The solvers take either environment type.
+template <typename R, int MS> struct EnvM {
+    R n, inv_n, c3;
+    int ns;
+    Env<R> s[MS];
+};
+
+template <typename R, int MS>
+PI_HD __forceinline__ void photo(const Params<R>& p, const EnvM<R, MS>& e, R x, R& A, R& dA,
+                                 R& G, R& dG)
+{
+    photo(p, e.s[0], x, A, dA, G, dG);
+#pragma unroll
+    for (int q = 1; q < MS; ++q) {
+        if (q < e.ns) {
+            R a, da, g, dg;
+            photo(p, e.s[q], x, a, da, g, dg);
+            A += a;
+            dA += da;
+            G += g;
+            dG += dg;
+        }
     }
 }
 
@@ -374,8 +423,8 @@ template <typename R> struct Rhs {
     R A, rec, T;
 };
 
-template <typename R>
-PI_HD __forceinline__ void rhs_xT(const Params<R>& p, const Env<R>& e, const Coef<R>& c, R x,
+template <typename R, typename EV>
+PI_HD __forceinline__ void rhs_xT(const Params<R>& p, const EV& e, const Coef<R>& c, R x,
                                        R& fx, R& dfx)
 {
     R A, dA, G, dG;
@@ -388,8 +437,8 @@ PI_HD __forceinline__ void rhs_xT(const Params<R>& p, const Env<R>& e, const Coe
 // Temperature floor: the coefficients see max(T, T_FLOOR) and the cooling is
 // tapered by max(0, 1 - T_FLOOR/T), so the floor is approached smoothly and
 // never crossed by cooling.
-template <typename R>
-PI_HD __forceinline__ void rhs_full(const Params<R>& p, const Env<R>& e, R x, R E, Rhs<R>& r)
+template <typename R, typename EV>
+PI_HD __forceinline__ void rhs_full(const Params<R>& p, const EV& e, R x, R E, Rhs<R>& r)
 {
     const R n = e.n;
     R T, Tc, dTdx = R(0), dTdE = R(0), above = R(1);
@@ -441,8 +490,8 @@ template <typename R> PI_HD __forceinline__ R e_floor(R n, R x)
 // Scalar stage solve x = xb + hg fx(x) at fixed temperature (coefficients c):
 // Newton safeguarded by the bracket [0, 1] (the residual increases with x); a
 // root outside [0, 1] is returned clamped.
-template <typename R>
-PI_HD R solve_x(const Params<R>& p, const Env<R>& e, const Coef<R>& c, R xb, R hg, R x, int& nit)
+template <typename R, typename EV>
+PI_HD R solve_x(const Params<R>& p, const EV& e, const Coef<R>& c, R xb, R hg, R x, int& nit)
 {
     x = r_min(r_max(x, R(0)), R(1));
     R lo = R(0), hi = R(1);
@@ -475,8 +524,8 @@ PI_HD R solve_x(const Params<R>& p, const Env<R>& e, const Coef<R>& c, R xb, R h
 }
 
 // Energy residual of the stage equation with T held, after solving x at that T.
-template <typename R>
-PI_HD R t_residual(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg, R T, R& xs)
+template <typename R, typename EV>
+PI_HD R t_residual(const Params<R>& p, const EV& e, R xb, R Eb, R hg, R T, R& xs)
 {
     const Coef<R> c = coefs(p, T);
     int nit = 0;
@@ -492,8 +541,8 @@ PI_HD R t_residual(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg, R T, R
 // solve in (x, T) -- x at fixed T by the scalar solve, and the energy residual
 // bracketed in ln T from the floor upwards and solved by the Illinois variant
 // of regula falsi.
-template <typename R>
-PI_HD void fallback_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg,
+template <typename R, typename EV>
+PI_HD void fallback_solve(const Params<R>& p, const EV& e, R xb, R Eb, R hg,
                                             R& x, R& E)
 {
     R xs;
@@ -554,8 +603,8 @@ struct Work {
     int fixed;   // cells re-solved in double (mixed precision)
 };
 
-template <typename R>
-PI_HD void stage_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg, R& x, R& E,
+template <typename R, typename EV>
+PI_HD void stage_solve(const Params<R>& p, const EV& e, R xb, R Eb, R hg, R& x, R& E,
                        Work& w)
 {
     if (p.thermal == 0) {
@@ -615,8 +664,8 @@ PI_HD void stage_solve(const Params<R>& p, const Env<R>& e, R xb, R Eb, R hg, R&
 // Initial substep count of one micro-integration: at least n_sub, and enough
 // that at the initial rate no substep moves x by more than SUB_DX; at most
 // SUB_MAX.
-template <typename R>
-PI_HD __forceinline__ int substeps(const Params<R>& p, const Env<R>& e, R x0, R E0, R h, Work& w,
+template <typename R, typename EV>
+PI_HD __forceinline__ int substeps(const Params<R>& p, const EV& e, R x0, R E0, R h, Work& w,
                                   R& fx0, R& fE0)
 {
     Rhs<R> r;
@@ -654,8 +703,8 @@ PI_HD __forceinline__ void stage_guess(R xb, R Eb, R hg, R fx, R fE, R& xg, R& E
 // solved stage equation Y = base + hg f(Y) gives f(Y) = (Y - base)/hg without
 // another evaluation.  Stage 1 starts from y + hg f(y), stage 2 from its base
 // + hg f(Y1).
-template <typename R>
-PI_HD __forceinline__ void sdirk_step(const Params<R>& p, const Env<R>& e, R hs, R& x, R& E,
+template <typename R, typename EV>
+PI_HD __forceinline__ void sdirk_step(const Params<R>& p, const EV& e, R hs, R& x, R& E,
                                       R& fx, R& fE, Work& w, R& x_stage1)
 {
     const R gam = R(0.29289321881345247560);          // 1 - 1/sqrt(2)
@@ -704,8 +753,8 @@ template <typename R> struct LseAcc {
 // integrated over h with the same SDIRK stages (weights 1 - gamma and gamma at
 // the two stage values of x of every accepted substep), and tau_avg returns
 // the time-averaged optical depth -ln <exp(-k x)>.
-template <typename R, bool AVG>
-PI_HD void micro_t(const Params<R>& p, const Env<R>& e, R h, R& x, R& E, Work& w, R* tau_avg)
+template <typename R, bool AVG, typename EV>
+PI_HD void micro_t(const Params<R>& p, const EV& e, R h, R& x, R& E, Work& w, R* tau_avg)
 {
     if constexpr (AVG) *tau_avg = e.k * x;
     if (!(h > R(0))) return;
@@ -749,8 +798,8 @@ PI_HD void micro_t(const Params<R>& p, const Env<R>& e, R h, R& x, R& E, Work& w
     if constexpr (AVG) *tau_avg = acc.m - r_log(acc.S / h);
 }
 
-template <typename R>
-PI_HD __forceinline__ void micro(const Params<R>& p, const Env<R>& e, R h, R& x, R& E, Work& w)
+template <typename R, typename EV>
+PI_HD __forceinline__ void micro(const Params<R>& p, const EV& e, R h, R& x, R& E, Work& w)
 {
     micro_t<R, false>(p, e, h, x, E, w, nullptr);
 }

@@ -57,6 +57,17 @@ pi_status validate_desc(const pi_grid_desc* d)
         if (!(d->K[i] >= 0)) return fail(PI_EINVAL, "K factors must be >= 0 (inf disables)");
     if (d->precision != PI_FP64 && d->precision != PI_FP32 && d->precision != PI_MIXED)
         return fail(PI_EINVAL, "precision");
+    if (d->nsrc < 0 || d->nsrc > PI_MAX_SRC) return fail(PI_EINVAL, "nsrc must be in 0..PI_MAX_SRC");
+    if (d->nsrc > 1) {
+        if (d->source != PI_SRC_POINT) return fail(PI_EINVAL, "several sources must be point sources");
+        for (int s = 0; s < d->nsrc - 1; ++s) {
+            for (int a = 0; a < 3; ++a)
+                if (d->src_more[s][a] < 0 || d->src_more[s][a] > d->n[a])
+                    return fail(PI_EINVAL, "source vertex outside [0, n]");
+            if (!(d->Q_more[s] >= 0) || !std::isfinite(d->Q_more[s]))
+                return fail(PI_EINVAL, "Q of every source must be >= 0");
+        }
+    }
     return PI_OK;
 }
 

@@ -365,6 +365,7 @@ pi_status pi_submit(pi_server* s, const pi_request* req, uint64_t* ticket)
     pi_status v = validate_desc(&req->desc);
     if (v != PI_OK) return v;
     if (req->desc.precision != s->desc.precision) return fail(PI_EINVAL, "precision differs from the server's");
+    if (req->desc.nsrc > 1) return fail(PI_EINVAL, "served requests have one source");
     if (!req->nH) return fail(PI_EINVAL, "nH is required");
     if (!std::isfinite(req->t_end) || !(req->t_end >= 0)) return fail(PI_EINVAL, "t_end must be finite and >= 0");
     if (req->desc.thermal == PI_T_EVOLVE && !(req->T0 > 0)) return fail(PI_EINVAL, "T0 must be > 0");

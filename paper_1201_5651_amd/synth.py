@@ -72,6 +72,7 @@ class GridSpec:
     t_rec: float = 0.0            # reference recombination time [s]
     precision: str = "fp64"       # "fp64" | "fp32" | "mixed"
     source: str = "point"         # "point" (at vertex src) | "plane" (from x = -inf)
+    more_sources: tuple = ()      # further point sources: ((i, j, k), Q) each
 
     @property
     def ncells(self) -> int:

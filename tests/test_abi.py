@@ -36,9 +36,18 @@ def test_library_loads_and_exports_every_declared_symbol():
     # the descriptor's field order and types as the header declares them
     body = re.search(r"typedef struct \{(.*?)\} pi_grid_desc;", header, re.S).group(1)
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-    decl = re.findall(r"(int32_t|double)\s+(\w+)(?:\[(\d)\])?;", body)
+    decl = re.findall(r"(int32_t|double)\s+(\w+)((?:\[[^\]]+\])*);", body)
     ctype = {"int32_t": C.c_int32, "double": C.c_double}
-    want = [(n, ctype[t] * int(k) if k else ctype[t]) for t, n, k in decl]
+    max_src = int(re.search(r"#define PI_MAX_SRC (\d+)", header).group(1))
+    assert binding.PI_MAX_SRC == max_src
+
+    def arr(t, dims):
+        ty = ctype[t]
+        for k in reversed(re.findall(r"\[([^\]]+)\]", dims)):
+            ty = ty * int(eval(k.replace("PI_MAX_SRC", str(max_src))))
+        return ty
+
+    want = [(n, arr(t, dims)) for t, n, dims in decl]
     got = [(n, t) for n, t in binding.GridDesc._fields_]
     assert [n for n, _ in want] == [n for n, _ in got]
     for (n, a), (_, b) in zip(want, got):
@@ -69,6 +78,11 @@ def test_descriptor_validation_rejects_bad_input():
     d = binding.desc_from_spec(spec)
     d.source = 2
     cases.append(d)
+    # several sources: count, vertices, Q, and point sources only
+    for nsrc, v, q, src in ((5, 0, 1.0, 0), (2, 33, 1.0, 0), (2, 0, -1.0, 0), (2, 0, 1.0, 1)):
+        d = binding.desc_from_spec(spec)
+        d.nsrc, d.src_more[0][:], d.Q_more[0], d.source = nsrc, (v, 0, 0), q, src
+        cases.append(d)
     for d in cases:
         h = C.c_void_p()
         st = binding.lib().pi_grid_create(C.byref(d), C.byref(f), C.byref(h))

@@ -1,0 +1,136 @@
+"""Several point sources on one grid: every source's columns, A3 steps and
+diagnostics on the GPU against the oracle (each source traced on its own, the
+rates of the sources added in every cell), and the limits of the form (one
+grid at a time, algorithm 3 and the single calls only)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1201_5651_amd import binding, synth
+from gpu_util import pair, rel, rel_x, to_np
+
+pytestmark = pytest.mark.gpu
+
+# a grid spanning several tiles of every edge with ragged tails, sources in
+# the interior, on an edge and at a corner of the box
+SHAPE = (20, 18, 17)
+SOURCES = [((15, 3, 12), 0.5), ((10, 18, 0), 0.25), ((0, 0, 17), 0.8)]
+
+
+def _spec(nsrc, precision="fp64", shape=SHAPE):
+    base = synth.cfg2(n=shape[0]).with_(n=shape, src=(5, 9, 4), precision=precision)
+    more = tuple((v, f * base.Q) for v, f in SOURCES[: nsrc - 1])
+    return base.with_(more_sources=more)
+
+
+def _nH(spec, seed=3):
+    return synth.lognormal_density(spec.shape, 10.0, 1.0, seed)
+
+
+@pytest.mark.parametrize("nsrc", [2, 4])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_columns_of_every_source(oracle_lib, nsrc, precision):
+    """Each source's columns are its own raytrace of the same state (FP64
+    within 1e-12 of the oracle, float 1e-5), and every tile edge gives the
+    same columns bit for bit."""
+    spec = _spec(nsrc, precision)
+    rng = np.random.default_rng(11)
+    x = rng.uniform(0.0, 1.0, spec.shape)
+    g, pb, _ = pair(spec, _nH(spec), x0=x, precision=precision)
+    assert tuple(g.tau.shape) == (nsrc,) + spec.shape
+    want = pb.raytrace(np.ascontiguousarray(to_np(g.nH)), np.ascontiguousarray(to_np(g.x)))
+    got = to_np(g.tau)
+    assert np.array_equal(got == 0, want == 0)
+    m = want > 0
+    assert np.max(rel(got[m], want[m])) < (1e-12 if precision == "fp64" else 1e-5)
+    cols = {}
+    for edge in (4, 8, 16):
+        g.raytrace_tile = edge
+        g.tau.zero_()
+        g.raytrace()
+        cols[edge] = to_np(g.tau)
+    assert np.array_equal(cols[4], cols[8]) and np.array_equal(cols[4], cols[16])
+    g.close()
+
+
+@pytest.mark.parametrize("nsrc", [2, 3, 4])
+def test_a3_steps_parity_fp64(oracle_lib, nsrc):
+    """A3 steps of a clumpy medium lit by several sources (table spectrum,
+    evolving temperature): state, columns of every source, clock and FP64
+    diagnostics within 1e-9 of the oracle."""
+    spec = _spec(nsrc)
+    g, pb, st = pair(spec, _nH(spec), T0=50.0)
+    for _ in range(8):
+        g.step_o2(spec.t_end)
+        pb.step(st, spec.t_end)
+    assert g.state()[0] == pytest.approx(st["t"], rel=1e-12)
+    assert np.max(rel_x(to_np(g.x), st["x"])) < 1e-9
+    Tg = pb.temperature(st["nH"], to_np(g.x), to_np(g.E))
+    Tw = pb.temperature(st["nH"], st["x"], st["E"])
+    assert np.max(rel(Tg, Tw)) < 1e-9
+    m = st["tau"] > 0
+    assert np.max(rel(to_np(g.tau)[m], st["tau"][m])) < 1e-9
+    dg, dw = g.diagnostics(), pb.diagnostics(st)
+    for k in ("n_ion", "v_ion", "r_ion", "photo_rate", "recomb_rate"):
+        assert dg[k] == pytest.approx(dw[k], rel=1e-9), k
+    # octants of every source: 8 around each interior vertex, 2 around the
+    # vertex on an edge of the box, 1 around the corner vertex
+    assert dg["octants"] == [8, 16, 18, 19][nsrc - 1]
+    assert (1 - st["x"]).sum() > 10.0
+    g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_a3_steps_parity_float(oracle_lib, precision):
+    spec = _spec(4, precision)
+    g, pb, st = pair(spec, _nH(spec), T0=50.0, precision=precision)
+    for _ in range(8):
+        g.step_o2(spec.t_end)
+        pb.step(st, spec.t_end)
+    errx = rel_x(to_np(g.x), st["x"])
+    Tg = pb.temperature(st["nH"], to_np(g.x), to_np(g.E))
+    Tw = pb.temperature(st["nH"], st["x"], st["E"])
+    print("%s x err max %.3g p999 %.3g; T err max %.3g" % (precision, errx.max(),
+                                                         np.quantile(errx, .999), rel(Tg, Tw).max()))
+    assert np.quantile(errx, 0.999) < 1e-4
+    assert np.quantile(rel(Tg, Tw), 0.999) < 1e-4
+    g.close()
+
+
+def test_mirrored_sources_on_gpu_give_a_mirrored_state():
+    """Two equal sources at mirror-image vertices of a mirror-symmetric
+    medium: the GPU state stays symmetric to rounding (a beam weighted from
+    the wrong vertex would break it)."""
+    n = 16
+    base = synth.cfg2(n=n)
+    spec = base.with_(src=(3, 5, 6), Q=0.5 * base.Q, more_sources=(((n - 3, 5, 6), 0.5 * base.Q),))
+    nH = _nH(spec, 5)
+    nH = 0.5 * (nH + nH[:, :, ::-1])
+    g = binding.Grid(spec)
+    g.load(nH, 1.0, T0=50.0)
+    for _ in range(6):
+        g.step_o2(spec.t_end)
+    x = to_np(g.x)
+    assert np.max(rel_x(x, x[:, :, ::-1])) < 1e-12
+    assert (1 - x).sum() > 1.0
+    g.close()
+
+
+def test_several_sources_limits():
+    """A grid with several sources runs on its own: batches, served requests
+    and algorithm 1 reject it with PI_EINVAL; a bad vertex is rejected at
+    creation."""
+    spec = _spec(2, shape=(8, 8, 8)).with_(src=(4, 4, 4), more_sources=(((1, 2, 3), 1e47),))
+    g = binding.Grid(spec)
+    g.load(_nH(spec), 1.0, T0=50.0)
+    with pytest.raises(binding.PiError) as e:
+        g.step_a1(spec.t_end)
+    assert e.value.status == binding.PI_EINVAL
+    g.step_o2(spec.t_end)   # the grid is still usable
+    g.close()
+    with pytest.raises(binding.PiError) as e:
+        binding.Batch([spec, spec.with_(more_sources=())])
+    assert e.value.status == binding.PI_EINVAL
+    with pytest.raises(binding.PiError) as e:
+        binding.Grid(spec.with_(more_sources=(((9, 0, 0), 1e47),)))
+    assert e.value.status == binding.PI_EINVAL
