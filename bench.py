@@ -17,7 +17,8 @@ Other workloads (--workload): batch (64 uneven grids advanced together, and
 the FP64 single-grid path on a sample of them), serve (Poisson requests to the
 library's server; p50/p99 latency), hardening (the 37 500 K blackbody runs of
 Sect. 4 as one batch, with A3-dt02 against smaller steps), a1 (algorithm 1
-steps on the same 256^3 medium).
+steps on the same 256^3 medium), sources (the same medium lit by four point
+sources).
 """
 from __future__ import annotations
 
@@ -289,6 +290,44 @@ def bench_a1(args, torch, binding, synth) -> dict:
     }
 
 
+def bench_sources(args, torch, binding, synth) -> dict:
+    """The same 256^3 clumpy medium lit by four point sources (the central
+    one and three off-centre ones of half its rate), A3 steps from the state
+    the pre-evolution reaches at 0.1 t_rec."""
+    n = args.n
+    base = synth.cfg3(n=n).with_(precision=args.precision)
+    more = tuple(((v[0] * n // 256, v[1] * n // 256, v[2] * n // 256), 0.5 * base.Q)
+                 for v in ((64, 64, 64), (192, 80, 160), (100, 200, 48)))
+    spec = base.with_(more_sources=more)
+    g = binding.Grid(spec, precision=args.precision)
+    g.load(synth.density(spec), 1.0, T0=spec.T0)
+    g.run(args.pre_trec * spec.t_rec, check_every=16)
+    stream = torch.cuda.current_stream()
+    t_end = 1e30
+    for _ in range(args.warmup):
+        g.step_o2(t_end)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        g.step_o2(t_end)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    d = g.diagnostics()
+    g.close()
+    return {
+        "metric": "cell-updates/s of A3 steps at 256^3 with four point sources",
+        "value": spec.ncells * args.steps / (ms * 1e-3), "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype_name(args.precision), "data": "synthetic",
+        "config": {"workload": f"cfg3 clumpy medium {n}^3 lit by 4 point sources (central "
+                               f"5e48 /s and three of 2.5e48 /s), A3-dt02 from {args.pre_trec} t_rec",
+                   "precision": args.precision, "octants": d["octants"]},
+    }
+
+
 def bench_serve(args, torch, binding, synth) -> dict:
     """Served form: Poisson arrivals of single-grid requests submitted to the
     library's server at their arrival times; latency from submission to
@@ -384,7 +423,7 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="cfg3",
-                    choices=["cfg3", "batch", "serve", "hardening", "a1"],
+                    choices=["cfg3", "batch", "serve", "hardening", "a1", "sources"],
                     help="cfg3: the 256^3 single grid (default); batch / serve: the batched and "
                          "served forms (their own JSON line)")
     ap.add_argument("--hardening-trec", type=float, default=1.0,
@@ -420,7 +459,7 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.workload != "cfg3":
         fn = {"batch": bench_batch, "serve": bench_serve, "hardening": bench_hardening,
-              "a1": bench_a1}[args.workload]
+              "a1": bench_a1, "sources": bench_sources}[args.workload]
         print(json.dumps(fn(args, torch, binding, synth)))
         return 0
     spec = synth.cfg3(n=args.n)
