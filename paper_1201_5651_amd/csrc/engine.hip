@@ -111,13 +111,19 @@ template <typename R> Params<R> make_params(const pi_grid_desc& d)
     p.src_rule = d.source_cell_rule;
     p.n_sub = d.n_sub;
     p.tab = nullptr;
-    p.nsrc = nsources(d);
-    for (int s = 1; s < MAX_SRC; ++s) {
-        const bool on = s < p.nsrc;
-        for (int a = 0; a < 3; ++a) p.msrc[s - 1][a] = on ? d.src_more[s - 1][a] : 0;
-        p.mQV[s - 1] = R(on ? d.Q_more[s - 1] / (d.dx * d.dx * d.dx) : 0.0);
-    }
     return p;
+}
+
+template <typename R> Sources<R> make_sources(const pi_grid_desc& d)
+{
+    Sources<R> m;
+    m.n = nsources(d);
+    for (int s = 1; s < MAX_SRC; ++s) {
+        const bool on = s < m.n;
+        for (int a = 0; a < 3; ++a) m.v[s - 1][a] = on ? d.src_more[s - 1][a] : 0;
+        m.QV[s - 1] = R(on ? d.Q_more[s - 1] / (d.dx * d.dx * d.dx) : 0.0);
+    }
+    return m;
 }
 
 // Device copies of the rate table of (spectrum, T_bb), shared by the grids of
@@ -180,6 +186,8 @@ template <typename R> pi_status upload_grids(Engine& e)
         GridDev<R>& D = h[g];
         D.p = make_params<R>(G.d);
         D.pd = make_params<double>(G.d);
+        D.src = make_sources<R>(G.d);
+        D.srcd = make_sources<double>(G.d);
         D.pd.tab = static_cast<const DevTable<double>*>(td);
         D.p.tab = static_cast<const DevTable<R>*>(sizeof(R) == sizeof(double) ? td : tf);
         D.nH = fld<R>(G.f.nH);

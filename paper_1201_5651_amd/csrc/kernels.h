@@ -81,6 +81,8 @@ constexpr int WORK_COUNTERS = 5, WORK_SLOTS = 64;
 template <typename R> struct GridDev {
     Params<R> p;          // parameters in the grid's arithmetic
     Params<double> pd;    // double parameters (mixed-precision re-solve)
+    Sources<R> src;       // the sources beyond source 0 (read only when several)
+    Sources<double> srcd;
     const R* nH;
     const R* nHr[2];      // density a raytrace of state 0 / 1 uses (1: time-centred, or nH)
     R* x[2];

@@ -306,23 +306,24 @@ template <typename C> struct EnvSel<C, 1> { using type = Env<C>; };
 // has its own geometry and its own columns, tau[s * ncell + q].  ok turns false
 // when one of the columns is not finite.
 template <int MS, typename C, typename S>
-__device__ __forceinline__ EnvM<C, MS> multi_env(const Params<C>& p, C n, const S* __restrict__ tau,
-                                                 int q, int i, int j, int k, C tq, bool& ok)
+__device__ __forceinline__ EnvM<C, MS> multi_env(const Params<C>& p, const Sources<C>& src, C n,
+                                                 const S* __restrict__ tau, int q, int i, int j,
+                                                 int k, C tq, bool& ok)
 {
     EnvM<C, MS> e{};
     e.s[0] = make_env(p, n, cell_geom(p, i, j, k), tq);
     e.n = e.s[0].n;
     e.inv_n = e.s[0].inv_n;
     e.c3 = e.s[0].c3;
-    e.ns = p.nsrc;
+    e.ns = src.n;
 #pragma unroll
     for (int s = 1; s < MS; ++s) {
-        if (s < p.nsrc) {
+        if (s < src.n) {
             const C ts = C(tau[(int64_t)s * p.ncell + q]);
             ok = ok && isfinite(ts);
             const CellGeom<C> cg =
-                cell_geom_at(p, p.msrc[s - 1][0], p.msrc[s - 1][1], p.msrc[s - 1][2], i, j, k);
-            e.s[s] = make_env_q(p, p.mQV[s - 1], n, cg, ts);
+                cell_geom_at(p, src.v[s - 1][0], src.v[s - 1][1], src.v[s - 1][2], i, j, k);
+            e.s[s] = make_env_q(p, src.QV[s - 1], n, cg, ts);
         }
     }
     return e;
@@ -332,9 +333,9 @@ __device__ __forceinline__ EnvM<C, MS> multi_env(const Params<C>& p, C n, const 
 // input stays non-finite (the bound projections of the solver would otherwise
 // turn it into a valid-looking state), so the grid's diagnostics report it.
 template <typename C, typename S, int MS>
-__device__ __forceinline__ void chem_cell(const Params<C>& p, int q, const S* __restrict__ nH,
-                                          const S* x0, const S* E0, const S* __restrict__ tau,
-                                          double hd, C& x, C& E, Work& w)
+__device__ __forceinline__ void chem_cell(const Params<C>& p, const Sources<C>& src, int q,
+                                          const S* __restrict__ nH, const S* x0, const S* E0,
+                                          const S* __restrict__ tau, double hd, C& x, C& E, Work& w)
 {
     x = C(x0[q]);
     E = E0 ? C(E0[q]) : C(0);
@@ -350,7 +351,7 @@ __device__ __forceinline__ void chem_cell(const Params<C>& p, int q, const S* __
         micro(p, e, C(hd), x, E, w);
     } else {
         bool ok = true;
-        const EnvM<C, MS> e = multi_env<MS>(p, n, tau, q, i, j, k, tq, ok);
+        const EnvM<C, MS> e = multi_env<MS>(p, src, n, tau, q, i, j, k, tq, ok);
         if (!ok) {
             x = E = C(__builtin_nan(""));
             return;
@@ -387,7 +388,8 @@ k_chem(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int 
     if (inside) {
         const double hd = dev_dt ? hscale * G.st->dt : hscale;
         R x, E;
-        chem_cell<R, R, MS>(pl, q, G.nH, G.x[from], G.E[from], G.tau[tau_buf], hd, x, E, w);
+        chem_cell<R, R, MS>(pl, G.src, q, G.nH, G.x[from], G.E[from], G.tau[tau_buf], hd, x, E,
+                            w);
         flag = mixed && w.close > 0;
         if (!flag) {
             G.x[to][q] = x;
@@ -429,8 +431,8 @@ k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int 
             const int q = (int)(e & 0xffffffffll);
             const double hd = dev_dt ? hscale * G.st->dt : hscale;
             double x, E;
-            chem_cell<double, float, MS>(G.pd, q, G.nH, G.x[from], G.E[from], G.tau[tau_buf], hd,
-                                         x, E, w);
+            chem_cell<double, float, MS>(G.pd, G.srcd, q, G.nH, G.x[from], G.E[from],
+                                         G.tau[tau_buf], hd, x, E, w);
             G.x[to][q] = (float)x;
             if (G.E[to]) G.E[to][q] = (float)E;
             ++w.fixed;
@@ -666,7 +668,7 @@ k_dtdiag(const GridDev<R>* __restrict__ grids, BatchDev bd)
             const Env<R> e = make_env(p, n, cg, tq);
             rhs_full(p, e, xq, Eq, r);
         } else {
-            const EnvM<R, MS> e = multi_env<MS>(p, n, tau, q, i, j, k, tq, ok);
+            const EnvM<R, MS> e = multi_env<MS>(p, G.src, n, tau, q, i, j, k, tq, ok);
             rhs_full(p, e, xq, Eq, r);
         }
         v[0] = fmin(v[0], cell_dt(p, r, n, xq, Eq));

@@ -84,11 +84,6 @@ template <typename R> struct Params {
     R K[4];
     int spectrum, thermal, recomb, collisional, cooling, weights, src_rule, n_sub;
     int plane;   // 1: plane-parallel source at x = -inf
-    // point sources of the grid: source 0 at (sx, sy, sz) with QV, source
-    // q >= 1 at msrc[q - 1] with mQV[q - 1]
-    int nsrc;
-    int msrc[MAX_SRC - 1][3];
-    R mQV[MAX_SRC - 1];
     const DevTable<R>* tab;
 };
 
@@ -325,6 +320,14 @@ PI_HD __forceinline__ void photo(const Params<R>& p, const Env<R>& e, R x, R& A,
         dG = -e.Qg * dH * e.k;
     }
 }
+
+// Further point sources of a grid with several: source 0 is (sx, sy, sz) with
+// QV of its Params, source q >= 1 sits at v[q - 1] with QV[q - 1].
+template <typename R> struct Sources {
+    int n;                    // point sources of the grid, >= 1
+    int v[MAX_SRC - 1][3];
+    R QV[MAX_SRC - 1];        // Q / dx^3
+};
 
 // Cell lit by up to MS point sources (a grid with several sources): one Env
 // per source (its own geometry and entering column, common n_H); the rates of
