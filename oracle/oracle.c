@@ -26,6 +26,9 @@
  *   - algorithm 2 (Sect. 2.2), the first-order variant, for order tests only
  *   - algorithm 1 (Sect. 2.1): one pass in raytrace order integrating every
  *     cell on its time-averaged entering column                -> orc_a1_pass
+ *   - several point sources on one grid: each traced on its own, their
+ *     photon-conserving rates added in every cell (the paper names several
+ *     sources only for its parallel decomposition; a reading)  -> nsrc > 1
  *   - 1D spherical and plane-parallel modes of Sect. 3 (tests only)
  *   - front locator (eq. 5)
  *
