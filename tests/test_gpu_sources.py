@@ -134,3 +134,30 @@ def test_several_sources_limits():
     with pytest.raises(binding.PiError) as e:
         binding.Grid(spec.with_(more_sources=(((9, 0, 0), 1e47),)))
     assert e.value.status == binding.PI_EINVAL
+
+
+def test_degenerate_sources_fp64(oracle_lib):
+    """Degenerate cases: a further source of Q = 0 leaves the one-source
+    result (the several-source kernels add exact zeros), and two sources of
+    Q/2 at one vertex give the single source of Q to rounding."""
+    base = synth.cfg2(n=12).with_(n=(12, 10, 9), src=(5, 4, 4))
+    nH = _nH(base, 8)
+    runs = {}
+    for key, spec in (("one", base),
+                      ("zero", base.with_(more_sources=(((2, 9, 1), 0.0),))),
+                      ("split", base.with_(Q=0.5 * base.Q, more_sources=((base.src, 0.5 * base.Q),)))):
+        g = binding.Grid(spec)
+        g.load(nH, 1.0, T0=50.0)
+        for _ in range(6):
+            g.step_o2(spec.t_end)
+        runs[key] = (to_np(g.x), to_np(g.E), g.state()[0], g.diagnostics())
+        g.close()
+    x1, E1, t1, d1 = runs["one"]
+    for key in ("zero", "split"):
+        x, E, t, d = runs[key]
+        assert t == pytest.approx(t1, rel=1e-12), key
+        assert np.max(rel_x(x, x1)) < 1e-10, key
+        assert np.max(rel(E, E1)) < 1e-10, key
+        assert d["photo_rate"] == pytest.approx(d1["photo_rate"], rel=1e-10), key
+    assert runs["zero"][3]["octants"] == 8 + 8
+    assert (1 - x1).sum() > 1.0
