@@ -102,8 +102,8 @@ typedef struct {
                               /* (dt02 of Table 1: {inf, inf, inf, 0.25})             */
     int32_t precision;        /* pi_precision                                         */
     int32_t source;           /* PI_SRC_POINT or PI_SRC_PLANE                         */
-    /* Several point sources (PI_SRC_POINT, single grids: pi_grid_create only).
-     * nsrc 0 or 1: the source at src with Q alone.  nsrc = m in 2..PI_MAX_SRC:
+    /* Several point sources (PI_SRC_POINT; grids, batches and served requests;
+     * not algorithm 1).  nsrc 0 or 1: the source at src with Q alone.  nsrc = m in 2..PI_MAX_SRC:
      * source 0 at src with Q, source s = 1..m-1 at vertex src_more[s-1] with
      * Q_more[s-1] photons per second (>= 0); all share the spectrum.  Each
      * source is traced on its own and the photoionisation and heating rates of
@@ -235,7 +235,7 @@ typedef struct pi_batch pi_batch;
 
 /* ngrids descriptors and fields (arrays of ngrids, copied; the fields stay
  * owned by the caller and valid until pi_batch_destroy).  All descriptors
- * share one precision and have one source each (PI_EINVAL for nsrc > 1).
+ * share one precision; grids with one and with several sources may be mixed.
  * Errors as pi_grid_create, prefixed with the grid. */
 pi_status pi_batch_create(int ngrids, const pi_grid_desc* descs, const pi_fields* fields,
                           pi_batch** out);
@@ -253,7 +253,8 @@ pi_status pi_batch_raytrace(pi_batch* batch, int state, int tau_buf, void* strea
  * t_end set by pi_batch_set_time), enqueued as one graph launch on stream. */
 pi_status pi_batch_step_o2(pi_batch* batch, void* stream);
 /* One algorithm-1 step (pi_step_a1) of every grid, each to its own t_end;
- * launched directly (not from a captured graph). */
+ * launched directly (not from a captured graph).  PI_EINVAL if a grid has a
+ * plane-parallel source or several sources. */
 pi_status pi_batch_step_a1(pi_batch* batch, void* stream);
 /* Per grid clock (host arrays of ngrids; NULL skips).  SYNCHRONISES. */
 pi_status pi_batch_state(pi_batch* batch, double* t, int64_t* nsteps, double* last_dt,
@@ -282,7 +283,7 @@ typedef struct {
 } pi_server_desc;
 
 typedef struct {
-    pi_grid_desc  desc;       /* precision must be the server's; one source      */
+    pi_grid_desc  desc;       /* precision must be the server's                  */
     const double* nH;         /* host, n[0]*n[1]*n[2] cells, > 0 (copied)         */
     const double* x0;         /* host initial neutral fraction, or NULL: 1       */
     double        T0;         /* initial temperature [K] (T evolving)            */

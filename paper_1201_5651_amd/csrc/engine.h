@@ -52,9 +52,9 @@ struct Engine {
     int chem_blocks = 0, dt_blocks = 0;
     int plane_rows = 0;   // rows along x of the plane-parallel grids
     // (grid, source) of the raytrace entries past the grids: the further
-    // sources of a grid with several; msrc is MAX_SRC when there are any
+    // sources of the grids with several; kinds as BatchDev::kinds
     std::vector<int2> extra;
-    int msrc = 1;
+    int kinds = 1;
     // raytrace schedules, one per tile edge of SWEEP_TILES
     int4* tiles[NSWEEP] = {};
     size_t tiles_cap[NSWEEP] = {};

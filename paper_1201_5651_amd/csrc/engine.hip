@@ -339,7 +339,7 @@ BatchDev Engine::bd() const
     b.fix_n = fix_n;
     b.fix_list = fix_list;
     b.fix_cap = (unsigned int)fix_cap;
-    b.msrc = msrc;
+    b.kinds = kinds;
     return b;
 }
 
@@ -405,11 +405,13 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
     const int G = e.ngrids();
     // further sources of each grid: raytrace entries G, G + 1, ...
     e.extra.clear();
-    for (int g = 0; g < G; ++g)
-        for (int s = 1; s < nsources(e.grids[g]->d); ++s) e.extra.push_back(make_int2(g, s));
-    e.msrc = e.extra.empty() ? 1 : MAX_SRC;
-    if (!e.extra.empty() && G > 1)
-        return fail(PI_EINVAL, "a grid with several sources is advanced on its own, not in a batch");
+    bool one = false;
+    for (int g = 0; g < G; ++g) {
+        const int ns = nsources(e.grids[g]->d);
+        one = one || ns == 1;
+        for (int s = 1; s < ns; ++s) e.extra.push_back(make_int2(g, s));
+    }
+    e.kinds = e.extra.empty() ? 1 : (one ? 3 : 2);
     // launch geometry
     // three prefix tables of G + 1 entries: micro-physics workgroups,
     // timestep workgroups, rows of plane-parallel grids

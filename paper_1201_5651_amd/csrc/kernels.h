@@ -107,8 +107,10 @@ struct BatchDev {
     unsigned int* fix_n;
     long long* fix_list;     // (grid << 32) | cell, for the double re-solve
     unsigned int fix_cap;    // entries fix_list holds
-    int msrc;                // MAX_SRC when a grid has several sources (their
-                             // micro-physics and timestep kernels), else 1
+    // Grid kinds present: bit 0 grids with one source, bit 1 grids with
+    // several.  The micro-physics and timestep kernels come in one variant per
+    // kind; with both kinds each launch skips the workgroups of the other.
+    int kinds;
 };
 
 // One tile-diagonal stage of the raytrace of every grid with tiles of edge

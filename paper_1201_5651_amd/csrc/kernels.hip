@@ -329,6 +329,14 @@ __device__ __forceinline__ EnvM<C, MS> multi_env(const Params<C>& p, const Sourc
     return e;
 }
 
+// With grids of both kinds in a batch, whether grid G belongs to the launch of
+// the kernel variant for MS sources.
+template <int MS, typename R>
+__device__ __forceinline__ bool other_kind(const BatchDev& bd, const GridDev<R>& G)
+{
+    return bd.kinds == 3 && ((G.src.n > 1) != (MS > 1));
+}
+
 // Micro-integration of cell q in arithmetic C from storage S.  A non-finite
 // input stays non-finite (the bound projections of the solver would otherwise
 // turn it into a valid-looking state), so the grid's diagnostics report it.
@@ -372,6 +380,7 @@ k_chem(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int 
     const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int g = find_grid(bd.chem_first, bd.ngrids, lb);
     const GridDev<R>& G = grids[g];
+    if (other_kind<MS>(bd, G)) return;   // uniform over the workgroup
     const Params<R> pl = table_to_lds(G.p, s_tab);
     const int brick = (lb - bd.chem_first[g]) * (CHEM_BLOCK / 64) + (int)(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -420,7 +429,7 @@ k_chem(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int 
 template <int MS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ChemWaves<double>::value)))
 k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int to, int tau_buf,
-           int dev_dt, double hscale, unsigned long long* ctr)
+           int dev_dt, double hscale, unsigned long long* ctr, int clear)
 {
     const unsigned n = min(bd.fix_n[0], bd.fix_cap);
     if (blockIdx.x * blockDim.x < n) {   // uniform over the workgroup
@@ -428,6 +437,7 @@ k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int 
         for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
             const long long e = bd.fix_list[i];
             const GridDev<float>& G = grids[(int)(e >> 32)];
+            if (other_kind<MS>(bd, G)) continue;
             const int q = (int)(e & 0xffffffffll);
             const double hd = dev_dt ? hscale * G.st->dt : hscale;
             double x, E;
@@ -439,6 +449,9 @@ k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int 
         }
         add_work(ctr, w);
     }
+    // With grids of both kinds the first of the two launches leaves the list
+    // to the second.
+    if (!clear) return;
     // Every wave has its value of the list length (its branch above waited for
     // the load), so once all workgroups have counted themselves no read of the
     // length is outstanding and the last one may clear it; no fence is needed.
@@ -650,6 +663,7 @@ k_dtdiag(const GridDev<R>* __restrict__ grids, BatchDev bd)
 {
     const int g = find_grid(bd.dt_first, bd.ngrids, blockIdx.x);
     const GridDev<R>& G = grids[g];
+    if (other_kind<MS>(bd, G)) return;   // uniform over the workgroup
     const Params<R> p = G.p;
     const int lb = blockIdx.x - bd.dt_first[g], nb = bd.dt_first[g + 1] - bd.dt_first[g];
     const R* __restrict__ nH = G.nH;
@@ -821,12 +835,12 @@ hipError_t launch_chem(const GridDev<R>* grids, const BatchDev& b, int nblocks, 
                        bool mixed, hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
-    if (b.msrc > 1)
-        hipLaunchKernelGGL((k_chem<R, MAX_SRC>), dim3(nblocks), dim3(CHEM_BLOCK), 0, s, grids, b,
-                           from, to, tau_buf, (int)dev_dt, hscale, ctr, (int)mixed);
-    else
+    if (b.kinds & 1)
         hipLaunchKernelGGL((k_chem<R, 1>), dim3(nblocks), dim3(CHEM_BLOCK), 0, s, grids, b, from,
                            to, tau_buf, (int)dev_dt, hscale, ctr, (int)mixed);
+    if (b.kinds & 2)
+        hipLaunchKernelGGL((k_chem<R, MAX_SRC>), dim3(nblocks), dim3(CHEM_BLOCK), 0, s, grids, b,
+                           from, to, tau_buf, (int)dev_dt, hscale, ctr, (int)mixed);
     return hipGetLastError();
 }
 
@@ -835,12 +849,12 @@ hipError_t launch_chem_fix(const GridDev<float>* grids, const BatchDev& b, int n
                            unsigned long long* ctr, hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
-    if (b.msrc > 1)
-        hipLaunchKernelGGL(k_chem_fix<MAX_SRC>, dim3(nblk), dim3(256), 0, s, grids, b, from, to,
-                           tau_buf, (int)dev_dt, hscale, ctr);
-    else
+    if (b.kinds & 1)
         hipLaunchKernelGGL(k_chem_fix<1>, dim3(nblk), dim3(256), 0, s, grids, b, from, to,
-                           tau_buf, (int)dev_dt, hscale, ctr);
+                           tau_buf, (int)dev_dt, hscale, ctr, (b.kinds & 2) ? 0 : 1);
+    if (b.kinds & 2)
+        hipLaunchKernelGGL(k_chem_fix<MAX_SRC>, dim3(nblk), dim3(256), 0, s, grids, b, from, to,
+                           tau_buf, (int)dev_dt, hscale, ctr, 1);
     return hipGetLastError();
 }
 
@@ -849,10 +863,10 @@ hipError_t launch_dtdiag(const GridDev<R>* grids, const BatchDev& b, int nblocks
                          hipStream_t s)
 {
     if (nblocks <= 0 || b.ngrids <= 0) return hipSuccess;
-    if (b.msrc > 1)
-        hipLaunchKernelGGL((k_dtdiag<R, MAX_SRC>), dim3(nblocks), dim3(DT_BLOCK), 0, s, grids, b);
-    else
+    if (b.kinds & 1)
         hipLaunchKernelGGL((k_dtdiag<R, 1>), dim3(nblocks), dim3(DT_BLOCK), 0, s, grids, b);
+    if (b.kinds & 2)
+        hipLaunchKernelGGL((k_dtdiag<R, MAX_SRC>), dim3(nblocks), dim3(DT_BLOCK), 0, s, grids, b);
     hipLaunchKernelGGL((k_finalize<R>), dim3(b.ngrids), dim3(256), 0, s, grids, b, t_end_arg);
     return hipGetLastError();
 }

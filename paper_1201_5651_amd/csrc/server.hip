@@ -84,10 +84,17 @@ size_t word_bytes(int precision) { return precision == PI_FP64 ? 8 : 4; }
 
 int nfields(const pi_grid_desc& d) { return d.thermal == PI_T_EVOLVE ? 7 : 5; }
 
+// columns per cell: one per point source
+int ncolumns(const pi_grid_desc& d)
+{
+    return (d.source == PI_SRC_POINT && d.nsrc > 1) ? d.nsrc : 1;
+}
+
+// fields of a request in the arena: tau and tau_half carry one array per source
 size_t footprint(const pi_grid_desc& d)
 {
     const size_t n = (size_t)d.n[0] * d.n[1] * d.n[2];
-    return (size_t)nfields(d) * Arena::round(n * word_bytes(d.precision));
+    return (size_t)(nfields(d) + 2 * (ncolumns(d) - 1)) * Arena::round(n * word_bytes(d.precision));
 }
 
 }  // namespace
@@ -135,7 +142,10 @@ pi_status pi_server::start(Request& r)
     char* p = static_cast<char*>(r.block);
     pi_fields f{};
     void** slots[7] = { &f.nH, &f.x, &f.tau, &f.x_half, &f.tau_half, &f.E, &f.E_half };
-    for (int k = 0; k < nfields(d); ++k) *slots[k] = p + k * fb;
+    for (int k = 0; k < nfields(d); ++k) {
+        *slots[k] = p;
+        p += (k == 2 || k == 4) ? ncolumns(d) * fb : fb;   // tau, tau_half
+    }
     pi_status s = grid_host_init(r.grid, d, f);
     if (s != PI_OK) return s;
     // initial state, converted to the field precision on the host
@@ -365,7 +375,6 @@ pi_status pi_submit(pi_server* s, const pi_request* req, uint64_t* ticket)
     pi_status v = validate_desc(&req->desc);
     if (v != PI_OK) return v;
     if (req->desc.precision != s->desc.precision) return fail(PI_EINVAL, "precision differs from the server's");
-    if (req->desc.nsrc > 1) return fail(PI_EINVAL, "served requests have one source");
     if (!req->nH) return fail(PI_EINVAL, "nH is required");
     if (!std::isfinite(req->t_end) || !(req->t_end >= 0)) return fail(PI_EINVAL, "t_end must be finite and >= 0");
     if (req->desc.thermal == PI_T_EVOLVE && !(req->T0 > 0)) return fail(PI_EINVAL, "T0 must be > 0");

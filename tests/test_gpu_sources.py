@@ -1,7 +1,8 @@
 """Several point sources on one grid: every source's columns, A3 steps and
 diagnostics on the GPU against the oracle (each source traced on its own, the
-rates of the sources added in every cell), and the limits of the form (one
-grid at a time, algorithm 3 and the single calls only)."""
+rates of the sources added in every cell), such grids batched and served
+beside one-source grids (bit for bit as alone), and the limit of the form
+(algorithm 1 follows one source)."""
 import numpy as np
 import pytest
 
@@ -117,9 +118,9 @@ def test_mirrored_sources_on_gpu_give_a_mirrored_state():
 
 
 def test_several_sources_limits():
-    """A grid with several sources runs on its own: batches, served requests
-    and algorithm 1 reject it with PI_EINVAL; a bad vertex is rejected at
-    creation."""
+    """Algorithm 1 follows one source's rays: a grid (or a batch holding a
+    grid) with several sources is rejected with PI_EINVAL there and stays
+    usable; a vertex outside the grid is rejected at creation."""
     spec = _spec(2, shape=(8, 8, 8)).with_(src=(4, 4, 4), more_sources=(((1, 2, 3), 1e47),))
     g = binding.Grid(spec)
     g.load(_nH(spec), 1.0, T0=50.0)
@@ -128,12 +129,87 @@ def test_several_sources_limits():
     assert e.value.status == binding.PI_EINVAL
     g.step_o2(spec.t_end)   # the grid is still usable
     g.close()
+    b = binding.Batch([spec, spec.with_(more_sources=())])
+    b.load([_nH(spec)] * 2, T0s=[50.0] * 2, t_end=[spec.t_end] * 2)
     with pytest.raises(binding.PiError) as e:
-        binding.Batch([spec, spec.with_(more_sources=())])
+        b.step_a1()
     assert e.value.status == binding.PI_EINVAL
+    b.close()
     with pytest.raises(binding.PiError) as e:
         binding.Grid(spec.with_(more_sources=(((9, 0, 0), 1e47),)))
     assert e.value.status == binding.PI_EINVAL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_of_one_and_several_source_grids_bitwise(precision):
+    """Grids with one source, with several, and a plane-parallel grid advanced
+    as one batch (both kernel variants launched, each skipping the other's
+    grids; one re-solve list) give bit for bit what each gives alone."""
+    specs = [_spec(3, precision),
+             synth.cfg2(n=14).with_(precision=precision),
+             _spec(1, precision, shape=(11, 16, 9)).with_(
+                 src=(3, 8, 4), more_sources=(((9, 2, 7), 4e47), ((0, 16, 0), 2e48),
+                                              ((11, 5, 3), 1e47))),
+             synth.plane(n=(40, 6, 5), density="lognormal", precision=precision)]
+    nHs = [_nH(specs[0], 1), _nH(specs[1], 2), _nH(specs[2], 3), synth.density(specs[3])]
+    alone = []
+    for s, nH in zip(specs, nHs):
+        g = binding.Grid(s, precision=precision)
+        g.load(nH, 1.0, T0=s.T0)
+        for _ in range(6):
+            g.step_o2(s.t_end)
+        alone.append((g.state(), to_np(g.x), None if g.E is None else to_np(g.E), to_np(g.tau),
+                      g.diagnostics()))
+        g.close()
+    b = binding.Batch(specs, precision=precision)
+    b.load(nHs, T0s=[s.T0 for s in specs], t_end=[s.t_end for s in specs])
+    for _ in range(6):
+        b.step_o2()
+    t, n, _ = b.state()
+    d = b.diagnostics()
+    for i, (st, xa, Ea, taua, da) in enumerate(alone):
+        assert (t[i], n[i]) == st[:2], i
+        assert np.array_equal(to_np(b.grids[i].x), xa), i
+        if Ea is not None:
+            assert np.array_equal(to_np(b.grids[i].E), Ea), i
+        assert np.array_equal(to_np(b.grids[i].tau), taua), i
+        assert d[i]["octants"] == da["octants"], i
+    assert [d[i]["octants"] for i in range(4)] == [18, 8, 8 + 8 + 1 + 4, 0]
+    b.close()
+
+
+def test_served_several_source_requests_match_alone():
+    """Served requests with several sources (their columns take one array per
+    source in the arena) next to one-source requests: each result is the grid
+    advanced alone, bit for bit."""
+    import time
+    reqs = [(_spec(3, "mixed"), 1), (synth.cfg2(n=12).with_(precision="mixed"), 2),
+            (_spec(1, "mixed", shape=(9, 10, 12)).with_(src=(4, 5, 6),
+                                                         more_sources=(((1, 9, 2), 5e47),)), 3)]
+    srv = binding.Server(precision="mixed", hbm_budget=64 << 20, max_active=4, steps_per_tick=2)
+    tickets = []
+    for s, seed in reqs:
+        tickets.append(srv.submit(s, _nH(s, seed), T0=s.T0, t_end=2e-3 * s.t_rec))
+    done, t0 = {}, time.time()
+    while len(done) < len(tickets):
+        assert time.time() - t0 < 120.0, "served requests did not finish"
+        for tk in tickets:
+            if tk not in done:
+                st, info, x, T = srv.poll(tk)
+                if st != binding.PI_PENDING:
+                    done[tk] = (st, info, x)
+        time.sleep(0.005)
+    srv.close()
+    for tk, (s, seed) in zip(tickets, reqs):
+        st, info, x = done[tk]
+        assert st == binding.PI_OK, info
+        g = binding.Grid(s, precision="mixed")
+        g.load(_nH(s, seed), 1.0, T0=s.T0)
+        g.run(2e-3 * s.t_rec, check_every=8)
+        t, n, _ = g.state()
+        assert (info["t"], info["nsteps"]) == (t, n)
+        assert np.array_equal(x, to_np(g.x))
+        g.close()
 
 
 def test_degenerate_sources_fp64(oracle_lib):
