@@ -21,6 +21,8 @@ namespace pi {
 
 namespace {
 
+static_assert(MAX_SRC == PI_MAX_SRC, "the kernels and the ABI agree on the most sources");
+
 // Point sources of a grid and the vertex of source s.
 int nsources(const pi_grid_desc& d)
 {
@@ -412,6 +414,9 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
         for (int s = 1; s < ns; ++s) e.extra.push_back(make_int2(g, s));
     }
     e.kinds = e.extra.empty() ? 1 : (one ? 3 : 2);
+    // a tile names its raytrace entry in the bits above its octant
+    if ((int64_t)G + (int64_t)e.extra.size() > (1 << 27))
+        return fail(PI_EINVAL, "too many grids and sources in one batch");
     // launch geometry
     // three prefix tables of G + 1 entries: micro-physics workgroups,
     // timestep workgroups, rows of plane-parallel grids

@@ -297,11 +297,6 @@ __device__ __forceinline__ Params<R> table_to_lds(const Params<R>& p, DevTable<R
     return pl;
 }
 
-// Environment of the kernels instantiated for MS sources: a one-source grid
-// takes Env, grids with several sources EnvM.
-template <typename C, int MS> struct EnvSel { using type = EnvM<C, MS>; };
-template <typename C> struct EnvSel<C, 1> { using type = Env<C>; };
-
 // Environment of cell q = (i, j, k) of a grid with several sources: source s
 // has its own geometry and its own columns, tau[s * ncell + q].  ok turns false
 // when one of the columns is not finite.
