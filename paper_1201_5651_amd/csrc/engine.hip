@@ -457,15 +457,56 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
             for (int s = 0; s < MAX_SRC; ++s) nst = std::max(nst, h->tiles[s][w].size());
         // entry r of the grid table traces grid g from source s
         const int R = G + (int)e.extra.size();
+        const int T = SWEEP_TILES[w];
+        const int line_shift = e.fp64() ? 4 : 5;   // cells per 128-byte line: 16 or 32
+        std::vector<int4> bucket[NXCD];
         for (size_t k = 0; k < nst; ++k) {
             e.stage_first[w].push_back((int)flat.size());
+            // The hardware deals the workgroups of a launch to the XCDs in
+            // turn.  Tiles are given slots by a hash of the 128-byte line
+            // their rows start in, so neighbours along x (swept by successive
+            // launches) and the same cells seen from another source share an
+            // XCD, while the tiles of one octant spread over all of them.  On
+            // the 256^3 medium this order makes the large middle stages
+            // shorter (raytrace 0.607 -> 0.584 ms), though the bytes fetched
+            // per raytrace do not change.
             for (int r = 0; r < R; ++r) {
                 const int g = r < G ? r : e.extra[r - G].x;
                 const int src = r < G ? 0 : e.extra[r - G].y;
                 const std::vector<std::vector<int4>>& tl = e.grids[g]->tiles[src][w];
                 if (k >= tl.size()) continue;
-                for (const int4& t : tl[k]) flat.push_back(make_int4((r << 3) | t.x, t.y, t.z, t.w));
+                const int32_t* v = source_vertex(e.grids[g]->d, src);
+                for (const int4& t : tl[k]) {
+                    const int o = t.x;
+                    const int gx = (o & 1) ? v[0] + T * t.y : std::max(v[0] - T * (t.y + 1), 0);
+                    const int gy = (o & 2) ? v[1] + T * t.z : v[1] - T * (t.z + 1);
+                    const int gz = (o & 4) ? v[2] + T * t.w : v[2] - T * (t.w + 1);
+                    const uint64_t key = (uint64_t)g * 0x9E3779B97F4A7C15ull ^
+                                         (uint64_t)(gx >> line_shift) * 0xC2B2AE3D27D4EB4Full ^
+                                         (uint64_t)(int64_t)gy * 0x165667B19E3779F9ull ^
+                                         (uint64_t)(int64_t)gz * 0xD6E8FEB86659FD93ull;
+                    bucket[(key ^ (key >> 29)) % NXCD].push_back(
+                        make_int4((r << 3) | o, t.y, t.z, t.w));
+                }
             }
+            // slot p runs on XCD p % NXCD: take from that XCD's bucket, or
+            // from the fullest one when it is empty
+            size_t left = 0;
+            for (int b = 0; b < NXCD; ++b) left += bucket[b].size();
+            size_t pos[NXCD] = {};
+            for (size_t p = 0; left > 0; ++p, --left) {
+                int b = (int)(p % NXCD);
+                if (pos[b] == bucket[b].size()) {
+                    size_t most = 0;
+                    for (int c = 0; c < NXCD; ++c)
+                        if (bucket[c].size() - pos[c] > most) {
+                            most = bucket[c].size() - pos[c];
+                            b = c;
+                        }
+                }
+                flat.push_back(bucket[b][pos[b]++]);
+            }
+            for (int b = 0; b < NXCD; ++b) bucket[b].clear();
             e.stage_count[w].push_back((int)flat.size() - e.stage_first[w].back());
         }
         if (flat.size() > e.tiles_cap[w]) {
