@@ -346,7 +346,7 @@ def bench_serve(args, torch, binding, synth) -> dict:
                          steps_per_tick=args.serve_steps_per_tick)
     # warm-up: a few requests of the same kind (other seed) run to completion
     # first, so the timed stream sees a server whose rate tables and raytrace
-    # tiles are set up (the survey's serving workload has a warm-up period)
+    # tiles are set up (a serving workload has a warm-up period)
     warm = synth.poisson_requests(args.serve_warmup, rate=args.serve_rate, seed=15651,
                                   nmin=args.serve_nmin, nmax=args.serve_nmax,
                                   precision=args.precision) if args.serve_warmup > 0 else []
