@@ -237,3 +237,28 @@ def test_degenerate_sources_fp64(oracle_lib):
         assert d["photo_rate"] == pytest.approx(d1["photo_rate"], rel=1e-10), key
     assert runs["zero"][3]["octants"] == 8 + 8
     assert (1 - x1).sum() > 1.0
+
+
+def test_four_sources_48cubed_mixed(oracle_lib):
+    """A 48^3 clumpy grid (three 16^3 tiles a side) lit by four sources, one
+    of them on an edge of the box, in mixed precision: six A3 steps against
+    the oracle at the float bar, every source's columns included."""
+    base = synth.cfg2(n=48).with_(src=(20, 30, 17), precision="mixed")
+    spec = base.with_(more_sources=(((40, 8, 33), 0.7 * base.Q), ((5, 44, 44), 0.3 * base.Q),
+                                    ((48, 24, 0), 1.5 * base.Q)))
+    nH = synth.lognormal_density(spec.shape, 10.0, 1.0, 12)
+    g, pb, st = pair(spec, nH, T0=50.0, precision="mixed")
+    for _ in range(6):
+        g.step_o2(spec.t_end)
+        pb.step(st, spec.t_end)
+    assert g.state()[0] == pytest.approx(st["t"], rel=1e-4)
+    errx = rel_x(to_np(g.x), st["x"])
+    Tg = pb.temperature(st["nH"], to_np(g.x), to_np(g.E))
+    Tw = pb.temperature(st["nH"], st["x"], st["E"])
+    assert np.quantile(errx, 0.999) < 1e-4
+    assert np.quantile(rel(Tg, Tw), 0.999) < 1e-4
+    m = st["tau"] > 1e-3
+    assert np.quantile(rel(to_np(g.tau)[m], st["tau"][m]), 0.999) < 1e-4
+    assert g.diagnostics()["octants"] == 8 + 8 + 8 + 2
+    assert (1 - st["x"]).sum() > 20.0
+    g.close()
