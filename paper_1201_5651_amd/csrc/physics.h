@@ -768,9 +768,10 @@ PI_HD void micro_t(const Params<R>& p, const EV& e, R h, R& x, R& E, Work& w, R*
     const int ns = substeps(p, e, x, E, h, w, fx, fE);
     const int top = 1 << SUB_LEVELS;
     const int U = ns * top;
+    const double hU = (double)h / (double)U;   // one division; substeps are s units of it
     int pos = 0, s = top;
     while (pos < U) {
-        const R hs = R((double)h * (double)s / (double)U);
+        const R hs = R(hU * (double)s);
         R xn = x, En = E, fxn = fx, fEn = fE, X1;
         sdirk_step(p, e, hs, xn, En, fxn, fEn, w, X1);
         const R dx = r_abs(xn - x);
