@@ -174,8 +174,8 @@ PI_HD __forceinline__ CellGeom<R> cell_geom_at(const Params<R>& p, int sx, int s
         c.g = R(0.125);
         c.ell = R(CORNER_CHORD);
     } else {
-        const R ds = r_sqrt(rr) / da;
-        c.g = R(1) / (R(4.0 * 3.14159265358979323846) * rr * ds);
+        const R ds = r_sqrt(rr) * r_rcp(da);
+        c.g = r_rcp(R(4.0 * 3.14159265358979323846) * rr * ds);
         c.ell = ds;
     }
     return c;
@@ -258,8 +258,8 @@ PI_HD __forceinline__ Env<R> make_env_q(const Params<R>& p, R QV, R n, CellGeom<
 {
     Env<R> e;
     e.n = n;
-    e.inv_n = R(1) / n;
-    e.c3 = R(1) / (R(3.0 * KB) * n);
+    e.inv_n = r_rcp(n);
+    e.c3 = e.inv_n * R(1.0 / (3.0 * KB));
     e.Qg = QV * c.g;
     e.k = n * p.sdx * c.ell;
     e.tau = tau;
@@ -270,7 +270,7 @@ PI_HD __forceinline__ Env<R> make_env_q(const Params<R>& p, R QV, R n, CellGeom<
     } else {
         R dP, dH;
         table_pair(p.tab, tau, e.Pin, dP, e.Hin, dH);
-        e.lin = e.Pin > R(0) ? -dP / e.Pin : R(0);
+        e.lin = e.Pin > R(0) ? -dP * r_rcp(e.Pin) : R(0);
     }
     return e;
 }
@@ -721,8 +721,9 @@ PI_HD __forceinline__ void sdirk_step(const Params<R>& p, const EV& e, R hs, R& 
     R X2, F2;
     stage_guess(xb, Eb, R(1), X1 - x, F1 - E, X2, F2);   // hg f(Y1) = Y1 - y
     stage_solve(p, e, xb, Eb, hg, X2, F2, w);
-    fx = (X2 - xb) / hg;
-    fE = (F2 - Eb) / hg;
+    const R ihg = r_rcp(hg);
+    fx = (X2 - xb) * ihg;
+    fE = (F2 - Eb) * ihg;
     x_stage1 = X1;
     x = X2;
     E = F2;
