@@ -89,17 +89,19 @@ template <typename R> struct Params {
 
 // Float arithmetic uses the hardware transcendental instructions (a few ulp,
 // far inside the 1e-4 float tolerance); double uses the correctly rounded
-// library routines.  Every logarithm taken here has a positive normal
-// argument (T >= 10 K, tau >= 1e-4), so the bare instruction needs no
-// denormal scaling.
+// library routines.  Every logarithm and square root taken here has a
+// positive normal argument (T >= 10 K, tau >= 1e-4, squared distances >=
+// 3/4 in cell units), so the bare instruction needs no denormal scaling.
 #if defined(__HIP_DEVICE_COMPILE__)
 #define PI_FEXP(v) __expf(v)
 #define PI_FLOG(v) (__builtin_amdgcn_logf(v) * 0.693147181f)
 #define PI_FPOW(a, b) __powf(a, b)
+#define PI_FSQRT(v) __builtin_amdgcn_sqrtf(v)
 #else   // host-side unit harnesses
 #define PI_FEXP(v) expf(v)
 #define PI_FLOG(v) logf(v)
 #define PI_FPOW(a, b) powf(a, b)
+#define PI_FSQRT(v) sqrtf(v)
 #endif
 template <typename R> PI_HD __forceinline__ R r_exp(R v);
 template <> PI_HD __forceinline__ double r_exp<double>(double v) { return exp(v); }
@@ -112,7 +114,7 @@ template <> PI_HD __forceinline__ double r_log<double>(double v) { return log(v)
 template <> PI_HD __forceinline__ float r_log<float>(float v) { return PI_FLOG(v); }
 template <typename R> PI_HD __forceinline__ R r_sqrt(R v);
 template <> PI_HD __forceinline__ double r_sqrt<double>(double v) { return sqrt(v); }
-template <> PI_HD __forceinline__ float r_sqrt<float>(float v) { return sqrtf(v); }
+template <> PI_HD __forceinline__ float r_sqrt<float>(float v) { return PI_FSQRT(v); }
 template <typename R> PI_HD __forceinline__ R r_pow(R a, R b);
 template <> PI_HD __forceinline__ double r_pow<double>(double a, double b) { return pow(a, b); }
 template <> PI_HD __forceinline__ float r_pow<float>(float a, float b) { return PI_FPOW(a, b); }
