@@ -335,10 +335,12 @@ __device__ __forceinline__ bool other_kind(const BatchDev& bd, const GridDev<R>&
 // Micro-integration of cell q in arithmetic C from storage S.  A non-finite
 // input stays non-finite (the bound projections of the solver would otherwise
 // turn it into a valid-looking state), so the grid's diagnostics report it.
+// (i, j, k) are the cell's coordinates, q = i + nx (j + ny k).
 template <typename C, typename S, int MS>
-__device__ __forceinline__ void chem_cell(const Params<C>& p, const Sources<C>& src, int q,
-                                          const S* __restrict__ nH, const S* x0, const S* E0,
-                                          const S* __restrict__ tau, double hd, C& x, C& E, Work& w)
+__device__ __forceinline__ void chem_cell(const Params<C>& p, const Sources<C>& src, int q, int i,
+                                          int j, int k, const S* __restrict__ nH, const S* x0,
+                                          const S* E0, const S* __restrict__ tau, double hd, C& x,
+                                          C& E, Work& w)
 {
     x = C(x0[q]);
     E = E0 ? C(E0[q]) : C(0);
@@ -347,7 +349,6 @@ __device__ __forceinline__ void chem_cell(const Params<C>& p, const Sources<C>& 
         x = E = C(__builtin_nan(""));
         return;
     }
-    const int i = q % p.nx, j = (q / p.nx) % p.ny, k = q / (p.nx * p.ny);
     if constexpr (MS == 1) {
         const CellGeom<C> cg = cell_geom(p, i, j, k);
         const Env<C> e = make_env(p, n, cg, tq);
@@ -377,7 +378,10 @@ k_chem(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int 
     const GridDev<R>& G = grids[g];
     if (other_kind<MS>(bd, G)) return;   // uniform over the workgroup
     const Params<R> pl = table_to_lds(G.p, s_tab);
-    const int brick = (lb - bd.chem_first[g]) * (CHEM_BLOCK / 64) + (int)(threadIdx.x >> 6);
+    // the brick is the same for the whole wavefront: its decomposition runs on
+    // the scalar unit
+    const int brick = __builtin_amdgcn_readfirstlane(
+        (lb - bd.chem_first[g]) * (CHEM_BLOCK / 64) + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int nbx = (pl.nx + CHEM_BX - 1) / CHEM_BX, nby = (pl.ny + CHEM_BY - 1) / CHEM_BY;
     const int i = CHEM_BX * (brick % nbx) + (lane & 3);
@@ -392,8 +396,8 @@ k_chem(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int 
     if (inside) {
         const double hd = dev_dt ? hscale * G.st->dt : hscale;
         R x, E;
-        chem_cell<R, R, MS>(pl, G.src, q, G.nH, G.x[from], G.E[from], G.tau[tau_buf], hd, x, E,
-                            w);
+        chem_cell<R, R, MS>(pl, G.src, q, i, j, k, G.nH, G.x[from], G.E[from], G.tau[tau_buf], hd,
+                            x, E, w);
         flag = mixed && w.close > 0;
         if (!flag) {
             G.x[to][q] = x;
@@ -434,9 +438,10 @@ k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int 
             const GridDev<float>& G = grids[(int)(e >> 32)];
             if (other_kind<MS>(bd, G)) continue;
             const int q = (int)(e & 0xffffffffll);
+            const int ci = q % G.pd.nx, cj = (q / G.pd.nx) % G.pd.ny, ck = q / (G.pd.nx * G.pd.ny);
             const double hd = dev_dt ? hscale * G.st->dt : hscale;
             double x, E;
-            chem_cell<double, float, MS>(G.pd, G.srcd, q, G.nH, G.x[from], G.E[from],
+            chem_cell<double, float, MS>(G.pd, G.srcd, q, ci, cj, ck, G.nH, G.x[from], G.E[from],
                                          G.tau[tau_buf], hd, x, E, w);
             G.x[to][q] = (float)x;
             if (G.E[to]) G.E[to][q] = (float)E;
