@@ -74,15 +74,36 @@ template <typename R> void fill_table(DevTable<R>& T, const double* tab, double 
     T.inv_delta = R(1.0 / delta);
     T.tau1 = R(tn[1]);
     T.tau_last = R(tn[PI_NTAB - 1]);
-    for (int j = 0; j < PI_NTAB; ++j) {
-        if (j == 0 || P[j] <= 0 || H[j] <= 0) {
-            T.lp[j] = T.mp[j] = T.lh[j] = T.mh[j] = R(0);
-            continue;
+    // ln V/V_0 and d ln V / d ln tau at node n (zero where a value vanishes)
+    auto node = [&](const double* V, const double* V1, int n, double& L, double& m) {
+        if (n == 0 || P[n] <= 0 || H[n] <= 0) {
+            L = m = 0.0;
+            return;
         }
-        T.lp[j] = R(std::log(P[j] / P[0]));
-        T.mp[j] = R(-tn[j] * P1[j] / P[j]);
-        T.lh[j] = R(std::log(H[j] / H[0]));
-        T.mh[j] = R(-tn[j] * H1[j] / H[j]);
+        L = std::log(V[n] / V[0]);
+        m = -tn[n] * V1[n] / V[n];
+    };
+    for (int j = 0; j < PI_NTAB; ++j)
+        for (int c = 0; c < 8; ++c) T.cp[j][c] = T.ch[j][c] = R(0);
+    // the cubic Hermite interpolant on interval j (nodes j + 1, j + 2) in
+    // powers of the local coordinate t = (ln tau - ln tau_{j+1}) / Delta
+    for (int j = 0; j + 2 < PI_NTAB; ++j) {
+        for (int which = 0; which < 2; ++which) {
+            const double* V = which ? H : P;
+            const double* V1 = which ? H1 : P1;
+            double L0, m0, L1, m1;
+            node(V, V1, j + 1, L0, m0);
+            node(V, V1, j + 2, L1, m1);
+            m0 *= delta;
+            m1 *= delta;
+            const double a[4] = { L0, m0, 3.0 * (L1 - L0) - 2.0 * m0 - m1,
+                                  2.0 * (L0 - L1) + m0 + m1 };
+            R* c = which ? T.ch[j] : T.cp[j];
+            for (int k = 0; k < 4; ++k) c[k] = R(a[k]);
+            c[4] = R(a[1] / delta);
+            c[5] = R(2.0 * a[2] / delta);
+            c[6] = R(3.0 * a[3] / delta);
+        }
     }
 }
 

@@ -63,13 +63,20 @@ template <> struct Tol<float> {
 };
 
 // Rate table as the kernels use it: values normalised by Q, and the log-Hermite
-// form (ln V_j/V_0 and d ln V / d ln tau at the log-spaced nodes) so that the
-// interpolation is accurate in float too.
+// form (the cubic Hermite interpolant of ln V/V_0 in ln tau between the
+// log-spaced nodes, from the values and logarithmic slopes at the nodes) so
+// that the interpolation is accurate in float too.  Each interval carries the
+// cubic's coefficients in its local coordinate t in [0, 1),
+// {a0, a1, a2, a3} for ln V/V_0 = a0 + a1 t + a2 t^2 + a3 t^3, and
+// {b1, b2, b3} = {a1, 2 a2, 3 a3} / Delta for its derivative in ln tau.
 template <typename R> struct DevTable {
     R p0, p1_0, h0, h1_0;    // P(0)/Q, -P'(0)/Q, H(0)/Q [erg], -H'(0)/Q [erg]
     R s1, inv_delta, delta;  // ln tau_1, 1/Delta, Delta (node spacing in ln tau)
     R tau1, tau_last;
-    R lp[NTAB], mp[NTAB], lh[NTAB], mh[NTAB];
+    // interval j runs from node j + 1 to node j + 2 (node 0 is tau = 0):
+    // {a0, a1, a2, a3, b1, b2, b3, 0}
+    alignas(16) R cp[NTAB][8];
+    alignas(16) R ch[NTAB][8];
 };
 
 // Per-grid constants, passed by value to every kernel.
@@ -214,25 +221,18 @@ PI_HD __forceinline__ void table_pair(const DevTable<R>* __restrict__ T, R tau, 
     int j = (int)f;                     // f >= 0 here
     j = j < 0 ? 0 : (j > NTAB - 3 ? NTAB - 3 : j);
     const R t = f - R(j);
-    const int n0 = j + 1, n1 = j + 2;   // node indices (node 0 is tau = 0)
-    const R t2 = t * t, t3 = t2 * t;
-    const R h00 = R(2) * t3 - R(3) * t2 + R(1), h10 = t3 - R(2) * t2 + t;
-    const R h01 = R(-2) * t3 + R(3) * t2, h11 = t3 - t2;
-    const R d00 = R(6) * t2 - R(6) * t, d10 = R(3) * t2 - R(4) * t + R(1);
-    const R d01 = R(-6) * t2 + R(6) * t, d11 = R(3) * t2 - R(2) * t;
-    const R dl = T->delta;
     const R itau = r_rcp(tau);
     {
-        const R L0 = T->lp[n0], L1 = T->lp[n1], m0 = T->mp[n0] * dl, m1 = T->mp[n1] * dl;
-        const R L = h00 * L0 + h10 * m0 + h01 * L1 + h11 * m1;
-        const R dL = (d00 * L0 + d10 * m0 + d01 * L1 + d11 * m1) * T->inv_delta;
+        const R* c = T->cp[j];
+        const R L = r_fma(r_fma(r_fma(c[3], t, c[2]), t, c[1]), t, c[0]);
+        const R dL = r_fma(r_fma(c[6], t, c[5]), t, c[4]);   // d ln V / d ln tau
         P = T->p0 * r_exp(L);
         dP = P * dL * itau;
     }
     {
-        const R L0 = T->lh[n0], L1 = T->lh[n1], m0 = T->mh[n0] * dl, m1 = T->mh[n1] * dl;
-        const R L = h00 * L0 + h10 * m0 + h01 * L1 + h11 * m1;
-        const R dL = (d00 * L0 + d10 * m0 + d01 * L1 + d11 * m1) * T->inv_delta;
+        const R* c = T->ch[j];
+        const R L = r_fma(r_fma(r_fma(c[3], t, c[2]), t, c[1]), t, c[0]);
+        const R dL = r_fma(r_fma(c[6], t, c[5]), t, c[4]);
         H = T->h0 * r_exp(L);
         dH = H * dL * itau;
     }
