@@ -37,13 +37,16 @@ HBM_PEAK_GBS = 8000.0
 # MI355X vector peaks [TFLOP/s]
 VALU_PEAK = {"fp32": 157.3, "fp64": 78.6, "mixed": 157.3}
 # Algorithmic flops of the micro-physics, counted from the source (add, mul,
-# fma-half, reciprocal, square root and transcendental = 1 flop each): one
-# Newton iteration of the coupled (x, E) stage solve with the tabulated
-# spectrum, evolving temperature, power-law recombination, collisional
-# ionisation and cooling, optically thick branch; and the per-cell set-up of
-# one micro-integration (geometry, entering-column table lookup, initial rate).
-FLOP_NEWTON = 262
-FLOP_CELL_SETUP = 330
+# each half of a fused multiply-add, reciprocal, square root and
+# transcendental = 1 flop each): one Newton iteration of the coupled (x, E)
+# stage solve with the tabulated spectrum, evolving temperature, power-law
+# recombination, collisional ionisation and cooling, optically thick branch;
+# and the per-cell set-up of one micro-integration (geometry, entering-column
+# table lookup, initial rate).  A table lookup of P and H (log of tau, the two
+# interval cubics and their derivatives in Horner form, two exponentials) is 33
+# of them: one in a Newton iteration, two in the set-up.
+FLOP_NEWTON = 222
+FLOP_CELL_SETUP = 250
 
 
 KERNEL_SOURCES = ("paper_1201_5651_amd/csrc/physics.h", "paper_1201_5651_amd/csrc/kernels.h",
