@@ -276,7 +276,9 @@ __device__ __forceinline__ void add_work(unsigned long long* ctr, const Work& w)
 }
 
 // Waves per SIMD the register allocation of k_chem aims at: the double
-// kernel otherwise needs more than the 256 registers that two waves share.
+// kernel otherwise needs more than the 256 registers that two waves share,
+// and so does the variant for several sources (one environment per source,
+// unrolled); it takes the double kernel's two.
 template <typename R> struct ChemWaves { static constexpr int value = 3; };
 template <> struct ChemWaves<double> { static constexpr int value = 2; };
 
@@ -368,7 +370,8 @@ __device__ __forceinline__ void chem_cell(const Params<C>& p, const Sources<C>& 
 // whose float integration took a precision-sensitive decision is not written;
 // it is appended to the batch's re-solve list for the double pass.
 template <typename R, int MS>
-__global__ void __launch_bounds__(CHEM_BLOCK) __attribute__((amdgpu_waves_per_eu(ChemWaves<R>::value)))
+__global__ void __launch_bounds__(CHEM_BLOCK)
+__attribute__((amdgpu_waves_per_eu(MS > 1 ? ChemWaves<double>::value : ChemWaves<R>::value)))
 k_chem(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int tau_buf,
        int dev_dt, double hscale, unsigned long long* ctr, int mixed)
 {
