@@ -20,6 +20,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# The same source built with OpenMP: the per-cell loops and the octants of the
+# raytrace run on all host cores, with bitwise the same results.  Loaded
+# instead of the plain build when ORACLE_OPENMP=1 is set before the first call
+# (the multi-core leg of the CPU baseline).
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 KB = 1.380649e-16
 EV = 1.602176634e-12
@@ -33,14 +38,16 @@ ALPHA_CONST, ALPHA_POWER = 0, 1
 W_GEOMETRIC, W_MELLEMA = 0, 1
 
 
-def build(force: bool = False) -> str:
-    """Compile oracle.c into liboracle.so with plain gcc (no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-ffp-contract=off", "-fPIC",
-               "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+def build(force: bool = False, openmp: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with plain gcc (no fast-math);
+    openmp: the OpenMP build liboracle_omp.so."""
+    out = _LIB_OMP if openmp else _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-ffp-contract=off", "-fPIC"] + \
+              (["-fopenmp"] if openmp else []) + ["-shared", "-o", out + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+        os.replace(out + ".tmp", out)
+    return out
 
 
 class Desc(C.Structure):
@@ -87,7 +94,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        path = _LIB if os.path.exists(_LIB) else build()
+        omp = os.environ.get("ORACLE_OPENMP") == "1"
+        target = _LIB_OMP if omp else _LIB
+        path = target if os.path.exists(target) else build(openmp=omp)
         L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         pd = C.POINTER(Desc)

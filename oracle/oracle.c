@@ -37,10 +37,18 @@
  *
  * Parity unpinned (no closed form, printed value or brute force fixes them;
  * they are documented choices that only GPU <-> oracle parity checks): the
- * cooling and collisional-ionisation coefficients (Cen 1992 fits), the power
- * law of the recombination coefficient, the 0.6 floor of the Mellema weights,
- * and the placement of the 64 table nodes.  Everything else is pinned by the
- * tests in tests/test_oracle_pins.py.
+ * values of the cooling and collisional-ionisation coefficients (the Cen 1992
+ * fits), the 0.6 floor of the Mellema weights, and the placement of the 64
+ * table nodes.  How those coefficients enter eq. (2) and its integration is
+ * pinned (closed forms for collisional ionisation alone and for the
+ * recombination power law, quadrature of the cooling of ionised gas, the
+ * taper at the temperature floor, an independent stiff solver), and so is
+ * eq. (4) (each criterion against the rates of the integrated solution).
+ * Everything else is pinned by the tests in tests/test_oracle_pins.py.
+ *
+ * Built plainly it runs on one thread.  Built with OpenMP (the multi-core
+ * timing leg only) the independent per-cell loops and the octants of the
+ * raytrace run in parallel, with bitwise the same results.
  */
 #include "oracle.h"
 
@@ -360,10 +368,11 @@ static int raytrace_sc_3d(const orc_desc* g, const double* nH, const double* x, 
     const int64_t N = (int64_t)nx * ny * nz;
     double* Nc = (double*)malloc(sizeof(double) * (size_t)N);
     if (!Nc) return -2;
-    for (int oz = -1; oz <= 1; oz += 2)
-    for (int oy = -1; oy <= 1; oy += 2)
-    for (int ox = -1; ox <= 1; ox += 2) {
-        int o[3] = { ox, oy, oz };
+    /* the octants hold disjoint cells and read only their own: with OpenMP
+     * (the multi-core timing build) they run in parallel */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int oct = 0; oct < 8; ++oct) {
+        int o[3] = { (oct & 1) ? 1 : -1, (oct & 2) ? 1 : -1, (oct & 4) ? 1 : -1 };
         int ext[3];
         for (int d = 0; d < 3; ++d) ext[d] = o[d] > 0 ? g->n[d] - g->src[d] : g->src[d];
         if (ext[0] <= 0 || ext[1] <= 0 || ext[2] <= 0) continue;
@@ -768,7 +777,10 @@ static int stage_solve(const orc_desc* g, const cellenv* c, double xb, double Eb
             double e = fabs(dx) / fmax(x, 1e-12);
             if (e <= NEWTON_RTOL || (e >= eprev && e <= NEWTON_STALL)) break;
             eprev = e;
-            if (it == NEWTON_MAXIT - 1) ++g_newton_fail;
+            if (it == NEWTON_MAXIT - 1) {
+#pragma omp atomic
+                ++g_newton_fail;
+            }
         }
         *xio = x;
         return 0;
@@ -850,7 +862,10 @@ static int stage_solve(const orc_desc* g, const cellenv* c, double xb, double Eb
                 if (side == 1) gb *= 0.5;
                 side = 1;
             }
-            if (it == FALLBACK_MAXIT - 1) ++g_newton_fail;
+            if (it == FALLBACK_MAXIT - 1) {
+#pragma omp atomic
+                ++g_newton_fail;
+            }
         }
         double T = exp(lc);
         t_residual(g, c, xb, Eb, hg, T, &xs);
@@ -1090,6 +1105,7 @@ int orc_timestep(const orc_desc* g, const double* nH, const double* x, const dou
 {
     const int64_t N = ncells(g);
     double dt = INFINITY;
+#pragma omp parallel for reduction(min : dt) schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         cellenv c;
         make_env_grid(g, i, nH[i], tau, &c);
@@ -1103,6 +1119,9 @@ int orc_chem(const orc_desc* g, const double* nH, const double* x0, const double
              const double* tau, double h, double* x1, double* E1)
 {
     const int64_t N = ncells(g);
+    /* cells are independent (the multi-core timing build runs them in
+     * parallel; the cost per cell varies, hence the dynamic schedule) */
+#pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < N; ++i) {
         cellenv c;
         make_env_grid(g, i, nH[i], tau, &c);
