@@ -47,13 +47,16 @@ typedef enum {
     PI_ECANCELLED = -6   /* served request cancelled                          */
 } pi_status;
 
-/* PI_MIXED: float fields and float bulk arithmetic.  A cell is re-solved in
- * double from the same float inputs when its float integration took a
- * decision that the precision can flip: a substep-control decision within a
- * relative 1e-3 of its threshold (initial substep count, rejection of a
- * substep), a stage solve that needed the bracketed fallback, or a neutral
- * fraction held at 1 on an unstable equilibrium.  Reductions (timestep,
- * diagnostics) are double in every precision. */
+/* PI_MIXED: float fields and float bulk arithmetic, with the ionisation-front
+ * cells in double.  A cell whose neutral fraction at the start of a
+ * micro-physics update lies in [1e-3, 0.999] (the front) is integrated in
+ * double only.  Any other cell is integrated in float and re-solved in double
+ * from the same float inputs when its float integration took a decision that
+ * the precision can flip: a substep-control decision within a relative 1e-3 of
+ * its threshold (initial substep count, rejection of a substep), a stage
+ * solve that needed the bracketed fallback, or a neutral fraction held at 1 on
+ * an unstable equilibrium.  Results are stored in float.  Reductions
+ * (timestep, diagnostics) are double in every precision. */
 typedef enum { PI_FP64 = 0, PI_FP32 = 1, PI_MIXED = 2 } pi_precision;
 enum { PI_SPEC_MONO = 0, PI_SPEC_TABLE = 1 };
 enum { PI_T_FIXED = 0, PI_T_EVOLVE = 1 };
@@ -136,7 +139,7 @@ typedef struct {
 typedef struct pi_grid pi_grid;
 
 /* Validate the descriptor (n >= 1, 0 <= src <= n, dx > 0, Q >= 0, sigma0 > 0,
- * n_sub in 1..64, K >= 0, known enums), build the rate table (TABLE mode), upload
+ * n_sub in 1..64, K > 0 (inf disables), known enums), build the rate table (TABLE mode), upload
  * the constants and bind the fields.  Allocates the grid's small private device
  * buffers (reduction partials, timestep scalars, tile schedule, table).
  * Returns PI_EINVAL, PI_ENOMEM or PI_EDEVICE on failure (nothing is leaked). */
@@ -145,6 +148,36 @@ pi_status pi_grid_create(const pi_grid_desc* desc, const pi_fields* fields, pi_g
 /* Free the grid's private buffers (synchronises the device first).  The
  * caller's fields are not touched.  NULL is accepted. */
 pi_status pi_grid_destroy(pi_grid* grid);
+
+/* Memory a grid of this description needs (host-only, no device call):
+ * *field_bytes = bytes of the caller-owned fields pi_fields points to, i.e.
+ *   nx*ny*nz*w * (3 + 2 m + (PI_T_EVOLVE ? 2 : 0)) with w = 8 (PI_FP64) or 4
+ *   and m sources (n_H, x, x_half, m arrays each of tau and tau_half, E and
+ *   E_half; nH_half not counted);
+ * *work_bytes = device bytes pi_grid_create allocates privately (clock,
+ *   reduction partials, tile schedules of every tile edge, launch tables,
+ *   work counters, the mixed-precision re-solve list of one entry per cell,
+ *   the rate table), before the allocator's rounding.
+ * Either pointer may be NULL.  PI_EINVAL for an invalid descriptor.  (The
+ * paper states the problem's inputs per cell, Sect. 2.1; this sizes them.) */
+pi_status pi_grid_required_bytes(const pi_grid_desc* desc, size_t* field_bytes,
+                                 size_t* work_bytes);
+
+/* Checkpoint of a grid's state (SYNCHRONISES the stream): a header with the
+ * layout and the clock (t, dt, t_end, last dt, step count), then n_H, x, E
+ * (PI_T_EVOLVE only) and the columns of every source, each nx*ny*nz values of
+ * the grid's word size in the field layout.  The half-step buffers are not
+ * saved (a step does not read them before writing them).  *needed (if not
+ * NULL) receives the size; host_buf NULL is a size query.  host_buf is host
+ * memory owned by the caller, at least *needed bytes (PI_EINVAL otherwise).
+ * A grid loaded from it continues bit for bit as the saved grid would have. */
+pi_status pi_grid_save(pi_grid* grid, void* host_buf, size_t bytes, size_t* needed,
+                       void* stream);
+/* Loads a checkpoint written by pi_grid_save (or pi_checkpoint) into the
+ * grid's fields and clock (SYNCHRONISES the stream).  PI_EINVAL unless the
+ * checkpoint has the grid's layout: cells per axis, precision, thermal mode
+ * and number of sources; the other parameters are the loading grid's own. */
+pi_status pi_grid_load(pi_grid* grid, const void* host_buf, size_t bytes, void* stream);
 
 /* Short-characteristics raytrace (Sect. 2; Sect. 5): columns tau of the
  * neutral fractions of state `state` (PI_BUF_N: x, PI_BUF_HALF: x_half) into
@@ -172,7 +205,10 @@ pi_status pi_timestep(pi_grid* grid, double t_end, void* stream);
  * over dt from (x, E) on tau_half in place; raytrace of the new state into
  * tau; t += dt.  Requires tau to hold the columns of (x, E) on entry (call
  * pi_raytrace(grid, PI_BUF_N, PI_BUF_N, s) once after loading a state).  Does
- * nothing useful once t >= t_end (dt = 0). */
+ * nothing useful once t >= t_end (dt = 0).  The step's kernels are replayed
+ * from a HIP graph the grid captures on its first step (the clock carries
+ * t_end into it); on a stream that is itself being captured they are launched
+ * directly, so they become part of the caller's graph. */
 pi_status pi_step_o2(pi_grid* grid, double t_end, void* stream);
 
 /* One step of algorithm 2 (Sect. 2.2), the first-order variant: timestep,
@@ -288,6 +324,12 @@ typedef struct {
     const double* x0;         /* host initial neutral fraction, or NULL: 1       */
     double        T0;         /* initial temperature [K] (T evolving)            */
     double        t_end;      /* time to advance to from t = 0 [s]               */
+    /* Optional (NULL: start from nH, x0, T0 at t = 0): a checkpoint written by
+     * pi_grid_save or pi_checkpoint for this desc's layout (copied).  The
+     * request then resumes from its state and clock (density included; nH,
+     * x0 and T0 are ignored) and runs to t_end. */
+    const void*   checkpoint;
+    size_t        checkpoint_bytes;
 } pi_request;
 
 typedef struct {
@@ -299,7 +341,10 @@ typedef struct {
 } pi_result;
 
 /* Starts the worker thread on the current device.  PI_ENOMEM if the arena
- * cannot be allocated. */
+ * cannot be allocated.  A running request whose clock does not advance over a
+ * whole tick before its t_end fails with PI_EDEVICE.  Finished requests' x and
+ * E are copied to pinned host memory on a second stream while the other
+ * grids go on; their arena space is reused once the copy is complete. */
 pi_status pi_server_create(const pi_server_desc* desc, pi_server** out);
 /* Validates and copies the request (host arrays); returns a ticket.
  * PI_EREJECTED if its fields can never fit in the arena. */
@@ -313,6 +358,14 @@ pi_status pi_poll(pi_server* server, uint64_t ticket, pi_result* out, double* x_
 /* Asks for a ticket to be dropped (queued: at once; running: at the next tick).
  * Its poll then returns PI_ECANCELLED. */
 pi_status pi_cancel(pi_server* server, uint64_t ticket);
+/* Checkpoint of a running request (the pi_grid_save format), taken by the
+ * worker at the end of its current tick of steps; the call BLOCKS until then.
+ * host_buf NULL is a size query (*needed).  Returns PI_PENDING if the request
+ * is still queued (nothing to save yet), PI_EINVAL if it has finished (poll
+ * it) or the buffer is too small, PI_EDEVICE if the tick failed.  Submitting
+ * the checkpoint (pi_request.checkpoint) continues the request bit for bit. */
+pi_status pi_checkpoint(pi_server* server, uint64_t ticket, void* host_buf, size_t bytes,
+                        size_t* needed);
 /* out[8]: completed requests, cell-updates done, busy seconds of the worker,
  * batch steps, running grids, queued requests, arena bytes in use, batch
  * rebuilds. */
@@ -342,7 +395,7 @@ const char* pi_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns the
  * value it was built with. */
-#define PI_ABI_VERSION 108
+#define PI_ABI_VERSION 109
 int pi_abi_version(void);
 
 #ifdef __cplusplus

@@ -42,6 +42,7 @@ ABI_SYMBOLS = (
     "pi_batch_get_raytrace_tile",
     "pi_step_a1",
     "pi_batch_step_a1",
+    "pi_grid_required_bytes", "pi_grid_save", "pi_grid_load", "pi_checkpoint",
 )
 
 
@@ -91,7 +92,8 @@ class ServerDesc(C.Structure):
 
 class Request(C.Structure):
     _fields_ = [("desc", GridDesc), ("nH", C.POINTER(C.c_double)), ("x0", C.POINTER(C.c_double)),
-                ("T0", C.c_double), ("t_end", C.c_double)]
+                ("T0", C.c_double), ("t_end", C.c_double), ("checkpoint", C.c_void_p),
+                ("checkpoint_bytes", C.c_size_t)]
 
 
 class Result(C.Structure):
@@ -147,6 +149,11 @@ def lib() -> C.CDLL:
         L.pi_get_raytrace_tile.argtypes = [vp, ip]
         L.pi_batch_set_raytrace_tile.argtypes = [vp, i32]
         L.pi_batch_get_raytrace_tile.argtypes = [vp, ip]
+        szp = C.POINTER(C.c_size_t)
+        L.pi_grid_required_bytes.argtypes = [C.POINTER(GridDesc), szp, szp]
+        L.pi_grid_save.argtypes = [vp, vp, C.c_size_t, szp, vp]
+        L.pi_grid_load.argtypes = [vp, vp, C.c_size_t, vp]
+        L.pi_checkpoint.argtypes = [vp, C.c_uint64, vp, C.c_size_t, szp]
         L.pi_last_error.restype = C.c_char_p
         L.pi_abi_version.restype = C.c_int
         for name in ABI_SYMBOLS:
@@ -167,6 +174,14 @@ def table_build(T_bb: float, Q: float):
     out = np.zeros(5 * PI_NTAB)
     check(lib().pi_table_build(T_bb, Q, out.ctypes.data_as(C.POINTER(C.c_double))))
     return out.reshape(5, PI_NTAB)
+
+
+def required_bytes(spec, precision: Optional[str] = None):
+    """pi_grid_required_bytes: (caller-owned field bytes, library device bytes)."""
+    d = desc_from_spec(spec, precision)
+    fb, wb = C.c_size_t(), C.c_size_t()
+    check(lib().pi_grid_required_bytes(C.byref(d), C.byref(fb), C.byref(wb)))
+    return fb.value, wb.value
 
 
 def desc_from_spec(spec, precision: Optional[str] = None, sigma0: float = 6.3e-18) -> GridDesc:
@@ -340,19 +355,37 @@ class Grid:
         return {"accepted": out[0], "rejected": out[1], "fallbacks": out[2], "newton": out[3],
                 "resolved_fp64": out[4]}
 
+    def save(self) -> bytes:
+        """pi_grid_save: the checkpoint of the grid's state and clock."""
+        need = C.c_size_t()
+        check(lib().pi_grid_save(self._h, None, 0, C.byref(need), self._stream()))
+        buf = C.create_string_buffer(need.value)
+        check(lib().pi_grid_save(self._h, buf, need.value, None, self._stream()))
+        return buf.raw
+
+    def restore(self, ckpt: bytes):
+        """pi_grid_load: state, columns and clock from a checkpoint."""
+        buf = C.create_string_buffer(bytes(ckpt), len(ckpt))
+        check(lib().pi_grid_load(self._h, buf, len(ckpt), self._stream()))
+
     def run(self, t_end: float, order: int = 2, max_steps: int = 10**8, check_every: int = 64):
         """Step until t_end (order 2: algorithm 3; order 1: algorithm 2).
-        Returns the number of steps taken."""
+        Returns the number of steps taken; raises PiError if a burst of steps
+        leaves the clock where it was before t_end."""
         t0, n0, _ = self.state()
-        taken = 0
+        taken, t = 0, t0
         while taken < max_steps:
             burst = min(check_every, max_steps - taken)
             for _ in range(burst):
                 (self.step_o2 if order == 2 else self.step_o1)(t_end)
+            t_prev = t
             t, n, _ = self.state()
-            taken = n - n0
             if t >= t_end:
+                taken = n - n0
                 break
+            if n - n0 == taken or t == t_prev:
+                raise PiError(PI_EDEVICE, "no progress: the timestep of eq. (4) is zero")
+            taken = n - n0
         return taken
 
     def close(self):
@@ -499,19 +532,39 @@ class Server:
         self._h = h
         self._specs = {}
 
-    def submit(self, spec, nH, x0=None, T0: Optional[float] = None, t_end: Optional[float] = None) -> int:
+    def submit(self, spec, nH=None, x0=None, T0: Optional[float] = None,
+               t_end: Optional[float] = None, checkpoint: Optional[bytes] = None) -> int:
+        """Queue a request; ``checkpoint`` (from Grid.save or Server.checkpoint)
+        resumes a saved state instead of starting from nH, x0, T0."""
         import numpy as np
-        nH = np.ascontiguousarray(nH, dtype=np.float64).reshape(-1)
-        x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64).reshape(-1)
         dp = C.POINTER(C.c_double)
-        r = Request(desc_from_spec(spec, self.precision), nH.ctypes.data_as(dp),
-                    None if x0a is None else x0a.ctypes.data_as(dp),
+        nHp = x0p = None
+        if checkpoint is None:
+            nH = np.ascontiguousarray(nH, dtype=np.float64).reshape(-1)
+            nHp = nH.ctypes.data_as(dp)
+            x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64).reshape(-1)
+            x0p = None if x0a is None else x0a.ctypes.data_as(dp)
+        ck = None if checkpoint is None else C.create_string_buffer(bytes(checkpoint), len(checkpoint))
+        r = Request(desc_from_spec(spec, self.precision), nHp, x0p,
                     float(T0 if T0 is not None else spec.T0),
-                    float(t_end if t_end is not None else spec.t_end))
+                    float(t_end if t_end is not None else spec.t_end),
+                    C.cast(ck, C.c_void_p) if ck is not None else None,
+                    0 if checkpoint is None else len(checkpoint))
         t = C.c_uint64()
         check(lib().pi_submit(self._h, C.byref(r), C.byref(t)))
         self._specs[t.value] = spec
         return t.value
+
+    def checkpoint(self, ticket: int):
+        """pi_checkpoint of a running request: bytes, or None while it is queued."""
+        need = C.c_size_t()
+        check(lib().pi_checkpoint(self._h, ticket, None, 0, C.byref(need)))
+        buf = C.create_string_buffer(need.value)
+        st = lib().pi_checkpoint(self._h, ticket, buf, need.value, None)
+        if st == PI_PENDING:
+            return None
+        check(st)
+        return buf.raw
 
     def poll(self, ticket: int):
         """(status, info, x, T): x and T are arrays of the grid's shape once

@@ -116,4 +116,25 @@ pi_status engine_write_states(Engine& e, const std::vector<DevState>& in, hipStr
 pi_status engine_diagnostics(Engine& e, std::vector<double>& out, hipStream_t s);
 pi_status engine_work(Engine& e, int64_t* out, int reset, hipStream_t s);
 
+// Device bytes the library allocates for one grid created alone
+// (pi_grid_required_bytes); also the bytes of its caller-owned fields.
+size_t grid_private_bytes(const pi_grid_desc& d);
+size_t grid_field_bytes(const pi_grid_desc& d);
+
+// Checkpoint of one grid's state (pi_grid_save / pi_grid_load, and served
+// requests): a header with the layout and the clock, then n_H, x, E (T
+// evolving only) and the columns of every source, each nx*ny*nz values of
+// the grid's word size in the field layout.
+size_t checkpoint_bytes(const pi_grid_desc& d);
+size_t checkpoint_header_bytes();
+// Writes the checkpoint of h into buf (bytes >= checkpoint_bytes); the fields
+// are read on s, which is synchronised.
+pi_status grid_save(const GridHost& h, void* buf, size_t bytes, hipStream_t s);
+// Checks that buf holds a checkpoint of h's layout (cells, precision,
+// thermal mode, sources) and writes it into h's fields and clock on s
+// (synchronised).
+pi_status grid_load(GridHost& h, const void* buf, size_t bytes, hipStream_t s);
+// Layout check of a checkpoint against a descriptor, without loading it.
+pi_status checkpoint_check(const pi_grid_desc& d, const void* buf, size_t bytes);
+
 }  // namespace pi

@@ -754,4 +754,169 @@ pi_status engine_work(Engine& e, int64_t* out, int reset, hipStream_t s)
     return PI_OK;
 }
 
+// ------------------------------------------------------------ memory sizes
+namespace {
+size_t word_of(const pi_grid_desc& d) { return d.precision == PI_FP64 ? 8 : 4; }
+int64_t cells_of(const pi_grid_desc& d) { return (int64_t)d.n[0] * d.n[1] * d.n[2]; }
+
+// tiles of every source's octants for tile edge T (as grid_host_init lists them)
+int64_t tile_count(const pi_grid_desc& d, int T)
+{
+    if (d.source == PI_SRC_PLANE) return 0;
+    int64_t k = 0;
+    for (int s = 0; s < nsources(d); ++s) {
+        const int32_t* v = source_vertex(d, s);
+        for (int o = 0; o < 8; ++o) {
+            int64_t c = 1;
+            for (int a = 0; a < 3; ++a) {
+                const int ext = ((o >> a) & 1) ? d.n[a] - v[a] : v[a];
+                c *= ext > 0 ? (ext + T - 1) / T : 0;
+            }
+            k += c;
+        }
+    }
+    return k;
+}
+}  // namespace
+
+size_t grid_field_bytes(const pi_grid_desc& d)
+{
+    const size_t f = (size_t)cells_of(d) * word_of(d);
+    const size_t ncol = (size_t)nsources(d);
+    const size_t evolve = d.thermal == PI_T_EVOLVE ? 2 : 0;
+    // nH, x, x_half, E, E_half; tau and tau_half one array per source
+    return f * (3 + evolve + 2 * ncol);
+}
+
+size_t grid_private_bytes(const pi_grid_desc& d)
+{
+    const int64_t n = cells_of(d);
+    const int64_t nblk = std::min<int64_t>((n + DT_BLOCK - 1) / DT_BLOCK, DT_MAX_BLOCKS);
+    size_t b = sizeof(DevState) + sizeof(double) * NPART * (size_t)nblk;
+    const size_t gd = d.precision == PI_FP64 ? sizeof(GridDev<double>) : sizeof(GridDev<float>);
+    b += gd * (size_t)nsources(d);                 // grid table (one entry per source)
+    b += sizeof(int) * 3 * 2;                      // launch prefix tables of one grid
+    for (int w = 0; w < NSWEEP; ++w) b += sizeof(int4) * (size_t)tile_count(d, SWEEP_TILES[w]);
+    b += sizeof(unsigned long long) * WORK_COUNTERS * WORK_SLOTS;
+    if (d.precision == PI_MIXED) b += 2 * sizeof(unsigned int) + sizeof(long long) * (size_t)n;
+    if (d.spectrum == PI_SPEC_TABLE) b += sizeof(DevTable<double>) + sizeof(DevTable<float>);
+    return b;
+}
+
+// -------------------------------------------------------------- checkpoints
+namespace {
+constexpr uint64_t CKPT_MAGIC = 0x31544b4350434950ull;   // "PICPCKT1"
+struct CkptHeader {
+    uint64_t magic;
+    int32_t precision, thermal, nsrc, word;
+    int32_t n[3], pad;
+    int64_t ncell, nsteps;
+    double t, dt, t_end, last_dt;
+    int64_t payload;   // bytes after the header
+};
+
+int64_t ckpt_arrays(const pi_grid_desc& d)
+{
+    return 2 + (d.thermal == PI_T_EVOLVE ? 1 : 0) + nsources(d);
+}
+
+CkptHeader header_of(const pi_grid_desc& d)
+{
+    CkptHeader h{};
+    h.magic = CKPT_MAGIC;
+    h.precision = d.precision;
+    h.thermal = d.thermal;
+    h.nsrc = nsources(d);
+    h.word = (int32_t)word_of(d);
+    for (int a = 0; a < 3; ++a) h.n[a] = d.n[a];
+    h.ncell = cells_of(d);
+    h.payload = ckpt_arrays(d) * h.ncell * h.word;
+    return h;
+}
+}  // namespace
+
+size_t checkpoint_header_bytes() { return sizeof(CkptHeader); }
+
+size_t checkpoint_bytes(const pi_grid_desc& d)
+{
+    return sizeof(CkptHeader) + (size_t)header_of(d).payload;
+}
+
+pi_status checkpoint_check(const pi_grid_desc& d, const void* buf, size_t bytes)
+{
+    if (!buf || bytes < sizeof(CkptHeader)) return fail(PI_EINVAL, "checkpoint too short");
+    CkptHeader h;
+    std::memcpy(&h, buf, sizeof(h));
+    const CkptHeader w = header_of(d);
+    if (h.magic != CKPT_MAGIC) return fail(PI_EINVAL, "not a checkpoint of this library");
+    if (h.precision != w.precision || h.thermal != w.thermal || h.nsrc != w.nsrc ||
+        h.word != w.word || h.n[0] != w.n[0] || h.n[1] != w.n[1] || h.n[2] != w.n[2])
+        return fail(PI_EINVAL, "checkpoint layout (cells, precision, thermal mode or sources) "
+                               "differs from the grid's");
+    if (h.payload != w.payload || bytes < sizeof(CkptHeader) + (size_t)h.payload)
+        return fail(PI_EINVAL, "checkpoint truncated");
+    if (!std::isfinite(h.t) || !std::isfinite(h.t_end) || h.nsteps < 0)
+        return fail(PI_EINVAL, "checkpoint clock is not valid");
+    return PI_OK;
+}
+
+pi_status grid_save(const GridHost& g, void* buf, size_t bytes, hipStream_t s)
+{
+    const pi_grid_desc& d = g.d;
+    if (!buf || bytes < checkpoint_bytes(d)) return fail(PI_EINVAL, "checkpoint buffer too small");
+    CkptHeader h = header_of(d);
+    DevState st{};
+    HIP_OR(hipMemcpyAsync(&st, g.st, sizeof(st), hipMemcpyDeviceToHost, s), "clock read");
+    char* p = static_cast<char*>(buf) + sizeof(CkptHeader);
+    const size_t fb = (size_t)h.ncell * h.word;
+    HIP_OR(hipMemcpyAsync(p, g.f.nH, fb, hipMemcpyDeviceToHost, s), "checkpoint read");
+    p += fb;
+    HIP_OR(hipMemcpyAsync(p, g.f.x, fb, hipMemcpyDeviceToHost, s), "checkpoint read");
+    p += fb;
+    if (d.thermal == PI_T_EVOLVE) {
+        HIP_OR(hipMemcpyAsync(p, g.f.E, fb, hipMemcpyDeviceToHost, s), "checkpoint read");
+        p += fb;
+    }
+    HIP_OR(hipMemcpyAsync(p, g.f.tau, fb * h.nsrc, hipMemcpyDeviceToHost, s), "checkpoint read");
+    HIP_OR(hipStreamSynchronize(s), "checkpoint sync");
+    h.t = st.t;
+    h.dt = st.dt;
+    h.t_end = st.t_end;
+    h.last_dt = st.last_dt;
+    h.nsteps = st.nsteps;
+    std::memcpy(buf, &h, sizeof(h));
+    return PI_OK;
+}
+
+pi_status grid_load(GridHost& g, const void* buf, size_t bytes, hipStream_t s)
+{
+    const pi_grid_desc& d = g.d;
+    pi_status r = checkpoint_check(d, buf, bytes);
+    if (r != PI_OK) return r;
+    CkptHeader h;
+    std::memcpy(&h, buf, sizeof(h));
+    const char* p = static_cast<const char*>(buf) + sizeof(CkptHeader);
+    const size_t fb = (size_t)h.ncell * h.word;
+    HIP_OR(hipMemcpyAsync(g.f.nH, p, fb, hipMemcpyHostToDevice, s), "checkpoint write");
+    p += fb;
+    HIP_OR(hipMemcpyAsync(g.f.x, p, fb, hipMemcpyHostToDevice, s), "checkpoint write");
+    p += fb;
+    if (d.thermal == PI_T_EVOLVE) {
+        HIP_OR(hipMemcpyAsync(g.f.E, p, fb, hipMemcpyHostToDevice, s), "checkpoint write");
+        p += fb;
+    }
+    HIP_OR(hipMemcpyAsync(g.f.tau, p, fb * h.nsrc, hipMemcpyHostToDevice, s), "checkpoint write");
+    DevState st{};
+    HIP_OR(hipMemcpyAsync(&st, g.st, sizeof(st), hipMemcpyDeviceToHost, s), "clock read");
+    HIP_OR(hipStreamSynchronize(s), "checkpoint sync");
+    st.t = h.t;
+    st.dt = h.dt;
+    st.t_end = h.t_end;
+    st.last_dt = h.last_dt;
+    st.nsteps = h.nsteps;
+    HIP_OR(hipMemcpyAsync(g.st, &st, sizeof(st), hipMemcpyHostToDevice, s), "clock write");
+    HIP_OR(hipStreamSynchronize(s), "checkpoint sync");
+    return PI_OK;
+}
+
 }  // namespace pi

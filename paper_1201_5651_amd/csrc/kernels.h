@@ -153,5 +153,8 @@ template <typename R>
 hipError_t launch_advance(const GridDev<R>* grids, int ngrids, hipStream_t s);
 template <typename R>
 hipError_t launch_energy(int64_t n, const R* nH, const R* x, R* E, double T0, hipStream_t s);
+// Sets the t_end of a grid clock (a step replayed from a captured graph reads
+// it there).
+hipError_t launch_set_t_end(DevState* st, double t_end, hipStream_t s);
 
 }  // namespace pi

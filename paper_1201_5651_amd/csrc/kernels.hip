@@ -366,9 +366,11 @@ __device__ __forceinline__ void chem_cell(const Params<C>& p, const Sources<C>& 
     }
 }
 
-// Micro-physics of every cell of every grid.  With mixed precision, a cell
-// whose float integration took a precision-sensitive decision is not written;
-// it is appended to the batch's re-solve list for the double pass.
+// Micro-physics of every cell of every grid.  With mixed precision, an
+// ionisation-front cell (front_cell of its starting neutral fraction) is not
+// integrated in float, and a cell whose float integration took a
+// precision-sensitive decision is not written; both are appended to the
+// batch's re-solve list for the double pass.
 template <typename R, int MS>
 __global__ void __launch_bounds__(CHEM_BLOCK)
 __attribute__((amdgpu_waves_per_eu(MS > 1 ? ChemWaves<double>::value : ChemWaves<R>::value)))
@@ -399,9 +401,13 @@ k_chem(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int 
     if (inside) {
         const double hd = dev_dt ? hscale * G.st->dt : hscale;
         R x, E;
-        chem_cell<R, R, MS>(pl, G.src, q, i, j, k, G.nH, G.x[from], G.E[from], G.tau[tau_buf], hd,
-                            x, E, w);
-        flag = mixed && w.close > 0;
+        // mixed: an ionisation-front cell goes straight to the double pass
+        flag = mixed && front_cell(G.x[from][q]);
+        if (!flag) {
+            chem_cell<R, R, MS>(pl, G.src, q, i, j, k, G.nH, G.x[from], G.E[from],
+                                G.tau[tau_buf], hd, x, E, w);
+            flag = mixed && w.close > 0;
+        }
         if (!flag) {
             G.x[to][q] = x;
             if (G.E[to]) G.E[to][q] = E;
@@ -474,9 +480,10 @@ k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int 
 // time-averaged optical depth per cell length, kbar = tau_avg / ell, in place
 // of sigma0 n_H x dx.  The state n is advanced in place; the half-step buffers
 // receive the pass's time-averaged entering columns (tau[1]) and kbar (x[1]),
-// which the tiles of later stages read as their halo.  With mixed precision a
-// cell whose float integration took a precision-sensitive decision is
-// integrated again in double at once (later cells depend on it).
+// which the tiles of later stages read as their halo.  With mixed precision an
+// ionisation-front cell is integrated in double, and a cell whose float
+// integration took a precision-sensitive decision is integrated again in
+// double at once (later cells depend on it).
 template <typename R>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ChemWaves<R>::value)))
 k_sweep_a1(const GridDev<R>* __restrict__ grids, const int4* __restrict__ tiles, int first,
@@ -573,9 +580,13 @@ k_sweep_a1(const GridDev<R>* __restrict__ grids, const int4* __restrict__ tiles,
                 xo = Eo = tb = R(__builtin_nan(""));
             } else {
                 Work wc{};
-                const Env<R> env = make_env(p, n, cg, tin);
-                micro_t<R, true>(p, env, R(hd), xo, Eo, wc, &tb);
-                if (mixed && wc.close > 0) {
+                // mixed: an ionisation-front cell is integrated in double only
+                const bool front = mixed && front_cell(x);
+                if (!front) {
+                    const Env<R> env = make_env(p, n, cg, tin);
+                    micro_t<R, true>(p, env, R(hd), xo, Eo, wc, &tb);
+                }
+                if (front || (mixed && wc.close > 0)) {
                     // precision-sensitive: the same cell in double, from the same inputs
                     const Params<double>& pd = G.pd;
                     const CellGeom<double> cgd = cell_geom(pd, gi, gj, gk);
@@ -787,7 +798,18 @@ k_energy(int64_t n, const R* __restrict__ nH, const R* __restrict__ x, R* __rest
     if (q < n) E[q] = R(1.5 * KB * T0) * nH[q] * (R(2) - x[q]);
 }
 
+__global__ void k_set_t_end(DevState* st, double t_end)
+{
+    if (threadIdx.x == 0) st->t_end = t_end;
+}
+
 // ---------------------------------------------------------------- launchers
+hipError_t launch_set_t_end(DevState* st, double t_end, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_t_end, dim3(1), dim3(64), 0, s, st, t_end);
+    return hipGetLastError();
+}
+
 template <typename R, int TT>
 void launch_sweep_t(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles, int first,
                     int count, hipStream_t s)

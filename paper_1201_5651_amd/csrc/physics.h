@@ -42,6 +42,15 @@ constexpr double REJ_E = 3.0;     // ... or changes E by more than this factor
 // other way under a change of precision; the mixed-precision path re-solves
 // such cells in double.
 constexpr double MIX_MARGIN = 1e-3;
+// Ionisation-front cells of the mixed-precision path: a cell whose neutral
+// fraction at the start of the micro-integration lies in [FRONT_X_LO,
+// FRONT_X_HI] is integrated in double only (the float pass skips it).
+constexpr double FRONT_X_LO = 1e-3;
+constexpr double FRONT_X_HI = 0.999;
+template <typename R> PI_HD __forceinline__ bool front_cell(R x)
+{
+    return x >= R(FRONT_X_LO) && x <= R(FRONT_X_HI);
+}
 
 template <typename R> struct Tol;
 template <> struct Tol<double> {

@@ -53,8 +53,10 @@ pi_status validate_desc(const pi_grid_desc* d)
     if (!(d->alpha_B >= 0)) return fail(PI_EINVAL, "alpha_B must be >= 0");
     if (d->weights != PI_W_GEOMETRIC && d->weights != PI_W_MELLEMA) return fail(PI_EINVAL, "weights");
     if (d->n_sub < 1 || d->n_sub > 64) return fail(PI_EINVAL, "n_sub must be in 1..64");
+    // a zero factor would make eq. (4) give dt = 0 and the clock could never
+    // advance
     for (int i = 0; i < 4; ++i)
-        if (!(d->K[i] >= 0)) return fail(PI_EINVAL, "K factors must be >= 0 (inf disables)");
+        if (!(d->K[i] > 0)) return fail(PI_EINVAL, "K factors must be > 0 (inf disables)");
     if (d->precision != PI_FP64 && d->precision != PI_FP32 && d->precision != PI_MIXED)
         return fail(PI_EINVAL, "precision");
     if (d->nsrc < 0 || d->nsrc > PI_MAX_SRC) return fail(PI_EINVAL, "nsrc must be in 0..PI_MAX_SRC");
@@ -233,7 +235,15 @@ pi_status pi_step_o2(pi_grid* g, double t_end, void* stream)
 {
     if (!g) return fail(PI_EINVAL, "null grid");
     if (!std::isfinite(t_end)) return fail(PI_EINVAL, "t_end must be finite");
-    return engine_step(g->e, t_end, 2, static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // Inside a caller's capture the kernels are launched directly (they become
+    // nodes of the caller's graph); otherwise the step is replayed from the
+    // grid's own captured graph, which reads t_end from the clock.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return fail(PI_EDEVICE, "capture query");
+    if (cs != hipStreamCaptureStatusNone) return engine_step(g->e, t_end, 2, s);
+    if (launch_set_t_end(g->h.st, t_end, s) != hipSuccess) return fail(PI_EDEVICE, "clock launch");
+    return engine_step_graph(g->e, s);
 }
 
 pi_status pi_step_o1(pi_grid* g, double t_end, void* stream)
@@ -282,6 +292,32 @@ pi_status pi_grid_state(pi_grid* g, double* t, int64_t* nsteps, double* last_dt,
     if (nsteps) *nsteps = st[0].nsteps;
     if (last_dt) *last_dt = st[0].last_dt;
     return PI_OK;
+}
+
+pi_status pi_grid_required_bytes(const pi_grid_desc* desc, size_t* field_bytes,
+                                 size_t* work_bytes)
+{
+    pi_status v = validate_desc(desc);
+    if (v != PI_OK) return v;
+    if (field_bytes) *field_bytes = grid_field_bytes(*desc);
+    if (work_bytes) *work_bytes = grid_private_bytes(*desc);
+    return PI_OK;
+}
+
+pi_status pi_grid_save(pi_grid* g, void* host_buf, size_t bytes, size_t* needed, void* stream)
+{
+    if (!g) return fail(PI_EINVAL, "null grid");
+    const size_t need = checkpoint_bytes(g->h.d);
+    if (needed) *needed = need;
+    if (!host_buf) return PI_OK;   // size query
+    if (bytes < need) return fail(PI_EINVAL, "checkpoint buffer too small");
+    return grid_save(g->h, host_buf, bytes, static_cast<hipStream_t>(stream));
+}
+
+pi_status pi_grid_load(pi_grid* g, const void* host_buf, size_t bytes, void* stream)
+{
+    if (!g || !host_buf) return fail(PI_EINVAL, "null argument");
+    return grid_load(g->h, host_buf, bytes, static_cast<hipStream_t>(stream));
 }
 
 pi_status pi_work_counters(pi_grid* g, int64_t* out, int reset, void* stream)

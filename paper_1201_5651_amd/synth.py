@@ -141,14 +141,16 @@ def cfg2(n: int = 128, **kw) -> GridSpec:
     return s.with_(**kw) if kw else s
 
 
-def cfg3(n: int = 256, **kw) -> GridSpec:
+def cfg3(n: int = 256, box_cells: int = 256, **kw) -> GridSpec:
     """256^3 clumpy medium: lognormal density (sigma_ln 1, spectrum k^-11/3,
     seed 1201), mean n_H = 5, central 1e5 K blackbody source of 5e48 /s, cfg2
-    physics, box 2.4 R_S(mean), FP32 bulk with FP64 front cells."""
+    physics, box 2.4 R_S(mean), FP32 bulk with FP64 front cells.  The cell
+    size is that of box_cells cells across 2.4 R_S: n < box_cells gives the
+    central part of the same medium, box_cells = n the whole box coarser."""
     Q, nH = 5e48, 5.0
     RS = stromgren_radius(Q, nH)
     tr = recombination_time(nH)
-    dx = 2.4 * RS / 256
+    dx = 2.4 * RS / box_cells
     s = GridSpec(name="cfg3", n=(n, n, n), src=(n // 2, n // 2, n // 2), dx=dx, Q=Q, nH_mean=nH,
                  density="lognormal", sigma_ln=1.0, seed=1201, spectrum="table",
                  thermal="evolve", recomb="power", collisional=True, t_end=0.3 * tr,
@@ -255,6 +257,22 @@ def poisson_requests(count: int, rate: float = 20.0, seed: int = 5651, nmin: int
                                 thermal="evolve", recomb="power", collisional=True,
                                 t_end=2.0 * tr, t_rec=tr, precision=precision)))
     return out
+
+
+def ionised_sphere(spec: GridSpec, radius_cells: float, width_cells: float = 1.5,
+                   x_in: float = 1e-4, T_in: float = 1e4):
+    """A partly ionised start: neutral fraction x_in inside a sphere of the
+    given radius (in cells) around the source vertex, 1 outside, joined by a
+    tanh profile of the given width; temperature T_in inside, spec.T0
+    outside, on the same profile.  Returns (x, T) in shape order.  Input
+    generation only (a profile, not a solution of the method)."""
+    k, j, i = np.meshgrid(*(np.arange(m) + 0.5 for m in spec.shape), indexing="ij")
+    sx, sy, sz = spec.src
+    r = np.sqrt((i - sx) ** 2 + (j - sy) ** 2 + (k - sz) ** 2)
+    inside = 0.5 * (1.0 - np.tanh((r - radius_cells) / width_cells))
+    x = x_in + (1.0 - x_in) * (1.0 - inside)
+    T = spec.T0 + (T_in - spec.T0) * inside
+    return x, T
 
 
 def random_cell_states(count: int, seed: int, thermal: bool = True):

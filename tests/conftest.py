@@ -4,6 +4,10 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# The oracle's OpenMP build (bitwise the plain build, a pinned test checks it)
+# keeps the full-size comparisons short on a many-core host.
+os.environ.setdefault("ORACLE_OPENMP", "1")
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 

@@ -75,6 +75,10 @@ def test_descriptor_validation_rejects_bad_input():
     d = binding.desc_from_spec(spec)
     d.K[3] = -1.0
     cases.append(d)
+    # a zero factor of eq. (4) would give dt = 0: the clock could never advance
+    d = binding.desc_from_spec(spec)
+    d.K[3] = 0.0
+    cases.append(d)
     d = binding.desc_from_spec(spec)
     d.source = 2
     cases.append(d)
@@ -109,3 +113,44 @@ def test_library_table_matches_oracle_table(oracle_lib):
         b = oracle.table_build(T_bb, Q)
         np.testing.assert_allclose(a[0], b[0], rtol=1e-14)
         np.testing.assert_allclose(a[1:], b[1:], rtol=1e-10, atol=0)
+
+
+def test_request_struct_matches_header():
+    header = open(os.path.join(ROOT, "include", "pi.h")).read()
+    body = header.split("} pi_request;")[0].rsplit("typedef struct {", 1)[1]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"\b(\w+)\s*;", body)
+    assert names == [n for n, _ in binding.Request._fields_]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "mixed"])
+@pytest.mark.parametrize("kind", ["cfg1", "cfg2", "sources"])
+def test_required_bytes(precision, kind):
+    """pi_grid_required_bytes: the caller's fields are the arrays the Python
+    layer allocates for the grid (counted here from numpy shapes, not from the
+    library's formula); the library's own device bytes grow with the cells and
+    include the re-solve list (one 8-byte entry per cell) only in mixed
+    precision."""
+    spec = {"cfg1": synth.cfg1(n=(17, 13, 11), src=(5, 0, 11)),
+            "cfg2": synth.cfg2(n=24),
+            "sources": synth.cfg2(n=20).with_(more_sources=(((3, 4, 5), 1e47), ((20, 0, 7), 2e47)))}[kind]
+    fb, wb = binding.required_bytes(spec, precision)
+    w = 8 if precision == "fp64" else 4
+    ns = 1 + len(spec.more_sources)
+    arrays = [spec.shape] * 3 + [(ns,) + spec.shape] * 2    # nH, x, x_half, tau, tau_half
+    if spec.thermal == "evolve":
+        arrays += [spec.shape] * 2                            # E, E_half
+    assert fb == sum(int(np.prod(a)) for a in arrays) * w
+    assert wb > 0
+    big = spec.with_(n=tuple(2 * v for v in spec.n), src=tuple(2 * v for v in spec.src),
+                     more_sources=tuple(((2 * a, 2 * b, 2 * c), q) for (a, b, c), q in spec.more_sources))
+    assert binding.required_bytes(big, precision)[1] > wb
+    if precision == "mixed":
+        assert wb - binding.required_bytes(spec, "fp32")[1] == 8 * spec.ncells + 8
+
+
+def test_required_bytes_rejects_bad_descriptor():
+    d = binding.desc_from_spec(synth.cfg1())
+    d.dx = -1.0
+    a, b = C.c_size_t(), C.c_size_t()
+    assert binding.lib().pi_grid_required_bytes(C.byref(d), C.byref(a), C.byref(b)) == binding.PI_EINVAL

@@ -1,15 +1,17 @@
 """Parity at the benchmark's full size, in the launch configuration bench.py
-times: the 256^3 clumpy medium in mixed precision, advanced on the GPU to a
-state with an ionisation front, then checked against the oracle on the same
-(float) state -- the raytrace on every cell, the timestep minimum over every
-cell, and one micro-physics update on a sample of cells the oracle integrates
-one by one."""
+times: the 256^3 clumpy medium in mixed precision, from a synthetic partly
+ionised start (an ionised sphere of 96 cells' radius, the front radius the
+benchmark state has, with a tanh front), given to the GPU and to the oracle
+alike -- the raytrace on every cell, the timestep minimum over every cell,
+one micro-physics update on a sample of cells the oracle integrates one by
+one, and one whole A3 step compared on every cell."""
 import numpy as np
 import pytest
+import torch
 
 import oracle
 from paper_1201_5651_amd import binding, synth
-from gpu_util import rel, rel_x, to_np
+from gpu_util import KB, backward_ok, float_bar, rel, rel_x, stored, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -17,43 +19,52 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def state256():
     spec = synth.cfg3(n=256)
-    nH = synth.density(spec)
+    nH = stored(synth.density(spec), "mixed")
+    x, T = synth.ionised_sphere(spec, 96.0)
+    x = stored(x, "mixed")
+    E = stored(1.5 * KB * nH * (2.0 - x) * T, "mixed")
     g = binding.Grid(spec, precision="mixed")
-    g.load(nH, 1.0, T0=spec.T0)
-    t_pre = 0.02 * spec.t_rec
-    g.run(t_pre, check_every=16)
-    yield spec, g, oracle.Problem.from_spec(spec)
+    pb = oracle.Problem.from_spec(spec)
+    inputs = {"nH": nH, "x": x, "E": E}
+    print("# 256^3 oracle raytrace of the start", flush=True)
+    tau = pb.raytrace(nH, x)
+    yield spec, g, pb, inputs, tau
     g.close()
 
 
-def test_raytrace_full_size(oracle_lib, state256):
-    spec, g, pb = state256
+def _reset(g, inputs):
+    """The grid back at the synthetic start (its own raytrace, t = 0)."""
+    for k, v in inputs.items():
+        getattr(g, k).copy_(torch.as_tensor(v, dtype=g.dtype))
     g.raytrace()
-    nH, x = np.ascontiguousarray(to_np(g.nH)), np.ascontiguousarray(to_np(g.x))
-    assert (x < 0.5).sum() > 1000   # a front exists
-    want = pb.raytrace(nH, x)
+    g.set_time(0.0, 0)
+
+
+def test_raytrace_full_size(oracle_lib, state256):
+    spec, g, pb, inp, tau = state256
+    _reset(g, inp)
+    assert ((inp["x"] > 1e-3) & (inp["x"] < 0.999)).sum() > 10000   # a front exists
     got = to_np(g.tau)
-    assert np.all((got == 0) == (want == 0))
-    m = want > 1e-3
-    assert np.max(rel(got[m], want[m])) < 1e-4
+    assert np.all((got == 0) == (tau == 0))
+    m = tau > 1e-3
+    float_bar(got[m], tau[m], 1e-4, "256^3 mixed columns")
+    assert np.max(np.abs(got[~m] - tau[~m])) < 1e-7
 
 
 def test_timestep_full_size(oracle_lib, state256):
-    spec, g, pb = state256
-    g.raytrace()
-    nH, x, E, tau = (np.ascontiguousarray(to_np(a)) for a in (g.nH, g.x, g.E, g.tau))
-    want = pb.timestep(nH, x, E, tau)
+    spec, g, pb, inp, tau = state256
+    _reset(g, inp)
+    want = pb.timestep(inp["nH"], inp["x"], inp["E"], tau)
     # one A2 step computes eq. (4) on this state and records the dt it took
-    t, _, _ = g.state()
-    g.step_o1(t + 1e3 * want)
+    g.step_o1(1e3 * want)
     _, _, got = g.state()
     assert got == pytest.approx(want, rel=1e-5)
 
 
 def test_chem_full_size_sampled(oracle_lib, state256):
-    spec, g, pb = state256
-    g.raytrace()
-    nH, x, E, tau = (np.ascontiguousarray(to_np(a)) for a in (g.nH, g.x, g.E, g.tau))
+    spec, g, pb, inp, tau = state256
+    _reset(g, inp)
+    nH, x, E = inp["nH"], inp["x"], inp["E"]
     h = 0.5 * pb.timestep(nH, x, E, tau)
     g.chem_step(h, binding.PI_BUF_N, binding.PI_BUF_N, binding.PI_BUF_HALF)
     xg, Eg = to_np(g.x_half).ravel(), to_np(g.E_half).ravel()
@@ -61,24 +72,47 @@ def test_chem_full_size_sampled(oracle_lib, state256):
     front = np.flatnonzero((x.ravel() > 1e-3) & (x.ravel() < 0.999))
     cells = np.concatenate([rng.choice(spec.ncells, 1500, replace=False),
                             rng.choice(front, min(1500, front.size), replace=False)])
-    errs, n_ill = [], 0
+    errs, ill = [], []
     for c in cells:
         geo, ell = pb.cell_env(int(c))
-        args = (nH.flat[c], geo, ell, tau.flat[c], x.flat[c], E.flat[c], h)
-        xw, Ew = pb.micro_cell(*args)
-        xp, _ = pb.micro_cell(nH.flat[c], geo, ell, tau.flat[c] * (1 + 1e-12), x.flat[c],
+        xw, Ew = pb.micro_cell(nH.flat[c], geo, ell, tau.flat[c], x.flat[c], E.flat[c], h)
+        xp, _ = pb.micro_cell(nH.flat[c], geo, ell, tau.flat[c] * (1 + 1e-7), x.flat[c],
                               E.flat[c], h)
-        if rel_x(np.array([xp]), np.array([xw]))[0] > 1e-10:
-            n_ill += 1
+        if rel_x(np.array([xp]), np.array([xw]))[0] > 1e-5:
+            ill.append(int(c))
             continue
-        Tg = 2 * Eg[c] / (3 * 1.380649e-16 * nH.flat[c] * (2 - xg[c]))
-        Tw = 2 * Ew / (3 * 1.380649e-16 * nH.flat[c] * (2 - xw))
+        Tg = 2 * Eg[c] / (3 * KB * nH.flat[c] * (2 - xg[c]))
+        Tw = 2 * Ew / (3 * KB * nH.flat[c] * (2 - xw))
         errs.append(max(rel_x(np.array([xg[c]]), np.array([xw]))[0], abs(Tg / Tw - 1)))
     errs = np.array(errs)
-    print("full-size chem: %d cells, %d ill-conditioned, max err %.3g, p99 %.3g"
-          % (cells.size, n_ill, errs.max(), np.quantile(errs, 0.99)))
-    assert n_ill < 0.05 * cells.size
+    Tgf = 2 * Eg / (3 * KB * nH.ravel() * (2 - xg))
+    bad = backward_ok(pb, spec, nH, x, E, tau, h, ill, xg, Tgf, 1e-4,
+                      (1e-7, -1e-7, 3e-7, -3e-7, 1e-6, -1e-6))
+    print("full-size chem: %d cells, %d ill-conditioned (%d not reproduced), max err %.3g"
+          % (cells.size, len(ill), len(bad), errs.max()))
+    assert len(ill) < 0.05 * cells.size and not bad
     assert errs.max() < 1e-4
+
+
+def test_a3_step_full_size_every_cell(oracle_lib, state256):
+    """One whole A3 step of the benchmark's configuration (mixed precision,
+    the tuned raytrace tile, the step replayed from its graph) against the
+    oracle's step from the same start, on all 16.8 M cells."""
+    spec, g, pb, inp, tau = state256
+    _reset(g, inp)
+    g.step_o2(1e30)
+    xg, Eg = to_np(g.x), to_np(g.E)
+    tg, dtg = to_np(g.tau), g.state()[2]
+    print("# 256^3 oracle A3 step", flush=True)
+    st = {"nH": inp["nH"], "x": inp["x"].copy(), "E": inp["E"].copy(), "tau": tau.copy(), "t": 0.0}
+    _, dt = pb.step(st, 1e30)
+    assert dtg == pytest.approx(dt, rel=1e-5)
+    Tg = pb.temperature(inp["nH"], xg, Eg)
+    Tw = pb.temperature(inp["nH"], st["x"], st["E"])
+    float_bar(xg, st["x"], 1e-4, "256^3 mixed A3 step x, every cell")
+    float_bar(Tg, Tw, 1e-4, "256^3 mixed A3 step T, every cell")
+    m = st["tau"] > 1e-3
+    float_bar(tg[m], st["tau"][m], 1e-4, "256^3 mixed A3 step columns")
 
 
 def test_batch_full_size_matches_grids_alone():

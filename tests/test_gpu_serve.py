@@ -100,3 +100,30 @@ def test_oversized_request_is_rejected_and_cancel_works():
     assert st == binding.PI_ECANCELLED
     assert srv.stats()["arena_bytes"] == 0
     srv.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_served_results_match_oracle(oracle_lib, precision):
+    """Served requests against the oracle's runs of the same problems (each
+    from its neutral start at 50 K to its own t_end): the neutral fraction
+    and temperature of every cell within the FP64 or the float bar."""
+    import oracle
+    from gpu_util import float_bar
+    reqs = _requests(precision)[:3]
+    srv = binding.Server(precision=precision, max_active=4, steps_per_tick=2)
+    tickets = [srv.submit(s, nH, T0=s.T0, t_end=te) for s, nH, te in reqs]
+    done = _wait(srv, tickets)
+    srv.close()
+    bar = 1e-9 if precision == "fp64" else 1e-4
+    for tk, (s, nH, te) in zip(tickets, reqs):
+        st, info, x, T = done[tk]
+        assert st == binding.PI_OK, info
+        pb = oracle.Problem.from_spec(s)
+        ref = pb.initial_state(nH, T0=s.T0)
+        n = pb.run(ref, te)
+        assert info["t"] == ref["t"] == te
+        if precision == "fp64":
+            assert info["nsteps"] == n
+        Tw = pb.temperature(ref["nH"], ref["x"], ref["E"])
+        float_bar(x, ref["x"], bar, "served %s %s x" % (s.name, precision))
+        float_bar(T, Tw, bar, "served %s %s T" % (s.name, precision))

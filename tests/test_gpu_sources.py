@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from paper_1201_5651_amd import binding, synth
-from gpu_util import pair, rel, rel_x, to_np
+from gpu_util import float_bar, pair, rel, rel_x, stored, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -39,7 +39,7 @@ def test_columns_of_every_source(oracle_lib, nsrc, precision):
     x = rng.uniform(0.0, 1.0, spec.shape)
     g, pb, _ = pair(spec, _nH(spec), x0=x, precision=precision)
     assert tuple(g.tau.shape) == (nsrc,) + spec.shape
-    want = pb.raytrace(np.ascontiguousarray(to_np(g.nH)), np.ascontiguousarray(to_np(g.x)))
+    want = pb.raytrace(stored(_nH(spec), precision), stored(x, precision))
     got = to_np(g.tau)
     assert np.array_equal(got == 0, want == 0)
     m = want > 0
@@ -88,13 +88,10 @@ def test_a3_steps_parity_float(oracle_lib, precision):
     for _ in range(8):
         g.step_o2(spec.t_end)
         pb.step(st, spec.t_end)
-    errx = rel_x(to_np(g.x), st["x"])
     Tg = pb.temperature(st["nH"], to_np(g.x), to_np(g.E))
     Tw = pb.temperature(st["nH"], st["x"], st["E"])
-    print("%s x err max %.3g p999 %.3g; T err max %.3g" % (precision, errx.max(),
-                                                         np.quantile(errx, .999), rel(Tg, Tw).max()))
-    assert np.quantile(errx, 0.999) < 1e-4
-    assert np.quantile(rel(Tg, Tw), 0.999) < 1e-4
+    float_bar(to_np(g.x), st["x"], 1e-4, precision + " four sources x after 8 steps")
+    float_bar(Tg, Tw, 1e-4, precision + " four sources T after 8 steps")
     g.close()
 
 
@@ -252,13 +249,16 @@ def test_four_sources_48cubed_mixed(oracle_lib):
         g.step_o2(spec.t_end)
         pb.step(st, spec.t_end)
     assert g.state()[0] == pytest.approx(st["t"], rel=1e-4)
-    errx = rel_x(to_np(g.x), st["x"])
     Tg = pb.temperature(st["nH"], to_np(g.x), to_np(g.E))
     Tw = pb.temperature(st["nH"], st["x"], st["E"])
-    assert np.quantile(errx, 0.999) < 1e-4
-    assert np.quantile(rel(Tg, Tw), 0.999) < 1e-4
-    m = st["tau"] > 1e-3
-    assert np.quantile(rel(to_np(g.tau)[m], st["tau"][m]), 0.999) < 1e-4
+    float_bar(to_np(g.x), st["x"], 1e-4, "mixed 48^3 four sources x")
+    float_bar(Tg, Tw, 1e-4, "mixed 48^3 four sources T")
+    # columns: relative where they are not tiny, absolute (in optical depth)
+    # below 1e-3, where float rounding of the sum dominates
+    tg, tw = to_np(g.tau), st["tau"]
+    m = tw > 1e-3
+    float_bar(tg[m], tw[m], 1e-4, "mixed 48^3 four sources columns")
+    assert np.max(np.abs(tg[~m] - tw[~m])) < 1e-7
     assert g.diagnostics()["octants"] == 8 + 8 + 8 + 2
     assert (1 - st["x"]).sum() > 20.0
     g.close()
