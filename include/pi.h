@@ -380,6 +380,22 @@ pi_status pi_server_destroy(pi_server* server);
  * cross-section sigma0 (nu0/nu)^3.  Nodes: 0, then 63 log-spaced in [1e-4, 1e4]. */
 pi_status pi_table_build(double T_bb, double Q, double* out);
 
+/* The raytrace of pi_raytrace for a grid given only by its description and
+ * fields, without a pi_grid and without allocating anything: for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  The grid table and the tile
+ * schedule the sweep reads live in a static device array of the library
+ * (4 MiB + 16 KiB on every device it runs on, held until the process ends),
+ * written by a set-up kernel on the stream before the sweep.  Limits: at most
+ * 262144 raytrace tiles of edge 8 over all sources and octants (e.g. 512^3
+ * cells with one source, 256^3 with four) and 4096 tile diagonals;
+ * PI_EINVAL beyond them, before anything is launched.  Validation, arguments
+ * and columns as pi_raytrace (bit for bit).  Every call on a device shares
+ * that device's array: calls that overlap on one device (another stream,
+ * another thread) race and must not overlap. */
+pi_status pi_raytrace_static(const pi_grid_desc* desc, const pi_fields* fields, int state,
+                             int tau_buf, void* stream);
+
 /* Raytrace tile edge: 4, 8 or 16 (cells of the cubic tile one workgroup
  * sweeps), or 0 to time them all on the next raytrace outside graph capture and keep the
  * faster (the default; that first raytrace then SYNCHRONISES its stream).  The

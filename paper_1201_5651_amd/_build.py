@@ -11,7 +11,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpi.so")
-SOURCES = ["kernels.hip", "engine.hip", "runtime.hip", "server.hip"]
+SOURCES = ["kernels.hip", "engine.hip", "runtime.hip", "server.hip", "noalloc.hip"]
 HEADERS = ["physics.h", "kernels.h", "engine.h", "arena.h"]
 
 HIPCC_FLAGS = [

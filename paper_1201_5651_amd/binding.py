@@ -43,6 +43,7 @@ ABI_SYMBOLS = (
     "pi_step_a1",
     "pi_batch_step_a1",
     "pi_grid_required_bytes", "pi_grid_save", "pi_grid_load", "pi_checkpoint",
+    "pi_raytrace_static",
 )
 
 
@@ -154,6 +155,7 @@ def lib() -> C.CDLL:
         L.pi_grid_save.argtypes = [vp, vp, C.c_size_t, szp, vp]
         L.pi_grid_load.argtypes = [vp, vp, C.c_size_t, vp]
         L.pi_checkpoint.argtypes = [vp, C.c_uint64, vp, C.c_size_t, szp]
+        L.pi_raytrace_static.argtypes = [C.POINTER(GridDesc), C.POINTER(Fields), i32, i32, vp]
         L.pi_last_error.restype = C.c_char_p
         L.pi_abi_version.restype = C.c_int
         for name in ABI_SYMBOLS:
@@ -219,6 +221,16 @@ def desc_from_spec(spec, precision: Optional[str] = None, sigma0: float = 6.3e-1
 
 
 FIELD_NAMES = ("nH", "x", "E", "tau", "x_half", "E_half", "tau_half", "nH_half")
+
+
+def raytrace_static(spec, fields, state=PI_BUF_N, tau_buf=PI_BUF_N, precision=None):
+    """pi_raytrace_static on a GridFields (no grid object, nothing allocated
+    by the library), on torch's current stream."""
+    import torch
+    d = desc_from_spec(spec, precision or fields.precision)
+    f = fields.abi_fields()
+    check(lib().pi_raytrace_static(C.byref(d), C.byref(f), state, tau_buf,
+                                   C.c_void_p(torch.cuda.current_stream().cuda_stream)))
 
 
 class GridFields:

@@ -137,4 +137,9 @@ pi_status grid_load(GridHost& h, const void* buf, size_t bytes, hipStream_t s);
 // Layout check of a checkpoint against a descriptor, without loading it.
 pi_status checkpoint_check(const pi_grid_desc& d, const void* buf, size_t bytes);
 
+// The raytrace entries of one grid (source 0, then one per further source)
+// as an engine builds them, without rate tables or clock: out holds
+// MAX_SRC entries; returns how many are used.
+template <typename R> int raytrace_entries(const pi_grid_desc& d, const pi_fields& f, GridDev<R>* out);
+
 }  // namespace pi

@@ -198,6 +198,45 @@ pi_status table_for(Engine& e, const pi_grid_desc& d, void** td, void** tf)
 
 template <typename R> R* fld(void* v) { return static_cast<R*>(v); }
 
+// Device view of a grid without its tables and clock (set by the caller).
+template <typename R> GridDev<R> base_entry(const pi_grid_desc& d, const pi_fields& f)
+{
+    GridDev<R> D{};
+    D.p = make_params<R>(d);
+    D.pd = make_params<double>(d);
+    D.src = make_sources<R>(d);
+    D.srcd = make_sources<double>(d);
+    D.nH = fld<R>(f.nH);
+    D.nHr[0] = D.nH;
+    D.nHr[1] = f.nH_half ? fld<R>(f.nH_half) : D.nH;
+    D.x[0] = fld<R>(f.x);
+    D.x[1] = fld<R>(f.x_half);
+    const bool ev = d.thermal == PI_T_EVOLVE;
+    D.E[0] = ev ? fld<R>(f.E) : nullptr;
+    D.E[1] = ev ? fld<R>(f.E_half) : nullptr;
+    D.tau[0] = fld<R>(f.tau);
+    D.tau[1] = fld<R>(f.tau_half);
+    D.cell_vol = d.dx * d.dx * d.dx;
+    D.face_area = d.source == PI_SRC_PLANE ? (double)d.n[1] * d.n[2] * d.dx * d.dx : 0.0;
+    D.noct = octant_count(d);
+    return D;
+}
+
+// The raytrace entry of further source s: the grid seen from that source,
+// whose columns follow the grid's columns at s arrays of cells.
+template <typename R> GridDev<R> source_entry(const GridDev<R>& base, const pi_grid_desc& d, int s)
+{
+    GridDev<R> D = base;
+    const int32_t* v = source_vertex(d, s);
+    D.p.sx = D.pd.sx = v[0];
+    D.p.sy = D.pd.sy = v[1];
+    D.p.sz = D.pd.sz = v[2];
+    const int64_t n = (int64_t)d.n[0] * d.n[1] * d.n[2];
+    D.tau[0] += (int64_t)s * n;
+    D.tau[1] += (int64_t)s * n;
+    return D;
+}
+
 template <typename R> pi_status upload_grids(Engine& e)
 {
     std::vector<GridDev<R>> h(e.grids.size() + e.extra.size());
@@ -207,41 +246,15 @@ template <typename R> pi_status upload_grids(Engine& e)
         pi_status r = table_for(e, G.d, &td, &tf);
         if (r != PI_OK) return r;
         GridDev<R>& D = h[g];
-        D.p = make_params<R>(G.d);
-        D.pd = make_params<double>(G.d);
-        D.src = make_sources<R>(G.d);
-        D.srcd = make_sources<double>(G.d);
+        D = base_entry<R>(G.d, G.f);
         D.pd.tab = static_cast<const DevTable<double>*>(td);
         D.p.tab = static_cast<const DevTable<R>*>(sizeof(R) == sizeof(double) ? td : tf);
-        D.nH = fld<R>(G.f.nH);
-        D.nHr[0] = D.nH;
-        D.nHr[1] = G.f.nH_half ? fld<R>(G.f.nH_half) : D.nH;
-        D.x[0] = fld<R>(G.f.x);
-        D.x[1] = fld<R>(G.f.x_half);
-        const bool ev = G.d.thermal == PI_T_EVOLVE;
-        D.E[0] = ev ? fld<R>(G.f.E) : nullptr;
-        D.E[1] = ev ? fld<R>(G.f.E_half) : nullptr;
-        D.tau[0] = fld<R>(G.f.tau);
-        D.tau[1] = fld<R>(G.f.tau_half);
         D.st = G.st;
         D.part = G.part;
-        D.cell_vol = G.cell_vol;
-        D.face_area = G.d.source == PI_SRC_PLANE ? (double)G.d.n[1] * G.d.n[2] * G.d.dx * G.d.dx : 0.0;
-        D.noct = G.noct;
     }
-    // the raytrace entries of further sources: the grid seen from source s,
-    // whose columns follow the grid's columns at s cells of arrays
     for (size_t m = 0; m < e.extra.size(); ++m) {
         const int g = e.extra[m].x, src = e.extra[m].y;
-        const GridHost& G = *e.grids[g];
-        GridDev<R>& D = h[e.grids.size() + m];
-        D = h[g];
-        const int32_t* v = source_vertex(G.d, src);
-        D.p.sx = D.pd.sx = v[0];
-        D.p.sy = D.pd.sy = v[1];
-        D.p.sz = D.pd.sz = v[2];
-        D.tau[0] += (int64_t)src * G.ncell;
-        D.tau[1] += (int64_t)src * G.ncell;
+        h[e.grids.size() + m] = source_entry(h[g], e.grids[g]->d, src);
     }
     const size_t bytes = sizeof(GridDev<R>) * std::max<size_t>(1, h.size());
     if (bytes > e.gdev_cap) {
@@ -918,5 +931,16 @@ pi_status grid_load(GridHost& g, const void* buf, size_t bytes, hipStream_t s)
     HIP_OR(hipStreamSynchronize(s), "checkpoint sync");
     return PI_OK;
 }
+
+// ------------------------------------------------- entries of a lone grid
+template <typename R> int raytrace_entries(const pi_grid_desc& d, const pi_fields& f, GridDev<R>* out)
+{
+    out[0] = base_entry<R>(d, f);
+    const int ns = nsources(d);
+    for (int s = 1; s < ns; ++s) out[s] = source_entry(out[0], d, s);
+    return ns;
+}
+template int raytrace_entries<double>(const pi_grid_desc&, const pi_fields&, GridDev<double>*);
+template int raytrace_entries<float>(const pi_grid_desc&, const pi_fields&, GridDev<float>*);
 
 }  // namespace pi
