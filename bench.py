@@ -11,7 +11,11 @@ half-step state, corrector micro-physics, raytrace of the new state.
 
 Prints ONE JSON line: cell-updates/s (whole job), ms per step, the roofline
 object of the dominant kernel (measured live with HIP events on the stream the
-kernels run on) and the FP64 oracle's rate on a bounded CPU sample.
+kernels run on; its HBM fraction and the whole step's beside the ALU figure),
+the FP64 oracle's rate on a bounded CPU sample (one thread and OpenMP, with the
+host's CPU model), the error of the same kernels against the oracle on that
+sample, and p50/p99 latency of a served stream of config-5-sized requests
+(n 48..256, each to 2 t_rec) at a stated arrival rate the GPU sustains.
 
 Other workloads (--workload): batch (64 uneven grids advanced together, and
 the FP64 single-grid path on a sample of them), serve (Poisson requests to the
@@ -34,8 +38,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# MI355X vector peaks [TFLOP/s]
-VALU_PEAK = {"fp32": 157.3, "fp64": 78.6, "mixed": 157.3}
+# MI355X vector peaks [TFLOP/s]: 256 CUs x 2.4 GHz x 2 flops per FMA x FMA
+# lanes per CU per clock.  FP64: 64 lanes, 78.6.  FP32: 128 lanes with packed
+# FP32 instructions (the published 157.3), 64 lanes without them -- and this
+# build turns packed FP32 off, so 78.6 is the FP32 issue rate it can reach.
+VALU_PEAK = {"fp32": 78.6, "fp64": 78.6, "mixed": 78.6, "mixed_front": 78.6}
+VALU_PEAK_NOTE = ("FMA issue rate without packed FP32: 256 CU x 64 lanes x 2 flops x 2.4 GHz "
+                  "(the published FP32 vector peak, 157.3, needs packed FP32, which the build "
+                  "disables)")
+# Algorithmic HBM bytes per cell-update of the whole step (two raytraces, two
+# micro-physics updates and the timestep, with the columns carried between
+# steps): read n_H, x, E, tau, write x, E, tau -- seven words.
+STEP_WORDS = 7
 # Algorithmic flops of the micro-physics, counted from the source (add, mul,
 # each half of a fused multiply-add, reciprocal, square root and
 # transcendental = 1 flop each): one Newton iteration of the coupled (x, E)
@@ -78,45 +92,137 @@ def word_bytes(precision: str) -> int:
 
 
 def dtype_name(precision: str) -> str:
-    return {"fp64": "f64", "fp32": "f32", "mixed": "f32+f64"}[precision]
+    # mixed: float cells; the double reductions and the (reported) double
+    # re-solves of precision-sensitive cells do not change the cells' type
+    return {"fp64": "f64", "fp32": "f32", "mixed": "f32", "mixed_front": "f32+f64"}[precision]
 
 
-def cpu_baseline(n: int, budget_s: float):
-    """The FP64 oracle, single thread, on a coarse copy of the same workload
-    (same recipe at n^3), advanced to 0.1 t_rec untimed, then timed for at
-    least budget_s seconds of whole steps."""
+PRECISION_DETAIL = {
+    "fp64": "double cells and reductions",
+    "fp32": "float cells, double timestep and diagnostic reductions",
+    "mixed": "float cells, double timestep and diagnostic reductions, double re-solve of the "
+             "cells whose float integration took a precision-sensitive decision "
+             "(fp64_resolved_frac)",
+    "mixed_front": "float cells, double reductions, double integration of the ionisation-front "
+                   "cells (starting x in [1e-3, 0.5]) and of precision-sensitive cells",
+}
+
+
+def host_cpu():
+    """Model name and logical CPU count of the host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def _cpu_case(n: int):
+    """The headline recipe on an n^3 grid of the same box (2.4 R_S), from the
+    synthetic partly ionised start (an ionised sphere of 0.375 n cells'
+    radius, the radius the 256^3 benchmark state has); inputs as the float
+    grid holds them."""
     import numpy as np
 
-    import oracle
     from paper_1201_5651_amd import synth
+    spec = synth.cfg3(n=n, box_cells=n)
+    f32 = lambda a: np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
+    nH = f32(synth.density(spec))
+    x, T = synth.ionised_sphere(spec, 0.375 * n)
+    x = f32(x)
+    E = f32(1.5 * 1.380649e-16 * nH * (2.0 - x) * T)
+    return spec, nH, x, E
 
-    oracle.build()
-    spec = synth.cfg3(n=n)
+
+def cpu_oracle_steps(n: int, budget_s: float, max_steps: int):
+    """The FP64 oracle on _cpu_case(n): whole A3 steps for at least budget_s
+    seconds (at most max_steps).  Returns the rate, the steps and the final
+    state (for the error of the GPU against it)."""
+    import oracle
+    spec, nH, x, E = _cpu_case(n)
     pb = oracle.Problem.from_spec(spec)
-    nH = synth.density(spec)
-    st = pb.initial_state(nH, T0=spec.T0)
-    t_pre = 0.1 * spec.t_rec
-    pre = 0
-    while st["t"] < t_pre and pre < 400:
-        pb.step(st, t_pre)
-        pre += 1
+    st = {"nH": nH, "x": x.copy(), "E": E.copy(), "t": 0.0}
+    st["tau"] = pb.raytrace(nH, st["x"])
     steps = 0
     t0 = time.perf_counter()
     while True:
         pb.step(st, 1e30)
         steps += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 200:
+        if el >= budget_s or steps >= max_steps:
             break
-    return {
-        "value": spec.ncells * steps / el,
+    return spec.ncells * steps / el, steps, el, pb, st
+
+
+def cpu_baseline(n: int, budget_s: float, n_omp: int, omp_steps: int):
+    """The FP64 oracle on the host: one thread on the headline recipe at n^3
+    (whole box, synthetic front start), timed over at least budget_s of whole
+    A3 steps; and its OpenMP build (bitwise the same results) on all host
+    cores at n_omp^3, timed over omp_steps steps, in a child process."""
+    import subprocess
+    rate, steps, el, pb, st = cpu_oracle_steps(n, budget_s, 200)
+    model, ncpu = host_cpu()
+    out = {
+        "value": rate,
         "unit": "cell-updates/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"FP64 oracle, 1 thread, {steps} A3 steps of the same workload recipe at {n}^3 "
-                  f"(box 2.4 R_S, lognormal seed 1201) after {pre} untimed steps to 0.1 t_rec; "
-                  f"{el:.1f} s",
+        "sample": f"FP64 oracle, 1 thread, {steps} A3 steps of the benchmark recipe at {n}^3 "
+                  f"(same 2.4 R_S box, lognormal seed 1201, from an ionised sphere of "
+                  f"{0.375 * n:.0f} cells' radius); {el:.1f} s",
+        "cpu_model": model,
+        "nproc": ncpu,
     }
+    env = dict(os.environ, ORACLE_OPENMP="1")
+    cmd = [sys.executable, os.path.abspath(__file__), "--omp-leg", str(n_omp), str(omp_steps)]
+    try:
+        r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
+        leg = json.loads(r.stdout.strip().splitlines()[-1])
+        out["openmp"] = leg
+    except Exception as e:   # reported, not fatal: the single-thread leg stands
+        out["openmp"] = {"error": str(e)[:200]}
+    return out, (steps, pb, st)
+
+
+def omp_leg(n: int, steps: int) -> int:
+    """Child process of cpu_baseline: the OpenMP oracle's rate at n^3."""
+    rate, k, el, _, _ = cpu_oracle_steps(n, 1e30, steps)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
+    print(json.dumps({"value": rate, "unit": "cell-updates/s", "cores": threads,
+                      "sample": f"FP64 oracle built with OpenMP, {threads} threads, {k} A3 steps "
+                                f"of the benchmark recipe at {n}^3 from the same start; {el:.1f} s"}))
+    return 0
+
+
+def error_vs_oracle(torch, binding, n: int, steps: int, pb, st, precision: str):
+    """The GPU path of the headline (same precision, same kernels) on the
+    same small case as the CPU baseline, stepped as many times: relative
+    error of x (floor 1e-12) and T on every cell against the oracle's state."""
+    import numpy as np
+    spec, nH, x, E = _cpu_case(n)
+    g = binding.Grid(spec, precision=precision)
+    g.nH.copy_(torch.as_tensor(nH, dtype=g.dtype))
+    g.x.copy_(torch.as_tensor(x, dtype=g.dtype))
+    g.E.copy_(torch.as_tensor(E, dtype=g.dtype))
+    g.raytrace()
+    g.set_time(0.0, 0)
+    for _ in range(steps):
+        g.step_o2(1e30)
+    torch.cuda.synchronize()
+    xg = g.x.double().cpu().numpy()
+    Eg = g.E.double().cpu().numpy()
+    g.close()
+    T = lambda xx, EE: 2.0 * EE / (3.0 * 1.380649e-16 * st["nH"] * (2.0 - xx))
+    ex = np.abs(xg - st["x"]) / np.maximum(np.abs(st["x"]), 1e-12)
+    eT = np.abs(T(xg, Eg) / T(st["x"], st["E"]) - 1.0)
+    return {"case": f"benchmark recipe at {n}^3, {steps} A3 steps from the synthetic front start",
+            "x_max": float(ex.max()), "x_p999": float(np.quantile(ex, 0.999)),
+            "T_max": float(eT.max()), "T_p999": float(np.quantile(eT, 0.999)),
+            "bar": 1e-9 if precision == "fp64" else 1e-4}
 
 
 def bench_batch(args, torch, binding, synth) -> dict:
@@ -338,7 +444,7 @@ def bench_serve(args, torch, binding, synth) -> dict:
     import numpy as np
     reqs = synth.poisson_requests(args.serve_requests, rate=args.serve_rate, seed=5651,
                                   nmin=args.serve_nmin, nmax=args.serve_nmax,
-                                  n_outlier=2 * args.serve_nmax, p_outlier=0.01,
+                                  n_outlier=2 * args.serve_nmax, p_outlier=args.serve_outliers,
                                   precision=args.precision)
     reqs = [(t, synth.GridSpec(**{**s.__dict__, "t_end": args.serve_trec * s.t_rec})) for t, s in reqs]
     tick = time.time()
@@ -351,7 +457,7 @@ def bench_serve(args, torch, binding, synth) -> dict:
     # first, so the timed stream sees a server whose rate tables and raytrace
     # tiles are set up (a serving workload has a warm-up period)
     warm = synth.poisson_requests(args.serve_warmup, rate=args.serve_rate, seed=15651,
-                                  nmin=args.serve_nmin, nmax=args.serve_nmax,
+                                  nmin=args.serve_nmin, nmax=args.serve_nmax, p_outlier=0.0,
                                   precision=args.precision) if args.serve_warmup > 0 else []
     wt = []
     for _, s in warm:
@@ -388,6 +494,8 @@ def bench_serve(args, torch, binding, synth) -> dict:
     lat = np.array([info["latency_s"] for st, info in done.values()])
     que = np.array([info["queue_s"] for st, info in done.values()])
     ok = sum(1 for st, _ in done.values() if st == binding.PI_OK)
+    # offered load: the cell-updates the stream asks for per second of arrivals
+    span = reqs[-1][0] if reqs else 1.0
     return {
         "metric": "served A3 solves: cell-updates/s and p50/p99 latency",
         "value": stats["cell_updates"] / wall, "unit": "cell-updates/s", "n_gpus": 1,
@@ -396,10 +504,13 @@ def bench_serve(args, torch, binding, synth) -> dict:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype_name(args.precision), "data": "synthetic",
         "config": {"workload": f"{len(reqs)} requests, Poisson arrivals at {args.serve_rate}/s, n "
-                               f"uniform in {args.serve_nmin}..{args.serve_nmax} (1% at "
-                               f"{2 * args.serve_nmax}), source in the central half, cfg2 physics, "
-                               f"each to {args.serve_trec} t_rec(mean)",
+                               f"uniform in {args.serve_nmin}..{args.serve_nmax} "
+                               f"({100 * args.serve_outliers:g}% at {2 * args.serve_nmax}), source "
+                               f"in the central half, uniform or lognormal media of mean 1..100 "
+                               f"cm^-3, Q 1e47..1e50 /s, cfg2 physics, each to {args.serve_trec} "
+                               f"t_rec(mean)",
                    "completed_ok": ok, "wall_s": wall, "busy_s": stats["busy_s"],
+                   "offered_cell_updates_per_s": stats["cell_updates"] / max(span, 1e-9),
                    "latency_p50_s": float(np.quantile(lat, 0.5)),
                    "latency_p99_s": float(np.quantile(lat, 0.99)),
                    "queue_p50_s": float(np.quantile(que, 0.5)),
@@ -414,7 +525,10 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--precision", default="mixed", choices=["fp64", "fp32", "mixed"])
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "fp32", "mixed", "mixed_front"])
+    ap.add_argument("--front-steps", type=int, default=6,
+                    help="default workload: steps timed with the FP64 front cells (mixed_front) "
+                         "from the same state; 0 skips")
     ap.add_argument("--pre-trec", type=float, default=0.1,
                     help="untimed evolution before timing, in units of t_rec")
     ap.add_argument("--pre-steps-max", type=int, default=400)
@@ -422,9 +536,17 @@ def main() -> int:
                     help="back-to-back launches per phase in the phase timing")
     ap.add_argument("--phase-steps", type=int, default=3,
                     help="extra steps timed phase by phase after the timed region")
-    ap.add_argument("--cpu-sample-n", type=int, default=32)
+    ap.add_argument("--cpu-sample-n", type=int, default=48,
+                    help="single-thread CPU baseline (and error check) at this n^3")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--cpu-omp-n", type=int, default=128,
+                    help="OpenMP CPU baseline leg at this n^3")
+    ap.add_argument("--cpu-omp-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="default workload: skip the served-stream leg (p50/p99 latency)")
+    ap.add_argument("--omp-leg", nargs=2, type=int, metavar=("N", "STEPS"), default=None,
+                    help=argparse.SUPPRESS)
     ap.add_argument("--workload", default="cfg3",
                     choices=["cfg3", "batch", "serve", "hardening", "a1", "sources"],
                     help="cfg3: the 256^3 single grid (default); batch / serve: the batched and "
@@ -433,13 +555,19 @@ def main() -> int:
                     help="hardening workload: accuracy runs end at this many t_rec")
     ap.add_argument("--batch-grids", type=int, default=64)
     ap.add_argument("--batch-fp64-sample", type=int, default=8)
-    ap.add_argument("--serve-requests", type=int, default=200)
-    ap.add_argument("--serve-warmup", type=int, default=8,
+    # the served stream: config 5's sizes and run length (n 48..256, each to
+    # 2 t_rec) at an arrival rate the GPU sustains (4 /s; config 5 names
+    # 20 /s, above this GPU's throughput for such requests), without the 1%
+    # of 512^3 outliers unless --serve-outliers says otherwise
+    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-warmup", type=int, default=4,
                     help="requests run to completion before the timed stream (not counted)")
-    ap.add_argument("--serve-rate", type=float, default=20.0)
-    ap.add_argument("--serve-nmin", type=int, default=32)
-    ap.add_argument("--serve-nmax", type=int, default=96)
-    ap.add_argument("--serve-trec", type=float, default=0.05)
+    ap.add_argument("--serve-rate", type=float, default=4.0)
+    ap.add_argument("--serve-nmin", type=int, default=48)
+    ap.add_argument("--serve-nmax", type=int, default=256)
+    ap.add_argument("--serve-trec", type=float, default=2.0)
+    ap.add_argument("--serve-outliers", type=float, default=0.0,
+                    help="fraction of requests at twice nmax (config 5: 0.01)")
     ap.add_argument("--serve-max-active", type=int, default=64)
     ap.add_argument("--serve-steps-per-tick", type=int, default=4)
     ap.add_argument("--time-tiles", action="store_true",
@@ -448,6 +576,8 @@ def main() -> int:
                     help="also run one plain device copy of this many MiB (a known-size "
                          "reference for hardware traffic counters)")
     args = ap.parse_args()
+    if args.omp_leg:
+        return omp_leg(*args.omp_leg)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (grids "
@@ -565,6 +695,31 @@ def main() -> int:
     diag = g.diagnostics()
     t_now, n_now, _ = g.state()
 
+    # the same state advanced with the ionisation-front cells in double
+    front_leg = None
+    if args.front_steps > 0 and args.precision == "mixed":
+        gf = binding.Grid(spec, precision="mixed_front")
+        for k in ("nH", "x", "E", "tau"):
+            getattr(gf, k).copy_(getattr(g, k))
+        gf.set_time(t_now, n_now)
+        gf.raytrace_tile = g.raytrace_tile
+        gf.step_o2(t_end)
+        gf.work_counters(reset=True)
+        torch.cuda.synchronize()
+        a, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.front_steps):
+            gf.step_o2(t_end)
+        b2.record(stream)
+        torch.cuda.synchronize()
+        fms = a.elapsed_time(b2) / args.front_steps
+        wf = gf.work_counters(reset=True)
+        front_leg = {"precision": "mixed_front", "dtype": dtype_name("mixed_front"),
+                     "detail": PRECISION_DETAIL["mixed_front"], "steps": args.front_steps,
+                     "ms_per_step": fms, "value": spec.ncells / (fms * 1e-3),
+                     "fp64_resolved_frac": wf["resolved_fp64"] / (2 * args.front_steps * spec.ncells)}
+        gf.close()
+
     W = word_bytes(args.precision)
     N = spec.ncells
     newton_per_launch = work_phase["newton"] / chem_launches
@@ -575,29 +730,38 @@ def main() -> int:
            "raytrace_half": 3 * W * N, "raytrace": 3 * W * N, "timestep": 4 * W * N}
     hbm = {k: alg[k] / (phases[k] * 1e-3) / 1e9 for k in phases}
     dom = max(phases, key=phases.get)
+    # the whole step against HBM: seven words per cell-update
+    step_gbs = STEP_WORDS * W * N / (ms_step * 1e-3) / 1e9
+    hbm_view = {"kernel": dom, "achieved": round(hbm[dom], 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(hbm[dom] / HBM_PEAK_GBS, 5),
+                "bytes_per_launch": alg[dom]}
+    step_view = {"bytes_per_cell_update": STEP_WORDS * W, "achieved": round(step_gbs, 2),
+                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 5)}
     if dom.startswith("chem"):
-        # the micro-physics is bound by vector arithmetic: its HBM traffic is
-        # a few words per cell against hundreds of flops
+        # the micro-physics (k_chem and, in mixed precision, the double pass
+        # k_chem_fix over the front cells that follows it) is bound by vector
+        # arithmetic: a few words of HBM per cell against hundreds of flops
         flops = newton_per_launch * FLOP_NEWTON + N * FLOP_CELL_SETUP
         t_chem = 0.5 * (phases["chem_predictor"] + phases["chem_corrector"])
         achieved = flops / (t_chem * 1e-3) / 1e12
         peak = VALU_PEAK[args.precision]
-        roofline = {"bound": "alu", "kernel": "k_chem (" + dom + ")",
+        roofline = {"bound": "alu", "kernel": "k_chem + k_chem_fix (" + dom + ")",
                     "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                    "frac": round(achieved / peak, 5),
+                    "frac": round(achieved / peak, 5), "peak_note": VALU_PEAK_NOTE,
                     "traffic": measured_traffic() if (args.precision == "mixed" and args.n == 256) else None,
-                    "flops_per_launch": flops,
-                    "hbm_GBs_of_dominant": round(hbm[dom], 2)}
+                    "flops_per_launch": flops}
     else:
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(hbm[dom], 2),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(hbm[dom] / HBM_PEAK_GBS, 5),
                     "traffic": None}
+    roofline["hbm_of_dominant"] = hbm_view
+    roofline["hbm_of_step"] = step_view
     roofline["phase_ms"] = {k: round(v, 4) for k, v in phases.items()}
     roofline["raytrace_hbm"] = {"achieved": round(hbm["raytrace"], 2), "unit": "GB/s",
                                 "frac": round(hbm["raytrace"] / HBM_PEAK_GBS, 5)}
 
     out = {
-        "metric": "cell-updates/s per raytrace+chemistry step at 256^3",
+        "metric": "cell-updates/s per raytrace+chemistry step at 256^3; p50/p99 batched solve latency",
         "value": value,
         "unit": "cell-updates/s",
         "n_gpus": 1,
@@ -625,12 +789,32 @@ def main() -> int:
             "fallbacks_per_cell_update": work_phase["fallbacks"] / (spec.ncells * chem_launches / 2),
             "newton_per_cell_update": work_phase["newton"] / (spec.ncells * chem_launches / 2),
             "fp64_resolved_frac": work_phase["resolved_fp64"] / (spec.ncells * chem_launches),
+            "precision_detail": PRECISION_DETAIL[args.precision],
         },
         "roofline": roofline,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, args.cpu_budget)
+    if front_leg is not None:
+        out["front_fp64"] = front_leg
     g.close()
+    del g
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        print("# cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"], (k, pb, st) = cpu_baseline(args.cpu_sample_n, args.cpu_budget,
+                                                        args.cpu_omp_n, args.cpu_omp_steps)
+        # the headline's kernels against the oracle's steps of that sample
+        out["error_vs_oracle"] = error_vs_oracle(torch, binding, args.cpu_sample_n, k, pb, st,
+                                                 args.precision)
+    if not args.no_serve:
+        print("# served stream", file=sys.stderr, flush=True)
+        sv = bench_serve(args, torch, binding, synth)
+        c = sv["config"]
+        out["latency"] = {"p50_s": c["latency_p50_s"], "p99_s": c["latency_p99_s"],
+                          "queue_p50_s": c["queue_p50_s"], "queue_p99_s": c["queue_p99_s"],
+                          "cell_updates_per_s": sv["value"],
+                          "offered_cell_updates_per_s": c["offered_cell_updates_per_s"],
+                          "requests": args.serve_requests, "completed_ok": c["completed_ok"],
+                          "stream": c["workload"], "wall_s": c["wall_s"]}
     print(json.dumps(out))
     return 0
 

@@ -18,7 +18,7 @@
  *    varying fastest: cell (i,j,k) is element i + nx*(j + ny*k).
  *  - Field pointers are DEVICE pointers owned by the caller (e.g. torch
  *    tensors); they must stay valid until pi_grid_destroy.  Element type is
- *    double for PI_FP64 and float for PI_FP32 / PI_MIXED.
+ *    double for PI_FP64 and float for PI_FP32 / PI_MIXED / PI_MIXED_FRONT.
  *  - Every call that takes a stream enqueues asynchronous work on that HIP
  *    stream (hipStream_t passed as void*; NULL = the null stream) and returns
  *    without waiting, except the calls documented as synchronising.
@@ -47,17 +47,19 @@ typedef enum {
     PI_ECANCELLED = -6   /* served request cancelled                          */
 } pi_status;
 
-/* PI_MIXED: float fields and float bulk arithmetic, with the ionisation-front
- * cells in double.  A cell whose neutral fraction at the start of a
- * micro-physics update lies in [1e-3, 0.999] (the front) is integrated in
- * double only.  Any other cell is integrated in float and re-solved in double
- * from the same float inputs when its float integration took a decision that
- * the precision can flip: a substep-control decision within a relative 1e-3 of
- * its threshold (initial substep count, rejection of a substep), a stage
- * solve that needed the bracketed fallback, or a neutral fraction held at 1 on
- * an unstable equilibrium.  Results are stored in float.  Reductions
- * (timestep, diagnostics) are double in every precision. */
-typedef enum { PI_FP64 = 0, PI_FP32 = 1, PI_MIXED = 2 } pi_precision;
+/* PI_MIXED: float fields and float bulk arithmetic.  A cell is re-solved in
+ * double from the same float inputs when its float integration took a
+ * decision that the precision can flip: a substep-control decision within a
+ * relative 1e-3 of its threshold (initial substep count, rejection of a
+ * substep), a stage solve that needed the bracketed fallback, or a neutral
+ * fraction held at 1 on an unstable equilibrium.
+ * PI_MIXED_FRONT: PI_MIXED, and the ionisation-front cells in double: a cell
+ * whose neutral fraction at the start of a micro-physics update lies in
+ * [1e-3, 0.5] (the front's transition layer between ionised and mostly
+ * neutral gas) is integrated in double only.
+ * Both store results in float.  Reductions (timestep, diagnostics) are double
+ * in every precision. */
+typedef enum { PI_FP64 = 0, PI_FP32 = 1, PI_MIXED = 2, PI_MIXED_FRONT = 3 } pi_precision;
 enum { PI_SPEC_MONO = 0, PI_SPEC_TABLE = 1 };
 enum { PI_T_FIXED = 0, PI_T_EVOLVE = 1 };
 enum { PI_ALPHA_CONST = 0, PI_ALPHA_POWER = 1 };
@@ -253,7 +255,7 @@ pi_status pi_diagnostics(pi_grid* grid, double* out, void* stream);
 /* Work of the micro-physics updates since the last reset (SYNCHRONISES):
  * out[0] accepted substeps, out[1] rejected substeps, out[2] stage solves that
  * needed the bracketed fallback, out[3] Newton iterations of the stage solves,
- * out[4] cells re-solved in double by PI_MIXED grids (out has PI_NWORK
+ * out[4] cells re-solved in double by PI_MIXED / PI_MIXED_FRONT grids (out has PI_NWORK
  * elements).  reset != 0 zeroes the counters after reading.
  * Counters are summed over all pi_chem_step / step calls of the grid. */
 pi_status pi_work_counters(pi_grid* grid, int64_t* out, int reset, void* stream);

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(HERE, "libpi.so")
 
 PI_OK, PI_PENDING = 0, 1
 PI_EINVAL, PI_ENOMEM, PI_EDEVICE, PI_EREJECTED, PI_ENAN, PI_ECANCELLED = -1, -2, -3, -4, -5, -6
-PI_FP64, PI_FP32, PI_MIXED = 0, 1, 2
+PI_FP64, PI_FP32, PI_MIXED, PI_MIXED_FRONT = 0, 1, 2, 3
+PRECISIONS = {"fp64": PI_FP64, "fp32": PI_FP32, "mixed": PI_MIXED, "mixed_front": PI_MIXED_FRONT}
 PI_SPEC_MONO, PI_SPEC_TABLE = 0, 1
 PI_T_FIXED, PI_T_EVOLVE = 0, 1
 PI_ALPHA_CONST, PI_ALPHA_POWER = 0, 1
@@ -208,7 +209,7 @@ def desc_from_spec(spec, precision: Optional[str] = None, sigma0: float = 6.3e-1
     d.n_sub = int(spec.n_sub)
     d.K[:] = tuple(float(k) for k in spec.K)
     prec = precision or spec.precision
-    d.precision = {"fp64": PI_FP64, "fp32": PI_FP32, "mixed": PI_MIXED}[prec]
+    d.precision = PRECISIONS[prec]
     d.source = PI_SRC_PLANE if getattr(spec, "source", "point") == "plane" else PI_SRC_POINT
     more = tuple(getattr(spec, "more_sources", ()))
     if len(more) > PI_MAX_SRC - 1:
@@ -537,7 +538,7 @@ class Server:
             raise RuntimeError("the photoionisation library needs a GPU (no CPU fallback)")
         torch.cuda.init()
         self.precision = precision
-        d = ServerDesc(hbm_budget, max_active, {"fp64": PI_FP64, "fp32": PI_FP32, "mixed": PI_MIXED}[precision],
+        d = ServerDesc(hbm_budget, max_active, PRECISIONS[precision],
                        steps_per_tick)
         h = C.c_void_p()
         check(lib().pi_server_create(C.byref(d), C.byref(h)))

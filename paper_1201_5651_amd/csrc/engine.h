@@ -80,7 +80,9 @@ struct Engine {
     hipGraphExec_t exec = nullptr;
 
     bool fp64() const { return precision == PI_FP64; }
-    bool mixed() const { return precision == PI_MIXED; }
+    bool mixed() const { return precision == PI_MIXED || precision == PI_MIXED_FRONT; }
+    // the double pass also takes the ionisation-front cells
+    bool front() const { return precision == PI_MIXED_FRONT; }
     int ngrids() const { return (int)grids.size(); }
     BatchDev bd() const;
 };

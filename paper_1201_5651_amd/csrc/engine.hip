@@ -310,7 +310,7 @@ pi_status chem_t(Engine& e, bool dev_dt, double h, int tau_buf, int from, int to
 {
     const BatchDev b = e.bd();
     HIP_OR(launch_chem<R>(gd<R>(e), b, e.chem_blocks, from, to, tau_buf, dev_dt, h, e.work,
-                          e.mixed(), s),
+                          e.mixed() ? (e.front() ? 2 : 1) : 0, s),
            "chemistry launch");
     if (e.mixed())
         HIP_OR(launch_chem_fix(gd<float>(e), b, e.fix_blocks, from, to, tau_buf, dev_dt, h, e.work,
@@ -355,7 +355,7 @@ template <typename R> pi_status step_a1_t(Engine& e, double t_end_arg, hipStream
     if (r != PI_OK) return r;
     for (size_t k = 0; k < e.stage_first[0].size(); ++k)
         HIP_OR(launch_sweep_a1<R>(gd<R>(e), e.tiles[0], e.stage_first[0][k], e.stage_count[0][k],
-                                  e.work, e.mixed(), s),
+                                  e.work, e.mixed() ? (e.front() ? 2 : 1) : 0, s),
                "algorithm 1 pass launch");
     if ((r = raytrace_t<R>(e, PI_BUF_N, PI_BUF_N, e.sweep >= 0 ? e.sweep : SWEEP_DEFAULT, s)) != PI_OK)
         return r;
@@ -811,7 +811,8 @@ size_t grid_private_bytes(const pi_grid_desc& d)
     b += sizeof(int) * 3 * 2;                      // launch prefix tables of one grid
     for (int w = 0; w < NSWEEP; ++w) b += sizeof(int4) * (size_t)tile_count(d, SWEEP_TILES[w]);
     b += sizeof(unsigned long long) * WORK_COUNTERS * WORK_SLOTS;
-    if (d.precision == PI_MIXED) b += 2 * sizeof(unsigned int) + sizeof(long long) * (size_t)n;
+    if (d.precision == PI_MIXED || d.precision == PI_MIXED_FRONT)
+        b += 2 * sizeof(unsigned int) + sizeof(long long) * (size_t)n;
     if (d.spectrum == PI_SPEC_TABLE) b += sizeof(DevTable<double>) + sizeof(DevTable<float>);
     return b;
 }

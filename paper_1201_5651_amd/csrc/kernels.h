@@ -133,11 +133,13 @@ hipError_t launch_plane_scan(const GridDev<R>* grids, const BatchDev& b, int row
 // cell length into x[1].
 template <typename R>
 hipError_t launch_sweep_a1(const GridDev<R>* grids, const int4* tiles, int first, int count,
-                           unsigned long long* ctr, bool mixed, hipStream_t s);
+                           unsigned long long* ctr, int mixed, hipStream_t s);
+// mixed: 0 none, 1 precision-sensitive cells to the double pass, 2 those and
+// the ionisation-front cells.
 template <typename R>
 hipError_t launch_chem(const GridDev<R>* grids, const BatchDev& b, int nblocks, int from, int to,
                        int tau_buf, bool dev_dt, double hscale, unsigned long long* ctr,
-                       bool mixed, hipStream_t s);
+                       int mixed, hipStream_t s);
 // Mixed precision: double re-solve of the cells listed by launch_chem, from the
 // unmodified float inputs; its last workgroup empties the list, so every
 // launch_chem with mixed must be followed by one launch_chem_fix.

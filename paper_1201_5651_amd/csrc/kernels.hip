@@ -366,11 +366,11 @@ __device__ __forceinline__ void chem_cell(const Params<C>& p, const Sources<C>& 
     }
 }
 
-// Micro-physics of every cell of every grid.  With mixed precision, an
-// ionisation-front cell (front_cell of its starting neutral fraction) is not
-// integrated in float, and a cell whose float integration took a
-// precision-sensitive decision is not written; both are appended to the
-// batch's re-solve list for the double pass.
+// Micro-physics of every cell of every grid.  With mixed precision a cell
+// whose float integration took a precision-sensitive decision is not
+// written, and with mixed == 2 an ionisation-front cell (front_cell of its
+// starting neutral fraction) is not integrated in float at all; both are
+// appended to the batch's re-solve list for the double pass.
 template <typename R, int MS>
 __global__ void __launch_bounds__(CHEM_BLOCK)
 __attribute__((amdgpu_waves_per_eu(MS > 1 ? ChemWaves<double>::value : ChemWaves<R>::value)))
@@ -401,8 +401,9 @@ k_chem(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int 
     if (inside) {
         const double hd = dev_dt ? hscale * G.st->dt : hscale;
         R x, E;
-        // mixed: an ionisation-front cell goes straight to the double pass
-        flag = mixed && front_cell(G.x[from][q]);
+        // with the front in double, an ionisation-front cell goes straight
+        // to the double pass
+        flag = mixed == 2 && front_cell(G.x[from][q]);
         if (!flag) {
             chem_cell<R, R, MS>(pl, G.src, q, i, j, k, G.nH, G.x[from], G.E[from],
                                 G.tau[tau_buf], hd, x, E, w);
@@ -581,7 +582,7 @@ k_sweep_a1(const GridDev<R>* __restrict__ grids, const int4* __restrict__ tiles,
             } else {
                 Work wc{};
                 // mixed: an ionisation-front cell is integrated in double only
-                const bool front = mixed && front_cell(x);
+                const bool front = mixed == 2 && front_cell(x);
                 if (!front) {
                     const Env<R> env = make_env(p, n, cg, tin);
                     micro_t<R, true>(p, env, R(hd), xo, Eo, wc, &tb);
@@ -836,11 +837,11 @@ hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, c
 
 template <typename R>
 hipError_t launch_sweep_a1(const GridDev<R>* grids, const int4* tiles, int first, int count,
-                           unsigned long long* ctr, bool mixed, hipStream_t s)
+                           unsigned long long* ctr, int mixed, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_sweep_a1<R>), dim3(count), dim3(64), 0, s, grids, tiles, first, ctr,
-                       (int)mixed);
+                       mixed);
     return hipGetLastError();
 }
 
@@ -857,15 +858,15 @@ hipError_t launch_plane_scan(const GridDev<R>* grids, const BatchDev& b, int row
 template <typename R>
 hipError_t launch_chem(const GridDev<R>* grids, const BatchDev& b, int nblocks, int from, int to,
                        int tau_buf, bool dev_dt, double hscale, unsigned long long* ctr,
-                       bool mixed, hipStream_t s)
+                       int mixed, hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
     if (b.kinds & 1)
         hipLaunchKernelGGL((k_chem<R, 1>), dim3(nblocks), dim3(CHEM_BLOCK), 0, s, grids, b, from,
-                           to, tau_buf, (int)dev_dt, hscale, ctr, (int)mixed);
+                           to, tau_buf, (int)dev_dt, hscale, ctr, mixed);
     if (b.kinds & 2)
         hipLaunchKernelGGL((k_chem<R, MAX_SRC>), dim3(nblocks), dim3(CHEM_BLOCK), 0, s, grids, b,
-                           from, to, tau_buf, (int)dev_dt, hscale, ctr, (int)mixed);
+                           from, to, tau_buf, (int)dev_dt, hscale, ctr, mixed);
     return hipGetLastError();
 }
 
@@ -916,14 +917,14 @@ hipError_t launch_energy(int64_t n, const R* nH, const R* x, R* E, double T0, hi
     template hipError_t launch_sweep_stage<R>(const GridDev<R>*, int, int, const int4*, int, int,  \
                                               int, hipStream_t);                                   \
     template hipError_t launch_chem<R>(const GridDev<R>*, const BatchDev&, int, int, int, int,    \
-                                       bool, double, unsigned long long*, bool, hipStream_t);      \
+                                       bool, double, unsigned long long*, int, hipStream_t);       \
     template hipError_t launch_dtdiag<R>(const GridDev<R>*, const BatchDev&, int, double,         \
                                          hipStream_t);                                             \
     template hipError_t launch_advance<R>(const GridDev<R>*, int, hipStream_t);                   \
     template hipError_t launch_plane_scan<R>(const GridDev<R>*, const BatchDev&, int, int, int,   \
                                              hipStream_t);                                         \
     template hipError_t launch_sweep_a1<R>(const GridDev<R>*, const int4*, int, int,              \
-                                           unsigned long long*, bool, hipStream_t);                \
+                                           unsigned long long*, int, hipStream_t);                 \
     template hipError_t launch_energy<R>(int64_t, const R*, const R*, R*, double, hipStream_t);
 PI_INSTANTIATE(double)
 PI_INSTANTIATE(float)

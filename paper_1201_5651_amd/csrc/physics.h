@@ -44,9 +44,12 @@ constexpr double REJ_E = 3.0;     // ... or changes E by more than this factor
 constexpr double MIX_MARGIN = 1e-3;
 // Ionisation-front cells of the mixed-precision path: a cell whose neutral
 // fraction at the start of the micro-integration lies in [FRONT_X_LO,
-// FRONT_X_HI] is integrated in double only (the float pass skips it).
+// FRONT_X_HI] -- the transition layer between the ionised gas (x < 1e-3) and
+// gas that is still mostly neutral (x > 1/2) -- is integrated in double only
+// (the float pass skips it).  Gas ahead of the front that the hardest photons
+// have only begun to ionise (1/2 < x < 1) is not part of the layer.
 constexpr double FRONT_X_LO = 1e-3;
-constexpr double FRONT_X_HI = 0.999;
+constexpr double FRONT_X_HI = 0.5;
 template <typename R> PI_HD __forceinline__ bool front_cell(R x)
 {
     return x >= R(FRONT_X_LO) && x <= R(FRONT_X_HI);

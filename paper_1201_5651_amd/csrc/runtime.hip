@@ -57,7 +57,8 @@ pi_status validate_desc(const pi_grid_desc* d)
     // advance
     for (int i = 0; i < 4; ++i)
         if (!(d->K[i] > 0)) return fail(PI_EINVAL, "K factors must be > 0 (inf disables)");
-    if (d->precision != PI_FP64 && d->precision != PI_FP32 && d->precision != PI_MIXED)
+    if (d->precision != PI_FP64 && d->precision != PI_FP32 && d->precision != PI_MIXED &&
+        d->precision != PI_MIXED_FRONT)
         return fail(PI_EINVAL, "precision");
     if (d->nsrc < 0 || d->nsrc > PI_MAX_SRC) return fail(PI_EINVAL, "nsrc must be in 0..PI_MAX_SRC");
     if (d->nsrc > 1) {

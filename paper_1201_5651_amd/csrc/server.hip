@@ -514,7 +514,8 @@ pi_status pi_server_create(const pi_server_desc* desc, pi_server** out)
     *out = nullptr;
     if (desc->max_active < 1 || desc->steps_per_tick < 1)
         return fail(PI_EINVAL, "max_active and steps_per_tick must be >= 1");
-    if (desc->precision != PI_FP64 && desc->precision != PI_FP32 && desc->precision != PI_MIXED)
+    if (desc->precision != PI_FP64 && desc->precision != PI_FP32 && desc->precision != PI_MIXED &&
+        desc->precision != PI_MIXED_FRONT)
         return fail(PI_EINVAL, "precision");
     std::unique_ptr<pi_server> s(new pi_server());
     s->desc = *desc;

@@ -186,15 +186,16 @@ def test_chem_parity_fp32(oracle_lib, thermal, spectrum):
     assert not bad, bad[:10]
 
 
+@pytest.mark.parametrize("precision", ["mixed", "mixed_front"])
 @pytest.mark.parametrize("thermal,spectrum", [("evolve", "mono"), ("evolve", "table")])
 @pytest.mark.parametrize("h", [1e10, 3e10])
-def test_chem_parity_mixed(oracle_lib, thermal, spectrum, h):
+def test_chem_parity_mixed(oracle_lib, thermal, spectrum, h, precision):
     """PI_MIXED: float bulk, and a double re-solve of every cell whose substep
     control decided within 1e-3 of a threshold.  The largest float errors come
     from such decisions going the other way (a different, equally valid choice
     of substeps), not from conditioning; with the re-solve every
     well-conditioned cell is within 1e-4 of the oracle on the same inputs."""
-    spec, g, pb, nH, x, E, tau = _chem_case(11, thermal, spectrum, "mixed")
+    spec, g, pb, nH, x, E, tau = _chem_case(11, thermal, spectrum, precision)
     g.work_counters(reset=True)
     g.chem_step(h, binding.PI_BUF_N, binding.PI_BUF_N, binding.PI_BUF_HALF)
     w = g.work_counters(reset=True)
@@ -203,11 +204,11 @@ def test_chem_parity_mixed(oracle_lib, thermal, spectrum, h):
     err = rel_x(to_np(g.x_half), xw)[well]
     Tg = pb.temperature(nH, to_np(g.x_half), to_np(g.E_half))
     Tw = pb.temperature(nH, xw, Ew)
-    front = int(((x >= 1e-3) & (x <= 0.999)).sum())
-    print("mixed: %d of %d cells re-solved in double (%d front cells); x err max %.3g, T err max %.3g"
-          % (w["resolved_fp64"], spec.ncells, front, err.max(), rel(Tg, Tw)[well].max()))
-    # every front cell is integrated in double, plus the cells whose float
-    # integration took a precision-sensitive decision
+    front = int(((x >= 1e-3) & (x <= 0.5)).sum()) if precision == "mixed_front" else 0
+    print("%s: %d of %d cells re-solved in double (%d front cells); x err max %.3g, T err max %.3g"
+          % (precision, w["resolved_fp64"], spec.ncells, front, err.max(), rel(Tg, Tw)[well].max()))
+    # the cells whose float integration took a precision-sensitive decision,
+    # and with mixed_front every front cell, are integrated in double
     assert front <= w["resolved_fp64"] < front + spec.ncells // 10
     assert err.max() < 1e-4
     assert rel(Tg, Tw)[well].max() < 1e-4
@@ -271,7 +272,7 @@ def test_cfg2_physics_steps_parity_fp64(oracle_lib):
     assert np.max(rel(Tg, Tw)) < 1e-9
 
 
-@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+@pytest.mark.parametrize("precision", ["fp32", "mixed", "mixed_front"])
 def test_cfg2_physics_steps_fp32(oracle_lib, precision):
     """Float and mixed A3 steps (the corrector updates the state in place)."""
     spec = synth.cfg2(n=24)
