@@ -399,10 +399,16 @@ pi_status pi_raytrace_static(const pi_grid_desc* desc, const pi_fields* fields, 
                              int tau_buf, void* stream);
 
 /* Raytrace tile edge: 4, 8 or 16 (cells of the cubic tile one workgroup
- * sweeps), or 0 to time them all on the next raytrace outside graph capture and keep the
- * faster (the default; that first raytrace then SYNCHRONISES its stream).  The
- * edge does not change any result: every cell's interpolation is the same.
- * pi_get_raytrace_tile returns 0 while untuned.  PI_EINVAL for other edges. */
+ * sweeps, one launch per tile diagonal), PI_TILE_PERSISTENT (8^3 tiles, the
+ * whole raytrace in one launch of persistent workgroups that claim tiles in
+ * wavefront order and wait on their upstream tiles' done-flags; a wait
+ * longer than 20 ms marks the raytrace invalid and the next
+ * synchronising call returns PI_EDEVICE), or 0 to time them all on the next
+ * raytrace outside graph capture and keep the fastest (the default; that
+ * first raytrace then SYNCHRONISES its stream).  The choice does not change
+ * any result: every cell's interpolation is the same.  pi_get_raytrace_tile
+ * returns 0 while untuned.  PI_EINVAL for other values. */
+#define PI_TILE_PERSISTENT 0x108
 pi_status pi_set_raytrace_tile(pi_grid* grid, int edge);
 pi_status pi_get_raytrace_tile(pi_grid* grid, int* edge);
 pi_status pi_batch_set_raytrace_tile(pi_batch* batch, int edge);

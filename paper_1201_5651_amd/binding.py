@@ -29,6 +29,7 @@ PI_NDIAG = 8
 PI_NWORK = 5
 PI_NTAB = 64
 PI_MAX_SRC = 4
+PI_TILE_PERSISTENT = 0x108
 
 # every symbol include/pi.h declares
 ABI_SYMBOLS = (

@@ -59,7 +59,19 @@ struct Engine {
     int4* tiles[NSWEEP] = {};
     size_t tiles_cap[NSWEEP] = {};
     std::vector<int> stage_first[NSWEEP], stage_count[NSWEEP];
-    int sweep = -1;                  // index into SWEEP_TILES; -1 until tuned
+    // raytrace variant: 0..NSWEEP-1 one launch per tile diagonal with tiles
+    // of edge SWEEP_TILES[sweep]; SWEEP_PERSIST one persistent launch over
+    // the schedule of edge PERSIST_TILE; -1 until tuned
+    int sweep = -1;
+    // persistent raytrace: per raytrace entry and octant (first done-flag,
+    // tiles along x, y, z), one done-flag per tile, the control block, and
+    // the workgroups of a launch
+    int4* octs = nullptr;
+    size_t octs_cap = 0;
+    unsigned* flags = nullptr;
+    size_t flags_cap = 0;
+    SweepCtl* ctl = nullptr;
+    int persist_wg = 0;
     unsigned int* fix_n = nullptr;
     long long* fix_list = nullptr;
     size_t fix_cap = 0;

@@ -283,11 +283,29 @@ template <typename R> const GridDev<R>* gd(const Engine& e)
     return static_cast<const GridDev<R>*>(e.gdev);
 }
 
+// Longest wait of a persistent raytrace tile for its upstream tiles before
+// the sweep gives up (ticks of the 100 MHz real-time counter): 20 ms, about
+// two hundred times the time a tile takes, so that a sweep whose waits all
+// failed would still end within a second.
+constexpr long long PERSIST_SPIN_TICKS = 2000000LL;
+
 template <typename R>
 pi_status raytrace_t(Engine& e, int state, int tau_buf, int which, hipStream_t s)
 {
+    static_assert(SWEEP_TILES[PERSIST_SCHEDULE] == PERSIST_TILE, "schedule of the persistent sweep");
     HIP_OR(launch_plane_scan<R>(gd<R>(e), e.bd(), e.plane_rows, state, tau_buf, s),
            "plane-parallel raytrace launch");
+    if (which == SWEEP_PERSIST) {
+        const int w = PERSIST_SCHEDULE;
+        const int ntiles = e.stage_first[w].empty()
+                               ? 0
+                               : e.stage_first[w].back() + e.stage_count[w].back();
+        HIP_OR(launch_sweep_persist<R>(gd<R>(e), state, tau_buf, e.tiles[w], ntiles, e.octs,
+                                       e.flags, e.ctl, std::min(ntiles, e.persist_wg),
+                                       PERSIST_SPIN_TICKS, s),
+               "persistent raytrace launch");
+        return PI_OK;
+    }
     for (size_t k = 0; k < e.stage_first[which].size(); ++k)
         HIP_OR(launch_sweep_stage<R>(gd<R>(e), state, tau_buf, e.tiles[which],
                                      e.stage_first[which][k], e.stage_count[which][k],
@@ -555,6 +573,63 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
                              hipMemcpyHostToDevice),
                    "tile schedule upload");
     }
+    // persistent raytrace: flag bases per raytrace entry and octant (edge
+    // PERSIST_TILE), one flag per tile, the control block
+    {
+        const int R = G + (int)e.extra.size();
+        std::vector<int4> oct(8 * (size_t)std::max(R, 1), make_int4(0, 0, 0, 0));
+        int64_t nflag = 0;
+        for (int r = 0; r < R; ++r) {
+            const int g = r < G ? r : e.extra[r - G].x;
+            const int src = r < G ? 0 : e.extra[r - G].y;
+            const pi_grid_desc& d = e.grids[g]->d;
+            if (d.source == PI_SRC_PLANE) continue;
+            const int32_t* v = source_vertex(d, src);
+            for (int o = 0; o < 8; ++o) {
+                int nt[3];
+                for (int a = 0; a < 3; ++a) {
+                    const int ext = ((o >> a) & 1) ? d.n[a] - v[a] : v[a];
+                    nt[a] = ext > 0 ? (ext + PERSIST_TILE - 1) / PERSIST_TILE : 0;
+                }
+                oct[8 * r + o] = make_int4((int)nflag, nt[0], nt[1], nt[2]);
+                nflag += (int64_t)nt[0] * nt[1] * nt[2];
+            }
+        }
+        if (nflag > 2147483647LL) return fail(PI_EINVAL, "batch too large for the raytrace flags");
+        const size_t ob = sizeof(int4) * oct.size();
+        if (ob > e.octs_cap) {
+            if (e.octs) (void)hipFree(e.octs);
+            e.octs = nullptr;
+            e.octs_cap = 0;
+            HIP_OR(hipMalloc(&e.octs, ob), "octant table allocation");
+            e.octs_cap = ob;
+        }
+        HIP_OR(hipMemcpy(e.octs, oct.data(), ob, hipMemcpyHostToDevice), "octant table upload");
+        const size_t fb = sizeof(unsigned) * (size_t)std::max<int64_t>(nflag, 1);
+        if (fb > e.flags_cap) {
+            // fresh flags are zero: below the done value of every call, so a
+            // flag left from another layout or an earlier call never reads done
+            if (e.flags) (void)hipFree(e.flags);
+            e.flags = nullptr;
+            e.flags_cap = 0;
+            HIP_OR(hipMalloc(&e.flags, fb), "raytrace flag allocation");
+            HIP_OR(hipMemset(e.flags, 0, fb), "raytrace flag clear");
+            e.flags_cap = fb;
+        }
+        if (!e.ctl) {
+            HIP_OR(hipMalloc(&e.ctl, sizeof(SweepCtl)), "raytrace control allocation");
+            HIP_OR(hipMemset(e.ctl, 0, sizeof(SweepCtl)), "raytrace control clear");
+        }
+        if (e.persist_wg == 0) {
+            int dev = 0, cus = 0;
+            HIP_OR(hipGetDevice(&dev), "device query");
+            HIP_OR(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev),
+                   "device query");
+            const int per = e.fp64() ? sweep_persist_occupancy<double>()
+                                     : sweep_persist_occupancy<float>();
+            e.persist_wg = std::max(1, per * cus);
+        }
+    }
     // work counters
     if (!e.work) {
         const size_t wb = sizeof(unsigned long long) * WORK_COUNTERS * WORK_SLOTS;
@@ -587,8 +662,14 @@ void engine_free(Engine& e)
     drop_graph(e);
     if (e.cap) (void)hipStreamDestroy(e.cap);
     e.cap = nullptr;
-    for (void* p : { e.gdev, (void*)e.first, (void*)e.fix_n, (void*)e.fix_list, (void*)e.work })
+    for (void* p : { e.gdev, (void*)e.first, (void*)e.fix_n, (void*)e.fix_list, (void*)e.work,
+                     (void*)e.octs, (void*)e.flags, (void*)e.ctl })
         if (p) (void)hipFree(p);
+    e.octs = nullptr;
+    e.flags = nullptr;
+    e.ctl = nullptr;
+    e.octs_cap = e.flags_cap = 0;
+    e.persist_wg = 0;
     for (int w = 0; w < NSWEEP; ++w) {
         if (e.tiles[w]) (void)hipFree(e.tiles[w]);
         e.tiles[w] = nullptr;
@@ -622,7 +703,8 @@ pi_status engine_autotune(Engine& e, int state, int tau_buf, hipStream_t s)
     float best = 0.0f;
     int pick = SWEEP_DEFAULT;
     pi_status r = PI_OK;
-    for (int w = 0; w < NSWEEP && r == PI_OK; ++w) {
+    for (int w = 0; w <= SWEEP_PERSIST && r == PI_OK; ++w) {
+        if (w >= NSWEEP && w != SWEEP_PERSIST) continue;
         // the second of two runs (the first warms the caches)
         r = raytrace_any(e, state, tau_buf, w, s);
         if (r == PI_OK && hipEventRecord(ev[0], s) != hipSuccess) r = fail(PI_EDEVICE, "event record");
@@ -718,7 +800,16 @@ pi_status engine_read_states(Engine& e, std::vector<DevState>& out, hipStream_t 
     for (size_t g = 0; g < e.grids.size(); ++g)
         HIP_OR(hipMemcpyAsync(&out[g], e.grids[g]->st, sizeof(DevState), hipMemcpyDeviceToHost, s),
                "state read");
+    SweepCtl c{};
+    if (e.ctl) HIP_OR(hipMemcpyAsync(&c, e.ctl, sizeof(c), hipMemcpyDeviceToHost, s), "state read");
     HIP_OR(hipStreamSynchronize(s), "state read sync");
+    if (c.err) {
+        // reported once; the columns of that raytrace are not valid
+        const unsigned zero = 0;
+        HIP_OR(hipMemcpy(&e.ctl->err, &zero, sizeof(zero), hipMemcpyHostToDevice), "state write");
+        return fail(PI_EDEVICE, "a persistent raytrace tile waited longer than its limit for its "
+                                "upstream tiles; the columns are not valid");
+    }
     return PI_OK;
 }
 

@@ -113,12 +113,35 @@ struct BatchDev {
     int kinds;
 };
 
+// Control block of the persistent raytrace (zeroed once when allocated): the
+// next tile ticket, the workgroups that have left, the epoch of the last
+// completed call (done-flags of the current call hold epoch + 1), and an
+// error flag set when a wait exceeded its limit.
+struct SweepCtl {
+    unsigned ticket, exited, epoch, err;
+};
+// Tile edge of the persistent raytrace, and the index of its variant after
+// the one-launch-per-stage variants of SWEEP_TILES.
+constexpr int PERSIST_TILE = 8;
+constexpr int SWEEP_PERSIST = 3;
+constexpr int PERSIST_SCHEDULE = 1;   // SWEEP_TILES[1] == PERSIST_TILE
+
 // One tile-diagonal stage of the raytrace of every grid with tiles of edge
 // `tile` (one of SWEEP_TILES): tiles[first .. first + count) are
 // (grid << 3 | octant, tx, ty, tz).
 template <typename R>
 hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,
                               int first, int count, int tile, hipStream_t s);
+// The whole raytrace of every grid in one launch of nwg persistent workgroups
+// over the schedule tiles[0 .. ntiles) of edge PERSIST_TILE (stage after
+// stage); octs[grid << 3 | octant] = (first done-flag, tiles along x, y, z);
+// flags: one per tile.  spin_ticks bounds each wait (100 MHz ticks).
+template <typename R>
+hipError_t launch_sweep_persist(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,
+                                int ntiles, const int4* octs, unsigned* flags, SweepCtl* ctl,
+                                int nwg, long long spin_ticks, hipStream_t s);
+// Resident workgroups of the persistent raytrace kernel on one CU.
+template <typename R> int sweep_persist_occupancy();
 // Micro-physics of every cell of every grid from state `from` on columns
 // `tau_buf` into state `to`, over h = hscale * (st->dt if dev_dt else 1).
 // With mixed, precision-sensitive cells are listed for launch_chem_fix.

@@ -112,19 +112,22 @@ template <int TT> struct SweepShape {
     static constexpr int CPT = CELLS / THREADS;
 };
 
-template <typename R, int TT>
-__global__ void __launch_bounds__(SweepShape<TT>::THREADS)
-k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
-        const int4* __restrict__ tiles, int first)
+// The sweep of one tile (the body of both raytrace kernels), with the LDS
+// arrays of the workgroup.  wait() runs between the loads that do not depend
+// on earlier tiles (sigma0 n_H x dx of the tile and its halo, the cells'
+// geometry) and the loads that do (the columns of the upstream halo); every
+// thread calls it, and the caller's synchronisation follows it.  Coherent:
+// the upstream columns are read and the tile's columns written as relaxed
+// atomics at agent scope (loads and stores that reach the device-wide point
+// of coherence, past the caches of the compute unit and of its XCD), for a
+// sweep whose tiles depend on tiles of the same launch.
+template <typename R, int TT, bool Coherent, typename Wait>
+__device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids, int state,
+                                           int tau_buf, int4 tl, R* s_tc, R* s_kap, Wait wait)
 {
     constexpr int TX = TT, TY = TT, TZ = TT;
     constexpr int NT = SweepShape<TT>::THREADS, CPT = SweepShape<TT>::CPT;
     constexpr int HX = TX + 1, HY = TY + 1, HZ = TZ + 1, NHALO = HX * HY * HZ;
-    static_assert(NHALO >= TX * TY * TZ, "the output reuses the halo buffer");
-    __shared__ R s_tc[NHALO];
-    __shared__ R s_kap[NHALO];
-
-    const int4 tl = tiles[first + blockIdx.x];
     const GridDev<R>& G = grids[tl.x >> 3];
     const Params<R> p = G.p;
     const R* __restrict__ nH = G.nHr[state];
@@ -140,23 +143,15 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     for (int q = threadIdx.x; q < NHALO; q += NT) {
         const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
         const int Lx = X0 + hx - 1, Ly = Y0 + hy - 1, Lz = Z0 + hz - 1;
-        R kap = R(0), tc = R(0);
+        R kap = R(0);
         if (Lx >= 0 && Ly >= 0 && Lz >= 0 && Lx < ex && Ly < ey && Lz < ez) {
             const int gi = px ? p.sx + Lx : p.sx - 1 - Lx;
             const int gj = py ? p.sy + Ly : p.sy - 1 - Ly;
             const int gk = pz ? p.sz + Lz : p.sz - 1 - Lz;
             const int64_t g = gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk);
             kap = p.sdx * nH[g] * xs[g];
-            if (hx == 0 || hy == 0 || hz == 0) {
-                const R ax = R(Lx) + R(0.5), ay = R(Ly) + R(0.5), az = R(Lz) + R(0.5);
-                const R da = (az >= ax && az >= ay) ? az : (ay >= ax ? ay : ax);
-                const R hds = R(0.5) * r_sqrt(ax * ax + ay * ay + az * az) / da;
-                // the centre column exactly as the cell's own tile formed it
-                tc = r_fma(hds, kap, tau[g]);
-            }
         }
         s_kap[q] = kap;
-        s_tc[q] = tc;
     }
     __syncthreads();
 
@@ -203,6 +198,32 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
         tin[k] = R(0);
     }
 
+    wait();
+    __syncthreads();
+    // centre columns of the upstream halo (the faces at local index -1)
+    for (int q = threadIdx.x; q < NHALO; q += NT) {
+        const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
+        const int Lx = X0 + hx - 1, Ly = Y0 + hy - 1, Lz = Z0 + hz - 1;
+        R tc = R(0);
+        if ((hx == 0 || hy == 0 || hz == 0) && Lx >= 0 && Ly >= 0 && Lz >= 0 && Lx < ex &&
+            Ly < ey && Lz < ez) {
+            const int gi = px ? p.sx + Lx : p.sx - 1 - Lx;
+            const int gj = py ? p.sy + Ly : p.sy - 1 - Ly;
+            const int gk = pz ? p.sz + Lz : p.sz - 1 - Lz;
+            const int64_t g = gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk);
+            const R ax = R(Lx) + R(0.5), ay = R(Ly) + R(0.5), az = R(Lz) + R(0.5);
+            const R da = (az >= ax && az >= ay) ? az : (ay >= ax ? ay : ax);
+            const R hh = R(0.5) * r_sqrt(ax * ax + ay * ay + az * az) / da;
+            // the centre column exactly as the cell's own tile formed it
+            const R up = Coherent
+                             ? __hip_atomic_load(&tau[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                             : tau[g];
+            tc = r_fma(hh, s_kap[q], up);
+        }
+        s_tc[q] = tc;
+    }
+    __syncthreads();
+
     for (int s = 0; s < TX + TY + TZ - 2; ++s) {
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
@@ -233,7 +254,125 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
             const int gi = px ? p.sx + Lx : p.sx - 1 - Lx;
             const int gj = py ? p.sy + Ly : p.sy - 1 - Ly;
             const int gk = pz ? p.sz + Lz : p.sz - 1 - Lz;
-            tau[gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk)] = s_out[t];
+            R* dst = &tau[gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk)];
+            if (Coherent)
+                __hip_atomic_store(dst, s_out[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                *dst = s_out[t];
+        }
+    }
+}
+
+// One tile-diagonal stage of the octant sweeps of every grid of a batch: one
+// workgroup per tile of the stage, all of whose upstream tiles belong to
+// earlier launches.
+template <typename R, int TT>
+__global__ void __launch_bounds__(SweepShape<TT>::THREADS)
+k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
+        const int4* __restrict__ tiles, int first)
+{
+    constexpr int NHALO = (TT + 1) * (TT + 1) * (TT + 1);
+    static_assert(NHALO >= TT * TT * TT, "the output reuses the halo buffer");
+    __shared__ R s_tc[NHALO];
+    __shared__ R s_kap[NHALO];
+    sweep_tile<R, TT, false>(grids, state, tau_buf, tiles[first + blockIdx.x], s_tc, s_kap,
+                             [] {});
+}
+
+// The whole raytrace in one launch: persistent workgroups claim tiles in the
+// order of the schedule (stage by stage) from a ticket and wait, before
+// reading a tile's upstream halo, until the tiles across its three upstream
+// faces are done (those tiles waited in turn for theirs, so every tile of
+// the halo is done).  Claiming in schedule order keeps every wait on a tile
+// that a running workgroup holds, so the sweep cannot deadlock.  Flags carry
+// the epoch of the call (ctl->epoch + 1); the last workgroup to leave resets
+// the ticket and advances the epoch, so replays of a captured graph need no
+// reset.  A wait longer than spin_ticks (of the 100 MHz real-time counter)
+// sets ctl->err and goes on, so every workgroup exits; the result is then
+// reported invalid.
+//
+// Columns pass between tiles without cache maintenance: a tile writes its
+// columns, and reads its upstream halo, as relaxed atomics at agent scope,
+// which go to the device-wide point of coherence instead of the caches of
+// one compute unit or one XCD.  Every wave waits for its column stores to
+// complete (vmcnt 0) before the workgroup barrier that precedes the flag
+// store, so a flag is seen only after the columns it covers are in place.
+// (An agent-scope release and acquire per tile would write back and
+// invalidate the L2 of the XCD on every tile instead.)
+//
+// The claims, waits and flag stores are made by the whole of wave 0, under
+// branches on values made uniform with readfirstlane, never under a branch
+// on the lane (threadIdx.x == 0): the compiler may merge the lane-0 flag
+// store at the end of one tile with the lane-0 claim at the start of the
+// next, and a branch on the lane then splits wave 0 into lane 0 (store and
+// claim) and the other lanes (straight back to the next tile), which loop
+// on the old ticket forever while lane 0 waits for them to rejoin.  Wave-
+// uniform branches keep every wave whole; all lanes of wave 0 store the same
+// value, and only lane 0 adds 1 to a counter (the others add 0).
+template <typename R, int TT>
+__global__ void __launch_bounds__(SweepShape<TT>::THREADS)
+k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
+                const int4* __restrict__ tiles, int ntiles, const int4* __restrict__ octs,
+                unsigned* __restrict__ flags, SweepCtl* ctl, long long spin_ticks)
+{
+    constexpr int NHALO = (TT + 1) * (TT + 1) * (TT + 1);
+    __shared__ R s_tc[NHALO];
+    __shared__ R s_kap[NHALO];
+    __shared__ int s_ticket;
+    const bool lead = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) == 0;
+    const unsigned add = (threadIdx.x & 63) == 0 ? 1u : 0u;
+    const unsigned done =
+        __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) + 1u;
+    for (;;) {
+        if (lead) {
+            // lane 0 takes the ticket (the others add 0); every lane of wave 0
+            // writes lane 0's value
+            const unsigned c = __hip_atomic_fetch_add(&ctl->ticket, add, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            s_ticket = (int)__builtin_amdgcn_readfirstlane(c);
+        }
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(s_ticket);
+        __syncthreads();   // (s_ticket is rewritten by the next claim)
+        if (t >= ntiles) break;
+        const int4 tl = tiles[t];
+        const int4 oc = octs[tl.x];                         // flag base, tiles per axis
+        const int idx = oc.x + (tl.w * oc.z + tl.z) * oc.y + tl.y;
+        sweep_tile<R, TT, true>(grids, state, tau_buf, tl, s_tc, s_kap, [&] {
+            if (lead) {
+                const int up[3] = { tl.y > 0 ? idx - 1 : -1, tl.z > 0 ? idx - oc.y : -1,
+                                    tl.w > 0 ? idx - oc.y * oc.z : -1 };
+                for (int u = 0; u < 3; ++u) {
+                    if (up[u] < 0) continue;
+                    const long long t0 = (long long)__builtin_amdgcn_s_memrealtime();
+                    for (;;) {
+                        const unsigned f = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                            &flags[up[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                        if (f == done) break;
+                        __builtin_amdgcn_s_sleep(2);
+                        if ((long long)__builtin_amdgcn_s_memrealtime() - t0 > spin_ticks) {
+                            __hip_atomic_store(&ctl->err, 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                            break;
+                        }
+                    }
+                }
+            }
+        });
+        // every wave's column stores complete, then the flag
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (lead)
+            __hip_atomic_store(&flags[idx], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (lead) {
+        const unsigned left = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(
+            &ctl->exited, add, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT));
+        if (left == gridDim.x - 1) {
+            __hip_atomic_store(&ctl->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->exited, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->epoch, done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -836,6 +975,28 @@ hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, c
 }
 
 template <typename R>
+hipError_t launch_sweep_persist(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,
+                                int ntiles, const int4* octs, unsigned* flags, SweepCtl* ctl,
+                                int nwg, long long spin_ticks, hipStream_t s)
+{
+    if (ntiles <= 0 || nwg <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_sweep_persist<R, PERSIST_TILE>), dim3(nwg),
+                       dim3(SweepShape<PERSIST_TILE>::THREADS), 0, s, grids, state, tau_buf, tiles,
+                       ntiles, octs, flags, ctl, spin_ticks);
+    return hipGetLastError();
+}
+
+template <typename R> int sweep_persist_occupancy()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sweep_persist<R, PERSIST_TILE>,
+                                                     SweepShape<PERSIST_TILE>::THREADS, 0) !=
+        hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+template <typename R>
 hipError_t launch_sweep_a1(const GridDev<R>* grids, const int4* tiles, int first, int count,
                            unsigned long long* ctr, int mixed, hipStream_t s)
 {
@@ -916,6 +1077,10 @@ hipError_t launch_energy(int64_t n, const R* nH, const R* x, R* E, double T0, hi
 #define PI_INSTANTIATE(R)                                                                          \
     template hipError_t launch_sweep_stage<R>(const GridDev<R>*, int, int, const int4*, int, int,  \
                                               int, hipStream_t);                                   \
+    template hipError_t launch_sweep_persist<R>(const GridDev<R>*, int, int, const int4*, int,     \
+                                                const int4*, unsigned*, SweepCtl*, int, long long, \
+                                                hipStream_t);                                      \
+    template int sweep_persist_occupancy<R>();                                                     \
     template hipError_t launch_chem<R>(const GridDev<R>*, const BatchDev&, int, int, int, int,    \
                                        bool, double, unsigned long long*, int, hipStream_t);       \
     template hipError_t launch_dtdiag<R>(const GridDev<R>*, const BatchDev&, int, double,         \

@@ -342,17 +342,24 @@ pi_status set_tile(Engine& e, int edge)
 {
     if (edge == 0) {
         e.sweep = -1;
+    } else if (edge == PI_TILE_PERSISTENT) {
+        e.sweep = SWEEP_PERSIST;
     } else {
         int w = -1;
         for (int k = 0; k < NSWEEP; ++k)
             if (SWEEP_TILES[k] == edge) w = k;
-        if (w < 0) return fail(PI_EINVAL, "raytrace tile edge must be 0, 4, 8 or 16");
+        if (w < 0)
+            return fail(PI_EINVAL, "raytrace tile edge must be 0, 4, 8, 16 or PI_TILE_PERSISTENT");
         e.sweep = w;
     }
     engine_build(e, e.grids);   // drops a graph captured with the old tiles
     return PI_OK;
 }
-int get_tile(const Engine& e) { return e.sweep >= 0 ? SWEEP_TILES[e.sweep] : 0; }
+int get_tile(const Engine& e)
+{
+    if (e.sweep == SWEEP_PERSIST) return PI_TILE_PERSISTENT;
+    return e.sweep >= 0 ? SWEEP_TILES[e.sweep] : 0;
+}
 }  // namespace
 
 pi_status pi_set_raytrace_tile(pi_grid* g, int edge)

@@ -56,22 +56,26 @@ def test_raytrace_parity_fp64(oracle_lib, shape, src, weights):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_raytrace_tile_edges_give_identical_columns(precision):
     """Tiling changes the order of the sweep, not the arithmetic of any cell:
-    4^3, 8^3 and 16^3 tiles give bitwise equal columns, and tuning settles on
-    one of them."""
+    4^3, 8^3 and 16^3 tiles, one launch per tile diagonal, and the persistent
+    single-launch sweep give bitwise equal columns, and tuning settles on one
+    of them."""
     spec = _spec((19, 22, 17), (7, 15, 9))
     rng = np.random.default_rng(21)
     g = binding.Grid(spec, precision=precision)
     assert g.raytrace_tile == 0
     g.load(rng.uniform(0.2, 5.0, spec.shape), rng.uniform(0.0, 1.0, spec.shape))
-    assert g.raytrace_tile in (4, 8, 16)
+    P = binding.PI_TILE_PERSISTENT
+    assert g.raytrace_tile in (4, 8, 16, P)
     cols = {}
-    for edge in (4, 8, 16):
+    for edge in (4, 8, 16, P, P):
         g.raytrace_tile = edge
         g.tau.zero_()
         g.raytrace()
         cols[edge] = to_np(g.tau)
+        assert g.state()[1] == 0   # (a synchronising read: no wait went over its limit)
     assert np.array_equal(cols[4], cols[8])
     assert np.array_equal(cols[4], cols[16])
+    assert np.array_equal(cols[4], cols[P])
     with pytest.raises(binding.PiError):
         g.raytrace_tile = 5
     g.close()

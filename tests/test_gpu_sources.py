@@ -45,12 +45,15 @@ def test_columns_of_every_source(oracle_lib, nsrc, precision):
     m = want > 0
     assert np.max(rel(got[m], want[m])) < (1e-12 if precision == "fp64" else 1e-5)
     cols = {}
-    for edge in (4, 8, 16):
+    P = binding.PI_TILE_PERSISTENT
+    for edge in (4, 8, 16, P):
         g.raytrace_tile = edge
         g.tau.zero_()
         g.raytrace()
         cols[edge] = to_np(g.tau)
     assert np.array_equal(cols[4], cols[8]) and np.array_equal(cols[4], cols[16])
+    assert np.array_equal(cols[4], cols[P])
+    g.state()   # no persistent wait went over its limit
     g.close()
 
 
