@@ -401,9 +401,8 @@ pi_status pi_raytrace_static(const pi_grid_desc* desc, const pi_fields* fields, 
 /* Raytrace tile edge: 4, 8 or 16 (cells of the cubic tile one workgroup
  * sweeps, one launch per tile diagonal), PI_TILE_PERSISTENT (8^3 tiles, the
  * whole raytrace in one launch of persistent workgroups that claim tiles in
- * wavefront order and wait on their upstream tiles' done-flags; a wait
- * longer than 20 ms marks the raytrace invalid and the next
- * synchronising call returns PI_EDEVICE), or 0 to time them all on the next
+ * wavefront order and wait on their upstream tiles' done-flags, each wait
+ * bounded by pi_set_raytrace_wait_limit), or 0 to time them all on the next
  * raytrace outside graph capture and keep the fastest (the default; that
  * first raytrace then SYNCHRONISES its stream).  The choice does not change
  * any result: every cell's interpolation is the same.  pi_get_raytrace_tile
@@ -414,12 +413,24 @@ pi_status pi_get_raytrace_tile(pi_grid* grid, int* edge);
 pi_status pi_batch_set_raytrace_tile(pi_batch* batch, int edge);
 pi_status pi_batch_get_raytrace_tile(pi_batch* batch, int* edge);
 
+/* Longest wait, in seconds, of a tile of the persistent raytrace
+ * (PI_TILE_PERSISTENT) for its upstream tiles; 0.02 by default.  A wait that
+ * runs out lets the workgroup go on with the columns as they stand, so the
+ * launch always ends; the raytrace is then invalid and the next
+ * synchronising call on the grid or batch returns PI_EDEVICE (once).  Any
+ * value in [0, PI_WAIT_LIMIT_MAX]; 0 fails every wait that is not met at its
+ * first look (a way to exercise that path).  Drops a captured step graph.
+ * PI_EINVAL outside the range.  The staged raytraces do not wait. */
+#define PI_WAIT_LIMIT_MAX 10.0
+pi_status pi_set_raytrace_wait_limit(pi_grid* grid, double seconds);
+pi_status pi_batch_set_raytrace_wait_limit(pi_batch* batch, double seconds);
+
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char* pi_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns the
  * value it was built with. */
-#define PI_ABI_VERSION 109
+#define PI_ABI_VERSION 110
 int pi_abi_version(void);
 
 #ifdef __cplusplus

@@ -30,6 +30,7 @@ PI_NWORK = 5
 PI_NTAB = 64
 PI_MAX_SRC = 4
 PI_TILE_PERSISTENT = 0x108
+PI_WAIT_LIMIT_MAX = 10.0
 
 # every symbol include/pi.h declares
 ABI_SYMBOLS = (
@@ -41,7 +42,7 @@ ABI_SYMBOLS = (
     "pi_batch_work_counters",
     "pi_server_create", "pi_submit", "pi_poll", "pi_cancel", "pi_server_stats", "pi_server_destroy",
     "pi_set_raytrace_tile", "pi_get_raytrace_tile", "pi_batch_set_raytrace_tile",
-    "pi_batch_get_raytrace_tile",
+    "pi_batch_get_raytrace_tile", "pi_set_raytrace_wait_limit", "pi_batch_set_raytrace_wait_limit",
     "pi_step_a1",
     "pi_batch_step_a1",
     "pi_grid_required_bytes", "pi_grid_save", "pi_grid_load", "pi_checkpoint",
@@ -152,6 +153,8 @@ def lib() -> C.CDLL:
         L.pi_get_raytrace_tile.argtypes = [vp, ip]
         L.pi_batch_set_raytrace_tile.argtypes = [vp, i32]
         L.pi_batch_get_raytrace_tile.argtypes = [vp, ip]
+        L.pi_set_raytrace_wait_limit.argtypes = [vp, C.c_double]
+        L.pi_batch_set_raytrace_wait_limit.argtypes = [vp, C.c_double]
         szp = C.POINTER(C.c_size_t)
         L.pi_grid_required_bytes.argtypes = [C.POINTER(GridDesc), szp, szp]
         L.pi_grid_save.argtypes = [vp, vp, C.c_size_t, szp, vp]
@@ -363,6 +366,10 @@ class Grid:
     def raytrace_tile(self, edge: int):
         check(lib().pi_set_raytrace_tile(self._h, int(edge)))
 
+    def set_raytrace_wait_limit(self, seconds: float):
+        """pi_set_raytrace_wait_limit: longest wait of a persistent raytrace tile."""
+        check(lib().pi_set_raytrace_wait_limit(self._h, float(seconds)))
+
     def work_counters(self, reset: bool = False):
         out = (C.c_int64 * PI_NWORK)()
         check(lib().pi_work_counters(self._h, out, int(reset), self._stream()))
@@ -482,6 +489,10 @@ class Batch:
     @raytrace_tile.setter
     def raytrace_tile(self, edge: int):
         check(lib().pi_batch_set_raytrace_tile(self._h, int(edge)))
+
+    def set_raytrace_wait_limit(self, seconds: float):
+        """pi_batch_set_raytrace_wait_limit: longest wait of a persistent raytrace tile."""
+        check(lib().pi_batch_set_raytrace_wait_limit(self._h, float(seconds)))
 
     def state(self):
         t, dt = (C.c_double * self.n)(), (C.c_double * self.n)()

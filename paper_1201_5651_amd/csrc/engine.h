@@ -72,6 +72,9 @@ struct Engine {
     size_t flags_cap = 0;
     SweepCtl* ctl = nullptr;
     int persist_wg = 0;
+    // longest wait of a persistent tile for its upstream tiles (ticks of the
+    // 100 MHz real-time counter); 2e6 = 20 ms unless the caller sets it
+    long long persist_spin = 2000000LL;
     unsigned int* fix_n = nullptr;
     long long* fix_list = nullptr;
     size_t fix_cap = 0;
@@ -103,6 +106,8 @@ struct Engine {
 // keeps allocations whose capacity suffices and drops a captured step graph.
 pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids);
 void engine_free(Engine& e);
+// Destroys a captured step graph (the next step captures a new one).
+void engine_drop_graph(Engine& e);
 void free_tables(std::vector<Engine::Table>& tables);
 
 // Raytrace with the tuned tile edge; the first call outside graph capture times

@@ -283,12 +283,6 @@ template <typename R> const GridDev<R>* gd(const Engine& e)
     return static_cast<const GridDev<R>*>(e.gdev);
 }
 
-// Longest wait of a persistent raytrace tile for its upstream tiles before
-// the sweep gives up (ticks of the 100 MHz real-time counter): 20 ms, about
-// two hundred times the time a tile takes, so that a sweep whose waits all
-// failed would still end within a second.
-constexpr long long PERSIST_SPIN_TICKS = 2000000LL;
-
 template <typename R>
 pi_status raytrace_t(Engine& e, int state, int tau_buf, int which, hipStream_t s)
 {
@@ -302,7 +296,7 @@ pi_status raytrace_t(Engine& e, int state, int tau_buf, int which, hipStream_t s
                                : e.stage_first[w].back() + e.stage_count[w].back();
         HIP_OR(launch_sweep_persist<R>(gd<R>(e), state, tau_buf, e.tiles[w], ntiles, e.octs,
                                        e.flags, e.ctl, std::min(ntiles, e.persist_wg),
-                                       PERSIST_SPIN_TICKS, s),
+                                       e.persist_spin, s),
                "persistent raytrace launch");
         return PI_OK;
     }
@@ -656,6 +650,8 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
     }
     return e.fp64() ? upload_grids<double>(e) : upload_grids<float>(e);
 }
+
+void engine_drop_graph(Engine& e) { drop_graph(e); }
 
 void engine_free(Engine& e)
 {

@@ -388,6 +388,29 @@ pi_status pi_batch_get_raytrace_tile(pi_batch* b, int* edge)
     return PI_OK;
 }
 
+namespace {
+pi_status set_wait_limit(Engine& e, double seconds)
+{
+    if (!(seconds >= 0.0 && seconds <= PI_WAIT_LIMIT_MAX))
+        return fail(PI_EINVAL, "raytrace wait limit must lie in [0, PI_WAIT_LIMIT_MAX] seconds");
+    e.persist_spin = (long long)(seconds * 1e8);
+    engine_drop_graph(e);   // a captured graph holds the old limit
+    return PI_OK;
+}
+}  // namespace
+
+pi_status pi_set_raytrace_wait_limit(pi_grid* g, double seconds)
+{
+    if (!g) return fail(PI_EINVAL, "null grid");
+    return set_wait_limit(g->e, seconds);
+}
+
+pi_status pi_batch_set_raytrace_wait_limit(pi_batch* b, double seconds)
+{
+    if (!b) return fail(PI_EINVAL, "null batch");
+    return set_wait_limit(b->e, seconds);
+}
+
 // ------------------------------------------------------------------ batch
 pi_status pi_batch_create(int ngrids, const pi_grid_desc* descs, const pi_fields* fields,
                           pi_batch** out)
