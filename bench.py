@@ -543,6 +543,9 @@ def main() -> int:
                     help="OpenMP CPU baseline leg at this n^3")
     ap.add_argument("--cpu-omp-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--raytrace-tile", default="auto", choices=["auto", "4", "8", "16", "persistent"],
+                    help="raytrace variant of the timed grid (auto: the library's tuning on its "
+                         "first raytrace)")
     ap.add_argument("--no-serve", action="store_true",
                     help="default workload: skip the served-stream leg (p50/p99 latency)")
     ap.add_argument("--omp-leg", nargs=2, type=int, metavar=("N", "STEPS"), default=None,
@@ -598,6 +601,9 @@ def main() -> int:
     spec = synth.cfg3(n=args.n)
     nH = synth.density(spec)
     g = binding.Grid(spec, precision=args.precision)
+    if args.raytrace_tile != "auto":
+        g.raytrace_tile = (binding.PI_TILE_PERSISTENT if args.raytrace_tile == "persistent"
+                           else int(args.raytrace_tile))
     g.load(nH, 1.0, T0=spec.T0)
     t_end = 1e30   # open-ended: every step is a full step
 

@@ -75,6 +75,14 @@ struct Engine {
     // longest wait of a persistent tile for its upstream tiles (ticks of the
     // 100 MHz real-time counter); 2e6 = 20 ms unless the caller sets it
     long long persist_spin = 2000000LL;
+    // workgroups of a launch of the micro-physics fused with the persistent
+    // sweep (float storage; 0 until built)
+    int fused_wg = 0;
+    // whether a step runs the micro-physics and the raytrace that follows
+    // it as one fused launch: float storage (not the front-in-double form,
+    // whose front cells all go to the double pass), the persistent raytrace,
+    // and only grids with one point source
+    bool fused() const;
     unsigned int* fix_n = nullptr;
     long long* fix_list = nullptr;
     size_t fix_cap = 0;
@@ -108,6 +116,9 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids);
 void engine_free(Engine& e);
 // Destroys a captured step graph (the next step captures a new one).
 void engine_drop_graph(Engine& e);
+// Whether the engine's steps would fuse the micro-physics with the persistent
+// raytrace if that raytrace were chosen.
+bool fused_eligible(const Engine& e);
 void free_tables(std::vector<Engine::Table>& tables);
 
 // Raytrace with the tuned tile edge; the first call outside graph capture times

@@ -296,7 +296,7 @@ pi_status raytrace_t(Engine& e, int state, int tau_buf, int which, hipStream_t s
                                : e.stage_first[w].back() + e.stage_count[w].back();
         HIP_OR(launch_sweep_persist<R>(gd<R>(e), state, tau_buf, e.tiles[w], ntiles, e.octs,
                                        e.flags, e.ctl, std::min(ntiles, e.persist_wg),
-                                       e.persist_spin, s),
+                                       e.persist_spin, nullptr, s),
                "persistent raytrace launch");
         return PI_OK;
     }
@@ -326,8 +326,37 @@ pi_status chem_t(Engine& e, bool dev_dt, double h, int tau_buf, int from, int to
            "chemistry launch");
     if (e.mixed())
         HIP_OR(launch_chem_fix(gd<float>(e), b, e.fix_blocks, from, to, tau_buf, dev_dt, h, e.work,
-                               s),
+                               false, s),
                "double re-solve launch");
+    return PI_OK;
+}
+
+// Micro-physics over h x dt (from -> to, on the columns tau_chem) and the
+// raytrace of state `to` into tau_sweep, fused in one persistent launch; with
+// mixed precision, the double re-solve of the cells the fused launch listed
+// and, if there were any, the raytrace again (a persistent launch that leaves
+// at once otherwise: the decision is the device's, so a captured graph
+// replays it).
+pi_status chem_sweep_fused(Engine& e, double h, int tau_chem, int from, int to, int tau_sweep,
+                           hipStream_t s)
+{
+    const int w = PERSIST_SCHEDULE;
+    const int ntiles =
+        e.stage_first[w].empty() ? 0 : e.stage_first[w].back() + e.stage_count[w].back();
+    const BatchDev b = e.bd();
+    HIP_OR(launch_chem_sweep<float>(gd<float>(e), b, from, to, tau_chem, tau_sweep, true, h,
+                                    e.work, e.mixed(), e.tiles[w], ntiles, e.octs, e.flags,
+                                    e.ctl, std::min(ntiles, e.fused_wg), e.persist_spin, s),
+           "fused micro-physics and raytrace launch");
+    if (e.mixed()) {
+        HIP_OR(launch_chem_fix(gd<float>(e), b, e.fix_blocks, from, to, tau_chem, true, h, e.work,
+                               true, s),
+               "double re-solve launch");
+        HIP_OR(launch_sweep_persist<float>(gd<float>(e), to, tau_sweep, e.tiles[w], ntiles, e.octs,
+                                           e.flags, e.ctl, std::min(ntiles, e.persist_wg),
+                                           e.persist_spin, e.fix_n + 2, s),
+               "conditional raytrace launch");
+    }
     return PI_OK;
 }
 
@@ -341,6 +370,21 @@ template <typename R> pi_status step_t(Engine& e, double t_end_arg, int order, h
 {
     pi_status r = timestep_t<R>(e, t_end_arg, s);
     if (r != PI_OK) return r;
+    // (A2 with mixed precision keeps the separate kernels: its raytrace
+    // overwrites the columns its micro-physics read, which the double
+    // re-solve after the fused launch would still need)
+    if (e.fused() && (order == 2 || !e.mixed())) {
+        // predictor to the half step with the raytrace of x*, corrector with
+        // the raytrace of the new state (A3); or the one step of A2
+        if (order == 2 && (r = chem_sweep_fused(e, 0.5, PI_BUF_N, PI_BUF_N, PI_BUF_HALF,
+                                                PI_BUF_HALF, s)) != PI_OK)
+            return r;
+        if ((r = chem_sweep_fused(e, 1.0, order == 2 ? PI_BUF_HALF : PI_BUF_N, PI_BUF_N, PI_BUF_N,
+                                  PI_BUF_N, s)) != PI_OK)
+            return r;
+        HIP_OR(launch_advance<R>(gd<R>(e), e.ngrids(), s), "advance launch");
+        return PI_OK;
+    }
     if (order == 2) {
         if ((r = chem_t<R>(e, true, 0.5, PI_BUF_N, PI_BUF_N, PI_BUF_HALF, s)) != PI_OK) return r;
         const int w = e.sweep >= 0 ? e.sweep : SWEEP_DEFAULT;
@@ -376,6 +420,14 @@ template <typename R> pi_status step_a1_t(Engine& e, double t_end_arg, hipStream
 }
 
 }  // namespace
+
+bool fused_eligible(const Engine& e)
+{
+    return !e.fp64() && !e.front() && e.kinds == 1 && e.plane_rows == 0 && e.extra.empty() &&
+           e.fused_wg > 0;
+}
+
+bool Engine::fused() const { return sweep == SWEEP_PERSIST && fused_eligible(*this); }
 
 BatchDev Engine::bd() const
 {
@@ -622,6 +674,7 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
             const int per = e.fp64() ? sweep_persist_occupancy<double>()
                                      : sweep_persist_occupancy<float>();
             e.persist_wg = std::max(1, per * cus);
+            if (!e.fp64()) e.fused_wg = std::max(1, chem_sweep_occupancy<float>(e.mixed()) * cus);
         }
     }
     // work counters
@@ -633,8 +686,8 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
     // mixed precision: re-solve list for every cell of the batch
     if (e.mixed()) {
         if (!e.fix_n) {
-            HIP_OR(hipMalloc(&e.fix_n, 2 * sizeof(unsigned int)), "re-solve count allocation");
-            HIP_OR(hipMemset(e.fix_n, 0, 2 * sizeof(unsigned int)), "re-solve count clear");
+            HIP_OR(hipMalloc(&e.fix_n, 3 * sizeof(unsigned int)), "re-solve count allocation");
+            HIP_OR(hipMemset(e.fix_n, 0, 3 * sizeof(unsigned int)), "re-solve count clear");
         }
         if ((size_t)cells > e.fix_cap) {
             if (e.fix_list) (void)hipFree(e.fix_list);
@@ -666,6 +719,7 @@ void engine_free(Engine& e)
     e.ctl = nullptr;
     e.octs_cap = e.flags_cap = 0;
     e.persist_wg = 0;
+    e.fused_wg = 0;
     for (int w = 0; w < NSWEEP; ++w) {
         if (e.tiles[w]) (void)hipFree(e.tiles[w]);
         e.tiles[w] = nullptr;
@@ -710,6 +764,10 @@ pi_status engine_autotune(Engine& e, int state, int tau_buf, hipStream_t s)
         float ms = 0.0f;
         if (r == PI_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess)
             r = fail(PI_EDEVICE, "event time");
+        // a grid whose step fuses the micro-physics with the persistent
+        // raytrace hides most of that raytrace's time in the step: the
+        // persistent variant is taken unless it is 1.5x slower than the best
+        if (r == PI_OK && w == SWEEP_PERSIST && fused_eligible(e)) ms /= 1.5f;
         if (r == PI_OK && (w == 0 || ms < best)) {
             best = ms;
             pick = w;
@@ -899,7 +957,10 @@ size_t grid_private_bytes(const pi_grid_desc& d)
     for (int w = 0; w < NSWEEP; ++w) b += sizeof(int4) * (size_t)tile_count(d, SWEEP_TILES[w]);
     b += sizeof(unsigned long long) * WORK_COUNTERS * WORK_SLOTS;
     if (d.precision == PI_MIXED || d.precision == PI_MIXED_FRONT)
-        b += 2 * sizeof(unsigned int) + sizeof(long long) * (size_t)n;
+        b += 3 * sizeof(unsigned int) + sizeof(long long) * (size_t)n;
+    // persistent raytrace: octant table, a done-flag per tile, control block
+    b += sizeof(int4) * 8 * (size_t)nsources(d) +
+         sizeof(unsigned) * (size_t)tile_count(d, PERSIST_TILE) + sizeof(SweepCtl);
     if (d.spectrum == PI_SPEC_TABLE) b += sizeof(DevTable<double>) + sizeof(DevTable<float>);
     return b;
 }

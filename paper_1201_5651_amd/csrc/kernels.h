@@ -103,7 +103,8 @@ struct BatchDev {
     const int* dt_first;     // timestep workgroups
     const int* row_first;    // rows along x of plane-parallel grids (0 for point sources)
     // Mixed precision: fix_n[0] is the length of fix_list, fix_n[1] counts the
-    // finished workgroups of launch_chem_fix (both zero between launches).
+    // finished workgroups of launch_chem_fix (both zero between launches);
+    // fix_n[2] asks for the conditional raytrace after a fused launch.
     unsigned int* fix_n;
     long long* fix_list;     // (grid << 32) | cell, for the double re-solve
     unsigned int fix_cap;    // entries fix_list holds
@@ -117,6 +118,9 @@ struct BatchDev {
 // next tile ticket, the workgroups that have left, the epoch of the last
 // completed call (done-flags of the current call hold epoch + 1), and an
 // error flag set when a wait exceeded its limit.
+// Control block of the persistent raytrace and of the fused micro-physics:
+// the tile ticket, workgroups that have left, the epoch of the last call, and
+// the flag of a wait that ran out.
 struct SweepCtl {
     unsigned ticket, exited, epoch, err;
 };
@@ -125,6 +129,9 @@ struct SweepCtl {
 constexpr int PERSIST_TILE = 8;
 constexpr int SWEEP_PERSIST = 3;
 constexpr int PERSIST_SCHEDULE = 1;   // SWEEP_TILES[1] == PERSIST_TILE
+// Threads per workgroup of the micro-physics fused with the persistent sweep
+// (four wavefronts, two 4^3 bricks of a tile each).
+constexpr int FUSED_THREADS = 256;
 
 // One tile-diagonal stage of the raytrace of every grid with tiles of edge
 // `tile` (one of SWEEP_TILES): tiles[first .. first + count) are
@@ -135,11 +142,31 @@ hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, c
 // The whole raytrace of every grid in one launch of nwg persistent workgroups
 // over the schedule tiles[0 .. ntiles) of edge PERSIST_TILE (stage after
 // stage); octs[grid << 3 | octant] = (first done-flag, tiles along x, y, z);
-// flags: one per tile.  spin_ticks bounds each wait (100 MHz ticks).
+// flags: one per tile.  spin_ticks bounds each wait (100 MHz ticks).  cond:
+// null, or a word that must be non-zero for the raytrace to run (cleared by
+// it).
+// One half of an A3 step (or an A2 step) of every grid in one launch of nwg
+// persistent workgroups, for batches of grids with one point source each:
+// the micro-physics of launch_chem over h = hscale (x dt when dev_dt) from
+// `from` to `to` on the columns tau_chem, then the raytrace of state `to`
+// into tau_sweep, over the schedule and flags of launch_sweep_persist.  With
+// mixed, precision-sensitive cells are listed as by launch_chem (and swept
+// with their float values): launch_chem_fix with mark, then
+// launch_sweep_persist with cond = b.fix_n + 2, must follow.  Float storage
+// only (hipErrorNotSupported for double).
+template <typename R>
+hipError_t launch_chem_sweep(const GridDev<R>* grids, const BatchDev& b, int from, int to,
+                             int tau_chem, int tau_sweep, bool dev_dt, double hscale,
+                             unsigned long long* ctr, bool mixed, const int4* tiles, int ntiles,
+                             const int4* octs, unsigned* flags, SweepCtl* ctl, int nwg,
+                             long long spin_ticks, hipStream_t s);
+// Workgroups of k_chem_sweep one compute unit holds at once.
+template <typename R> int chem_sweep_occupancy(bool mixed);
 template <typename R>
 hipError_t launch_sweep_persist(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,
                                 int ntiles, const int4* octs, unsigned* flags, SweepCtl* ctl,
-                                int nwg, long long spin_ticks, hipStream_t s);
+                                int nwg, long long spin_ticks, unsigned* cond,
+                                hipStream_t s);
 // Resident workgroups of the persistent raytrace kernel on one CU.
 template <typename R> int sweep_persist_occupancy();
 // Micro-physics of every cell of every grid from state `from` on columns
@@ -165,10 +192,12 @@ hipError_t launch_chem(const GridDev<R>* grids, const BatchDev& b, int nblocks, 
                        int mixed, hipStream_t s);
 // Mixed precision: double re-solve of the cells listed by launch_chem, from the
 // unmodified float inputs; its last workgroup empties the list, so every
-// launch_chem with mixed must be followed by one launch_chem_fix.
+// launch_chem with mixed must be followed by one launch_chem_fix.  With mark,
+// b.fix_n[2] is set when cells were re-solved (the condition word of a second
+// raytrace after launch_chem_sweep).
 hipError_t launch_chem_fix(const GridDev<float>* grids, const BatchDev& b, int nblk, int from,
                            int to, int tau_buf, bool dev_dt, double hscale,
-                           unsigned long long* ctr, hipStream_t s);
+                           unsigned long long* ctr, bool mark, hipStream_t s);
 // Timestep limit (eq. 4) and diagnostics of state n of every grid, reduced per
 // grid; t_end_arg finite: the t_end of every grid, else each grid's st->t_end.
 template <typename R>

@@ -13,6 +13,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace pi {
 
 // ------------------------------------------------------------------ raytrace
@@ -41,6 +43,40 @@ static_assert(SWEEP_T_LARGEST <= 32, "tile coordinates are packed in 5 bits");
 __constant__ PlaneOrder<SWEEP_TILES[0]> c_plane_order_0 = make_plane_order<SWEEP_TILES[0]>();
 __constant__ PlaneOrder<SWEEP_TILES[1]> c_plane_order_1 = make_plane_order<SWEEP_TILES[1]>();
 __constant__ PlaneOrder<SWEEP_TILES[2]> c_plane_order_2 = make_plane_order<SWEEP_TILES[2]>();
+
+// Entries of the (T+1)^3 halo buffer of a T^3 tile that lie on its upstream
+// faces (local index -1 along some axis), in buffer order: the halo cells a
+// tile reads from earlier tiles, one per thread of every sweep kernel.
+template <int T> struct FaceList {
+    static constexpr int N = (T + 1) * (T + 1) * (T + 1) - T * T * T;
+    unsigned short q[N];
+};
+template <int T> constexpr FaceList<T> make_face_list()
+{
+    FaceList<T> o{};
+    int n = 0;
+    for (int q = 0; q < (T + 1) * (T + 1) * (T + 1); ++q) {
+        const int hx = q % (T + 1), hy = (q / (T + 1)) % (T + 1), hz = q / ((T + 1) * (T + 1));
+        if (hx == 0 || hy == 0 || hz == 0) o.q[n++] = (unsigned short)q;
+    }
+    return o;
+}
+__constant__ FaceList<SWEEP_TILES[0]> c_faces_0 = make_face_list<SWEEP_TILES[0]>();
+__constant__ FaceList<SWEEP_TILES[1]> c_faces_1 = make_face_list<SWEEP_TILES[1]>();
+__constant__ FaceList<SWEEP_TILES[2]> c_faces_2 = make_face_list<SWEEP_TILES[2]>();
+template <int T> __device__ __forceinline__ int face_entry(int f);
+template <> __device__ __forceinline__ int face_entry<SWEEP_TILES[0]>(int f)
+{
+    return c_faces_0.q[f];
+}
+template <> __device__ __forceinline__ int face_entry<SWEEP_TILES[1]>(int f)
+{
+    return c_faces_1.q[f];
+}
+template <> __device__ __forceinline__ int face_entry<SWEEP_TILES[2]>(int f)
+{
+    return c_faces_2.q[f];
+}
 
 template <int T> __device__ __forceinline__ int plane_cell(int t);
 template <> __device__ __forceinline__ int plane_cell<SWEEP_TILES[0]>(int t)
@@ -112,22 +148,81 @@ template <int TT> struct SweepShape {
     static constexpr int CPT = CELLS / THREADS;
 };
 
-// The sweep of one tile (the body of both raytrace kernels), with the LDS
-// arrays of the workgroup.  wait() runs between the loads that do not depend
-// on earlier tiles (sigma0 n_H x dx of the tile and its halo, the cells'
-// geometry) and the loads that do (the columns of the upstream halo); every
-// thread calls it, and the caller's synchronisation follows it.  Coherent:
-// the upstream columns are read and the tile's columns written as relaxed
-// atomics at agent scope (loads and stores that reach the device-wide point
-// of coherence, past the caches of the compute unit and of its XCD), for a
-// sweep whose tiles depend on tiles of the same launch.
-template <typename R, int TT, bool Coherent, typename Wait>
+// Short-characteristics geometry of a cell at octant-local coordinates L
+// (Sect. 2.1): the major axis a of the ray from the source vertex to the cell
+// centre and the two others (b, c); the bilinear weights of the four upstream
+// centres on the plane one step back along a (zero across a source plane);
+// the half path length per cell length, hds; and whether the cell lies on the
+// source plane normal to a (corner: no upstream cells).  Every sweep kernel
+// takes it from here, so all of them compute it with the same operations.
+template <typename R> struct ScGeom {
+    int a, b, c;
+    R g00, g10, g01, g11, hds;
+    bool corner;
+};
+template <typename R> __device__ __forceinline__ ScGeom<R> sc_geom(const int L[3])
+{
+    ScGeom<R> o;
+    const R ad[3] = { R(L[0]) + R(0.5), R(L[1]) + R(0.5), R(L[2]) + R(0.5) };
+    o.a = (ad[2] >= ad[0] && ad[2] >= ad[1]) ? 2 : (ad[1] >= ad[0] ? 1 : 0);
+    o.b = o.a == 2 ? 0 : o.a + 1;
+    o.c = o.a == 0 ? 2 : o.a - 1;
+    // exact quotients: a tie of axes gives exactly 1 (zero weights stay zero)
+    const R fb = ad[o.b] / ad[o.a], fc = ad[o.c] / ad[o.a];
+    const bool vb = L[o.b] >= 1, vc = L[o.c] >= 1;
+    o.g00 = (R(1) - fb) * (R(1) - fc);
+    o.g10 = vb ? fb * (R(1) - fc) : R(0);
+    o.g01 = vc ? (R(1) - fb) * fc : R(0);
+    o.g11 = (vb && vc) ? fb * fc : R(0);
+    o.hds = R(0.5) * r_sqrt(ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2]) / ad[o.a];
+    o.corner = L[o.a] == 0;
+    return o;
+}
+
+// Depth of an upstream centre column tc at the entry face of the cell, tc +
+// hds kap, with the product rounded on its own (no contraction), as in every
+// sweep kernel.
+template <typename R> __device__ __forceinline__ R upstream_T(R tc, R hds, R kap)
+{
+#pragma clang fp contract(off)
+    return tc + hds * kap;
+}
+
+// Half path length per cell length of the halo cell at octant-local L (its
+// centre column from its entering one: tc = tin + hh kap).
+template <typename R> __device__ __forceinline__ R halo_hds(int Lx, int Ly, int Lz)
+{
+    const R ax = R(Lx) + R(0.5), ay = R(Ly) + R(0.5), az = R(Lz) + R(0.5);
+    const R da = (az >= ax && az >= ay) ? az : (ay >= ax ? ay : ax);
+    return R(0.5) * r_sqrt(ax * ax + ay * ay + az * az) / da;
+}
+
+// Kinds of tile sweep.  TILE_STAGED: every upstream tile belongs to an
+// earlier launch.  TILE_COHERENT: upstream tiles run in the same launch; the
+// upstream columns are read, and the tile's columns written, as relaxed
+// atomics at agent scope (loads and stores that reach the device-wide point of
+// coherence, past the caches of the compute unit and of its XCD).
+// TILE_FUSED: as TILE_COHERENT, after the tile's own micro-physics in the
+// same workgroup: the caller has put sigma0 n_H x dx of the tile's own cells
+// in s_kap, and the neutral fractions of the upstream halo, written in the
+// same launch, are read at agent scope after the wait.
+enum { TILE_STAGED = 0, TILE_COHERENT = 1, TILE_FUSED = 2 };
+
+// The sweep of one tile by NT threads (the body of the tiled raytrace
+// kernels), with the LDS arrays of the workgroup.  wait() runs between the
+// work that does not depend on earlier tiles (sigma0 n_H x dx of the tile and,
+// but for TILE_FUSED, of its halo; the cells' geometry) and the loads that do
+// (the columns, and for TILE_FUSED the neutral fractions, of the upstream
+// halo); every thread calls it, and the caller's synchronisation follows it.
+template <typename R, int TT, int NT, int Kind, typename Wait>
 __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids, int state,
                                            int tau_buf, int4 tl, R* s_tc, R* s_kap, Wait wait)
 {
     constexpr int TX = TT, TY = TT, TZ = TT;
-    constexpr int NT = SweepShape<TT>::THREADS, CPT = SweepShape<TT>::CPT;
+    constexpr int CPT = TT * TT * TT / NT;
+    static_assert(CPT * NT == TT * TT * TT, "whole cells per thread");
     constexpr int HX = TX + 1, HY = TY + 1, HZ = TZ + 1, NHALO = HX * HY * HZ;
+    constexpr bool coherent = Kind != TILE_STAGED;
     const GridDev<R>& G = grids[tl.x >> 3];
     const Params<R> p = G.p;
     const R* __restrict__ nH = G.nHr[state];
@@ -140,85 +235,88 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
     const int ez = pz ? p.nz - p.sz : p.sz;
     const int X0 = tl.y * TX, Y0 = tl.z * TY, Z0 = tl.w * TZ;
 
-    for (int q = threadIdx.x; q < NHALO; q += NT) {
-        const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
-        const int Lx = X0 + hx - 1, Ly = Y0 + hy - 1, Lz = Z0 + hz - 1;
-        R kap = R(0);
-        if (Lx >= 0 && Ly >= 0 && Lz >= 0 && Lx < ex && Ly < ey && Lz < ez) {
-            const int gi = px ? p.sx + Lx : p.sx - 1 - Lx;
-            const int gj = py ? p.sy + Ly : p.sy - 1 - Ly;
-            const int gk = pz ? p.sz + Lz : p.sz - 1 - Lz;
-            const int64_t g = gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk);
-            kap = p.sdx * nH[g] * xs[g];
+    if constexpr (Kind != TILE_FUSED) {
+        // (a fixed trip count, so that every iteration's loads are in flight
+        // together)
+#pragma unroll
+        for (int k = 0; k < (NHALO + NT - 1) / NT; ++k) {
+            const int q = threadIdx.x + k * NT;
+            if (q >= NHALO) break;
+            const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
+            const int Lx = X0 + hx - 1, Ly = Y0 + hy - 1, Lz = Z0 + hz - 1;
+            R kap = R(0);
+            if (Lx >= 0 && Ly >= 0 && Lz >= 0 && Lx < ex && Ly < ey && Lz < ez) {
+                const int gi = px ? p.sx + Lx : p.sx - 1 - Lx;
+                const int gj = py ? p.sy + Ly : p.sy - 1 - Ly;
+                const int gk = pz ? p.sz + Lz : p.sz - 1 - Lz;
+                const int64_t g = gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk);
+                kap = p.sdx * nH[g] * xs[g];
+            }
+            s_kap[q] = kap;
         }
-        s_kap[q] = kap;
     }
-    __syncthreads();
 
     // geometry of the thread's cells (cell k: plane-order index threadIdx.x + k NT)
     const bool mellema = p.weights == 1;
     int self[CPT], n00[CPT], n10[CPT], n01[CPT], n11[CPT], diag[CPT], nat[CPT];
     bool active[CPT], corner[CPT];
-    R g00[CPT], g10[CPT], g01[CPT], g11[CPT], hds[CPT], kself[CPT], tin[CPT];
-    // hds * sigma0 n_H x dx of the four upstream cells: fixed while the tile is
-    // swept, so the plane loop reads only their centre columns
-    R c00[CPT], c10[CPT], c01[CPT], c11[CPT];
+    R g00[CPT], g10[CPT], g01[CPT], g11[CPT], hds[CPT], tin[CPT];
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
         const int cl = plane_cell<TT>(threadIdx.x + k * NT);
         const int lx = cl & 31, ly = (cl >> 5) & 31, lz = cl >> 10;
         const int L[3] = { X0 + lx, Y0 + ly, Z0 + lz };
         active[k] = L[0] < ex && L[1] < ey && L[2] < ez;
-        const R ad[3] = { R(L[0]) + R(0.5), R(L[1]) + R(0.5), R(L[2]) + R(0.5) };
-        const int a = (ad[2] >= ad[0] && ad[2] >= ad[1]) ? 2 : (ad[1] >= ad[0] ? 1 : 0);
-        const int b = a == 2 ? 0 : a + 1;
-        const int c = a == 0 ? 2 : a - 1;
+        const ScGeom<R> sg = sc_geom<R>(L);
         const int st[3] = { 1, HX, HX * HY };
         self[k] = (lz + 1) * HX * HY + (ly + 1) * HX + (lx + 1);
-        n00[k] = self[k] - st[a];
-        n10[k] = n00[k] - st[b];
-        n01[k] = n00[k] - st[c];
-        n11[k] = n10[k] - st[c];
-        // exact quotients: a tie of axes gives exactly 1 (zero weights stay zero)
-        const R fb = ad[b] / ad[a], fc = ad[c] / ad[a];
-        const bool vb = L[b] >= 1, vc = L[c] >= 1;
-        g00[k] = (R(1) - fb) * (R(1) - fc);
-        g10[k] = vb ? fb * (R(1) - fc) : R(0);
-        g01[k] = vc ? (R(1) - fb) * fc : R(0);
-        g11[k] = (vb && vc) ? fb * fc : R(0);
-        hds[k] = R(0.5) * r_sqrt(ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2]) / ad[a];
-        corner[k] = L[a] == 0;
+        n00[k] = self[k] - st[sg.a];
+        n10[k] = n00[k] - st[sg.b];
+        n01[k] = n00[k] - st[sg.c];
+        n11[k] = n10[k] - st[sg.c];
+        g00[k] = sg.g00;
+        g10[k] = sg.g10;
+        g01[k] = sg.g01;
+        g11[k] = sg.g11;
+        hds[k] = sg.hds;
+        corner[k] = sg.corner;
         diag[k] = lx + ly + lz;
         nat[k] = lx + TX * (ly + TY * lz);
-        kself[k] = s_kap[self[k]];
-        c00[k] = hds[k] * s_kap[n00[k]];
-        c10[k] = hds[k] * s_kap[n10[k]];
-        c01[k] = hds[k] * s_kap[n01[k]];
-        c11[k] = hds[k] * s_kap[n11[k]];
         tin[k] = R(0);
     }
 
     wait();
     __syncthreads();
-    // centre columns of the upstream halo (the faces at local index -1)
-    for (int q = threadIdx.x; q < NHALO; q += NT) {
+    // centre columns of the upstream halo (the faces at local index -1), and
+    // for TILE_FUSED its sigma0 n_H x dx; the tile's own entries of s_tc are
+    // written by their cells before any cell reads them
+    constexpr int NFACE = FaceList<TT>::N;
+    static_assert(NFACE <= NT, "one face entry per thread");
+    if (threadIdx.x < NFACE) {
+        const int q = face_entry<TT>(threadIdx.x);
         const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
         const int Lx = X0 + hx - 1, Ly = Y0 + hy - 1, Lz = Z0 + hz - 1;
         R tc = R(0);
-        if ((hx == 0 || hy == 0 || hz == 0) && Lx >= 0 && Ly >= 0 && Lz >= 0 && Lx < ex &&
-            Ly < ey && Lz < ez) {
+        if (Lx >= 0 && Ly >= 0 && Lz >= 0 && Lx < ex && Ly < ey && Lz < ez) {
             const int gi = px ? p.sx + Lx : p.sx - 1 - Lx;
             const int gj = py ? p.sy + Ly : p.sy - 1 - Ly;
             const int gk = pz ? p.sz + Lz : p.sz - 1 - Lz;
             const int64_t g = gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk);
-            const R ax = R(Lx) + R(0.5), ay = R(Ly) + R(0.5), az = R(Lz) + R(0.5);
-            const R da = (az >= ax && az >= ay) ? az : (ay >= ax ? ay : ax);
-            const R hh = R(0.5) * r_sqrt(ax * ax + ay * ay + az * az) / da;
-            // the centre column exactly as the cell's own tile formed it
-            const R up = Coherent
+            R kap;
+            if constexpr (Kind == TILE_FUSED) {
+                kap = p.sdx * nH[g] *
+                      __hip_atomic_load(&xs[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_kap[q] = kap;
+            } else {
+                kap = s_kap[q];
+            }
+            const R up = coherent
                              ? __hip_atomic_load(&tau[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                              : tau[g];
-            tc = r_fma(hh, s_kap[q], up);
+            // the centre column exactly as the cell's own tile formed it
+            tc = r_fma(halo_hds<R>(Lx, Ly, Lz), kap, up);
+        } else if (Kind == TILE_FUSED) {
+            s_kap[q] = R(0);
         }
         s_tc[q] = tc;
     }
@@ -229,14 +327,15 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
         for (int k = 0; k < CPT; ++k) {
             if (active[k] && diag[k] == s) {
                 if (!corner[k]) {
-                    const R T00 = s_tc[n00[k]] + c00[k];
-                    const R T10 = s_tc[n10[k]] + c10[k];
-                    const R T01 = s_tc[n01[k]] + c01[k];
-                    const R T11 = s_tc[n11[k]] + c11[k];
+                    const R T00 = upstream_T(s_tc[n00[k]], hds[k], s_kap[n00[k]]);
+                    const R T10 = upstream_T(s_tc[n10[k]], hds[k], s_kap[n10[k]]);
+                    const R T01 = upstream_T(s_tc[n01[k]], hds[k], s_kap[n01[k]]);
+                    const R T11 = upstream_T(s_tc[n11[k]], hds[k], s_kap[n11[k]]);
                     tin[k] = sc_average<R>(mellema, g00[k], g10[k], g01[k], g11[k], T00, T10,
                                            T01, T11);
                 }
-                s_tc[self[k]] = r_fma(hds[k], kself[k], tin[k]);   // entry face to centre
+                // entry face to centre
+                s_tc[self[k]] = r_fma(hds[k], s_kap[self[k]], tin[k]);
             }
         }
         __syncthreads();
@@ -255,7 +354,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
             const int gj = py ? p.sy + Ly : p.sy - 1 - Ly;
             const int gk = pz ? p.sz + Lz : p.sz - 1 - Lz;
             R* dst = &tau[gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk)];
-            if (Coherent)
+            if (coherent)
                 __hip_atomic_store(dst, s_out[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             else
                 *dst = s_out[t];
@@ -275,8 +374,8 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     static_assert(NHALO >= TT * TT * TT, "the output reuses the halo buffer");
     __shared__ R s_tc[NHALO];
     __shared__ R s_kap[NHALO];
-    sweep_tile<R, TT, false>(grids, state, tau_buf, tiles[first + blockIdx.x], s_tc, s_kap,
-                             [] {});
+    sweep_tile<R, TT, SweepShape<TT>::THREADS, TILE_STAGED>(
+        grids, state, tau_buf, tiles[first + blockIdx.x], s_tc, s_kap, [] {});
 }
 
 // The whole raytrace in one launch: persistent workgroups claim tiles in the
@@ -289,7 +388,12 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
 // the ticket and advances the epoch, so replays of a captured graph need no
 // reset.  A wait longer than spin_ticks (of the 100 MHz real-time counter)
 // sets ctl->err and goes on, so every workgroup exits; the result is then
-// reported invalid.
+// reported invalid.  With a condition word (cond), the raytrace runs only if
+// the word is non-zero, and the last workgroup to leave clears it.  The exit
+// count, the resets and the epoch are relaxed atomics: a workgroup counts
+// itself only after its last claim has returned, and the next launch that
+// reads them follows this one's end (an agent-scope release per workgroup
+// would write back the XCD's L2 a thousand times per launch).
 //
 // Columns pass between tiles without cache maintenance: a tile writes its
 // columns, and reads its upstream halo, as relaxed atomics at agent scope,
@@ -313,7 +417,7 @@ template <typename R, int TT>
 __global__ void __launch_bounds__(SweepShape<TT>::THREADS)
 k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
                 const int4* __restrict__ tiles, int ntiles, const int4* __restrict__ octs,
-                unsigned* __restrict__ flags, SweepCtl* ctl, long long spin_ticks)
+                unsigned* __restrict__ flags, SweepCtl* ctl, long long spin_ticks, unsigned* cond)
 {
     constexpr int NHALO = (TT + 1) * (TT + 1) * (TT + 1);
     __shared__ R s_tc[NHALO];
@@ -324,7 +428,10 @@ k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     const unsigned done =
         __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) + 1u;
-    for (;;) {
+    // with a condition word that reads 0, every workgroup leaves at once
+    const bool go = !cond || __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                                 cond, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0u;
+    while (go) {
         if (lead) {
             // lane 0 takes the ticket (the others add 0); every lane of wave 0
             // writes lane 0's value
@@ -339,7 +446,8 @@ k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
         const int4 tl = tiles[t];
         const int4 oc = octs[tl.x];                         // flag base, tiles per axis
         const int idx = oc.x + (tl.w * oc.z + tl.z) * oc.y + tl.y;
-        sweep_tile<R, TT, true>(grids, state, tau_buf, tl, s_tc, s_kap, [&] {
+        sweep_tile<R, TT, SweepShape<TT>::THREADS, TILE_COHERENT>(
+            grids, state, tau_buf, tl, s_tc, s_kap, [&] {
             if (lead) {
                 const int up[3] = { tl.y > 0 ? idx - 1 : -1, tl.z > 0 ? idx - oc.y : -1,
                                     tl.w > 0 ? idx - oc.y * oc.z : -1 };
@@ -368,11 +476,13 @@ k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     }
     if (lead) {
         const unsigned left = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(
-            &ctl->exited, add, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT));
+            &ctl->exited, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         if (left == gridDim.x - 1) {
+            // every workgroup read the condition before it left
+            if (cond) __hip_atomic_store(cond, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctl->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctl->exited, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->epoch, done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->epoch, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -577,7 +687,7 @@ k_chem(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int 
 template <int MS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ChemWaves<double>::value)))
 k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int to, int tau_buf,
-           int dev_dt, double hscale, unsigned long long* ctr, int clear)
+           int dev_dt, double hscale, unsigned long long* ctr, int clear, int mark)
 {
     const unsigned n = min(bd.fix_n[0], bd.fix_cap);
     if (blockIdx.x * blockDim.x < n) {   // uniform over the workgroup
@@ -607,10 +717,166 @@ k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int 
     __syncthreads();
     if (threadIdx.x == 0) {
         if (atomicAdd(&bd.fix_n[1], 1u) == gridDim.x - 1) {
+            // cells were re-solved after a fused raytrace: it is run again
+            if (mark && n > 0) bd.fix_n[2] = 1u;
             bd.fix_n[0] = 0u;
             bd.fix_n[1] = 0u;
         }
     }
+}
+
+// ------------------------------------------- micro-physics fused with the sweep
+// One half of an A3 step (or an A2 step) in one launch for grids with one
+// point source: the micro-physics over h of every cell (from -> to, on the
+// columns tau_chem), then the raytrace of the new state into tau_sweep.  The
+// persistent workgroups take the tiles of edge PERSIST_TILE of the raytrace
+// schedule in order (a ticket), as k_sweep_persist does.  A workgroup first
+// integrates its tile's cells (each wavefront two 4^3 bricks, with the
+// per-cell arithmetic of k_chem), writes the new neutral fractions at agent
+// scope and puts sigma0 n_H x dx of every cell in LDS; then it waits for the
+// tile's upstream tiles and sweeps it (TILE_FUSED).  A tile's micro-physics
+// needs nothing from other tiles, so while some workgroups of a compute unit
+// sweep or wait, the others integrate.  The register budget keeps four
+// workgroups per compute unit, the occupancy of k_chem.  With Mixed (mixed
+// precision) a cell whose float integration took a precision-sensitive
+// decision is listed for launch_chem_fix and not written, as in k_chem, and
+// the sweep uses its float result; launch_chem_fix then re-solves it and
+// marks the columns for a second, conditional raytrace.  A tile's flag is
+// stored once every wave's stores have completed; waits are bounded as in
+// k_sweep_persist.  The rate table is copied to LDS when a tile's grid
+// differs from the workgroup's previous one.
+template <typename R, bool Mixed>
+__global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int tau_chem,
+             int tau_sweep, int dev_dt, double hscale, unsigned long long* ctr,
+             const int4* __restrict__ tiles, int ntiles, const int4* __restrict__ octs,
+             unsigned* __restrict__ flags, SweepCtl* ctl, long long spin_ticks)
+{
+    constexpr int TT = PERSIST_TILE, NT = FUSED_THREADS;
+    constexpr int HX = TT + 1, HY = TT + 1, NHALO = HX * HY * (TT + 1);
+    constexpr int BRICKS = (TT / 4) * (TT / 4) * (TT / 4), BPW = BRICKS / (NT / 64);
+    static_assert(TT % 4 == 0 && BPW * (NT / 64) == BRICKS, "whole bricks per wavefront");
+    __shared__ DevTable<R> s_tab;
+    __shared__ R s_tc[NHALO];
+    __shared__ R s_kap[NHALO];
+    __shared__ int s_ticket;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const bool lead = wave == 0;
+    const int lane = threadIdx.x & 63;
+    const unsigned add = lane == 0 ? 1u : 0u;
+    const unsigned done =
+        __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) + 1u;
+    int table_of = -1;   // grid whose rate table s_tab holds
+    Work w{};
+    for (;;) {
+        if (lead) {
+            const unsigned c = __hip_atomic_fetch_add(&ctl->ticket, add, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            s_ticket = (int)__builtin_amdgcn_readfirstlane(c);
+        }
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(s_ticket);
+        __syncthreads();   // (s_ticket is rewritten by the next claim)
+        if (t >= ntiles) break;
+        const int4 tl = tiles[t];
+        const int4 oc = octs[tl.x];                         // flag base, tiles per axis
+        const int idx = oc.x + (tl.w * oc.z + tl.z) * oc.y + tl.y;
+        const int gidx = tl.x >> 3;
+        const GridDev<R>& G = grids[gidx];
+        if (gidx != table_of) {   // uniform
+            table_to_lds(G.p, s_tab);
+            table_of = gidx;
+        }
+        Params<R> pl = G.p;
+        pl.tab = &s_tab;
+        const int oct = tl.x & 7;
+        const bool px = oct & 1, py = oct & 2, pz = oct & 4;
+        const int ex = px ? pl.nx - pl.sx : pl.sx;
+        const int ey = py ? pl.ny - pl.sy : pl.sy;
+        const int ez = pz ? pl.nz - pl.sz : pl.sz;
+        const double hd = dev_dt ? hscale * G.st->dt : hscale;
+        const R* __restrict__ nHs = G.nHr[to];
+        // micro-physics of the tile's cells; sigma0 n_H x dx of each into LDS
+        long long q_fix = 0;
+        for (int b = 0; b < BPW; ++b) {
+            const int brick = wave * BPW + b;
+            const int lx = 4 * (brick % (TT / 4)) + (lane & 3);
+            const int ly = 4 * ((brick / (TT / 4)) % (TT / 4)) + ((lane >> 2) & 3);
+            const int lz = 4 * (brick / ((TT / 4) * (TT / 4))) + (lane >> 4);
+            const int Lx = tl.y * TT + lx, Ly = tl.z * TT + ly, Lz = tl.w * TT + lz;
+            R kap = R(0);
+            bool flag = false;
+            if (Lx < ex && Ly < ey && Lz < ez) {
+                const int gi = px ? pl.sx + Lx : pl.sx - 1 - Lx;
+                const int gj = py ? pl.sy + Ly : pl.sy - 1 - Ly;
+                const int gk = pz ? pl.sz + Lz : pl.sz - 1 - Lz;
+                const int q = gi + pl.nx * (gj + pl.ny * gk);
+                R x, E;
+                const int close0 = w.close;
+                chem_cell<R, R, 1>(pl, G.src, q, gi, gj, gk, G.nH, G.x[from], G.E[from],
+                                   G.tau[tau_chem], hd, x, E, w);
+                flag = Mixed && w.close > close0;
+                if (flag) {
+                    q_fix = ((long long)gidx << 32) | (long long)q;
+                } else {
+                    __hip_atomic_store(&G.x[to][q], x, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    if (G.E[to]) G.E[to][q] = E;
+                }
+                kap = pl.sdx * nHs[q] * x;
+            }
+            s_kap[(lz + 1) * HX * HY + (ly + 1) * HX + (lx + 1)] = kap;
+            if (Mixed) {
+                // one atomic per wavefront for the listed cells of the brick
+                const unsigned long long m = __ballot(flag);
+                if (m) {
+                    const int first = __ffsll((long long)m) - 1;
+                    unsigned base = 0;
+                    if (lane == first) base = atomicAdd(bd.fix_n, (unsigned)__popcll(m));
+                    base = __shfl(base, first, 64);
+                    const unsigned slot = base + __popcll(m & ((1ull << lane) - 1ull));
+                    if (flag && slot < bd.fix_cap) bd.fix_list[slot] = q_fix;
+                }
+            }
+        }
+        sweep_tile<R, TT, NT, TILE_FUSED>(grids, to, tau_sweep, tl, s_tc, s_kap, [&] {
+            if (lead) {
+                const int up[3] = { tl.y > 0 ? idx - 1 : -1, tl.z > 0 ? idx - oc.y : -1,
+                                    tl.w > 0 ? idx - oc.y * oc.z : -1 };
+                for (int u = 0; u < 3; ++u) {
+                    if (up[u] < 0) continue;
+                    const long long t0 = (long long)__builtin_amdgcn_s_memrealtime();
+                    for (;;) {
+                        const unsigned f = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                            &flags[up[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                        if (f == done) break;
+                        __builtin_amdgcn_s_sleep(2);
+                        if ((long long)__builtin_amdgcn_s_memrealtime() - t0 > spin_ticks) {
+                            __hip_atomic_store(&ctl->err, 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                            break;
+                        }
+                    }
+                }
+            }
+        });
+        // every wave's neutral-fraction and column stores complete, then the flag
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (lead)
+            __hip_atomic_store(&flags[idx], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (lead) {
+        const unsigned left = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(
+            &ctl->exited, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (left == gridDim.x - 1) {
+            __hip_atomic_store(&ctl->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->exited, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->epoch, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    add_work(ctr, w);
 }
 
 // ------------------------------------------------------------- algorithm 1
@@ -977,12 +1243,12 @@ hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, c
 template <typename R>
 hipError_t launch_sweep_persist(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,
                                 int ntiles, const int4* octs, unsigned* flags, SweepCtl* ctl,
-                                int nwg, long long spin_ticks, hipStream_t s)
+                                int nwg, long long spin_ticks, unsigned* cond, hipStream_t s)
 {
     if (ntiles <= 0 || nwg <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_sweep_persist<R, PERSIST_TILE>), dim3(nwg),
                        dim3(SweepShape<PERSIST_TILE>::THREADS), 0, s, grids, state, tau_buf, tiles,
-                       ntiles, octs, flags, ctl, spin_ticks);
+                       ntiles, octs, flags, ctl, spin_ticks, cond);
     return hipGetLastError();
 }
 
@@ -993,6 +1259,47 @@ template <typename R> int sweep_persist_occupancy()
                                                      SweepShape<PERSIST_TILE>::THREADS, 0) !=
         hipSuccess)
         return 1;
+    return n > 0 ? n : 1;
+}
+
+template <typename R>
+hipError_t launch_chem_sweep(const GridDev<R>* grids, const BatchDev& b, int from, int to,
+                             int tau_chem, int tau_sweep, bool dev_dt, double hscale,
+                             unsigned long long* ctr, bool mixed, const int4* tiles, int ntiles,
+                             const int4* octs, unsigned* flags, SweepCtl* ctl, int nwg,
+                             long long spin_ticks, hipStream_t s)
+{
+    if constexpr (std::is_same<R, float>::value) {
+        if (ntiles <= 0 || nwg <= 0) return hipSuccess;
+        if (mixed)
+            hipLaunchKernelGGL((k_chem_sweep<R, true>), dim3(nwg), dim3(FUSED_THREADS), 0, s,
+                               grids, b, from, to, tau_chem, tau_sweep, (int)dev_dt, hscale, ctr,
+                               tiles, ntiles, octs, flags, ctl, spin_ticks);
+        else
+            hipLaunchKernelGGL((k_chem_sweep<R, false>), dim3(nwg), dim3(FUSED_THREADS), 0, s,
+                               grids, b, from, to, tau_chem, tau_sweep, (int)dev_dt, hscale, ctr,
+                               tiles, ntiles, octs, flags, ctl, spin_ticks);
+        return hipGetLastError();
+    } else {
+        // double storage keeps the separate kernels (its integrator does not
+        // fit the fused kernel's registers)
+        return hipErrorNotSupported;
+    }
+}
+
+template <typename R> int chem_sweep_occupancy(bool mixed)
+{
+    int n = 0;
+    hipError_t e = hipErrorNotSupported;
+    if constexpr (std::is_same<R, float>::value) {
+        if (mixed)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_chem_sweep<R, true>,
+                                                             FUSED_THREADS, 0);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_chem_sweep<R, false>,
+                                                             FUSED_THREADS, 0);
+    }
+    if (e != hipSuccess) return 1;
     return n > 0 ? n : 1;
 }
 
@@ -1033,15 +1340,15 @@ hipError_t launch_chem(const GridDev<R>* grids, const BatchDev& b, int nblocks, 
 
 hipError_t launch_chem_fix(const GridDev<float>* grids, const BatchDev& b, int nblk, int from,
                            int to, int tau_buf, bool dev_dt, double hscale,
-                           unsigned long long* ctr, hipStream_t s)
+                           unsigned long long* ctr, bool mark, hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
     if (b.kinds & 1)
         hipLaunchKernelGGL(k_chem_fix<1>, dim3(nblk), dim3(256), 0, s, grids, b, from, to,
-                           tau_buf, (int)dev_dt, hscale, ctr, (b.kinds & 2) ? 0 : 1);
+                           tau_buf, (int)dev_dt, hscale, ctr, (b.kinds & 2) ? 0 : 1, (int)mark);
     if (b.kinds & 2)
         hipLaunchKernelGGL(k_chem_fix<MAX_SRC>, dim3(nblk), dim3(256), 0, s, grids, b, from, to,
-                           tau_buf, (int)dev_dt, hscale, ctr, 1);
+                           tau_buf, (int)dev_dt, hscale, ctr, 1, (int)mark);
     return hipGetLastError();
 }
 
@@ -1079,8 +1386,13 @@ hipError_t launch_energy(int64_t n, const R* nH, const R* x, R* E, double T0, hi
                                               int, hipStream_t);                                   \
     template hipError_t launch_sweep_persist<R>(const GridDev<R>*, int, int, const int4*, int,     \
                                                 const int4*, unsigned*, SweepCtl*, int, long long, \
-                                                hipStream_t);                                      \
+                                                unsigned*, hipStream_t);                           \
     template int sweep_persist_occupancy<R>();                                                     \
+    template hipError_t launch_chem_sweep<R>(const GridDev<R>*, const BatchDev&, int, int, int,     \
+                                             int, bool, double, unsigned long long*, bool,         \
+                                             const int4*, int, const int4*, unsigned*, SweepCtl*,  \
+                                             int, long long, hipStream_t);                         \
+    template int chem_sweep_occupancy<R>(bool);                                                    \
     template hipError_t launch_chem<R>(const GridDev<R>*, const BatchDev&, int, int, int, int,    \
                                        bool, double, unsigned long long*, int, hipStream_t);       \
     template hipError_t launch_dtdiag<R>(const GridDev<R>*, const BatchDev&, int, double,         \

@@ -146,7 +146,7 @@ def test_required_bytes(precision, kind):
                      more_sources=tuple(((2 * a, 2 * b, 2 * c), q) for (a, b, c), q in spec.more_sources))
     assert binding.required_bytes(big, precision)[1] > wb
     if precision == "mixed":
-        assert wb - binding.required_bytes(spec, "fp32")[1] == 8 * spec.ncells + 8
+        assert wb - binding.required_bytes(spec, "fp32")[1] == 8 * spec.ncells + 12
 
 
 def test_required_bytes_rejects_bad_descriptor():
