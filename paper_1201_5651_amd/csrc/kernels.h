@@ -130,8 +130,8 @@ constexpr int PERSIST_TILE = 8;
 constexpr int SWEEP_PERSIST = 3;
 constexpr int PERSIST_SCHEDULE = 1;   // SWEEP_TILES[1] == PERSIST_TILE
 // Threads per workgroup of the micro-physics fused with the persistent sweep
-// (four wavefronts, two 4^3 bricks of a tile each).
-constexpr int FUSED_THREADS = 256;
+// (two wavefronts, four 4^3 bricks of a tile each).
+constexpr int FUSED_THREADS = 128;
 
 // One tile-diagonal stage of the raytrace of every grid with tiles of edge
 // `tile` (one of SWEEP_TILES): tiles[first .. first + count) are

@@ -291,9 +291,11 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
     // for TILE_FUSED its sigma0 n_H x dx; the tile's own entries of s_tc are
     // written by their cells before any cell reads them
     constexpr int NFACE = FaceList<TT>::N;
-    static_assert(NFACE <= NT, "one face entry per thread");
-    if (threadIdx.x < NFACE) {
-        const int q = face_entry<TT>(threadIdx.x);
+#pragma unroll
+    for (int k = 0; k < (NFACE + NT - 1) / NT; ++k) {
+        const int f = threadIdx.x + k * NT;
+        if (f >= NFACE) break;
+        const int q = face_entry<TT>(f);
         const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
         const int Lx = X0 + hx - 1, Ly = Y0 + hy - 1, Lz = Z0 + hz - 1;
         R tc = R(0);
@@ -731,7 +733,7 @@ k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int 
 // columns tau_chem), then the raytrace of the new state into tau_sweep.  The
 // persistent workgroups take the tiles of edge PERSIST_TILE of the raytrace
 // schedule in order (a ticket), as k_sweep_persist does.  A workgroup first
-// integrates its tile's cells (each wavefront two 4^3 bricks, with the
+// integrates its tile's cells (each wavefront four 4^3 bricks, with the
 // per-cell arithmetic of k_chem), writes the new neutral fractions at agent
 // scope and puts sigma0 n_H x dx of every cell in LDS; then it waits for the
 // tile's upstream tiles and sweeps it (TILE_FUSED).  A tile's micro-physics
@@ -798,7 +800,6 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
         const double hd = dev_dt ? hscale * G.st->dt : hscale;
         const R* __restrict__ nHs = G.nHr[to];
         // micro-physics of the tile's cells; sigma0 n_H x dx of each into LDS
-        long long q_fix = 0;
         for (int b = 0; b < BPW; ++b) {
             const int brick = wave * BPW + b;
             const int lx = 4 * (brick % (TT / 4)) + (lane & 3);
@@ -807,19 +808,18 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
             const int Lx = tl.y * TT + lx, Ly = tl.z * TT + ly, Lz = tl.w * TT + lz;
             R kap = R(0);
             bool flag = false;
+            int q = 0;
             if (Lx < ex && Ly < ey && Lz < ez) {
                 const int gi = px ? pl.sx + Lx : pl.sx - 1 - Lx;
                 const int gj = py ? pl.sy + Ly : pl.sy - 1 - Ly;
                 const int gk = pz ? pl.sz + Lz : pl.sz - 1 - Lz;
-                const int q = gi + pl.nx * (gj + pl.ny * gk);
+                q = gi + pl.nx * (gj + pl.ny * gk);
                 R x, E;
                 const int close0 = w.close;
                 chem_cell<R, R, 1>(pl, G.src, q, gi, gj, gk, G.nH, G.x[from], G.E[from],
                                    G.tau[tau_chem], hd, x, E, w);
                 flag = Mixed && w.close > close0;
-                if (flag) {
-                    q_fix = ((long long)gidx << 32) | (long long)q;
-                } else {
+                if (!flag) {
                     __hip_atomic_store(&G.x[to][q], x, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                     if (G.E[to]) G.E[to][q] = E;
@@ -836,7 +836,8 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
                     if (lane == first) base = atomicAdd(bd.fix_n, (unsigned)__popcll(m));
                     base = __shfl(base, first, 64);
                     const unsigned slot = base + __popcll(m & ((1ull << lane) - 1ull));
-                    if (flag && slot < bd.fix_cap) bd.fix_list[slot] = q_fix;
+                    if (flag && slot < bd.fix_cap)
+                        bd.fix_list[slot] = ((long long)gidx << 32) | (long long)q;
                 }
             }
         }
