@@ -61,16 +61,22 @@ STEP_WORDS = 7
 # of them: one in a Newton iteration, two in the set-up.
 FLOP_NEWTON = 222
 FLOP_CELL_SETUP = 250
+# The raytrace's arithmetic per cell, counted the same way: the geometry of
+# the short characteristic (offsets, two quotients, the path length), the
+# four upstream depths, the Mellema-weighted average and the cell's own
+# depth -- small beside the micro-physics it is fused with.
+FLOP_SWEEP_CELL = 60
 
 
 KERNEL_SOURCES = ("paper_1201_5651_amd/csrc/physics.h", "paper_1201_5651_amd/csrc/kernels.h",
                   "paper_1201_5651_amd/csrc/kernels.hip")
-TRAFFIC_PROFILE = "profiles/cfg3_256_mixed_k_chem_traffic.md"
+TRAFFIC_PROFILE = "profiles/cfg3_256_mixed_k_chem_sweep_traffic.md"
 
 
 def measured_traffic():
-    """HBM bytes per micro-physics launch from the committed hardware-counter
-    summary, or None when the kernel sources have changed since it was taken."""
+    """HBM bytes per launch of the fused micro-physics and raytrace from the
+    committed hardware-counter summary, or None when the kernel sources have
+    changed since it was taken."""
     import hashlib
     import re
     try:
@@ -81,7 +87,7 @@ def measured_traffic():
     for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     m = re.search(r"kernel_source_sha256: ([0-9a-f]+)", text)
-    t = re.search(r"k_chem_traffic_bytes_per_launch: ([0-9.eE+-]+)", text)
+    t = re.search(r"k_chem_sweep_traffic_bytes_per_launch: ([0-9.eE+-]+)", text)
     if not m or not t or m.group(1) != h.hexdigest():
         return None
     return float(t.group(1))
@@ -640,32 +646,36 @@ def main() -> int:
 
     work = g.work_counters(reset=True)   # over pre-evolution + warm-up + timed steps
 
-    # phase-by-phase timing of the same kernels (same stream, HIP events): each
-    # phase is launched `phase_reps` times back to back between two events on
-    # inputs it does not modify, so that the per-launch figure carries no event
-    # overhead; the corrector's repetitions write its result to the half-step
-    # buffer, and one untimed corrector then moves state n on as in a step
-    phases = {"timestep": 0.0, "chem_predictor": 0.0, "raytrace_half": 0.0,
-              "chem_corrector": 0.0, "raytrace": 0.0}
+    # phase-by-phase timing of the same launches (same stream, HIP events):
+    # each phase is launched `phase_reps` times back to back between two events
+    # on inputs it does not modify, so that the per-launch figure carries no
+    # event overhead.  predictor and corrector are the step's two halves, each
+    # the micro-physics followed by the raytrace of its result (pi_chem_raytrace:
+    # one fused launch when the grid's raytrace is the persistent one, and for
+    # mixed precision the double re-solve and the conditional second raytrace
+    # after it).  The corrector's repetitions write their state to the
+    # half-step buffers and their columns to tau (both rewritten before they
+    # are read again); one untimed corrector then moves state n on as in a
+    # step.  raytrace_alone: the raytrace by itself, for reference.
+    phases = {"timestep": 0.0, "predictor": 0.0, "corrector": 0.0, "raytrace_alone": 0.0}
     R = args.phase_reps
     P_N, P_H = binding.PI_BUF_N, binding.PI_BUF_HALF
     timed = {
         "timestep": lambda: g.timestep(t_end),
-        "chem_predictor": lambda: g.chem_step(0.5, P_N, P_N, P_H, use_device_dt=True),
-        "raytrace_half": lambda: g.raytrace(P_H, P_H),
-        "chem_corrector": lambda: g.chem_step(1.0, P_H, P_N, P_H, use_device_dt=True),
-        "raytrace": lambda: g.raytrace(P_N, P_N),
+        "predictor": lambda: g.chem_raytrace(0.5, P_N, P_N, P_H, P_H, use_device_dt=True),
+        "corrector": lambda: g.chem_raytrace(1.0, P_H, P_N, P_H, P_N, use_device_dt=True),
+        "raytrace_alone": lambda: g.raytrace(P_N, P_N),
     }
     g.work_counters(reset=True)
     work_phase = {}
     for _ in range(args.phase_steps):
         for k, fn in timed.items():
-            if k == "raytrace":
+            if k == "raytrace_alone":
                 # the step's own corrector (untimed, counters excluded)
                 w = g.work_counters(reset=True)
                 for c, v in w.items():
                     work_phase[c] = work_phase.get(c, 0) + v
-                g.chem_step(1.0, P_H, P_N, P_N, use_device_dt=True)
+                g.chem_raytrace(1.0, P_H, P_N, P_N, P_N, use_device_dt=True)
                 torch.cuda.synchronize()
                 g.work_counters(reset=True)
             a, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -729,13 +739,15 @@ def main() -> int:
     W = word_bytes(args.precision)
     N = spec.ncells
     newton_per_launch = work_phase["newton"] / chem_launches
-    # algorithmic bytes per launch: chemistry reads n_H, x, E, tau and writes
-    # x, E (6 words per cell); a raytrace reads n_H, x and writes tau (3 words);
-    # the timestep reads n_H, x, E, tau (4 words)
-    alg = {"chem_predictor": 6 * W * N, "chem_corrector": 6 * W * N,
-           "raytrace_half": 3 * W * N, "raytrace": 3 * W * N, "timestep": 4 * W * N}
+    fused = g.raytrace_tile == binding.PI_TILE_PERSISTENT and args.precision in ("fp32", "mixed")
+    # algorithmic bytes per launch: a half step (micro-physics and the raytrace
+    # of its result) reads n_H, x, E, tau and writes x, E, tau (7 words per
+    # cell); the timestep reads n_H, x, E, tau (4 words); a raytrace alone reads
+    # n_H, x and writes tau (3 words)
+    alg = {"predictor": 7 * W * N, "corrector": 7 * W * N, "timestep": 4 * W * N,
+           "raytrace_alone": 3 * W * N}
     hbm = {k: alg[k] / (phases[k] * 1e-3) / 1e9 for k in phases}
-    dom = max(phases, key=phases.get)
+    dom = max(("timestep", "predictor", "corrector"), key=phases.get)
     # the whole step against HBM: seven words per cell-update
     step_gbs = STEP_WORDS * W * N / (ms_step * 1e-3) / 1e9
     hbm_view = {"kernel": dom, "achieved": round(hbm[dom], 2), "peak": HBM_PEAK_GBS,
@@ -743,19 +755,25 @@ def main() -> int:
                 "bytes_per_launch": alg[dom]}
     step_view = {"bytes_per_cell_update": STEP_WORDS * W, "achieved": round(step_gbs, 2),
                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 5)}
-    if dom.startswith("chem"):
-        # the micro-physics (k_chem and, in mixed precision, the double pass
-        # k_chem_fix over the front cells that follows it) is bound by vector
-        # arithmetic: a few words of HBM per cell against hundreds of flops
-        flops = newton_per_launch * FLOP_NEWTON + N * FLOP_CELL_SETUP
-        t_chem = 0.5 * (phases["chem_predictor"] + phases["chem_corrector"])
-        achieved = flops / (t_chem * 1e-3) / 1e12
+    if fused:
+        kname = "k_chem_sweep" + (" (+ k_chem_fix, conditional k_sweep_persist)"
+                                  if args.precision == "mixed" else "")
+    else:
+        kname = "k_chem" + (" + k_chem_fix" if args.precision in ("mixed", "mixed_front") else "") \
+                + " + raytrace"
+    if dom != "timestep":
+        # a half step is bound by the vector arithmetic of the micro-physics:
+        # a few words of HBM per cell against hundreds of flops
+        flops = newton_per_launch * FLOP_NEWTON + N * (FLOP_CELL_SETUP + FLOP_SWEEP_CELL)
+        t_half = 0.5 * (phases["predictor"] + phases["corrector"])
+        achieved = flops / (t_half * 1e-3) / 1e12
         peak = VALU_PEAK[args.precision]
-        roofline = {"bound": "alu", "kernel": "k_chem + k_chem_fix (" + dom + ")",
+        roofline = {"bound": "alu", "kernel": kname + " (" + dom + ")",
                     "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                     "frac": round(achieved / peak, 5), "peak_note": VALU_PEAK_NOTE,
-                    "traffic": measured_traffic() if (args.precision == "mixed" and args.n == 256) else None,
-                    "flops_per_launch": flops}
+                    "traffic": measured_traffic() if (args.precision == "mixed" and args.n == 256
+                                                      and fused) else None,
+                    "flops_per_launch": flops, "launch_ms": round(t_half, 4)}
     else:
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(hbm[dom], 2),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(hbm[dom] / HBM_PEAK_GBS, 5),
@@ -763,8 +781,8 @@ def main() -> int:
     roofline["hbm_of_dominant"] = hbm_view
     roofline["hbm_of_step"] = step_view
     roofline["phase_ms"] = {k: round(v, 4) for k, v in phases.items()}
-    roofline["raytrace_hbm"] = {"achieved": round(hbm["raytrace"], 2), "unit": "GB/s",
-                                "frac": round(hbm["raytrace"] / HBM_PEAK_GBS, 5)}
+    roofline["raytrace_alone_hbm"] = {"achieved": round(hbm["raytrace_alone"], 2), "unit": "GB/s",
+                                      "frac": round(hbm["raytrace_alone"] / HBM_PEAK_GBS, 5)}
 
     out = {
         "metric": "cell-updates/s per raytrace+chemistry step at 256^3; p50/p99 batched solve latency",

@@ -196,6 +196,17 @@ pi_status pi_raytrace(pi_grid* grid, int state, int tau_buf, void* stream);
 pi_status pi_chem_step(pi_grid* grid, int use_device_dt, double h_value, int tau_buf,
                        int from_state, int to_state, void* stream);
 
+/* pi_chem_step followed by pi_raytrace(grid, to_state, tau_out): the
+ * micro-physics of the cells and then the columns of the new state, the pair
+ * each half of the step of Sect. 2.2 runs.  With the persistent raytrace
+ * (PI_TILE_PERSISTENT) on a grid of float storage with one point source
+ * (not PI_MIXED_FRONT; with PI_MIXED, tau_buf != tau_out), the two run as one
+ * launch in which every tile integrates its cells and then sweeps them;
+ * otherwise as the two calls.  The results are the same either way, bit for
+ * bit.  Arguments as for the two calls. */
+pi_status pi_chem_raytrace(pi_grid* grid, int use_device_dt, double h_value, int tau_buf,
+                           int from_state, int to_state, int tau_out, void* stream);
+
 /* Timestep (eq. 4 with the grid's K1..K4): min over cells of the limit
  * evaluated at state PI_BUF_N with columns tau, reduced in FP64, capped at
  * t_end - t (a remainder below 1e-12 t_end is absorbed).  The result stays on
@@ -430,7 +441,7 @@ const char* pi_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns the
  * value it was built with. */
-#define PI_ABI_VERSION 110
+#define PI_ABI_VERSION 111
 int pi_abi_version(void);
 
 #ifdef __cplusplus

@@ -42,7 +42,8 @@ ABI_SYMBOLS = (
     "pi_batch_work_counters",
     "pi_server_create", "pi_submit", "pi_poll", "pi_cancel", "pi_server_stats", "pi_server_destroy",
     "pi_set_raytrace_tile", "pi_get_raytrace_tile", "pi_batch_set_raytrace_tile",
-    "pi_batch_get_raytrace_tile", "pi_set_raytrace_wait_limit", "pi_batch_set_raytrace_wait_limit",
+    "pi_batch_get_raytrace_tile", "pi_set_raytrace_wait_limit", "pi_chem_raytrace",
+    "pi_batch_set_raytrace_wait_limit",
     "pi_step_a1",
     "pi_batch_step_a1",
     "pi_grid_required_bytes", "pi_grid_save", "pi_grid_load", "pi_checkpoint",
@@ -154,6 +155,7 @@ def lib() -> C.CDLL:
         L.pi_batch_set_raytrace_tile.argtypes = [vp, i32]
         L.pi_batch_get_raytrace_tile.argtypes = [vp, ip]
         L.pi_set_raytrace_wait_limit.argtypes = [vp, C.c_double]
+        L.pi_chem_raytrace.argtypes = [vp, i32, C.c_double, i32, i32, i32, i32, vp]
         L.pi_batch_set_raytrace_wait_limit.argtypes = [vp, C.c_double]
         szp = C.POINTER(C.c_size_t)
         L.pi_grid_required_bytes.argtypes = [C.POINTER(GridDesc), szp, szp]
@@ -328,6 +330,12 @@ class Grid:
                   use_device_dt: bool = False):
         check(lib().pi_chem_step(self._h, int(use_device_dt), float(h), tau_buf, from_state,
                                  to_state, self._stream()))
+
+    def chem_raytrace(self, h: float, tau_buf=PI_BUF_N, from_state=PI_BUF_N, to_state=PI_BUF_N,
+                      tau_out=PI_BUF_N, use_device_dt: bool = False):
+        """pi_chem_raytrace: chem_step, then the raytrace of to_state into tau_out."""
+        check(lib().pi_chem_raytrace(self._h, int(use_device_dt), float(h), tau_buf, from_state,
+                                     to_state, tau_out, self._stream()))
 
     def timestep(self, t_end: float):
         check(lib().pi_timestep(self._h, float(t_end), self._stream()))

@@ -127,6 +127,10 @@ void free_tables(std::vector<Engine::Table>& tables);
 pi_status engine_raytrace(Engine& e, int state, int tau_buf, hipStream_t s);
 // The timing itself: raytraces of (state -> tau_buf) with each tile edge.
 pi_status engine_autotune(Engine& e, int state, int tau_buf, hipStream_t s);
+// Micro-physics, then the raytrace of state `to` into tau_out: fused when
+// the engine's steps fuse and the buffers allow it, else the two in turn.
+pi_status engine_chem_raytrace(Engine& e, bool dev_dt, double h, int tau_buf, int from, int to,
+                               int tau_out, hipStream_t s);
 pi_status engine_chem(Engine& e, bool dev_dt, double h, int tau_buf, int from, int to,
                       hipStream_t s);
 // t_end_arg finite: the common t_end, else each grid's stored t_end.

@@ -337,20 +337,20 @@ pi_status chem_t(Engine& e, bool dev_dt, double h, int tau_buf, int from, int to
 // and, if there were any, the raytrace again (a persistent launch that leaves
 // at once otherwise: the decision is the device's, so a captured graph
 // replays it).
-pi_status chem_sweep_fused(Engine& e, double h, int tau_chem, int from, int to, int tau_sweep,
-                           hipStream_t s)
+pi_status chem_sweep_fused(Engine& e, bool dev_dt, double h, int tau_chem, int from, int to,
+                           int tau_sweep, hipStream_t s)
 {
     const int w = PERSIST_SCHEDULE;
     const int ntiles =
         e.stage_first[w].empty() ? 0 : e.stage_first[w].back() + e.stage_count[w].back();
     const BatchDev b = e.bd();
-    HIP_OR(launch_chem_sweep<float>(gd<float>(e), b, from, to, tau_chem, tau_sweep, true, h,
+    HIP_OR(launch_chem_sweep<float>(gd<float>(e), b, from, to, tau_chem, tau_sweep, dev_dt, h,
                                     e.work, e.mixed(), e.tiles[w], ntiles, e.octs, e.flags,
                                     e.ctl, std::min(ntiles, e.fused_wg), e.persist_spin, s),
            "fused micro-physics and raytrace launch");
     if (e.mixed()) {
-        HIP_OR(launch_chem_fix(gd<float>(e), b, e.fix_blocks, from, to, tau_chem, true, h, e.work,
-                               true, s),
+        HIP_OR(launch_chem_fix(gd<float>(e), b, e.fix_blocks, from, to, tau_chem, dev_dt, h,
+                               e.work, true, s),
                "double re-solve launch");
         HIP_OR(launch_sweep_persist<float>(gd<float>(e), to, tau_sweep, e.tiles[w], ntiles, e.octs,
                                            e.flags, e.ctl, std::min(ntiles, e.persist_wg),
@@ -376,11 +376,11 @@ template <typename R> pi_status step_t(Engine& e, double t_end_arg, int order, h
     if (e.fused() && (order == 2 || !e.mixed())) {
         // predictor to the half step with the raytrace of x*, corrector with
         // the raytrace of the new state (A3); or the one step of A2
-        if (order == 2 && (r = chem_sweep_fused(e, 0.5, PI_BUF_N, PI_BUF_N, PI_BUF_HALF,
+        if (order == 2 && (r = chem_sweep_fused(e, true, 0.5, PI_BUF_N, PI_BUF_N, PI_BUF_HALF,
                                                 PI_BUF_HALF, s)) != PI_OK)
             return r;
-        if ((r = chem_sweep_fused(e, 1.0, order == 2 ? PI_BUF_HALF : PI_BUF_N, PI_BUF_N, PI_BUF_N,
-                                  PI_BUF_N, s)) != PI_OK)
+        if ((r = chem_sweep_fused(e, true, 1.0, order == 2 ? PI_BUF_HALF : PI_BUF_N, PI_BUF_N,
+                                  PI_BUF_N, PI_BUF_N, s)) != PI_OK)
             return r;
         HIP_OR(launch_advance<R>(gd<R>(e), e.ngrids(), s), "advance launch");
         return PI_OK;
@@ -787,6 +787,22 @@ pi_status engine_raytrace(Engine& e, int state, int tau_buf, hipStream_t s)
         if (r != PI_OK) return r;
     }
     return raytrace_any(e, state, tau_buf, e.sweep >= 0 ? e.sweep : SWEEP_DEFAULT, s);
+}
+
+pi_status engine_chem_raytrace(Engine& e, bool dev_dt, double h, int tau_buf, int from, int to,
+                               int tau_out, hipStream_t s)
+{
+    if (e.sweep < 0) {
+        pi_status r = engine_autotune(e, PI_BUF_N, PI_BUF_N, s);
+        if (r != PI_OK) return r;
+    }
+    // (with mixed precision the double re-solve after a fused launch reads
+    // the columns tau_buf, which the fused raytrace must not overwrite)
+    if (e.fused() && !(e.mixed() && tau_buf == tau_out))
+        return chem_sweep_fused(e, dev_dt, h, tau_buf, from, to, tau_out, s);
+    pi_status r = engine_chem(e, dev_dt, h, tau_buf, from, to, s);
+    if (r != PI_OK) return r;
+    return raytrace_any(e, to, tau_out, e.sweep >= 0 ? e.sweep : SWEEP_DEFAULT, s);
 }
 
 pi_status engine_chem(Engine& e, bool dev_dt, double h, int tau_buf, int from, int to, hipStream_t s)

@@ -225,6 +225,17 @@ pi_status pi_chem_step(pi_grid* g, int use_device_dt, double h_value, int tau_bu
                        static_cast<hipStream_t>(stream));
 }
 
+pi_status pi_chem_raytrace(pi_grid* g, int use_device_dt, double h_value, int tau_buf,
+                           int from_state, int to_state, int tau_out, void* stream)
+{
+    if (!g) return fail(PI_EINVAL, "null grid");
+    if (!(h_value >= 0) || !std::isfinite(h_value)) return fail(PI_EINVAL, "h must be finite and >= 0");
+    if (!buf_ok(tau_buf) || !buf_ok(from_state) || !buf_ok(to_state) || !buf_ok(tau_out))
+        return fail(PI_EINVAL, "buffer selector");
+    return engine_chem_raytrace(g->e, use_device_dt != 0, h_value, tau_buf, from_state, to_state,
+                                tau_out, static_cast<hipStream_t>(stream));
+}
+
 pi_status pi_timestep(pi_grid* g, double t_end, void* stream)
 {
     if (!g) return fail(PI_EINVAL, "null grid");

@@ -146,3 +146,49 @@ def test_fused_step_full_size_mixed():
     assert out[8][0] == out[P][0]
     for a, b in zip(out[8][1:], out[P][1:]):
         assert np.array_equal(a, b)
+
+
+CR_CASES = [  # (h, tau_buf, from, to, tau_out): predictor, corrector, corrector timing form, A2
+    (0.5, binding.PI_BUF_N, binding.PI_BUF_N, binding.PI_BUF_HALF, binding.PI_BUF_HALF),
+    (1.0, binding.PI_BUF_HALF, binding.PI_BUF_N, binding.PI_BUF_N, binding.PI_BUF_N),
+    (1.0, binding.PI_BUF_HALF, binding.PI_BUF_N, binding.PI_BUF_HALF, binding.PI_BUF_N),
+    (1.0, binding.PI_BUF_N, binding.PI_BUF_N, binding.PI_BUF_N, binding.PI_BUF_N),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed", "mixed_front", "fp64"])
+def test_chem_raytrace_equals_chem_step_then_raytrace(precision):
+    """pi_chem_raytrace (fused where the grid allows it) against pi_chem_step
+    followed by pi_raytrace on tiles of 8, for the buffer pairings of the
+    step's predictor and corrector, the corrector's timing form and A2: every
+    state, column and work counter equal bit for bit."""
+    import torch
+    spec = synth.cfg2(n=40).with_(n=(40, 36, 44), src=(13, 20, 30))
+    nH, x, T = _start(spec, 5, 6.0)
+    out = {}
+    for edge, fused in ((8, False), (P, True)):
+        g = binding.Grid(spec, precision=precision)
+        g.raytrace_tile = edge
+        g.load(nH, x, T0=50.0)
+        g.E.copy_(torch.as_tensor(1.5 * KB * nH * (2.0 - x) * T, dtype=g.dtype))
+        g.raytrace()
+        g.timestep(spec.t_end)
+        # the half-step buffers start as copies of state n
+        for a, b in (("x_half", "x"), ("E_half", "E"), ("tau_half", "tau")):
+            getattr(g, a).copy_(getattr(g, b))
+        g.work_counters(reset=True)
+        res = []
+        for h, tb, fr, to, tout in CR_CASES:
+            if fused:
+                g.chem_raytrace(h, tb, fr, to, tout, use_device_dt=True)
+            else:
+                g.chem_step(h, tb, fr, to, use_device_dt=True)
+                g.raytrace(to, tout)
+            res.append([to_np(getattr(g, k)) for k in ("x", "E", "tau", "x_half", "E_half",
+                                                        "tau_half")])
+        out[fused] = (res, g.work_counters(), g.state())
+        g.close()
+    assert out[False][1] == out[True][1] and out[False][2] == out[True][2]
+    for ra, rb in zip(out[False][0], out[True][0]):
+        for a, b in zip(ra, rb):
+            assert np.array_equal(a, b)
