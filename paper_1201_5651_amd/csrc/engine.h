@@ -70,6 +70,8 @@ struct Engine {
     size_t octs_cap = 0;
     unsigned* flags = nullptr;
     size_t flags_cap = 0;
+    void* fbuf = nullptr;        // face buffer: FACE_WORDS words of the grids' type per tile
+    size_t fbuf_cap = 0;
     SweepCtl* ctl = nullptr;
     int persist_wg = 0;
     // longest wait of a persistent tile for its upstream tiles (ticks of the

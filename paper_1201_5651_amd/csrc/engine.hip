@@ -295,7 +295,7 @@ pi_status raytrace_t(Engine& e, int state, int tau_buf, int which, hipStream_t s
                                ? 0
                                : e.stage_first[w].back() + e.stage_count[w].back();
         HIP_OR(launch_sweep_persist<R>(gd<R>(e), state, tau_buf, e.tiles[w], ntiles, e.octs,
-                                       e.flags, e.ctl, std::min(ntiles, e.persist_wg),
+                                       e.flags, e.fbuf, e.ctl, std::min(ntiles, e.persist_wg),
                                        e.persist_spin, nullptr, s),
                "persistent raytrace launch");
         return PI_OK;
@@ -346,14 +346,15 @@ pi_status chem_sweep_fused(Engine& e, bool dev_dt, double h, int tau_chem, int f
     const BatchDev b = e.bd();
     HIP_OR(launch_chem_sweep<float>(gd<float>(e), b, from, to, tau_chem, tau_sweep, dev_dt, h,
                                     e.work, e.mixed(), e.tiles[w], ntiles, e.octs, e.flags,
-                                    e.ctl, std::min(ntiles, e.fused_wg), e.persist_spin, s),
+                                    e.fbuf, e.ctl, std::min(ntiles, e.fused_wg), e.persist_spin,
+                                    s),
            "fused micro-physics and raytrace launch");
     if (e.mixed()) {
         HIP_OR(launch_chem_fix(gd<float>(e), b, e.fix_blocks, from, to, tau_chem, dev_dt, h,
                                e.work, true, s),
                "double re-solve launch");
         HIP_OR(launch_sweep_persist<float>(gd<float>(e), to, tau_sweep, e.tiles[w], ntiles, e.octs,
-                                           e.flags, e.ctl, std::min(ntiles, e.persist_wg),
+                                           e.flags, e.fbuf, e.ctl, std::min(ntiles, e.persist_wg),
                                            e.persist_spin, e.fix_n + 2, s),
                "conditional raytrace launch");
     }
@@ -662,6 +663,16 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
             HIP_OR(hipMemset(e.flags, 0, fb), "raytrace flag clear");
             e.flags_cap = fb;
         }
+        const size_t bb = (e.fp64() ? sizeof(double) : sizeof(float)) * FACE_WORDS *
+                          (size_t)std::max<int64_t>(nflag, 1);
+        if (bb > e.fbuf_cap) {
+            // (never read before a tile of the same call has written it)
+            if (e.fbuf) (void)hipFree(e.fbuf);
+            e.fbuf = nullptr;
+            e.fbuf_cap = 0;
+            HIP_OR(hipMalloc(&e.fbuf, bb), "raytrace face buffer allocation");
+            e.fbuf_cap = bb;
+        }
         if (!e.ctl) {
             HIP_OR(hipMalloc(&e.ctl, sizeof(SweepCtl)), "raytrace control allocation");
             HIP_OR(hipMemset(e.ctl, 0, sizeof(SweepCtl)), "raytrace control clear");
@@ -712,8 +723,10 @@ void engine_free(Engine& e)
     if (e.cap) (void)hipStreamDestroy(e.cap);
     e.cap = nullptr;
     for (void* p : { e.gdev, (void*)e.first, (void*)e.fix_n, (void*)e.fix_list, (void*)e.work,
-                     (void*)e.octs, (void*)e.flags, (void*)e.ctl })
+                     (void*)e.octs, (void*)e.flags, e.fbuf, (void*)e.ctl })
         if (p) (void)hipFree(p);
+    e.fbuf = nullptr;
+    e.fbuf_cap = 0;
     e.octs = nullptr;
     e.flags = nullptr;
     e.ctl = nullptr;
@@ -976,7 +989,9 @@ size_t grid_private_bytes(const pi_grid_desc& d)
         b += 3 * sizeof(unsigned int) + sizeof(long long) * (size_t)n;
     // persistent raytrace: octant table, a done-flag per tile, control block
     b += sizeof(int4) * 8 * (size_t)nsources(d) +
-         sizeof(unsigned) * (size_t)tile_count(d, PERSIST_TILE) + sizeof(SweepCtl);
+         (sizeof(unsigned) + (d.precision == PI_FP64 ? sizeof(double) : sizeof(float)) * FACE_WORDS) *
+             (size_t)tile_count(d, PERSIST_TILE) +
+         sizeof(SweepCtl);
     if (d.spectrum == PI_SPEC_TABLE) b += sizeof(DevTable<double>) + sizeof(DevTable<float>);
     return b;
 }

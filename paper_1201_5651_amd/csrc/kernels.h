@@ -129,6 +129,9 @@ struct SweepCtl {
 constexpr int PERSIST_TILE = 8;
 constexpr int SWEEP_PERSIST = 3;
 constexpr int PERSIST_SCHEDULE = 1;   // SWEEP_TILES[1] == PERSIST_TILE
+// Words of the face buffer per tile of the persistent raytrace: for its three
+// downstream faces, sigma0 n_H x dx and the centre column of every cell.
+constexpr int FACE_WORDS = 6 * PERSIST_TILE * PERSIST_TILE;
 // Threads per workgroup of the micro-physics fused with the persistent sweep
 // (two wavefronts, four 4^3 bricks of a tile each).
 constexpr int FUSED_THREADS = 128;
@@ -142,7 +145,8 @@ hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, c
 // The whole raytrace of every grid in one launch of nwg persistent workgroups
 // over the schedule tiles[0 .. ntiles) of edge PERSIST_TILE (stage after
 // stage); octs[grid << 3 | octant] = (first done-flag, tiles along x, y, z);
-// flags: one per tile.  spin_ticks bounds each wait (100 MHz ticks).  cond:
+// flags: one per tile; fbuf: the face buffer, FACE_WORDS words of R per tile.
+// spin_ticks bounds each wait (100 MHz ticks).  cond:
 // null, or a word that must be non-zero for the raytrace to run (cleared by
 // it).
 // One half of an A3 step (or an A2 step) of every grid in one launch of nwg
@@ -158,14 +162,14 @@ template <typename R>
 hipError_t launch_chem_sweep(const GridDev<R>* grids, const BatchDev& b, int from, int to,
                              int tau_chem, int tau_sweep, bool dev_dt, double hscale,
                              unsigned long long* ctr, bool mixed, const int4* tiles, int ntiles,
-                             const int4* octs, unsigned* flags, SweepCtl* ctl, int nwg,
-                             long long spin_ticks, hipStream_t s);
+                             const int4* octs, unsigned* flags, void* fbuf, SweepCtl* ctl,
+                             int nwg, long long spin_ticks, hipStream_t s);
 // Workgroups of k_chem_sweep one compute unit holds at once.
 template <typename R> int chem_sweep_occupancy(bool mixed);
 template <typename R>
 hipError_t launch_sweep_persist(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,
-                                int ntiles, const int4* octs, unsigned* flags, SweepCtl* ctl,
-                                int nwg, long long spin_ticks, unsigned* cond,
+                                int ntiles, const int4* octs, unsigned* flags, void* fbuf,
+                                SweepCtl* ctl, int nwg, long long spin_ticks, unsigned* cond,
                                 hipStream_t s);
 // Resident workgroups of the persistent raytrace kernel on one CU.
 template <typename R> int sweep_persist_occupancy();

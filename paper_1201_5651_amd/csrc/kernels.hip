@@ -148,6 +148,16 @@ template <int TT> struct SweepShape {
     static constexpr int CPT = CELLS / THREADS;
 };
 
+// Half path length per cell length through the cell whose centre sits at
+// offsets (ax, ay, az) from the source vertex, da the largest of them:
+// sqrt(ax^2 + ay^2 + az^2) / (2 da), with the same operations (no
+// contraction) wherever a sweep needs it.
+template <typename R> __device__ __forceinline__ R half_path(R ax, R ay, R az, R da)
+{
+#pragma clang fp contract(off)
+    return R(0.5) * r_sqrt(ax * ax + ay * ay + az * az) / da;
+}
+
 // Short-characteristics geometry of a cell at octant-local coordinates L
 // (Sect. 2.1): the major axis a of the ray from the source vertex to the cell
 // centre and the two others (b, c); the bilinear weights of the four upstream
@@ -174,7 +184,7 @@ template <typename R> __device__ __forceinline__ ScGeom<R> sc_geom(const int L[3
     o.g10 = vb ? fb * (R(1) - fc) : R(0);
     o.g01 = vc ? (R(1) - fb) * fc : R(0);
     o.g11 = (vb && vc) ? fb * fc : R(0);
-    o.hds = R(0.5) * r_sqrt(ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2]) / ad[o.a];
+    o.hds = half_path<R>(ad[0], ad[1], ad[2], ad[o.a]);
     o.corner = L[o.a] == 0;
     return o;
 }
@@ -194,35 +204,52 @@ template <typename R> __device__ __forceinline__ R halo_hds(int Lx, int Ly, int 
 {
     const R ax = R(Lx) + R(0.5), ay = R(Ly) + R(0.5), az = R(Lz) + R(0.5);
     const R da = (az >= ax && az >= ay) ? az : (ay >= ax ? ay : ax);
-    return R(0.5) * r_sqrt(ax * ax + ay * ay + az * az) / da;
+    return half_path<R>(ax, ay, az, da);
 }
 
 // Kinds of tile sweep.  TILE_STAGED: every upstream tile belongs to an
-// earlier launch.  TILE_COHERENT: upstream tiles run in the same launch; the
-// upstream columns are read, and the tile's columns written, as relaxed
-// atomics at agent scope (loads and stores that reach the device-wide point of
-// coherence, past the caches of the compute unit and of its XCD).
+// earlier launch; the halo's sigma0 n_H x dx and columns are read from the
+// grid.  TILE_COHERENT: upstream tiles run in the same launch.  A finished
+// tile publishes sigma0 n_H x dx and the centre column of the cells on its
+// three downstream faces in its slot of a face buffer (FACE_WORDS words per
+// tile), written and read as relaxed atomics at agent scope (loads and stores
+// that reach the device-wide point of coherence, past the caches of the
+// compute unit and of its XCD); a tile takes its halo from the slots of the
+// up to seven upstream tiles that own it -- contiguous rows instead of
+// scattered cells -- and writes its columns to the grid with plain stores.
+// The published values are those a halo read from the grid would form.
 // TILE_FUSED: as TILE_COHERENT, after the tile's own micro-physics in the
-// same workgroup: the caller has put sigma0 n_H x dx of the tile's own cells
-// in s_kap, and the neutral fractions of the upstream halo, written in the
-// same launch, are read at agent scope after the wait.
+// same workgroup, which has put sigma0 n_H x dx of the tile's own cells in
+// s_kap.
 enum { TILE_STAGED = 0, TILE_COHERENT = 1, TILE_FUSED = 2 };
+
+// Face buffer slot of a tile of edge T: for the faces at local x, y, z =
+// T - 1 in turn, T^2 values of sigma0 n_H x dx and then T^2 centre columns,
+// the face's cells in order (ly, lz), (lx, lz), (lx, ly) with the first index
+// fastest.
+template <int T> struct FaceSlot {
+    static constexpr int WORDS = 6 * T * T;
+    __host__ __device__ static constexpr int kap(int face, int i, int j) { return (2 * face) * T * T + j * T + i; }
+    __host__ __device__ static constexpr int col(int face, int i, int j) { return (2 * face + 1) * T * T + j * T + i; }
+};
 
 // The sweep of one tile by NT threads (the body of the tiled raytrace
 // kernels), with the LDS arrays of the workgroup.  wait() runs between the
-// work that does not depend on earlier tiles (sigma0 n_H x dx of the tile and,
-// but for TILE_FUSED, of its halo; the cells' geometry) and the loads that do
-// (the columns, and for TILE_FUSED the neutral fractions, of the upstream
-// halo); every thread calls it, and the caller's synchronisation follows it.
+// work that does not depend on earlier tiles (sigma0 n_H x dx of the tile --
+// and for TILE_STAGED of its halo -- and the cells' geometry) and the loads
+// that do (the halo); every thread calls it, and the caller's
+// synchronisation follows it.  For the coherent kinds, fbuf is the face
+// buffer, idx the tile's flag index and oc its octant's (first flag, tiles
+// along x, y, z).
 template <typename R, int TT, int NT, int Kind, typename Wait>
 __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids, int state,
-                                           int tau_buf, int4 tl, R* s_tc, R* s_kap, Wait wait)
+                                           int tau_buf, int4 tl, R* s_tc, R* s_kap, Wait wait,
+                                           R* fbuf = nullptr, int idx = 0, int4 oc = int4{})
 {
     constexpr int TX = TT, TY = TT, TZ = TT;
     constexpr int CPT = TT * TT * TT / NT;
     static_assert(CPT * NT == TT * TT * TT, "whole cells per thread");
     constexpr int HX = TX + 1, HY = TY + 1, HZ = TZ + 1, NHALO = HX * HY * HZ;
-    constexpr bool coherent = Kind != TILE_STAGED;
     const GridDev<R>& G = grids[tl.x >> 3];
     const Params<R> p = G.p;
     const R* __restrict__ nH = G.nHr[state];
@@ -235,9 +262,9 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
     const int ez = pz ? p.nz - p.sz : p.sz;
     const int X0 = tl.y * TX, Y0 = tl.z * TY, Z0 = tl.w * TZ;
 
-    if constexpr (Kind != TILE_FUSED) {
-        // (a fixed trip count, so that every iteration's loads are in flight
-        // together)
+    if constexpr (Kind == TILE_STAGED) {
+        // the tile and its halo (a fixed trip count, so that every
+        // iteration's loads are in flight together)
 #pragma unroll
         for (int k = 0; k < (NHALO + NT - 1) / NT; ++k) {
             const int q = threadIdx.x + k * NT;
@@ -253,6 +280,23 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
                 kap = p.sdx * nH[g] * xs[g];
             }
             s_kap[q] = kap;
+        }
+    } else if constexpr (Kind == TILE_COHERENT) {
+        // the tile's own cells (its halo comes from the face buffer)
+#pragma unroll
+        for (int k = 0; k < TX * TY * TZ / NT; ++k) {
+            const int t = threadIdx.x + k * NT;
+            const int ox = t % TX, oy = (t / TX) % TY, oz = t / (TX * TY);
+            const int Lx = X0 + ox, Ly = Y0 + oy, Lz = Z0 + oz;
+            R kap = R(0);
+            if (Lx < ex && Ly < ey && Lz < ez) {
+                const int gi = px ? p.sx + Lx : p.sx - 1 - Lx;
+                const int gj = py ? p.sy + Ly : p.sy - 1 - Ly;
+                const int gk = pz ? p.sz + Lz : p.sz - 1 - Lz;
+                const int64_t g = gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk);
+                kap = p.sdx * nH[g] * xs[g];
+            }
+            s_kap[(oz + 1) * HX * HY + (oy + 1) * HX + (ox + 1)] = kap;
         }
     }
 
@@ -287,9 +331,9 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
 
     wait();
     __syncthreads();
-    // centre columns of the upstream halo (the faces at local index -1), and
-    // for TILE_FUSED its sigma0 n_H x dx; the tile's own entries of s_tc are
-    // written by their cells before any cell reads them
+    // the upstream halo (the faces at local index -1): centre columns and,
+    // for the coherent kinds, sigma0 n_H x dx; the tile's own entries of s_tc
+    // are written by their cells before any cell reads them
     constexpr int NFACE = FaceList<TT>::N;
 #pragma unroll
     for (int k = 0; k < (NFACE + NT - 1) / NT; ++k) {
@@ -298,28 +342,33 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
         const int q = face_entry<TT>(f);
         const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
         const int Lx = X0 + hx - 1, Ly = Y0 + hy - 1, Lz = Z0 + hz - 1;
-        R tc = R(0);
+        R tc = R(0), kap = R(0);
         if (Lx >= 0 && Ly >= 0 && Lz >= 0 && Lx < ex && Ly < ey && Lz < ez) {
-            const int gi = px ? p.sx + Lx : p.sx - 1 - Lx;
-            const int gj = py ? p.sy + Ly : p.sy - 1 - Ly;
-            const int gk = pz ? p.sz + Lz : p.sz - 1 - Lz;
-            const int64_t g = gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk);
-            R kap;
-            if constexpr (Kind == TILE_FUSED) {
-                kap = p.sdx * nH[g] *
-                      __hip_atomic_load(&xs[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s_kap[q] = kap;
-            } else {
+            if constexpr (Kind == TILE_STAGED) {
+                const int gi = px ? p.sx + Lx : p.sx - 1 - Lx;
+                const int gj = py ? p.sy + Ly : p.sy - 1 - Ly;
+                const int gk = pz ? p.sz + Lz : p.sz - 1 - Lz;
+                const int64_t g = gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk);
                 kap = s_kap[q];
+                // the centre column exactly as the cell's own tile formed it
+                tc = r_fma(halo_hds<R>(Lx, Ly, Lz), kap, tau[g]);
+            } else {
+                // the owner: the upstream tile across every face the entry lies
+                // on; its local coordinates; and the owner's face that holds it
+                const int ux = hx == 0, uy = hy == 0, uz = hz == 0;
+                const int owner = idx - ux - uy * oc.y - uz * oc.y * oc.z;
+                const int ox = ux ? TT - 1 : hx - 1, oy = uy ? TT - 1 : hy - 1;
+                const int oz = uz ? TT - 1 : hz - 1;
+                const int face = ux ? 0 : (uy ? 1 : 2);
+                const int i = face == 0 ? oy : ox, j = face == 2 ? oy : oz;
+                const R* slot = fbuf + (int64_t)owner * FaceSlot<TT>::WORDS;
+                kap = __hip_atomic_load(&slot[FaceSlot<TT>::kap(face, i, j)], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+                tc = __hip_atomic_load(&slot[FaceSlot<TT>::col(face, i, j)], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             }
-            const R up = coherent
-                             ? __hip_atomic_load(&tau[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                             : tau[g];
-            // the centre column exactly as the cell's own tile formed it
-            tc = r_fma(halo_hds<R>(Lx, Ly, Lz), kap, up);
-        } else if (Kind == TILE_FUSED) {
-            s_kap[q] = R(0);
         }
+        if constexpr (Kind != TILE_STAGED) s_kap[q] = kap;
         s_tc[q] = tc;
     }
     __syncthreads();
@@ -342,6 +391,24 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
         }
         __syncthreads();
     }
+    if constexpr (Kind != TILE_STAGED) {
+        // publish the downstream faces: entry (face, i, j) is the cell at local
+        // TT - 1 along the face's axis (cells outside the octant give 0)
+        R* slot = fbuf + (int64_t)idx * FaceSlot<TT>::WORDS;
+        for (int e = threadIdx.x; e < 3 * TT * TT; e += NT) {
+            const int face = e / (TT * TT), i = e % TT, j = (e / TT) % TT;
+            const int lx = face == 0 ? TT - 1 : i;
+            const int ly = face == 0 ? i : (face == 1 ? TT - 1 : j);
+            const int lz = face == 2 ? TT - 1 : j;
+            const bool in = X0 + lx < ex && Y0 + ly < ey && Z0 + lz < ez;
+            const int c = (lz + 1) * HX * HY + (ly + 1) * HX + (lx + 1);
+            __hip_atomic_store(&slot[FaceSlot<TT>::kap(face, i, j)], in ? s_kap[c] : R(0),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&slot[FaceSlot<TT>::col(face, i, j)], in ? s_tc[c] : R(0),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();   // (s_kap becomes the output buffer)
+    }
     // entering columns back to natural order (in the halo buffer, no longer
     // read) for a coalesced store
     R* s_out = s_kap;
@@ -355,11 +422,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
             const int gi = px ? p.sx + Lx : p.sx - 1 - Lx;
             const int gj = py ? p.sy + Ly : p.sy - 1 - Ly;
             const int gk = pz ? p.sz + Lz : p.sz - 1 - Lz;
-            R* dst = &tau[gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk)];
-            if (coherent)
-                __hip_atomic_store(dst, s_out[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            else
-                *dst = s_out[t];
+            tau[gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk)] = s_out[t];
         }
     }
 }
@@ -419,7 +482,8 @@ template <typename R, int TT>
 __global__ void __launch_bounds__(SweepShape<TT>::THREADS)
 k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
                 const int4* __restrict__ tiles, int ntiles, const int4* __restrict__ octs,
-                unsigned* __restrict__ flags, SweepCtl* ctl, long long spin_ticks, unsigned* cond)
+                unsigned* __restrict__ flags, R* fbuf, SweepCtl* ctl, long long spin_ticks,
+                unsigned* cond)
 {
     constexpr int NHALO = (TT + 1) * (TT + 1) * (TT + 1);
     __shared__ R s_tc[NHALO];
@@ -469,7 +533,7 @@ k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
                     }
                 }
             }
-        });
+        }, fbuf, idx, oc);
         // every wave's column stores complete, then the flag
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
@@ -752,7 +816,7 @@ __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per
 k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int tau_chem,
              int tau_sweep, int dev_dt, double hscale, unsigned long long* ctr,
              const int4* __restrict__ tiles, int ntiles, const int4* __restrict__ octs,
-             unsigned* __restrict__ flags, SweepCtl* ctl, long long spin_ticks)
+             unsigned* __restrict__ flags, R* fbuf, SweepCtl* ctl, long long spin_ticks)
 {
     constexpr int TT = PERSIST_TILE, NT = FUSED_THREADS;
     constexpr int HX = TT + 1, HY = TT + 1, NHALO = HX * HY * (TT + 1);
@@ -820,8 +884,7 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
                                    G.tau[tau_chem], hd, x, E, w);
                 flag = Mixed && w.close > close0;
                 if (!flag) {
-                    __hip_atomic_store(&G.x[to][q], x, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+                    G.x[to][q] = x;
                     if (G.E[to]) G.E[to][q] = E;
                 }
                 kap = pl.sdx * nHs[q] * x;
@@ -861,7 +924,7 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
                     }
                 }
             }
-        });
+        }, fbuf, idx, oc);
         // every wave's neutral-fraction and column stores complete, then the flag
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
@@ -1243,13 +1306,14 @@ hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, c
 
 template <typename R>
 hipError_t launch_sweep_persist(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,
-                                int ntiles, const int4* octs, unsigned* flags, SweepCtl* ctl,
-                                int nwg, long long spin_ticks, unsigned* cond, hipStream_t s)
+                                int ntiles, const int4* octs, unsigned* flags, void* fbuf,
+                                SweepCtl* ctl, int nwg, long long spin_ticks, unsigned* cond,
+                                hipStream_t s)
 {
     if (ntiles <= 0 || nwg <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_sweep_persist<R, PERSIST_TILE>), dim3(nwg),
                        dim3(SweepShape<PERSIST_TILE>::THREADS), 0, s, grids, state, tau_buf, tiles,
-                       ntiles, octs, flags, ctl, spin_ticks, cond);
+                       ntiles, octs, flags, static_cast<R*>(fbuf), ctl, spin_ticks, cond);
     return hipGetLastError();
 }
 
@@ -1267,19 +1331,19 @@ template <typename R>
 hipError_t launch_chem_sweep(const GridDev<R>* grids, const BatchDev& b, int from, int to,
                              int tau_chem, int tau_sweep, bool dev_dt, double hscale,
                              unsigned long long* ctr, bool mixed, const int4* tiles, int ntiles,
-                             const int4* octs, unsigned* flags, SweepCtl* ctl, int nwg,
-                             long long spin_ticks, hipStream_t s)
+                             const int4* octs, unsigned* flags, void* fbuf, SweepCtl* ctl,
+                             int nwg, long long spin_ticks, hipStream_t s)
 {
     if constexpr (std::is_same<R, float>::value) {
         if (ntiles <= 0 || nwg <= 0) return hipSuccess;
         if (mixed)
             hipLaunchKernelGGL((k_chem_sweep<R, true>), dim3(nwg), dim3(FUSED_THREADS), 0, s,
                                grids, b, from, to, tau_chem, tau_sweep, (int)dev_dt, hscale, ctr,
-                               tiles, ntiles, octs, flags, ctl, spin_ticks);
+                               tiles, ntiles, octs, flags, static_cast<R*>(fbuf), ctl, spin_ticks);
         else
             hipLaunchKernelGGL((k_chem_sweep<R, false>), dim3(nwg), dim3(FUSED_THREADS), 0, s,
                                grids, b, from, to, tau_chem, tau_sweep, (int)dev_dt, hscale, ctr,
-                               tiles, ntiles, octs, flags, ctl, spin_ticks);
+                               tiles, ntiles, octs, flags, static_cast<R*>(fbuf), ctl, spin_ticks);
         return hipGetLastError();
     } else {
         // double storage keeps the separate kernels (its integrator does not
@@ -1386,13 +1450,13 @@ hipError_t launch_energy(int64_t n, const R* nH, const R* x, R* E, double T0, hi
     template hipError_t launch_sweep_stage<R>(const GridDev<R>*, int, int, const int4*, int, int,  \
                                               int, hipStream_t);                                   \
     template hipError_t launch_sweep_persist<R>(const GridDev<R>*, int, int, const int4*, int,     \
-                                                const int4*, unsigned*, SweepCtl*, int, long long, \
-                                                unsigned*, hipStream_t);                           \
+                                                const int4*, unsigned*, void*, SweepCtl*, int,     \
+                                                long long, unsigned*, hipStream_t);                \
     template int sweep_persist_occupancy<R>();                                                     \
     template hipError_t launch_chem_sweep<R>(const GridDev<R>*, const BatchDev&, int, int, int,     \
                                              int, bool, double, unsigned long long*, bool,         \
-                                             const int4*, int, const int4*, unsigned*, SweepCtl*,  \
-                                             int, long long, hipStream_t);                         \
+                                             const int4*, int, const int4*, unsigned*, void*,      \
+                                             SweepCtl*, int, long long, hipStream_t);              \
     template int chem_sweep_occupancy<R>(bool);                                                    \
     template hipError_t launch_chem<R>(const GridDev<R>*, const BatchDev&, int, int, int, int,    \
                                        bool, double, unsigned long long*, int, hipStream_t);       \
