@@ -571,7 +571,7 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-warmup", type=int, default=4,
                     help="requests run to completion before the timed stream (not counted)")
-    ap.add_argument("--serve-rate", type=float, default=4.0)
+    ap.add_argument("--serve-rate", type=float, default=2.0)
     ap.add_argument("--serve-nmin", type=int, default=48)
     ap.add_argument("--serve-nmax", type=int, default=256)
     ap.add_argument("--serve-trec", type=float, default=2.0)
