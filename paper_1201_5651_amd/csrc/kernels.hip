@@ -802,8 +802,11 @@ k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int 
 // scope and puts sigma0 n_H x dx of every cell in LDS; then it waits for the
 // tile's upstream tiles and sweeps it (TILE_FUSED).  A tile's micro-physics
 // needs nothing from other tiles, so while some workgroups of a compute unit
-// sweep or wait, the others integrate.  The register budget keeps four
-// workgroups per compute unit, the occupancy of k_chem.  With Mixed (mixed
+// sweep or wait, the others integrate.  The register budget is that of three
+// wavefronts per SIMD (168 registers), which the integrator and the sweep fit
+// without spilling: at four (128) the spills' scratch traffic, with many
+// workgroups resident, went past the L2s and exceeded the fields' own bytes
+// for no gain in time.  With Mixed (mixed
 // precision) a cell whose float integration took a precision-sensitive
 // decision is listed for launch_chem_fix and not written, as in k_chem, and
 // the sweep uses its float result; launch_chem_fix then re-solves it and
@@ -812,7 +815,7 @@ k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int 
 // k_sweep_persist.  The rate table is copied to LDS when a tile's grid
 // differs from the workgroup's previous one.
 template <typename R, bool Mixed>
-__global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
 k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int tau_chem,
              int tau_sweep, int dev_dt, double hscale, unsigned long long* ctr,
              const int4* __restrict__ tiles, int ntiles, const int4* __restrict__ octs,
