@@ -72,6 +72,11 @@ struct Engine {
     size_t flags_cap = 0;
     void* fbuf = nullptr;        // face buffer: FACE_WORDS words of the grids' type per tile
     size_t fbuf_cap = 0;
+    // the persistent schedule dealt into one list per XCD (TileLists), for
+    // the fused launches
+    int4* xtiles = nullptr;
+    size_t xtiles_cap = 0;
+    TileLists xlists{};
     SweepCtl* ctl = nullptr;
     int persist_wg = 0;
     // longest wait of a persistent tile for its upstream tiles (ticks of the

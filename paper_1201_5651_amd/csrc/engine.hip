@@ -344,10 +344,15 @@ pi_status chem_sweep_fused(Engine& e, bool dev_dt, double h, int tau_chem, int f
     const int ntiles =
         e.stage_first[w].empty() ? 0 : e.stage_first[w].back() + e.stage_count[w].back();
     const BatchDev b = e.bd();
+    const int nwg = std::min(ntiles, e.fused_wg);
+    TileLists one{};
+    one.n = 1;
+    one.first[1] = ntiles;
+    const bool per_xcd = nwg >= NXCD;
     HIP_OR(launch_chem_sweep<float>(gd<float>(e), b, from, to, tau_chem, tau_sweep, dev_dt, h,
-                                    e.work, e.mixed(), e.tiles[w], ntiles, e.octs, e.flags,
-                                    e.fbuf, e.ctl, std::min(ntiles, e.fused_wg), e.persist_spin,
-                                    s),
+                                    e.work, e.mixed(), per_xcd ? e.xtiles : e.tiles[w],
+                                    per_xcd ? e.xlists : one, e.octs, e.flags, e.fbuf, e.ctl, nwg,
+                                    e.persist_spin, s),
            "fused micro-physics and raytrace launch");
     if (e.mixed()) {
         HIP_OR(launch_chem_fix(gd<float>(e), b, e.fix_blocks, from, to, tau_chem, dev_dt, h,
@@ -619,6 +624,32 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
             HIP_OR(hipMemcpy(e.tiles[w], flat.data(), sizeof(int4) * flat.size(),
                              hipMemcpyHostToDevice),
                    "tile schedule upload");
+        if (w == PERSIST_SCHEDULE) {
+            // the persistent schedule in one list per XCD: slot p of a stage
+            // (dealt above to XCD p % NXCD) goes to list p % NXCD, stage after
+            // stage, so every list keeps the schedule's order
+            std::vector<int4> xl;
+            xl.reserve(flat.size());
+            e.xlists.n = NXCD;
+            for (int b = 0; b < NXCD; ++b) {
+                e.xlists.first[b] = (int)xl.size();
+                for (size_t k = 0; k < e.stage_first[w].size(); ++k)
+                    for (int q = b; q < e.stage_count[w][k]; q += NXCD)
+                        xl.push_back(flat[e.stage_first[w][k] + q]);
+            }
+            e.xlists.first[NXCD] = (int)xl.size();
+            if (xl.size() > e.xtiles_cap) {
+                if (e.xtiles) (void)hipFree(e.xtiles);
+                e.xtiles = nullptr;
+                e.xtiles_cap = 0;
+                HIP_OR(hipMalloc(&e.xtiles, sizeof(int4) * xl.size()), "tile list allocation");
+                e.xtiles_cap = xl.size();
+            }
+            if (!xl.empty())
+                HIP_OR(hipMemcpy(e.xtiles, xl.data(), sizeof(int4) * xl.size(),
+                                 hipMemcpyHostToDevice),
+                       "tile list upload");
+        }
     }
     // persistent raytrace: flag bases per raytrace entry and octant (edge
     // PERSIST_TILE), one flag per tile, the control block
@@ -723,10 +754,12 @@ void engine_free(Engine& e)
     if (e.cap) (void)hipStreamDestroy(e.cap);
     e.cap = nullptr;
     for (void* p : { e.gdev, (void*)e.first, (void*)e.fix_n, (void*)e.fix_list, (void*)e.work,
-                     (void*)e.octs, (void*)e.flags, e.fbuf, (void*)e.ctl })
+                     (void*)e.octs, (void*)e.flags, e.fbuf, (void*)e.xtiles, (void*)e.ctl })
         if (p) (void)hipFree(p);
     e.fbuf = nullptr;
     e.fbuf_cap = 0;
+    e.xtiles = nullptr;
+    e.xtiles_cap = 0;
     e.octs = nullptr;
     e.flags = nullptr;
     e.ctl = nullptr;
@@ -987,9 +1020,11 @@ size_t grid_private_bytes(const pi_grid_desc& d)
     b += sizeof(unsigned long long) * WORK_COUNTERS * WORK_SLOTS;
     if (d.precision == PI_MIXED || d.precision == PI_MIXED_FRONT)
         b += 3 * sizeof(unsigned int) + sizeof(long long) * (size_t)n;
-    // persistent raytrace: octant table, a done-flag per tile, control block
+    // persistent raytrace: octant table, a done-flag, a face-buffer slot and a
+    // per-XCD list entry per tile, control block
     b += sizeof(int4) * 8 * (size_t)nsources(d) +
-         (sizeof(unsigned) + (d.precision == PI_FP64 ? sizeof(double) : sizeof(float)) * FACE_WORDS) *
+         (sizeof(unsigned) + sizeof(int4) +
+          (d.precision == PI_FP64 ? sizeof(double) : sizeof(float)) * FACE_WORDS) *
              (size_t)tile_count(d, PERSIST_TILE) +
          sizeof(SweepCtl);
     if (d.spectrum == PI_SPEC_TABLE) b += sizeof(DevTable<double>) + sizeof(DevTable<float>);

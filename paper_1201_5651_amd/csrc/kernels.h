@@ -123,6 +123,14 @@ struct BatchDev {
 // the flag of a wait that ran out.
 struct SweepCtl {
     unsigned ticket, exited, epoch, err;
+    unsigned lticket[NXCD];   // tickets of the per-XCD tile lists
+};
+// Tile lists of a persistent launch: list l holds tiles[first[l] ..
+// first[l + 1]) in schedule order; with n = NXCD, workgroup w takes from list
+// w % NXCD, the list of the XCD the hardware deals it to.
+struct TileLists {
+    int n;
+    int first[NXCD + 1];
 };
 // Tile edge of the persistent raytrace, and the index of its variant after
 // the one-launch-per-stage variants of SWEEP_TILES.
@@ -161,9 +169,9 @@ hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, c
 template <typename R>
 hipError_t launch_chem_sweep(const GridDev<R>* grids, const BatchDev& b, int from, int to,
                              int tau_chem, int tau_sweep, bool dev_dt, double hscale,
-                             unsigned long long* ctr, bool mixed, const int4* tiles, int ntiles,
-                             const int4* octs, unsigned* flags, void* fbuf, SweepCtl* ctl,
-                             int nwg, long long spin_ticks, hipStream_t s);
+                             unsigned long long* ctr, bool mixed, const int4* tiles,
+                             const TileLists& lists, const int4* octs, unsigned* flags, void* fbuf,
+                             SweepCtl* ctl, int nwg, long long spin_ticks, hipStream_t s);
 // Workgroups of k_chem_sweep one compute unit holds at once.
 template <typename R> int chem_sweep_occupancy(bool mixed);
 template <typename R>

@@ -796,7 +796,12 @@ k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int 
 // point source: the micro-physics over h of every cell (from -> to, on the
 // columns tau_chem), then the raytrace of the new state into tau_sweep.  The
 // persistent workgroups take the tiles of edge PERSIST_TILE of the raytrace
-// schedule in order (a ticket), as k_sweep_persist does.  A workgroup first
+// schedule in order (a ticket), as k_sweep_persist does -- from one list per
+// XCD (TileLists), each in schedule order, into which the tiles are dealt by
+// the 128-byte lines their rows lie in, so that the tiles sharing a line are
+// integrated and swept behind one L2.  Every list being in schedule order,
+// the lowest unfinished tile is always held or next in its list, so the
+// sweep cannot deadlock.  A workgroup first
 // integrates its tile's cells (each wavefront four 4^3 bricks, with the
 // per-cell arithmetic of k_chem), writes the new neutral fractions at agent
 // scope and puts sigma0 n_H x dx of every cell in LDS; then it waits for the
@@ -818,7 +823,7 @@ template <typename R, bool Mixed>
 __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
 k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int tau_chem,
              int tau_sweep, int dev_dt, double hscale, unsigned long long* ctr,
-             const int4* __restrict__ tiles, int ntiles, const int4* __restrict__ octs,
+             const int4* __restrict__ tiles, TileLists lists, const int4* __restrict__ octs,
              unsigned* __restrict__ flags, R* fbuf, SweepCtl* ctl, long long spin_ticks)
 {
     constexpr int TT = PERSIST_TILE, NT = FUSED_THREADS;
@@ -837,18 +842,21 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
         __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) + 1u;
     int table_of = -1;   // grid whose rate table s_tab holds
+    // the tile list of this workgroup's XCD
+    const int list = lists.n > 1 ? (int)(blockIdx.x % NXCD) : 0;
+    const int lfirst = lists.first[list], lcount = lists.first[list + 1] - lfirst;
     Work w{};
     for (;;) {
         if (lead) {
-            const unsigned c = __hip_atomic_fetch_add(&ctl->ticket, add, __ATOMIC_RELAXED,
+            const unsigned c = __hip_atomic_fetch_add(&ctl->lticket[list], add, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
             s_ticket = (int)__builtin_amdgcn_readfirstlane(c);
         }
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(s_ticket);
         __syncthreads();   // (s_ticket is rewritten by the next claim)
-        if (t >= ntiles) break;
-        const int4 tl = tiles[t];
+        if (t >= lcount) break;
+        const int4 tl = tiles[lfirst + t];
         const int4 oc = octs[tl.x];                         // flag base, tiles per axis
         const int idx = oc.x + (tl.w * oc.z + tl.z) * oc.y + tl.y;
         const int gidx = tl.x >> 3;
@@ -938,7 +946,8 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
         const unsigned left = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(
             &ctl->exited, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         if (left == gridDim.x - 1) {
-            __hip_atomic_store(&ctl->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int l = 0; l < NXCD; ++l)
+                __hip_atomic_store(&ctl->lticket[l], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctl->exited, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctl->epoch, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -1333,20 +1342,22 @@ template <typename R> int sweep_persist_occupancy()
 template <typename R>
 hipError_t launch_chem_sweep(const GridDev<R>* grids, const BatchDev& b, int from, int to,
                              int tau_chem, int tau_sweep, bool dev_dt, double hscale,
-                             unsigned long long* ctr, bool mixed, const int4* tiles, int ntiles,
-                             const int4* octs, unsigned* flags, void* fbuf, SweepCtl* ctl,
-                             int nwg, long long spin_ticks, hipStream_t s)
+                             unsigned long long* ctr, bool mixed, const int4* tiles,
+                             const TileLists& lists, const int4* octs, unsigned* flags, void* fbuf,
+                             SweepCtl* ctl, int nwg, long long spin_ticks, hipStream_t s)
 {
     if constexpr (std::is_same<R, float>::value) {
-        if (ntiles <= 0 || nwg <= 0) return hipSuccess;
+        if (lists.first[lists.n] <= 0 || nwg <= 0) return hipSuccess;
+        // every list needs a workgroup
+        if (lists.n > 1 && nwg < NXCD) return hipErrorInvalidValue;
         if (mixed)
             hipLaunchKernelGGL((k_chem_sweep<R, true>), dim3(nwg), dim3(FUSED_THREADS), 0, s,
                                grids, b, from, to, tau_chem, tau_sweep, (int)dev_dt, hscale, ctr,
-                               tiles, ntiles, octs, flags, static_cast<R*>(fbuf), ctl, spin_ticks);
+                               tiles, lists, octs, flags, static_cast<R*>(fbuf), ctl, spin_ticks);
         else
             hipLaunchKernelGGL((k_chem_sweep<R, false>), dim3(nwg), dim3(FUSED_THREADS), 0, s,
                                grids, b, from, to, tau_chem, tau_sweep, (int)dev_dt, hscale, ctr,
-                               tiles, ntiles, octs, flags, static_cast<R*>(fbuf), ctl, spin_ticks);
+                               tiles, lists, octs, flags, static_cast<R*>(fbuf), ctl, spin_ticks);
         return hipGetLastError();
     } else {
         // double storage keeps the separate kernels (its integrator does not
@@ -1458,8 +1469,9 @@ hipError_t launch_energy(int64_t n, const R* nH, const R* x, R* E, double T0, hi
     template int sweep_persist_occupancy<R>();                                                     \
     template hipError_t launch_chem_sweep<R>(const GridDev<R>*, const BatchDev&, int, int, int,     \
                                              int, bool, double, unsigned long long*, bool,         \
-                                             const int4*, int, const int4*, unsigned*, void*,      \
-                                             SweepCtl*, int, long long, hipStream_t);              \
+                                             const int4*, const TileLists&, const int4*,           \
+                                             unsigned*, void*, SweepCtl*, int, long long,          \
+                                             hipStream_t);                                         \
     template int chem_sweep_occupancy<R>(bool);                                                    \
     template hipError_t launch_chem<R>(const GridDev<R>*, const BatchDev&, int, int, int, int,    \
                                        bool, double, unsigned long long*, int, hipStream_t);       \
