@@ -44,6 +44,92 @@ __constant__ PlaneOrder<SWEEP_TILES[0]> c_plane_order_0 = make_plane_order<SWEEP
 __constant__ PlaneOrder<SWEEP_TILES[1]> c_plane_order_1 = make_plane_order<SWEEP_TILES[1]>();
 __constant__ PlaneOrder<SWEEP_TILES[2]> c_plane_order_2 = make_plane_order<SWEEP_TILES[2]>();
 
+// Level order of a tile of edge PERSIST_TILE by its class.  Only the cells of
+// one layer back along a cell's major axis feed it, so a cell's level -- one
+// more than the highest level it reads inside the tile -- depends on which
+// axes can be major in the tile, which the tile indices (tx, ty, tz) in the
+// octant decide:
+//   one index largest: every cell's major axis is that axis a, level = l_a
+//     (PERSIST_TILE levels of T^2 cells);
+//   two indices tie for largest: the major axis is one of those two, p and q,
+//     and level = l_p + l_q (2T - 1 levels);
+//   all three equal: the diagonal planes, level = lx + ly + lz (3T - 2).
+// Cells of one level are independent, so a sweep by levels computes the same
+// columns as one by diagonal planes, in fewer steps.  Classes 0-2: a = x, y,
+// z; 3-5: the tied pair xy, yz, xz; 6: diagonal.  Every level lies in one
+// group of 64 consecutive slots (a wavefront's lanes for the sweep kernels):
+// single levels for the first classes, pairs of levels whose sizes add up to
+// 64 for the second (sizes 8 min(l + 1, 15 - l) for T = 8).  Packed as
+// lx | ly << 5 | lz << 10 | level << 15.
+constexpr int LEVEL_CLASSES = 7;
+struct LevelOrder {
+    unsigned cell[LEVEL_CLASSES][PERSIST_TILE * PERSIST_TILE * PERSIST_TILE];
+};
+constexpr LevelOrder make_level_order()
+{
+    constexpr int T = PERSIST_TILE;
+    static_assert(T == 8, "the level pairing below is that of 8^3 tiles");
+    LevelOrder o{};
+    for (int a = 0; a < 3; ++a) {
+        // one major axis: level la, lanes over the two other axes (lower one fastest)
+        const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+        int q = 0;
+        for (int la = 0; la < T; ++la)
+            for (int lc = 0; lc < T; ++lc)
+                for (int lb = 0; lb < T; ++lb) {
+                    int L[3] = { 0, 0, 0 };
+                    L[a] = la;
+                    L[b] = lb;
+                    L[c] = lc;
+                    o.cell[a][q++] = (unsigned)(L[0] | L[1] << 5 | L[2] << 10 | la << 15);
+                }
+    }
+    const int groups[8][2] = { { 7, -1 }, { 0, 6 }, { 1, 5 }, { 2, 4 },
+                               { 3, 11 }, { 8, 14 }, { 9, 13 }, { 10, 12 } };
+    for (int t = 0; t < 3; ++t) {
+        // tied pair (p, q), the third axis r
+        const int p = t == 2 ? 0 : t, qx = t == 2 ? 2 : t + 1, r = 3 - p - qx;
+        int n = 0;
+        for (int g = 0; g < 8; ++g)
+            for (int h = 0; h < 2; ++h) {
+                const int lev = groups[g][h];
+                if (lev < 0) continue;
+                for (int lr = 0; lr < T; ++lr)
+                    for (int lp = 0; lp < T; ++lp) {
+                        const int lq = lev - lp;
+                        if (lq < 0 || lq >= T) continue;
+                        int L[3] = { 0, 0, 0 };
+                        L[p] = lp;
+                        L[qx] = lq;
+                        L[r] = lr;
+                        o.cell[3 + t][n++] = (unsigned)(L[0] | L[1] << 5 | L[2] << 10 | lev << 15);
+                    }
+            }
+    }
+    int n = 0;
+    for (int sd = 0; sd < 3 * T - 2; ++sd)
+        for (int lz = 0; lz < T; ++lz)
+            for (int ly = 0; ly < T; ++ly) {
+                const int lx = sd - ly - lz;
+                if (lx >= 0 && lx < T)
+                    o.cell[6][n++] = (unsigned)(lx | ly << 5 | lz << 10 | sd << 15);
+            }
+    return o;
+}
+__constant__ LevelOrder c_level_order = make_level_order();
+
+// Class of a tile for c_level_order from its indices in the octant, and its
+// number of levels.
+__device__ __forceinline__ int level_class(int tx, int ty, int tz, int& nlev)
+{
+    const int m = max(tx, max(ty, tz));
+    const int top = (tx == m) + (ty == m) + (tz == m);
+    nlev = top == 1 ? PERSIST_TILE : (top == 2 ? 2 * PERSIST_TILE - 1 : 3 * PERSIST_TILE - 2);
+    if (top == 1) return tx == m ? 0 : (ty == m ? 1 : 2);
+    if (top == 2) return tz != m ? 3 : (tx != m ? 4 : 5);
+    return 6;
+}
+
 // Entries of the (T+1)^3 halo buffer of a T^3 tile that lie on its upstream
 // faces (local index -1 along some axis), in buffer order: the halo cells a
 // tile reads from earlier tiles, one per thread of every sweep kernel.
@@ -130,7 +216,9 @@ __device__ __forceinline__ double sc_average<double>(bool mellema, double g00, d
 //   s_kap: sigma0 n_H x dx (optical depth per cell length),
 //   s_tc : optical depth from the source to the cell centre (halo only, from
 //          the stored entering depth of the earlier stage);
-// the tile is then swept diagonal plane by diagonal plane, lx+ly+lz = s.
+// the tile is then swept level by level: a tile of edge PERSIST_TILE in the
+// level order of its class (c_level_order), other edges diagonal plane by
+// diagonal plane, lx+ly+lz = s.
 //
 // A cell C with dominant axis a interpolates, on the plane through the centres
 // of the layer one step back along a, the four upstream centres around the
@@ -139,9 +227,9 @@ __device__ __forceinline__ double sc_average<double>(bool mellema, double g00, d
 // bilinear weights divided by max(0.6, T) (Mellema weighting).  Neighbours
 // across a source plane (octant-local index -1) get weight 0.
 // Threads of the sweep workgroup for tile edge TT: one per cell up to 1024,
-// then several cells per thread (consecutive planes are whole thread ranges,
-// and a plane never exceeds the thread count, so a thread owns at most one
-// cell of any plane).
+// then several cells per thread (consecutive planes or levels are whole thread
+// ranges, and none exceeds the thread count, so a thread owns at most one cell
+// of any of them).
 template <int TT> struct SweepShape {
     static constexpr int CELLS = TT * TT * TT;
     static constexpr int THREADS = CELLS < 1024 ? CELLS : 1024;
@@ -300,15 +388,24 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
         }
     }
 
-    // geometry of the thread's cells (cell k: plane-order index threadIdx.x + k NT)
+    // geometry of the thread's cells (cell k: index threadIdx.x + k NT of the
+    // tile's level order, or of the diagonal-plane order for other edges)
     const bool mellema = p.weights == 1;
-    int self[CPT], n00[CPT], n10[CPT], n01[CPT], n11[CPT], diag[CPT], nat[CPT];
+    int nlev = TX + TY + TZ - 2;
+    int cls = 0;
+    if constexpr (TT == PERSIST_TILE) cls = level_class(tl.y, tl.z, tl.w, nlev);
+    int self[CPT], n00[CPT], n10[CPT], n01[CPT], n11[CPT], lev[CPT], nat[CPT];
     bool active[CPT], corner[CPT];
     R g00[CPT], g10[CPT], g01[CPT], g11[CPT], hds[CPT], tin[CPT];
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
-        const int cl = plane_cell<TT>(threadIdx.x + k * NT);
-        const int lx = cl & 31, ly = (cl >> 5) & 31, lz = cl >> 10;
+        int cl;
+        if constexpr (TT == PERSIST_TILE) {
+            cl = (int)c_level_order.cell[cls][threadIdx.x + k * NT];
+        } else {
+            cl = plane_cell<TT>(threadIdx.x + k * NT);
+        }
+        const int lx = cl & 31, ly = (cl >> 5) & 31, lz = (cl >> 10) & 31;
         const int L[3] = { X0 + lx, Y0 + ly, Z0 + lz };
         active[k] = L[0] < ex && L[1] < ey && L[2] < ez;
         const ScGeom<R> sg = sc_geom<R>(L);
@@ -324,7 +421,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
         g11[k] = sg.g11;
         hds[k] = sg.hds;
         corner[k] = sg.corner;
-        diag[k] = lx + ly + lz;
+        lev[k] = TT == PERSIST_TILE ? cl >> 15 : lx + ly + lz;
         nat[k] = lx + TX * (ly + TY * lz);
         tin[k] = R(0);
     }
@@ -373,10 +470,10 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
     }
     __syncthreads();
 
-    for (int s = 0; s < TX + TY + TZ - 2; ++s) {
+    for (int s = 0; s < nlev; ++s) {
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
-            if (active[k] && diag[k] == s) {
+            if (active[k] && lev[k] == s) {
                 if (!corner[k]) {
                     const R T00 = upstream_T(s_tc[n00[k]], hds[k], s_kap[n00[k]]);
                     const R T10 = upstream_T(s_tc[n10[k]], hds[k], s_kap[n10[k]]);
@@ -441,6 +538,33 @@ k_sweep(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     __shared__ R s_kap[NHALO];
     sweep_tile<R, TT, SweepShape<TT>::THREADS, TILE_STAGED>(
         grids, state, tau_buf, tiles[first + blockIdx.x], s_tc, s_kap, [] {});
+}
+
+// Wait of a persistent tile (its first wavefront) for the flags of its upstream
+// tiles to read `done`: lanes 0, 1 and 2 poll the tiles upstream along x, y
+// and z (where there is one), so one round trip reads all three, and the loop
+// is uniform over the wavefront.  After spin_ticks of the 100 MHz clock the
+// error word is set and the wait gives up.
+__device__ __forceinline__ void wait_upstream(const unsigned* __restrict__ flags, int idx, int4 tl,
+                                              int4 oc, unsigned done, long long spin_ticks,
+                                              SweepCtl* ctl)
+{
+    const int lane = threadIdx.x & 63;
+    int up = -1;
+    if (lane == 0 && tl.y > 0) up = idx - 1;
+    if (lane == 1 && tl.z > 0) up = idx - oc.y;
+    if (lane == 2 && tl.w > 0) up = idx - oc.y * oc.z;
+    const long long t0 = (long long)__builtin_amdgcn_s_memrealtime();
+    for (;;) {
+        unsigned f = done;
+        if (up >= 0) f = __hip_atomic_load(&flags[up], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__ballot(f != done) == 0ull) break;
+        __builtin_amdgcn_s_sleep(2);
+        if ((long long)__builtin_amdgcn_s_memrealtime() - t0 > spin_ticks) {
+            __hip_atomic_store(&ctl->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+    }
 }
 
 // The whole raytrace in one launch: persistent workgroups claim tiles in the
@@ -514,25 +638,7 @@ k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
         const int idx = oc.x + (tl.w * oc.z + tl.z) * oc.y + tl.y;
         sweep_tile<R, TT, SweepShape<TT>::THREADS, TILE_COHERENT>(
             grids, state, tau_buf, tl, s_tc, s_kap, [&] {
-            if (lead) {
-                const int up[3] = { tl.y > 0 ? idx - 1 : -1, tl.z > 0 ? idx - oc.y : -1,
-                                    tl.w > 0 ? idx - oc.y * oc.z : -1 };
-                for (int u = 0; u < 3; ++u) {
-                    if (up[u] < 0) continue;
-                    const long long t0 = (long long)__builtin_amdgcn_s_memrealtime();
-                    for (;;) {
-                        const unsigned f = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
-                            &flags[up[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                        if (f == done) break;
-                        __builtin_amdgcn_s_sleep(2);
-                        if ((long long)__builtin_amdgcn_s_memrealtime() - t0 > spin_ticks) {
-                            __hip_atomic_store(&ctl->err, 1u, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                            break;
-                        }
-                    }
-                }
-            }
+            if (lead) wait_upstream(flags, idx, tl, oc, done, spin_ticks, ctl);
         }, fbuf, idx, oc);
         // every wave's column stores complete, then the flag
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -915,32 +1021,19 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
                 }
             }
         }
+        // the sweep is on the launch's critical path (later tiles wait for it):
+        // its instructions go before those of the integrating wavefronts of
+        // the compute unit
+        __builtin_amdgcn_s_setprio(3);
         sweep_tile<R, TT, NT, TILE_FUSED>(grids, to, tau_sweep, tl, s_tc, s_kap, [&] {
-            if (lead) {
-                const int up[3] = { tl.y > 0 ? idx - 1 : -1, tl.z > 0 ? idx - oc.y : -1,
-                                    tl.w > 0 ? idx - oc.y * oc.z : -1 };
-                for (int u = 0; u < 3; ++u) {
-                    if (up[u] < 0) continue;
-                    const long long t0 = (long long)__builtin_amdgcn_s_memrealtime();
-                    for (;;) {
-                        const unsigned f = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
-                            &flags[up[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                        if (f == done) break;
-                        __builtin_amdgcn_s_sleep(2);
-                        if ((long long)__builtin_amdgcn_s_memrealtime() - t0 > spin_ticks) {
-                            __hip_atomic_store(&ctl->err, 1u, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                            break;
-                        }
-                    }
-                }
-            }
+            if (lead) wait_upstream(flags, idx, tl, oc, done, spin_ticks, ctl);
         }, fbuf, idx, oc);
         // every wave's neutral-fraction and column stores complete, then the flag
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         if (lead)
             __hip_atomic_store(&flags[idx], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_setprio(0);
     }
     if (lead) {
         const unsigned left = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(

@@ -113,6 +113,8 @@ def test_a3_step_full_size_every_cell(oracle_lib, state256):
     float_bar(Tg, Tw, 1e-4, "256^3 mixed A3 step T, every cell")
     m = st["tau"] > 1e-3
     float_bar(tg[m], st["tau"][m], 1e-4, "256^3 mixed A3 step columns")
+    assert np.all((tg == 0) == (st["tau"] == 0))
+    assert np.max(np.abs(tg[~m] - st["tau"][~m])) < 1e-7
 
 
 def test_batch_full_size_matches_grids_alone():
