@@ -618,10 +618,14 @@ k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     const unsigned done =
         __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) + 1u;
-    // with a condition word that reads 0, every workgroup leaves at once
-    const bool go = !cond || __builtin_amdgcn_readfirstlane(__hip_atomic_load(
-                                 cond, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0u;
-    while (go) {
+    // with a condition word that reads 0, every workgroup leaves at once and
+    // nothing is counted or reset (all of them read the same value: the word
+    // is cleared only after every workgroup of a running launch has counted
+    // itself)
+    if (cond && __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                    cond, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0u)
+        return;
+    for (;;) {
         if (lead) {
             // lane 0 takes the ticket (the others add 0); every lane of wave 0
             // writes lane 0's value
@@ -862,6 +866,10 @@ k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int 
            int dev_dt, double hscale, unsigned long long* ctr, int clear, int mark)
 {
     const unsigned n = min(bd.fix_n[0], bd.fix_cap);
+    // an empty list: nothing to re-solve, mark or clear (every workgroup reads
+    // the same length, which only the last workgroup of a non-empty launch
+    // resets)
+    if (n == 0) return;
     if (blockIdx.x * blockDim.x < n) {   // uniform over the workgroup
         Work w{};
         for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -890,7 +898,7 @@ k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int 
     if (threadIdx.x == 0) {
         if (atomicAdd(&bd.fix_n[1], 1u) == gridDim.x - 1) {
             // cells were re-solved after a fused raytrace: it is run again
-            if (mark && n > 0) bd.fix_n[2] = 1u;
+            if (mark) bd.fix_n[2] = 1u;
             bd.fix_n[0] = 0u;
             bd.fix_n[1] = 0u;
         }
@@ -1245,15 +1253,16 @@ template <typename T> __device__ __forceinline__ T wave_min(T v)
 }
 
 // Per-workgroup partials of the timestep limit and diagnostics of state n; the
-// workgroups of grid g stride over its cells.
+// workgroups of grid g stride over its cells, with the rate table in LDS.
 template <typename R, int MS>
 __global__ void __launch_bounds__(DT_BLOCK)
 k_dtdiag(const GridDev<R>* __restrict__ grids, BatchDev bd)
 {
+    __shared__ DevTable<R> s_tab;
     const int g = find_grid(bd.dt_first, bd.ngrids, blockIdx.x);
     const GridDev<R>& G = grids[g];
     if (other_kind<MS>(bd, G)) return;   // uniform over the workgroup
-    const Params<R> p = G.p;
+    const Params<R> p = table_to_lds(G.p, s_tab);
     const int lb = blockIdx.x - bd.dt_first[g], nb = bd.dt_first[g + 1] - bd.dt_first[g];
     const R* __restrict__ nH = G.nH;
     const R* __restrict__ x = G.x[0];
