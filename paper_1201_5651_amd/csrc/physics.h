@@ -376,6 +376,7 @@ PI_HD __forceinline__ void photo(const Params<R>& p, const EnvM<R, MS>& e, R x, 
 // free-free (times n_e n_HII), collisional excitation and ionisation (times
 // n_e n_HI).
 template <typename R> struct Coef {
+    R invT;        // 1 / T
     R alpha, dla;
     R aci, dlci;
     R cii, dcii;   // value and dT-derivative (not logarithmic)
@@ -391,6 +392,7 @@ PI_HD __forceinline__ Coef<R> coefs(const Params<R>& p, R T)
 {
     Coef<R> c;
     const R invT = r_rcp(T);
+    c.invT = invT;
     const bool pw = p.recomb != 0, cool = p.thermal == 1 && p.cooling != 0;
     const R lT = (pw || cool) ? r_log(T) : R(0);
     if (!pw) {
@@ -486,7 +488,8 @@ PI_HD __forceinline__ void rhs_full(const Params<R>& p, const EV& e, R x, R E, R
         r.fE = r.jEx = r.jEE = R(0);
         return;
     }
-    const R iT = r_rcp(T);
+    // 1/T where it is used (above the floor, where Tc is T)
+    const R iT = c.invT;
     const R w = T > R(T_FLOOR) ? R(1) - R(T_FLOOR) * iT : R(0);
     const R dw = T > R(T_FLOOR) ? R(T_FLOOR) * iT * iT : R(0);
     const R n2 = n * n;
