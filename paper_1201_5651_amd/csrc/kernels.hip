@@ -474,16 +474,23 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
             if (active[k] && lev[k] == s) {
-                if (!corner[k]) {
-                    const R T00 = upstream_T(s_tc[n00[k]], hds[k], s_kap[n00[k]]);
-                    const R T10 = upstream_T(s_tc[n10[k]], hds[k], s_kap[n10[k]]);
-                    const R T01 = upstream_T(s_tc[n01[k]], hds[k], s_kap[n01[k]]);
-                    const R T11 = upstream_T(s_tc[n11[k]], hds[k], s_kap[n11[k]]);
-                    tin[k] = sc_average<R>(mellema, g00[k], g10[k], g01[k], g11[k], T00, T10,
-                                           T01, T11);
-                }
+                // every LDS value of the cell is read before any arithmetic, so
+                // the reads share one round trip (the neighbour entries of a
+                // corner cell lie in the halo buffer too; it discards them)
+                const R c00 = s_tc[n00[k]], c10 = s_tc[n10[k]];
+                const R c01 = s_tc[n01[k]], c11 = s_tc[n11[k]];
+                const R k00 = s_kap[n00[k]], k10 = s_kap[n10[k]];
+                const R k01 = s_kap[n01[k]], k11 = s_kap[n11[k]];
+                const R kself = s_kap[self[k]];
+                const R T00 = upstream_T(c00, hds[k], k00);
+                const R T10 = upstream_T(c10, hds[k], k10);
+                const R T01 = upstream_T(c01, hds[k], k01);
+                const R T11 = upstream_T(c11, hds[k], k11);
+                const R avg = sc_average<R>(mellema, g00[k], g10[k], g01[k], g11[k], T00, T10,
+                                            T01, T11);
+                tin[k] = corner[k] ? R(0) : avg;
                 // entry face to centre
-                s_tc[self[k]] = r_fma(hds[k], s_kap[self[k]], tin[k]);
+                s_tc[self[k]] = r_fma(hds[k], kself, tin[k]);
             }
         }
         __syncthreads();
