@@ -70,7 +70,7 @@ struct Engine {
     size_t octs_cap = 0;
     unsigned* flags = nullptr;
     size_t flags_cap = 0;
-    void* fbuf = nullptr;        // face buffer: FACE_WORDS words of the grids' type per tile
+    void* fbuf = nullptr;        // face buffer: FACE_WORDS entries of FACE_BYTES per tile
     size_t fbuf_cap = 0;
     // the persistent schedule dealt into one list per XCD (TileLists), for
     // the fused launches

@@ -351,7 +351,7 @@ pi_status chem_sweep_fused(Engine& e, bool dev_dt, double h, int tau_chem, int f
     const bool per_xcd = nwg >= NXCD;
     HIP_OR(launch_chem_sweep<float>(gd<float>(e), b, from, to, tau_chem, tau_sweep, dev_dt, h,
                                     e.work, e.mixed(), per_xcd ? e.xtiles : e.tiles[w],
-                                    per_xcd ? e.xlists : one, e.octs, e.flags, e.fbuf, e.ctl, nwg,
+                                    per_xcd ? e.xlists : one, e.octs, e.fbuf, e.ctl, nwg,
                                     e.persist_spin, s),
            "fused micro-physics and raytrace launch");
     if (e.mixed()) {
@@ -694,14 +694,16 @@ pi_status engine_build(Engine& e, const std::vector<GridHost*>& grids)
             HIP_OR(hipMemset(e.flags, 0, fb), "raytrace flag clear");
             e.flags_cap = fb;
         }
-        const size_t bb = (e.fp64() ? sizeof(double) : sizeof(float)) * FACE_WORDS *
-                          (size_t)std::max<int64_t>(nflag, 1);
+        const size_t bb = (size_t)FACE_BYTES * FACE_WORDS * (size_t)std::max<int64_t>(nflag, 1);
         if (bb > e.fbuf_cap) {
-            // (never read before a tile of the same call has written it)
+            // zero: float entries then carry epoch 0, below the epoch of every
+            // call (double entries are never read before a tile of the same
+            // call has written them)
             if (e.fbuf) (void)hipFree(e.fbuf);
             e.fbuf = nullptr;
             e.fbuf_cap = 0;
             HIP_OR(hipMalloc(&e.fbuf, bb), "raytrace face buffer allocation");
+            HIP_OR(hipMemset(e.fbuf, 0, bb), "raytrace face buffer clear");
             e.fbuf_cap = bb;
         }
         if (!e.ctl) {
@@ -1024,7 +1026,7 @@ size_t grid_private_bytes(const pi_grid_desc& d)
     // per-XCD list entry per tile, control block
     b += sizeof(int4) * 8 * (size_t)nsources(d) +
          (sizeof(unsigned) + sizeof(int4) +
-          (d.precision == PI_FP64 ? sizeof(double) : sizeof(float)) * FACE_WORDS) *
+          (size_t)FACE_BYTES * FACE_WORDS) *
              (size_t)tile_count(d, PERSIST_TILE) +
          sizeof(SweepCtl);
     if (d.spectrum == PI_SPEC_TABLE) b += sizeof(DevTable<double>) + sizeof(DevTable<float>);

@@ -137,9 +137,12 @@ struct TileLists {
 constexpr int PERSIST_TILE = 8;
 constexpr int SWEEP_PERSIST = 3;
 constexpr int PERSIST_SCHEDULE = 1;   // SWEEP_TILES[1] == PERSIST_TILE
-// Words of the face buffer per tile of the persistent raytrace: for its three
-// downstream faces, sigma0 n_H x dx and the centre column of every cell.
+// Entries of the face buffer per tile of the persistent raytrace (for its
+// three downstream faces, sigma0 n_H x dx and the centre column of every
+// cell), FACE_BYTES each: a double, or a float with the epoch of the launch
+// that wrote it.
 constexpr int FACE_WORDS = 6 * PERSIST_TILE * PERSIST_TILE;
+constexpr int FACE_BYTES = 8;
 // Threads per workgroup of the micro-physics fused with the persistent sweep
 // (two wavefronts, four 4^3 bricks of a tile each).
 constexpr int FUSED_THREADS = 128;
@@ -152,33 +155,34 @@ hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, c
                               int first, int count, int tile, hipStream_t s);
 // The whole raytrace of every grid in one launch of nwg persistent workgroups
 // over the schedule tiles[0 .. ntiles) of edge PERSIST_TILE (stage after
-// stage); octs[grid << 3 | octant] = (first done-flag, tiles along x, y, z);
-// flags: one per tile; fbuf: the face buffer, FACE_WORDS words of R per tile.
-// spin_ticks bounds each wait (100 MHz ticks).  cond:
-// null, or a word that must be non-zero for the raytrace to run (cleared by
-// it).
+// stage); octs[grid << 3 | octant] = (first flag/slot index, tiles along x,
+// y, z); fbuf: the face buffer, FACE_WORDS entries per tile, zeroed when
+// allocated; flags: one done-flag per tile (used by double grids, whose face
+// entries carry no epoch).  spin_ticks bounds each wait (100 MHz ticks).
+// cond: null, or a word that must be non-zero for the raytrace to run
+// (cleared by it).
+template <typename R>
+hipError_t launch_sweep_persist(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,
+                                int ntiles, const int4* octs, unsigned* flags, void* fbuf,
+                                SweepCtl* ctl, int nwg, long long spin_ticks, unsigned* cond,
+                                hipStream_t s);
 // One half of an A3 step (or an A2 step) of every grid in one launch of nwg
 // persistent workgroups, for batches of grids with one point source each:
 // the micro-physics of launch_chem over h = hscale (x dt when dev_dt) from
 // `from` to `to` on the columns tau_chem, then the raytrace of state `to`
-// into tau_sweep, over the schedule and flags of launch_sweep_persist.  With
-// mixed, precision-sensitive cells are listed as by launch_chem (and swept
-// with their float values): launch_chem_fix with mark, then
+// into tau_sweep, over the schedule and face buffer of launch_sweep_persist.
+// With mixed, precision-sensitive cells are listed as by launch_chem (and
+// swept with their float values): launch_chem_fix with mark, then
 // launch_sweep_persist with cond = b.fix_n + 2, must follow.  Float storage
 // only (hipErrorNotSupported for double).
 template <typename R>
 hipError_t launch_chem_sweep(const GridDev<R>* grids, const BatchDev& b, int from, int to,
                              int tau_chem, int tau_sweep, bool dev_dt, double hscale,
                              unsigned long long* ctr, bool mixed, const int4* tiles,
-                             const TileLists& lists, const int4* octs, unsigned* flags, void* fbuf,
-                             SweepCtl* ctl, int nwg, long long spin_ticks, hipStream_t s);
+                             const TileLists& lists, const int4* octs, void* fbuf, SweepCtl* ctl,
+                             int nwg, long long spin_ticks, hipStream_t s);
 // Workgroups of k_chem_sweep one compute unit holds at once.
 template <typename R> int chem_sweep_occupancy(bool mixed);
-template <typename R>
-hipError_t launch_sweep_persist(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,
-                                int ntiles, const int4* octs, unsigned* flags, void* fbuf,
-                                SweepCtl* ctl, int nwg, long long spin_ticks, unsigned* cond,
-                                hipStream_t s);
 // Resident workgroups of the persistent raytrace kernel on one CU.
 template <typename R> int sweep_persist_occupancy();
 // Micro-physics of every cell of every grid from state `from` on columns

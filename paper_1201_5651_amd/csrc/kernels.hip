@@ -299,17 +299,37 @@ template <typename R> __device__ __forceinline__ R halo_hds(int Lx, int Ly, int 
 // earlier launch; the halo's sigma0 n_H x dx and columns are read from the
 // grid.  TILE_COHERENT: upstream tiles run in the same launch.  A finished
 // tile publishes sigma0 n_H x dx and the centre column of the cells on its
-// three downstream faces in its slot of a face buffer (FACE_WORDS words per
+// three downstream faces in its slot of a face buffer (FACE_WORDS entries per
 // tile), written and read as relaxed atomics at agent scope (loads and stores
 // that reach the device-wide point of coherence, past the caches of the
 // compute unit and of its XCD); a tile takes its halo from the slots of the
 // up to seven upstream tiles that own it -- contiguous rows instead of
 // scattered cells -- and writes its columns to the grid with plain stores.
-// The published values are those a halo read from the grid would form.
+// The published values are those a halo read from the grid would form.  A
+// float entry carries the epoch of the launch that wrote it (FaceWord), so
+// the reader polls the entries themselves; double tiles wait for the
+// upstream tiles' done-flags first.
 // TILE_FUSED: as TILE_COHERENT, after the tile's own micro-physics in the
 // same workgroup, which has put sigma0 n_H x dx of the tile's own cells in
 // s_kap.
 enum { TILE_STAGED = 0, TILE_COHERENT = 1, TILE_FUSED = 2 };
+
+// Entry of the face buffer: for float, one 64-bit word holding the value's
+// bits in its lower half and the epoch of the launch that wrote it in its
+// upper half, written and read whole, so that a reader tells a current entry
+// from one of an earlier launch without a flag; for double, the value (its
+// sweeps order the entries with done-flags).  Eight bytes either way.
+template <typename R> struct FaceWord {
+    using type = double;
+    static constexpr bool tagged = false;
+};
+template <> struct FaceWord<float> {
+    using type = unsigned long long;
+    static constexpr bool tagged = true;
+};
+template <typename R> using face_t = typename FaceWord<R>::type;
+static_assert(sizeof(face_t<float>) == FACE_BYTES && sizeof(face_t<double>) == FACE_BYTES,
+              "face buffer entries are FACE_BYTES wide");
 
 // Face buffer slot of a tile of edge T: for the faces at local x, y, z =
 // T - 1 in turn, T^2 values of sigma0 n_H x dx and then T^2 centre columns,
@@ -327,12 +347,16 @@ template <int T> struct FaceSlot {
 // and for TILE_STAGED of its halo -- and the cells' geometry) and the loads
 // that do (the halo); every thread calls it, and the caller's
 // synchronisation follows it.  For the coherent kinds, fbuf is the face
-// buffer, idx the tile's flag index and oc its octant's (first flag, tiles
-// along x, y, z).
+// buffer, idx the tile's flag (and slot) index and oc its octant's (first
+// flag, tiles along x, y, z); done is the launch's epoch, which float entries
+// are tagged with and polled for, at most spin_ticks of the 100 MHz clock
+// before ctl->err is set.
 template <typename R, int TT, int NT, int Kind, typename Wait>
 __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids, int state,
                                            int tau_buf, int4 tl, R* s_tc, R* s_kap, Wait wait,
-                                           R* fbuf = nullptr, int idx = 0, int4 oc = int4{})
+                                           face_t<R>* fbuf = nullptr, int idx = 0,
+                                           int4 oc = int4{}, unsigned done = 0u,
+                                           long long spin_ticks = 0, SweepCtl* ctl = nullptr)
 {
     constexpr int TX = TT, TY = TT, TZ = TT;
     constexpr int CPT = TT * TT * TT / NT;
@@ -431,42 +455,105 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
     // the upstream halo (the faces at local index -1): centre columns and,
     // for the coherent kinds, sigma0 n_H x dx; the tile's own entries of s_tc
     // are written by their cells before any cell reads them
-    constexpr int NFACE = FaceList<TT>::N;
+    constexpr int NFACE = FaceList<TT>::N, KF = (NFACE + NT - 1) / NT;
+    if constexpr (Kind == TILE_STAGED) {
 #pragma unroll
-    for (int k = 0; k < (NFACE + NT - 1) / NT; ++k) {
-        const int f = threadIdx.x + k * NT;
-        if (f >= NFACE) break;
-        const int q = face_entry<TT>(f);
-        const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
-        const int Lx = X0 + hx - 1, Ly = Y0 + hy - 1, Lz = Z0 + hz - 1;
-        R tc = R(0), kap = R(0);
-        if (Lx >= 0 && Ly >= 0 && Lz >= 0 && Lx < ex && Ly < ey && Lz < ez) {
-            if constexpr (Kind == TILE_STAGED) {
+        for (int k = 0; k < KF; ++k) {
+            const int f = threadIdx.x + k * NT;
+            if (f >= NFACE) break;
+            const int q = face_entry<TT>(f);
+            const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
+            const int Lx = X0 + hx - 1, Ly = Y0 + hy - 1, Lz = Z0 + hz - 1;
+            R tc = R(0);
+            if (Lx >= 0 && Ly >= 0 && Lz >= 0 && Lx < ex && Ly < ey && Lz < ez) {
                 const int gi = px ? p.sx + Lx : p.sx - 1 - Lx;
                 const int gj = py ? p.sy + Ly : p.sy - 1 - Ly;
                 const int gk = pz ? p.sz + Lz : p.sz - 1 - Lz;
                 const int64_t g = gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk);
-                kap = s_kap[q];
                 // the centre column exactly as the cell's own tile formed it
-                tc = r_fma(halo_hds<R>(Lx, Ly, Lz), kap, tau[g]);
-            } else {
-                // the owner: the upstream tile across every face the entry lies
-                // on; its local coordinates; and the owner's face that holds it
-                const int ux = hx == 0, uy = hy == 0, uz = hz == 0;
-                const int owner = idx - ux - uy * oc.y - uz * oc.y * oc.z;
-                const int ox = ux ? TT - 1 : hx - 1, oy = uy ? TT - 1 : hy - 1;
-                const int oz = uz ? TT - 1 : hz - 1;
-                const int face = ux ? 0 : (uy ? 1 : 2);
-                const int i = face == 0 ? oy : ox, j = face == 2 ? oy : oz;
-                const R* slot = fbuf + (int64_t)owner * FaceSlot<TT>::WORDS;
-                kap = __hip_atomic_load(&slot[FaceSlot<TT>::kap(face, i, j)], __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
-                tc = __hip_atomic_load(&slot[FaceSlot<TT>::col(face, i, j)], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+                tc = r_fma(halo_hds<R>(Lx, Ly, Lz), s_kap[q], tau[g]);
+            }
+            s_tc[q] = tc;
+        }
+    } else {
+        // every halo entry of the thread from the slot of its owner -- the
+        // upstream tile across every face the entry lies on -- at the owner's
+        // local coordinates and on the owner's face that holds it; all loads
+        // in flight together
+        int qf[KF];
+        const face_t<R>* pk[KF];
+        const face_t<R>* pc[KF];
+        face_t<R> wk[KF], wc[KF];
+#pragma unroll
+        for (int k = 0; k < KF; ++k) {
+            const int f = threadIdx.x + k * NT;
+            qf[k] = -1;
+            pk[k] = pc[k] = nullptr;
+            wk[k] = wc[k] = face_t<R>(0);
+            if (f < NFACE) {
+                const int q = face_entry<TT>(f);
+                qf[k] = q;
+                const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
+                const int Lx = X0 + hx - 1, Ly = Y0 + hy - 1, Lz = Z0 + hz - 1;
+                if (Lx >= 0 && Ly >= 0 && Lz >= 0 && Lx < ex && Ly < ey && Lz < ez) {
+                    const int ux = hx == 0, uy = hy == 0, uz = hz == 0;
+                    const int owner = idx - ux - uy * oc.y - uz * oc.y * oc.z;
+                    const int ox = ux ? TT - 1 : hx - 1, oy = uy ? TT - 1 : hy - 1;
+                    const int oz = uz ? TT - 1 : hz - 1;
+                    const int face = ux ? 0 : (uy ? 1 : 2);
+                    const int i = face == 0 ? oy : ox, j = face == 2 ? oy : oz;
+                    const face_t<R>* slot = fbuf + (int64_t)owner * FaceSlot<TT>::WORDS;
+                    pk[k] = &slot[FaceSlot<TT>::kap(face, i, j)];
+                    pc[k] = &slot[FaceSlot<TT>::col(face, i, j)];
+                    wk[k] = __hip_atomic_load(pk[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    wc[k] = __hip_atomic_load(pc[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
         }
-        if constexpr (Kind != TILE_STAGED) s_kap[q] = kap;
-        s_tc[q] = tc;
+        if constexpr (FaceWord<R>::tagged) {
+            // an entry still of an earlier launch is polled until its owner
+            // writes it (each lane for its own entries; the owners are held by
+            // running workgroups)
+            auto stale = [&](face_t<R> w) { return (unsigned)(w >> 32) != done; };
+            bool pending = false;
+#pragma unroll
+            for (int k = 0; k < KF; ++k)
+                pending |= pk[k] != nullptr && (stale(wk[k]) || stale(wc[k]));
+            if (pending) {
+                const long long t0 = (long long)__builtin_amdgcn_s_memrealtime();
+                while (pending) {
+                    if ((long long)__builtin_amdgcn_s_memrealtime() - t0 > spin_ticks) {
+                        __hip_atomic_store(&ctl->err, 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    pending = false;
+#pragma unroll
+                    for (int k = 0; k < KF; ++k) {
+                        if (pk[k] == nullptr) continue;
+                        if (stale(wk[k]))
+                            wk[k] = __hip_atomic_load(pk[k], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                        if (stale(wc[k]))
+                            wc[k] = __hip_atomic_load(pc[k], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                        pending |= stale(wk[k]) || stale(wc[k]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KF; ++k) {
+            if (qf[k] < 0) continue;
+            if constexpr (FaceWord<R>::tagged) {
+                s_kap[qf[k]] = __uint_as_float((unsigned)wk[k]);
+                s_tc[qf[k]] = __uint_as_float((unsigned)wc[k]);
+            } else {
+                s_kap[qf[k]] = wk[k];
+                s_tc[qf[k]] = wc[k];
+            }
+        }
     }
     __syncthreads();
 
@@ -498,7 +585,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
     if constexpr (Kind != TILE_STAGED) {
         // publish the downstream faces: entry (face, i, j) is the cell at local
         // TT - 1 along the face's axis (cells outside the octant give 0)
-        R* slot = fbuf + (int64_t)idx * FaceSlot<TT>::WORDS;
+        face_t<R>* slot = fbuf + (int64_t)idx * FaceSlot<TT>::WORDS;
         for (int e = threadIdx.x; e < 3 * TT * TT; e += NT) {
             const int face = e / (TT * TT), i = e % TT, j = (e / TT) % TT;
             const int lx = face == 0 ? TT - 1 : i;
@@ -506,10 +593,20 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
             const int lz = face == 2 ? TT - 1 : j;
             const bool in = X0 + lx < ex && Y0 + ly < ey && Z0 + lz < ez;
             const int c = (lz + 1) * HX * HY + (ly + 1) * HX + (lx + 1);
-            __hip_atomic_store(&slot[FaceSlot<TT>::kap(face, i, j)], in ? s_kap[c] : R(0),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&slot[FaceSlot<TT>::col(face, i, j)], in ? s_tc[c] : R(0),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const R kv = in ? s_kap[c] : R(0), cv = in ? s_tc[c] : R(0);
+            face_t<R> wk, wc;
+            if constexpr (FaceWord<R>::tagged) {
+                const face_t<R> tag = (face_t<R>)done << 32;
+                wk = tag | __float_as_uint(kv);
+                wc = tag | __float_as_uint(cv);
+            } else {
+                wk = kv;
+                wc = cv;
+            }
+            __hip_atomic_store(&slot[FaceSlot<TT>::kap(face, i, j)], wk, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&slot[FaceSlot<TT>::col(face, i, j)], wc, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();   // (s_kap becomes the output buffer)
     }
@@ -613,7 +710,7 @@ template <typename R, int TT>
 __global__ void __launch_bounds__(SweepShape<TT>::THREADS)
 k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
                 const int4* __restrict__ tiles, int ntiles, const int4* __restrict__ octs,
-                unsigned* __restrict__ flags, R* fbuf, SweepCtl* ctl, long long spin_ticks,
+                unsigned* __restrict__ flags, face_t<R>* fbuf, SweepCtl* ctl, long long spin_ticks,
                 unsigned* cond)
 {
     constexpr int NHALO = (TT + 1) * (TT + 1) * (TT + 1);
@@ -649,13 +746,18 @@ k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
         const int idx = oc.x + (tl.w * oc.z + tl.z) * oc.y + tl.y;
         sweep_tile<R, TT, SweepShape<TT>::THREADS, TILE_COHERENT>(
             grids, state, tau_buf, tl, s_tc, s_kap, [&] {
-            if (lead) wait_upstream(flags, idx, tl, oc, done, spin_ticks, ctl);
-        }, fbuf, idx, oc);
-        // every wave's column stores complete, then the flag
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        if (lead)
-            __hip_atomic_store(&flags[idx], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if constexpr (!FaceWord<R>::tagged)
+                if (lead) wait_upstream(flags, idx, tl, oc, done, spin_ticks, ctl);
+        }, fbuf, idx, oc, done, spin_ticks, ctl);
+        if constexpr (!FaceWord<R>::tagged) {
+            // every wave's column stores complete, then the flag
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            if (lead)
+                __hip_atomic_store(&flags[idx], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // (tagged entries need no flag; the claim's barrier keeps the next
+        // tile's LDS writes behind this tile's last reads)
     }
     if (lead) {
         const unsigned left = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(
@@ -924,9 +1026,11 @@ k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int 
 // the lowest unfinished tile is always held or next in its list, so the
 // sweep cannot deadlock.  A workgroup first
 // integrates its tile's cells (each wavefront four 4^3 bricks, with the
-// per-cell arithmetic of k_chem), writes the new neutral fractions at agent
-// scope and puts sigma0 n_H x dx of every cell in LDS; then it waits for the
-// tile's upstream tiles and sweeps it (TILE_FUSED).  A tile's micro-physics
+// per-cell arithmetic of k_chem), writes the new state (plain stores: no
+// other tile of the launch reads it) and puts sigma0 n_H x dx of every cell
+// in LDS; then it sweeps the tile (TILE_FUSED), polling its halo entries in
+// the face buffer until the upstream tiles have written them (the entries
+// carry the launch's epoch, so no done-flag is stored).  A tile's micro-physics
 // needs nothing from other tiles, so while some workgroups of a compute unit
 // sweep or wait, the others integrate.  The register budget is that of three
 // wavefronts per SIMD (168 registers), which the integrator and the sweep fit
@@ -936,16 +1040,15 @@ k_chem_fix(const GridDev<float>* __restrict__ grids, BatchDev bd, int from, int 
 // precision) a cell whose float integration took a precision-sensitive
 // decision is listed for launch_chem_fix and not written, as in k_chem, and
 // the sweep uses its float result; launch_chem_fix then re-solves it and
-// marks the columns for a second, conditional raytrace.  A tile's flag is
-// stored once every wave's stores have completed; waits are bounded as in
-// k_sweep_persist.  The rate table is copied to LDS when a tile's grid
+// marks the columns for a second, conditional raytrace.  Polls are bounded
+// as in k_sweep_persist.  The rate table is copied to LDS when a tile's grid
 // differs from the workgroup's previous one.
 template <typename R, bool Mixed>
 __global__ void __launch_bounds__(FUSED_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
 k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to, int tau_chem,
              int tau_sweep, int dev_dt, double hscale, unsigned long long* ctr,
              const int4* __restrict__ tiles, TileLists lists, const int4* __restrict__ octs,
-             unsigned* __restrict__ flags, R* fbuf, SweepCtl* ctl, long long spin_ticks)
+             face_t<R>* fbuf, SweepCtl* ctl, long long spin_ticks)
 {
     constexpr int TT = PERSIST_TILE, NT = FUSED_THREADS;
     constexpr int HX = TT + 1, HY = TT + 1, NHALO = HX * HY * (TT + 1);
@@ -1040,14 +1143,8 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
         // its instructions go before those of the integrating wavefronts of
         // the compute unit
         __builtin_amdgcn_s_setprio(3);
-        sweep_tile<R, TT, NT, TILE_FUSED>(grids, to, tau_sweep, tl, s_tc, s_kap, [&] {
-            if (lead) wait_upstream(flags, idx, tl, oc, done, spin_ticks, ctl);
-        }, fbuf, idx, oc);
-        // every wave's neutral-fraction and column stores complete, then the flag
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        if (lead)
-            __hip_atomic_store(&flags[idx], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sweep_tile<R, TT, NT, TILE_FUSED>(grids, to, tau_sweep, tl, s_tc, s_kap, [] {}, fbuf,
+                                          idx, oc, done, spin_ticks, ctl);
         __builtin_amdgcn_s_setprio(0);
     }
     if (lead) {
@@ -1434,7 +1531,8 @@ hipError_t launch_sweep_persist(const GridDev<R>* grids, int state, int tau_buf,
     if (ntiles <= 0 || nwg <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_sweep_persist<R, PERSIST_TILE>), dim3(nwg),
                        dim3(SweepShape<PERSIST_TILE>::THREADS), 0, s, grids, state, tau_buf, tiles,
-                       ntiles, octs, flags, static_cast<R*>(fbuf), ctl, spin_ticks, cond);
+                       ntiles, octs, flags, static_cast<face_t<R>*>(fbuf), ctl, spin_ticks,
+                       cond);
     return hipGetLastError();
 }
 
@@ -1452,8 +1550,8 @@ template <typename R>
 hipError_t launch_chem_sweep(const GridDev<R>* grids, const BatchDev& b, int from, int to,
                              int tau_chem, int tau_sweep, bool dev_dt, double hscale,
                              unsigned long long* ctr, bool mixed, const int4* tiles,
-                             const TileLists& lists, const int4* octs, unsigned* flags, void* fbuf,
-                             SweepCtl* ctl, int nwg, long long spin_ticks, hipStream_t s)
+                             const TileLists& lists, const int4* octs, void* fbuf, SweepCtl* ctl,
+                             int nwg, long long spin_ticks, hipStream_t s)
 {
     if constexpr (std::is_same<R, float>::value) {
         if (lists.first[lists.n] <= 0 || nwg <= 0) return hipSuccess;
@@ -1462,11 +1560,13 @@ hipError_t launch_chem_sweep(const GridDev<R>* grids, const BatchDev& b, int fro
         if (mixed)
             hipLaunchKernelGGL((k_chem_sweep<R, true>), dim3(nwg), dim3(FUSED_THREADS), 0, s,
                                grids, b, from, to, tau_chem, tau_sweep, (int)dev_dt, hscale, ctr,
-                               tiles, lists, octs, flags, static_cast<R*>(fbuf), ctl, spin_ticks);
+                               tiles, lists, octs, static_cast<face_t<R>*>(fbuf), ctl,
+                               spin_ticks);
         else
             hipLaunchKernelGGL((k_chem_sweep<R, false>), dim3(nwg), dim3(FUSED_THREADS), 0, s,
                                grids, b, from, to, tau_chem, tau_sweep, (int)dev_dt, hscale, ctr,
-                               tiles, lists, octs, flags, static_cast<R*>(fbuf), ctl, spin_ticks);
+                               tiles, lists, octs, static_cast<face_t<R>*>(fbuf), ctl,
+                               spin_ticks);
         return hipGetLastError();
     } else {
         // double storage keeps the separate kernels (its integrator does not
@@ -1579,8 +1679,7 @@ hipError_t launch_energy(int64_t n, const R* nH, const R* x, R* E, double T0, hi
     template hipError_t launch_chem_sweep<R>(const GridDev<R>*, const BatchDev&, int, int, int,     \
                                              int, bool, double, unsigned long long*, bool,         \
                                              const int4*, const TileLists&, const int4*,           \
-                                             unsigned*, void*, SweepCtl*, int, long long,          \
-                                             hipStream_t);                                         \
+                                             void*, SweepCtl*, int, long long, hipStream_t);       \
     template int chem_sweep_occupancy<R>(bool);                                                    \
     template hipError_t launch_chem<R>(const GridDev<R>*, const BatchDev&, int, int, int, int,    \
                                        bool, double, unsigned long long*, int, hipStream_t);       \
