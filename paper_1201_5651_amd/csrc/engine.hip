@@ -283,6 +283,28 @@ template <typename R> const GridDev<R>* gd(const Engine& e)
     return static_cast<const GridDev<R>*>(e.gdev);
 }
 
+// Tiles of the persistent schedule, and the lists a launch of nwg persistent
+// workgroups takes them from: one per XCD (tiles dealt by their 128-byte
+// lines, so that the tiles sharing a line go through one L2) when every list
+// gets a workgroup, else the schedule as one list.
+int persist_tiles(const Engine& e)
+{
+    const int w = PERSIST_SCHEDULE;
+    return e.stage_first[w].empty() ? 0 : e.stage_first[w].back() + e.stage_count[w].back();
+}
+const int4* persist_tiles_of(const Engine& e, int nwg)
+{
+    return nwg >= NXCD ? e.xtiles : e.tiles[PERSIST_SCHEDULE];
+}
+TileLists persist_lists(const Engine& e, int nwg)
+{
+    if (nwg >= NXCD) return e.xlists;
+    TileLists one{};
+    one.n = 1;
+    one.first[1] = persist_tiles(e);
+    return one;
+}
+
 template <typename R>
 pi_status raytrace_t(Engine& e, int state, int tau_buf, int which, hipStream_t s)
 {
@@ -290,12 +312,9 @@ pi_status raytrace_t(Engine& e, int state, int tau_buf, int which, hipStream_t s
     HIP_OR(launch_plane_scan<R>(gd<R>(e), e.bd(), e.plane_rows, state, tau_buf, s),
            "plane-parallel raytrace launch");
     if (which == SWEEP_PERSIST) {
-        const int w = PERSIST_SCHEDULE;
-        const int ntiles = e.stage_first[w].empty()
-                               ? 0
-                               : e.stage_first[w].back() + e.stage_count[w].back();
-        HIP_OR(launch_sweep_persist<R>(gd<R>(e), state, tau_buf, e.tiles[w], ntiles, e.octs,
-                                       e.flags, e.fbuf, e.ctl, std::min(ntiles, e.persist_wg),
+        const int nwg = std::min(persist_tiles(e), e.persist_wg);
+        HIP_OR(launch_sweep_persist<R>(gd<R>(e), state, tau_buf, persist_tiles_of(e, nwg),
+                                       persist_lists(e, nwg), e.octs, e.flags, e.fbuf, e.ctl, nwg,
                                        e.persist_spin, nullptr, s),
                "persistent raytrace launch");
         return PI_OK;
@@ -340,27 +359,22 @@ pi_status chem_t(Engine& e, bool dev_dt, double h, int tau_buf, int from, int to
 pi_status chem_sweep_fused(Engine& e, bool dev_dt, double h, int tau_chem, int from, int to,
                            int tau_sweep, hipStream_t s)
 {
-    const int w = PERSIST_SCHEDULE;
-    const int ntiles =
-        e.stage_first[w].empty() ? 0 : e.stage_first[w].back() + e.stage_count[w].back();
+    const int ntiles = persist_tiles(e);
     const BatchDev b = e.bd();
     const int nwg = std::min(ntiles, e.fused_wg);
-    TileLists one{};
-    one.n = 1;
-    one.first[1] = ntiles;
-    const bool per_xcd = nwg >= NXCD;
     HIP_OR(launch_chem_sweep<float>(gd<float>(e), b, from, to, tau_chem, tau_sweep, dev_dt, h,
-                                    e.work, e.mixed(), per_xcd ? e.xtiles : e.tiles[w],
-                                    per_xcd ? e.xlists : one, e.octs, e.fbuf, e.ctl, nwg,
+                                    e.work, e.mixed(), persist_tiles_of(e, nwg),
+                                    persist_lists(e, nwg), e.octs, e.fbuf, e.ctl, nwg,
                                     e.persist_spin, s),
            "fused micro-physics and raytrace launch");
     if (e.mixed()) {
         HIP_OR(launch_chem_fix(gd<float>(e), b, e.fix_blocks, from, to, tau_chem, dev_dt, h,
                                e.work, true, s),
                "double re-solve launch");
-        HIP_OR(launch_sweep_persist<float>(gd<float>(e), to, tau_sweep, e.tiles[w], ntiles, e.octs,
-                                           e.flags, e.fbuf, e.ctl, std::min(ntiles, e.persist_wg),
-                                           e.persist_spin, e.fix_n + 2, s),
+        const int nwr = std::min(ntiles, e.persist_wg);
+        HIP_OR(launch_sweep_persist<float>(gd<float>(e), to, tau_sweep, persist_tiles_of(e, nwr),
+                                           persist_lists(e, nwr), e.octs, e.flags, e.fbuf, e.ctl,
+                                           nwr, e.persist_spin, e.fix_n + 2, s),
                "conditional raytrace launch");
     }
     return PI_OK;

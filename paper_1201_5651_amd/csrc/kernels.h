@@ -122,8 +122,8 @@ struct BatchDev {
 // the tile ticket, workgroups that have left, the epoch of the last call, and
 // the flag of a wait that ran out.
 struct SweepCtl {
-    unsigned ticket, exited, epoch, err;
-    unsigned lticket[NXCD];   // tickets of the per-XCD tile lists
+    unsigned exited, epoch, err;
+    unsigned lticket[NXCD];   // tickets of the tile lists (TileLists)
 };
 // Tile lists of a persistent launch: list l holds tiles[first[l] ..
 // first[l + 1]) in schedule order; with n = NXCD, workgroup w takes from list
@@ -154,8 +154,8 @@ template <typename R>
 hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,
                               int first, int count, int tile, hipStream_t s);
 // The whole raytrace of every grid in one launch of nwg persistent workgroups
-// over the schedule tiles[0 .. ntiles) of edge PERSIST_TILE (stage after
-// stage); octs[grid << 3 | octant] = (first flag/slot index, tiles along x,
+// over the schedule of edge PERSIST_TILE (stage after stage) in `lists` of
+// tiles (one list, or one per XCD when nwg >= NXCD); octs[grid << 3 | octant] = (first flag/slot index, tiles along x,
 // y, z); fbuf: the face buffer, FACE_WORDS entries per tile, zeroed when
 // allocated; flags: one done-flag per tile (used by double grids, whose face
 // entries carry no epoch).  spin_ticks bounds each wait (100 MHz ticks).
@@ -163,9 +163,9 @@ hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, c
 // (cleared by it).
 template <typename R>
 hipError_t launch_sweep_persist(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,
-                                int ntiles, const int4* octs, unsigned* flags, void* fbuf,
-                                SweepCtl* ctl, int nwg, long long spin_ticks, unsigned* cond,
-                                hipStream_t s);
+                                const TileLists& lists, const int4* octs, unsigned* flags,
+                                void* fbuf, SweepCtl* ctl, int nwg, long long spin_ticks,
+                                unsigned* cond, hipStream_t s);
 // One half of an A3 step (or an A2 step) of every grid in one launch of nwg
 // persistent workgroups, for batches of grids with one point source each:
 // the micro-physics of launch_chem over h = hscale (x dt when dev_dt) from

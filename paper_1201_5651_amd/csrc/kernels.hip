@@ -672,29 +672,34 @@ __device__ __forceinline__ void wait_upstream(const unsigned* __restrict__ flags
 }
 
 // The whole raytrace in one launch: persistent workgroups claim tiles in the
-// order of the schedule (stage by stage) from a ticket and wait, before
-// reading a tile's upstream halo, until the tiles across its three upstream
-// faces are done (those tiles waited in turn for theirs, so every tile of
-// the halo is done).  Claiming in schedule order keeps every wait on a tile
-// that a running workgroup holds, so the sweep cannot deadlock.  Flags carry
-// the epoch of the call (ctl->epoch + 1); the last workgroup to leave resets
-// the ticket and advances the epoch, so replays of a captured graph need no
-// reset.  A wait longer than spin_ticks (of the 100 MHz real-time counter)
-// sets ctl->err and goes on, so every workgroup exits; the result is then
-// reported invalid.  With a condition word (cond), the raytrace runs only if
-// the word is non-zero, and the last workgroup to leave clears it.  The exit
-// count, the resets and the epoch are relaxed atomics: a workgroup counts
-// itself only after its last claim has returned, and the next launch that
-// reads them follows this one's end (an agent-scope release per workgroup
-// would write back the XCD's L2 a thousand times per launch).
+// order of the schedule (stage by stage) from a ticket -- of one list per XCD
+// (TileLists, as k_chem_sweep), into which the tiles are dealt by the 128-byte
+// lines their rows lie in, each list in schedule order -- and read a tile's
+// upstream halo only once the tiles across its three upstream faces have
+// published it (those tiles waited in turn for theirs).  Every list being in
+// schedule order, the lowest unfinished tile is always held by a running
+// workgroup or next in its list, so the sweep cannot deadlock.  On float
+// grids the halo entries carry the epoch of the call (ctl->epoch + 1) and are
+// polled until current; on double grids the tile waits for the upstream
+// tiles' done-flags, which carry the epoch, and sets its own once its stores
+// have completed.  The last workgroup to leave resets the tickets and
+// advances the epoch, so replays of a captured graph need no reset.  A wait
+// longer than spin_ticks (of the 100 MHz real-time counter) sets ctl->err and
+// goes on, so every workgroup exits; the result is then reported invalid.
+// With a condition word (cond), the raytrace runs only if the word is
+// non-zero, and the last workgroup to leave clears it.  The exit count, the
+// resets and the epoch are relaxed atomics: a workgroup counts itself only
+// after its last claim has returned, and the next launch that reads them
+// follows this one's end (an agent-scope release per workgroup would write
+// back the XCD's L2 a thousand times per launch).
 //
 // Columns pass between tiles without cache maintenance: a tile writes its
-// columns, and reads its upstream halo, as relaxed atomics at agent scope,
-// which go to the device-wide point of coherence instead of the caches of
-// one compute unit or one XCD.  Every wave waits for its column stores to
-// complete (vmcnt 0) before the workgroup barrier that precedes the flag
-// store, so a flag is seen only after the columns it covers are in place.
-// (An agent-scope release and acquire per tile would write back and
+// face entries, and reads its upstream halo, as relaxed atomics at agent
+// scope, which go to the device-wide point of coherence instead of the caches
+// of one compute unit or one XCD.  With done-flags, every wave waits for its
+// stores to complete (vmcnt 0) before the workgroup barrier that precedes the
+// flag store, so a flag is seen only after the entries it covers are in
+// place.  (An agent-scope release and acquire per tile would write back and
 // invalidate the L2 of the XCD on every tile instead.)
 //
 // The claims, waits and flag stores are made by the whole of wave 0, under
@@ -709,7 +714,7 @@ __device__ __forceinline__ void wait_upstream(const unsigned* __restrict__ flags
 template <typename R, int TT>
 __global__ void __launch_bounds__(SweepShape<TT>::THREADS)
 k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
-                const int4* __restrict__ tiles, int ntiles, const int4* __restrict__ octs,
+                const int4* __restrict__ tiles, TileLists lists, const int4* __restrict__ octs,
                 unsigned* __restrict__ flags, face_t<R>* fbuf, SweepCtl* ctl, long long spin_ticks,
                 unsigned* cond)
 {
@@ -729,19 +734,22 @@ k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     if (cond && __builtin_amdgcn_readfirstlane(__hip_atomic_load(
                     cond, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0u)
         return;
+    // the tile list of this workgroup's XCD
+    const int list = lists.n > 1 ? (int)(blockIdx.x % NXCD) : 0;
+    const int lfirst = lists.first[list], lcount = lists.first[list + 1] - lfirst;
     for (;;) {
         if (lead) {
             // lane 0 takes the ticket (the others add 0); every lane of wave 0
             // writes lane 0's value
-            const unsigned c = __hip_atomic_fetch_add(&ctl->ticket, add, __ATOMIC_RELAXED,
+            const unsigned c = __hip_atomic_fetch_add(&ctl->lticket[list], add, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
             s_ticket = (int)__builtin_amdgcn_readfirstlane(c);
         }
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(s_ticket);
         __syncthreads();   // (s_ticket is rewritten by the next claim)
-        if (t >= ntiles) break;
-        const int4 tl = tiles[t];
+        if (t >= lcount) break;
+        const int4 tl = tiles[lfirst + t];
         const int4 oc = octs[tl.x];                         // flag base, tiles per axis
         const int idx = oc.x + (tl.w * oc.z + tl.z) * oc.y + tl.y;
         sweep_tile<R, TT, SweepShape<TT>::THREADS, TILE_COHERENT>(
@@ -765,7 +773,8 @@ k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
         if (left == gridDim.x - 1) {
             // every workgroup read the condition before it left
             if (cond) __hip_atomic_store(cond, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int l = 0; l < NXCD; ++l)
+                __hip_atomic_store(&ctl->lticket[l], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctl->exited, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctl->epoch, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -1524,15 +1533,16 @@ hipError_t launch_sweep_stage(const GridDev<R>* grids, int state, int tau_buf, c
 
 template <typename R>
 hipError_t launch_sweep_persist(const GridDev<R>* grids, int state, int tau_buf, const int4* tiles,
-                                int ntiles, const int4* octs, unsigned* flags, void* fbuf,
-                                SweepCtl* ctl, int nwg, long long spin_ticks, unsigned* cond,
-                                hipStream_t s)
+                                const TileLists& lists, const int4* octs, unsigned* flags,
+                                void* fbuf, SweepCtl* ctl, int nwg, long long spin_ticks,
+                                unsigned* cond, hipStream_t s)
 {
-    if (ntiles <= 0 || nwg <= 0) return hipSuccess;
+    if (lists.first[lists.n] <= 0 || nwg <= 0) return hipSuccess;
+    // every list needs a workgroup
+    if (lists.n > 1 && nwg < NXCD) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_sweep_persist<R, PERSIST_TILE>), dim3(nwg),
                        dim3(SweepShape<PERSIST_TILE>::THREADS), 0, s, grids, state, tau_buf, tiles,
-                       ntiles, octs, flags, static_cast<face_t<R>*>(fbuf), ctl, spin_ticks,
-                       cond);
+                       lists, octs, flags, static_cast<face_t<R>*>(fbuf), ctl, spin_ticks, cond);
     return hipGetLastError();
 }
 
@@ -1672,9 +1682,10 @@ hipError_t launch_energy(int64_t n, const R* nH, const R* x, R* E, double T0, hi
 #define PI_INSTANTIATE(R)                                                                          \
     template hipError_t launch_sweep_stage<R>(const GridDev<R>*, int, int, const int4*, int, int,  \
                                               int, hipStream_t);                                   \
-    template hipError_t launch_sweep_persist<R>(const GridDev<R>*, int, int, const int4*, int,     \
-                                                const int4*, unsigned*, void*, SweepCtl*, int,     \
-                                                long long, unsigned*, hipStream_t);                \
+    template hipError_t launch_sweep_persist<R>(const GridDev<R>*, int, int, const int4*,          \
+                                                const TileLists&, const int4*, unsigned*, void*,   \
+                                                SweepCtl*, int, long long, unsigned*,              \
+                                                hipStream_t);                                      \
     template int sweep_persist_occupancy<R>();                                                     \
     template hipError_t launch_chem_sweep<R>(const GridDev<R>*, const BatchDev&, int, int, int,     \
                                              int, bool, double, unsigned long long*, bool,         \
