@@ -238,7 +238,7 @@ pi_status pi_step_o1(pi_grid* grid, double t_end, void* stream);
  * time-averaged optical depth per cell length (sigma0 dx units), tau_half the
  * time-averaged entering columns, and tau the columns of the new state (a
  * raytrace, for the next timestep).  One point source only (PI_EINVAL for
- * PI_SRC_PLANE or nsrc > 1); the pass runs on 4^3 tiles whatever the raytrace
+ * PI_SRC_PLANE or nsrc > 1); the pass runs on 8^3 tiles whatever the raytrace
  * tile. */
 pi_status pi_step_a1(pi_grid* grid, double t_end, void* stream);
 

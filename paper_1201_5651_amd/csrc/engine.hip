@@ -419,18 +419,19 @@ template <typename R> pi_status step_t(Engine& e, double t_end_arg, int order, h
     return PI_OK;
 }
 
-// Algorithm 1 (Sect. 2.1): timestep, the combined pass (stages of the 4^3
-// tile schedule), the raytrace of the new state for the next timestep, clock.
+// Algorithm 1 (Sect. 2.1): timestep, the combined pass (stages of the
+// schedule of edge PERSIST_TILE), the raytrace of the new state for the next
+// timestep, clock.
 template <typename R> pi_status step_a1_t(Engine& e, double t_end_arg, hipStream_t s)
 {
-    static_assert(SWEEP_TILES[0] == 4, "the algorithm 1 pass runs on the 4^3 tile schedule");
     for (GridHost* h : e.grids)
         if (h->d.source != PI_SRC_POINT || nsources(h->d) > 1)
             return fail(PI_EINVAL, "algorithm 1 needs grids with one point source");
     pi_status r = timestep_t<R>(e, t_end_arg, s);
     if (r != PI_OK) return r;
-    for (size_t k = 0; k < e.stage_first[0].size(); ++k)
-        HIP_OR(launch_sweep_a1<R>(gd<R>(e), e.tiles[0], e.stage_first[0][k], e.stage_count[0][k],
+    const int w = PERSIST_SCHEDULE;
+    for (size_t k = 0; k < e.stage_first[w].size(); ++k)
+        HIP_OR(launch_sweep_a1<R>(gd<R>(e), e.tiles[w], e.stage_first[w][k], e.stage_count[w][k],
                                   e.work, e.mixed() ? (e.front() ? 2 : 1) : 0, s),
                "algorithm 1 pass launch");
     if ((r = raytrace_t<R>(e, PI_BUF_N, PI_BUF_N, e.sweep >= 0 ? e.sweep : SWEEP_DEFAULT, s)) != PI_OK)

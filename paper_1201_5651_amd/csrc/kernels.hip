@@ -116,7 +116,27 @@ constexpr LevelOrder make_level_order()
             }
     return o;
 }
+// First slot of every level in the level order of each class: the level's
+// cells lie in the 64 slots from there (-1 for a level the class lacks).
+struct LevelStart {
+    short first[LEVEL_CLASSES][3 * PERSIST_TILE - 2];
+};
+constexpr LevelStart make_level_start()
+{
+    constexpr int N = PERSIST_TILE * PERSIST_TILE * PERSIST_TILE;
+    const LevelOrder o = make_level_order();
+    LevelStart w{};
+    for (int c = 0; c < LEVEL_CLASSES; ++c) {
+        for (int l = 0; l < 3 * PERSIST_TILE - 2; ++l) w.first[c][l] = -1;
+        for (int i = 0; i < N; ++i) {
+            const int l = (int)(o.cell[c][i] >> 15);
+            if (w.first[c][l] < 0) w.first[c][l] = (short)i;
+        }
+    }
+    return w;
+}
 __constant__ LevelOrder c_level_order = make_level_order();
+__constant__ LevelStart c_level_start = make_level_start();
 
 // Class of a tile for c_level_order from its indices in the octant, and its
 // number of levels.
@@ -1170,23 +1190,43 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
 }
 
 // ------------------------------------------------------------- algorithm 1
-// Algorithm 1's pass (Sect. 2.1): the raytrace of k_sweep on 4^3 tiles (one
-// wavefront each) in which every cell, when its plane comes, is integrated
+// Double integration of one cell of a float grid's algorithm-1 pass (mixed
+// precision) over hd on the entering column tin, out of line: it is rarely
+// taken, and inline its registers would spill into the float path.
+__device__ __attribute__((noinline)) void a1_cell_double(const GridDev<float>& G, int gi, int gj,
+                                                         int gk, double n, double tin, double hd,
+                                                         double& x, double& E, double& tb, Work& w)
+{
+    const Params<double>& pd = G.pd;
+    const CellGeom<double> cgd = cell_geom(pd, gi, gj, gk);
+    const Env<double> ed = make_env(pd, n, cgd, tin);
+    micro_t<double, true>(pd, ed, hd, x, E, w, &tb);
+}
+
+// Algorithm 1's pass (Sect. 2.1): the raytrace on tiles of edge PERSIST_TILE,
+// one wavefront per tile and one launch per tile diagonal, in which every
+// cell, when its level comes (c_level_order, as in sweep_tile), is integrated
 // over dt on the time-averaged column entering it and then passes on its own
 // time-averaged optical depth per cell length, kbar = tau_avg / ell, in place
-// of sigma0 n_H x dx.  The state n is advanced in place; the half-step buffers
-// receive the pass's time-averaged entering columns (tau[1]) and kbar (x[1]),
-// which the tiles of later stages read as their halo.  With mixed precision an
-// ionisation-front cell is integrated in double, and a cell whose float
-// integration took a precision-sensitive decision is integrated again in
-// double at once (later cells depend on it).
+// of sigma0 n_H x dx.  At level s lane t takes the slot of the level's 64
+// slots (from c_level_start) that is t modulo 64, so one copy of the
+// integrator serves every level and a level of 64 cells fills the wavefront.
+// The state n is advanced in place; the half-step buffers receive the pass's
+// time-averaged entering columns (tau[1]) and kbar (x[1]), which the tiles of
+// later stages read as their halo.  With mixed precision an ionisation-front
+// cell is integrated in double, and a cell whose float integration took a
+// precision-sensitive decision is integrated again in double at once (later
+// cells depend on it), both out of line.
+// (A stage has at most a few thousand tiles, one wavefront each: two
+// wavefronts per SIMD are all a launch fills, so the kernel takes their
+// register budget.)
 template <typename R>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ChemWaves<R>::value)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 k_sweep_a1(const GridDev<R>* __restrict__ grids, const int4* __restrict__ tiles, int first,
            unsigned long long* ctr, int mixed)
 {
-    constexpr int TT = 4, TX = TT, TY = TT, TZ = TT, NC = TT * TT * TT;
-    constexpr int HX = TX + 1, HY = TY + 1, HZ = TZ + 1, NHALO = HX * HY * HZ;
+    constexpr int TT = PERSIST_TILE, NC = TT * TT * TT;
+    constexpr int HX = TT + 1, HY = TT + 1, NHALO = HX * HY * (TT + 1);
     __shared__ R s_tc[NHALO];
     __shared__ R s_kap[NHALO];
 
@@ -1200,76 +1240,60 @@ k_sweep_a1(const GridDev<R>* __restrict__ grids, const int4* __restrict__ tiles,
     const int ex = px ? p.nx - p.sx : p.sx;
     const int ey = py ? p.ny - p.sy : p.sy;
     const int ez = pz ? p.nz - p.sz : p.sz;
-    const int X0 = tl.y * TX, Y0 = tl.z * TY, Z0 = tl.w * TZ;
+    const int X0 = tl.y * TT, Y0 = tl.z * TT, Z0 = tl.w * TT;
 
-    // halo from the earlier stages of this pass; the tile's own cells are
-    // written when their planes come
-    for (int q = threadIdx.x; q < NHALO; q += NC) {
+    // the upstream halo from the earlier stages of this pass (time-averaged
+    // centre columns as the owner formed them); the tile's own cells are
+    // written when their levels come
+    for (int f = threadIdx.x; f < FaceList<TT>::N; f += 64) {
+        const int q = face_entry<TT>(f);
         const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
         const int Lx = X0 + hx - 1, Ly = Y0 + hy - 1, Lz = Z0 + hz - 1;
         R kap = R(0), tc = R(0);
-        if ((hx == 0 || hy == 0 || hz == 0) && Lx >= 0 && Ly >= 0 && Lz >= 0 && Lx < ex &&
-            Ly < ey && Lz < ez) {
+        if (Lx >= 0 && Ly >= 0 && Lz >= 0 && Lx < ex && Ly < ey && Lz < ez) {
             const int gi = px ? p.sx + Lx : p.sx - 1 - Lx;
             const int gj = py ? p.sy + Ly : p.sy - 1 - Ly;
             const int gk = pz ? p.sz + Lz : p.sz - 1 - Lz;
             const int64_t g = gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk);
             kap = kbar_in[g];
-            const R ax = R(Lx) + R(0.5), ay = R(Ly) + R(0.5), az = R(Lz) + R(0.5);
-            const R da = (az >= ax && az >= ay) ? az : (ay >= ax ? ay : ax);
-            const R hds = R(0.5) * r_sqrt(ax * ax + ay * ay + az * az) / da;
-            tc = r_fma(hds, kap, tavg_in[g]);
+            tc = r_fma(halo_hds<R>(Lx, Ly, Lz), kap, tavg_in[g]);
         }
         s_kap[q] = kap;
         s_tc[q] = tc;
     }
-
-    // the thread's cell (plane order) and its geometry, as in k_sweep
-    const int cl = plane_cell<TT>(threadIdx.x);
-    const int lx = cl & 31, ly = (cl >> 5) & 31, lz = cl >> 10;
-    const int L[3] = { X0 + lx, Y0 + ly, Z0 + lz };
-    const bool active = L[0] < ex && L[1] < ey && L[2] < ez;
-    const R ad[3] = { R(L[0]) + R(0.5), R(L[1]) + R(0.5), R(L[2]) + R(0.5) };
-    const int a = (ad[2] >= ad[0] && ad[2] >= ad[1]) ? 2 : (ad[1] >= ad[0] ? 1 : 0);
-    const int b = a == 2 ? 0 : a + 1;
-    const int c = a == 0 ? 2 : a - 1;
-    const int st[3] = { 1, HX, HX * HY };
-    const int self = (lz + 1) * HX * HY + (ly + 1) * HX + (lx + 1);
-    const int n00 = self - st[a], n10 = n00 - st[b], n01 = n00 - st[c], n11 = n10 - st[c];
-    const R fb = ad[b] / ad[a], fc = ad[c] / ad[a];
-    const bool vb = L[b] >= 1, vc = L[c] >= 1;
-    const R g00 = (R(1) - fb) * (R(1) - fc);
-    const R g10 = vb ? fb * (R(1) - fc) : R(0);
-    const R g01 = vc ? (R(1) - fb) * fc : R(0);
-    const R g11 = (vb && vc) ? fb * fc : R(0);
-    const R hds = R(0.5) * r_sqrt(ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2]) / ad[a];
-    const bool corner = L[a] == 0;
-    const int diag = lx + ly + lz;
-    const int gi = px ? p.sx + L[0] : p.sx - 1 - L[0];
-    const int gj = py ? p.sy + L[1] : p.sy - 1 - L[1];
-    const int gk = pz ? p.sz + L[2] : p.sz - 1 - L[2];
-    const int64_t q = active ? gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk) : 0;
-    R n = R(1), x = R(1), E = R(0);
-    if (active) {
-        n = G.nH[q];
-        x = G.x[0][q];
-        E = G.E[0] ? G.E[0][q] : R(0);
-    }
-    const double hd = G.st->dt;
+    int nlev = 0;
+    const int cls = level_class(tl.y, tl.z, tl.w, nlev);
     const bool mellema = p.weights == 1;
+    const double hd = G.st->dt;
     Work w{};
-    R tin = R(0), kbar = R(0);
     __syncthreads();
 
-    for (int s = 0; s < TX + TY + TZ - 2; ++s) {
-        if (active && diag == s) {
-            if (!corner) {
-                const R T00 = s_tc[n00] + hds * s_kap[n00];
-                const R T10 = s_tc[n10] + hds * s_kap[n10];
-                const R T01 = s_tc[n01] + hds * s_kap[n01];
-                const R T11 = s_tc[n11] + hds * s_kap[n11];
-                tin = sc_average<R>(mellema, g00, g10, g01, g11, T00, T10, T01, T11);
+    for (int s = 0; s < nlev; ++s) {
+        const int w0 = c_level_start.first[cls][s];
+        const int slot = w0 + (((int)threadIdx.x - w0) & 63);
+        const int cl = slot < NC ? (int)c_level_order.cell[cls][slot] : -1;
+        const int lx = cl & 31, ly = (cl >> 5) & 31, lz = (cl >> 10) & 31;
+        const int L[3] = { X0 + lx, Y0 + ly, Z0 + lz };
+        if (cl >= 0 && (cl >> 15) == s && L[0] < ex && L[1] < ey && L[2] < ez) {
+            const ScGeom<R> sg = sc_geom<R>(L);
+            const int st[3] = { 1, HX, HX * HY };
+            const int self = (lz + 1) * HX * HY + (ly + 1) * HX + (lx + 1);
+            R tin = R(0);
+            if (!sg.corner) {
+                const int n00 = self - st[sg.a], n10 = n00 - st[sg.b];
+                const int n01 = n00 - st[sg.c], n11 = n10 - st[sg.c];
+                const R T00 = upstream_T(s_tc[n00], sg.hds, s_kap[n00]);
+                const R T10 = upstream_T(s_tc[n10], sg.hds, s_kap[n10]);
+                const R T01 = upstream_T(s_tc[n01], sg.hds, s_kap[n01]);
+                const R T11 = upstream_T(s_tc[n11], sg.hds, s_kap[n11]);
+                tin = sc_average<R>(mellema, sg.g00, sg.g10, sg.g01, sg.g11, T00, T10, T01, T11);
             }
+            const int gi = px ? p.sx + L[0] : p.sx - 1 - L[0];
+            const int gj = py ? p.sy + L[1] : p.sy - 1 - L[1];
+            const int gk = pz ? p.sz + L[2] : p.sz - 1 - L[2];
+            const int64_t q = gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk);
+            const R n = G.nH[q], x = G.x[0][q];
+            const R E = G.E[0] ? G.E[0][q] : R(0);
             const CellGeom<R> cg = cell_geom(p, gi, gj, gk);
             R xo = x, Eo = E, tb;
             if (!(isfinite(n) && isfinite(x) && isfinite(E) && isfinite(tin))) {
@@ -1280,19 +1304,26 @@ k_sweep_a1(const GridDev<R>* __restrict__ grids, const int4* __restrict__ tiles,
                 const bool front = mixed == 2 && front_cell(x);
                 if (!front) {
                     const Env<R> env = make_env(p, n, cg, tin);
-                    micro_t<R, true>(p, env, R(hd), xo, Eo, wc, &tb);
+                    if constexpr (std::is_same<R, float>::value) {
+                        // inline: a call here would save and restore the
+                        // wavefront's registers around every cell (the
+                        // double integrator spills more inline than called)
+                        [[clang::always_inline]] micro_t<R, true>(p, env, R(hd), xo, Eo, wc,
+                                                                  &tb);
+                    } else {
+                        micro_t<R, true>(p, env, R(hd), xo, Eo, wc, &tb);
+                    }
                 }
-                if (front || (mixed && wc.close > 0)) {
-                    // precision-sensitive: the same cell in double, from the same inputs
-                    const Params<double>& pd = G.pd;
-                    const CellGeom<double> cgd = cell_geom(pd, gi, gj, gk);
-                    const Env<double> ed = make_env(pd, (double)n, cgd, (double)tin);
-                    double xd = (double)x, Ed = (double)E, tbd;
-                    micro_t<double, true>(pd, ed, hd, xd, Ed, wc, &tbd);
-                    xo = R(xd);
-                    Eo = R(Ed);
-                    tb = R(tbd);
-                    ++wc.fixed;
+                if constexpr (std::is_same<R, float>::value) {
+                    if (front || (mixed && wc.close > 0)) {
+                        // precision-sensitive: the same cell in double, from the same inputs
+                        double xd = (double)x, Ed = (double)E, tbd;
+                        a1_cell_double(G, gi, gj, gk, (double)n, (double)tin, hd, xd, Ed, tbd, wc);
+                        xo = R(xd);
+                        Eo = R(Ed);
+                        tb = R(tbd);
+                        ++wc.fixed;
+                    }
                 }
                 w.accepted += wc.accepted;
                 w.rejected += wc.rejected;
@@ -1300,19 +1331,15 @@ k_sweep_a1(const GridDev<R>* __restrict__ grids, const int4* __restrict__ tiles,
                 w.newton += wc.newton;
                 w.fixed += wc.fixed;
             }
-            kbar = tb / cg.ell;
+            const R kbar = tb / cg.ell;
             s_kap[self] = kbar;
-            s_tc[self] = r_fma(hds, kbar, tin);   // entry face to centre
-            x = xo;
-            E = Eo;
+            s_tc[self] = r_fma(sg.hds, kbar, tin);   // entry face to centre
+            G.x[0][q] = xo;
+            if (G.E[0]) G.E[0][q] = Eo;
+            G.tau[1][q] = tin;
+            G.x[1][q] = kbar;
         }
         __syncthreads();
-    }
-    if (active) {
-        G.x[0][q] = x;
-        if (G.E[0]) G.E[0][q] = E;
-        G.tau[1][q] = tin;
-        G.x[1][q] = kbar;
     }
     add_work(ctr, w);
 }
