@@ -1408,6 +1408,9 @@ k_dtdiag(const GridDev<R>* __restrict__ grids, BatchDev bd)
     const R* __restrict__ x = G.x[0];
     const R* __restrict__ E = G.E[0];
     const R* __restrict__ tau = G.tau[0];
+    // the energy criterion reads dE/dt; without it the cooling terms are not
+    // formed (uniform over the grid)
+    const bool energy = p.K[1] < R(1e30) && p.thermal == 1;
     double v[NPART] = { __builtin_huge_val(), 0.0, 0.0, 0.0, 0.0, 0.0 };
     for (int q = lb * DT_BLOCK + threadIdx.x; q < p.ncell; q += nb * DT_BLOCK) {
         const int i = q % p.nx, j = (q / p.nx) % p.ny, k = q / (p.nx * p.ny);
@@ -1418,10 +1421,12 @@ k_dtdiag(const GridDev<R>* __restrict__ grids, BatchDev bd)
         bool ok = true;
         if constexpr (MS == 1) {
             const Env<R> e = make_env(p, n, cg, tq);
-            rhs_full(p, e, xq, Eq, r);
+            if (energy) rhs_full(p, e, xq, Eq, r);
+            else rhs_full<R, Env<R>, false>(p, e, xq, Eq, r);
         } else {
             const EnvM<R, MS> e = multi_env<MS>(p, G.src, n, tau, q, i, j, k, tq, ok);
-            rhs_full(p, e, xq, Eq, r);
+            if (energy) rhs_full(p, e, xq, Eq, r);
+            else rhs_full<R, EnvM<R, MS>, false>(p, e, xq, Eq, r);
         }
         v[0] = fmin(v[0], cell_dt(p, r, n, xq, Eq));
         v[1] += (double)n * (1.0 - (double)xq);

@@ -387,13 +387,15 @@ template <typename R> struct Coef {
 //   (T/1e4)^-0.7          = exp(-0.7 l + 0.7 ln 1e4)
 //   (T/1e6)^0.7           = exp( 0.7 l - 0.7 ln 1e6)
 //   T^1/2 (T/1e3)^-0.2    = 10^0.6 exp(0.3 l)
-template <typename R>
+// Without Cool the cooling coefficients are left at zero (for a caller that
+// needs no dE/dt).
+template <typename R, bool Cool = true>
 PI_HD __forceinline__ Coef<R> coefs(const Params<R>& p, R T)
 {
     Coef<R> c;
     const R invT = r_rcp(T);
     c.invT = invT;
-    const bool pw = p.recomb != 0, cool = p.thermal == 1 && p.cooling != 0;
+    const bool pw = p.recomb != 0, cool = Cool && p.thermal == 1 && p.cooling != 0;
     const R lT = (pw || cool) ? r_log(T) : R(0);
     if (!pw) {
         c.alpha = p.alpha_B;
@@ -456,7 +458,10 @@ PI_HD __forceinline__ void rhs_xT(const Params<R>& p, const EV& e, const Coef<R>
 // Temperature floor: the coefficients see max(T, T_FLOOR) and the cooling is
 // tapered by max(0, 1 - T_FLOOR/T), so the floor is approached smoothly and
 // never crossed by cooling.
-template <typename R, typename EV>
+// Without Cool only the x-rate and its Jacobian row, A, rec and T are formed
+// (fE and its derivatives are zero): what the timestep needs when the energy
+// criterion is off, bit for bit as with it.
+template <typename R, typename EV, bool Cool = true>
 PI_HD __forceinline__ void rhs_full(const Params<R>& p, const EV& e, R x, R E, Rhs<R>& r)
 {
     const R n = e.n;
@@ -471,7 +476,7 @@ PI_HD __forceinline__ void rhs_full(const Params<R>& p, const EV& e, R x, R E, R
         above = T > R(T_FLOOR) ? R(1) : R(0);
         Tc = T > R(T_FLOOR) ? T : R(T_FLOOR);
     }
-    Coef<R> c = coefs(p, Tc);
+    Coef<R> c = coefs<R, Cool>(p, Tc);
     c.dla *= above;
     c.dlci *= above;
     R A, dA, G, dG;
@@ -484,7 +489,7 @@ PI_HD __forceinline__ void rhs_full(const Params<R>& p, const EV& e, R x, R E, R
     const R dfx_dT = -c.aci * c.dlci * n * x * y + c.alpha * c.dla * n * y * y;
     r.jxx = -dA * e.inv_n - c.aci * n * (R(1) - R(2) * x) - R(2) * c.alpha * n * y + dfx_dT * dTdx;
     r.jxE = dfx_dT * dTdE;
-    if (p.thermal == 0) {
+    if (p.thermal == 0 || !Cool) {
         r.fE = r.jEx = r.jEE = R(0);
         return;
     }
