@@ -64,6 +64,25 @@ def test_a1_step_parity_mixed(oracle_lib):
     g.close()
 
 
+def test_a1_step_parity_mixed_front(oracle_lib):
+    """PI_MIXED_FRONT: the pass integrates every ionisation-front cell (starting
+    x in [1e-3, 0.5]) in double, out of line from the float integration: the
+    double re-solve counter is positive once a front has formed, and x and T
+    after 4 steps are within 1e-4 of the oracle on every cell."""
+    spec, nH = _case("mixed_front")
+    g, pb, st = pair(spec, nH, T0=50.0, precision="mixed_front")
+    g.work_counters(reset=True)
+    for _ in range(4):
+        g.step_a1(spec.t_end)
+        pb.step(st, spec.t_end, algo=1)
+    assert g.work_counters()["resolved_fp64"] > 0
+    Tg = pb.temperature(st["nH"], to_np(g.x), to_np(g.E))
+    Tw = pb.temperature(st["nH"], st["x"], st["E"])
+    float_bar(to_np(g.x), st["x"], 1e-4, "front-in-double algorithm-1 x after 4 steps")
+    float_bar(Tg, Tw, 1e-4, "front-in-double algorithm-1 T after 4 steps")
+    g.close()
+
+
 def test_a1_stromgren_on_gpu(oracle_lib):
     """Config 1 with A1-dt02: 0.1 t_rec in one step, the front within 2% of
     R_S (1 - exp(-t/t_rec))^(1/3) up to 4 t_rec, and the oracle's state."""
