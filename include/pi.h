@@ -412,8 +412,9 @@ pi_status pi_raytrace_static(const pi_grid_desc* desc, const pi_fields* fields, 
 /* Raytrace tile edge: 4, 8 or 16 (cells of the cubic tile one workgroup
  * sweeps, one launch per tile diagonal), PI_TILE_PERSISTENT (8^3 tiles, the
  * whole raytrace in one launch of persistent workgroups that claim tiles in
- * wavefront order and wait on their upstream tiles' done-flags, each wait
- * bounded by pi_set_raytrace_wait_limit), or 0 to time them all on the next
+ * wavefront order and wait until their upstream tiles have published the
+ * halo they need, each wait bounded by pi_set_raytrace_wait_limit), or 0 to
+ * time them all on the next
  * raytrace outside graph capture and keep the fastest (the default; that
  * first raytrace then SYNCHRONISES its stream).  The choice does not change
  * any result: every cell's interpolation is the same.  pi_get_raytrace_tile

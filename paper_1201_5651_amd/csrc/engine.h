@@ -63,9 +63,9 @@ struct Engine {
     // of edge SWEEP_TILES[sweep]; SWEEP_PERSIST one persistent launch over
     // the schedule of edge PERSIST_TILE; -1 until tuned
     int sweep = -1;
-    // persistent raytrace: per raytrace entry and octant (first done-flag,
-    // tiles along x, y, z), one done-flag per tile, the control block, and
-    // the workgroups of a launch
+    // persistent raytrace: per raytrace entry and octant (first flag and slot
+    // index, tiles along x, y, z), one done-flag per tile (double grids), the
+    // face buffer, the control block, and the workgroups of a launch
     int4* octs = nullptr;
     size_t octs_cap = 0;
     unsigned* flags = nullptr;

@@ -114,13 +114,11 @@ struct BatchDev {
     int kinds;
 };
 
-// Control block of the persistent raytrace (zeroed once when allocated): the
-// next tile ticket, the workgroups that have left, the epoch of the last
-// completed call (done-flags of the current call hold epoch + 1), and an
-// error flag set when a wait exceeded its limit.
-// Control block of the persistent raytrace and of the fused micro-physics:
-// the tile ticket, workgroups that have left, the epoch of the last call, and
-// the flag of a wait that ran out.
+// Control block of the persistent raytrace and of the fused micro-physics
+// (zeroed once when allocated): the workgroups that have left, the epoch of
+// the last completed call (the face entries and done-flags of the current
+// call carry epoch + 1), an error flag set when a wait exceeded its limit,
+// and the tickets of the tile lists.
 struct SweepCtl {
     unsigned exited, epoch, err;
     unsigned lticket[NXCD];   // tickets of the tile lists (TileLists)
