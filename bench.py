@@ -258,6 +258,7 @@ def bench_batch(args, torch, binding, synth) -> dict:
         bt.step_o2()
     torch.cuda.synchronize()
     _, n0, _ = bt.state()
+    bt.work_counters(reset=True)   # the timed steps' work only
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(args.steps):
@@ -291,6 +292,22 @@ def bench_batch(args, torch, binding, synth) -> dict:
         tot_ms += a.elapsed_time(b2)
         g.close()
     fp64_plain = tot_cells / (tot_ms * 1e-3)
+    # the whole batched step against the FP32 issue rate (counted flops, as
+    # for the single grid: Newton iterations from the work counters, two
+    # micro-integration set-ups and raytraces per cell-update) and against HBM
+    # (seven words per cell-update)
+    flops = work["newton"] * FLOP_NEWTON + 2 * cells * (FLOP_CELL_SETUP + FLOP_SWEEP_CELL)
+    achieved = flops / (ms * 1e-3) / 1e12
+    step_gbs = STEP_WORDS * word_bytes(args.precision) * cells / (ms * 1e-3) / 1e9
+    roofline = {"bound": "alu", "kernel": "whole batched step (timestep, micro-physics, "
+                                          "re-solve, raytrace)",
+                "achieved": round(achieved, 3), "peak": VALU_PEAK[args.precision],
+                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK[args.precision], 5),
+                "peak_note": VALU_PEAK_NOTE, "traffic": None,
+                "flops_per_step": flops / args.steps,
+                "hbm_of_step": {"bytes_per_cell_update": STEP_WORDS * word_bytes(args.precision),
+                                "achieved": round(step_gbs, 2), "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 5)}}
     return {
         "metric": "cell-updates/s of the batched A3 step, 64 uneven grids",
         "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -306,6 +323,7 @@ def bench_batch(args, torch, binding, synth) -> dict:
                    "fp64_single_grid_sample": len(sample),
                    "ratio_to_fp64_single_grid": value / fp64_plain,
                    "fp64_resolved_frac": work["resolved_fp64"] / max(1, cells)},
+        "roofline": roofline,
     }
 
 
