@@ -256,6 +256,22 @@ template <int TT> struct SweepShape {
     static constexpr int CPT = CELLS / THREADS;
 };
 
+// Quotient num / den of the sweep geometry.  Float: the hardware reciprocal
+// and one correction by a fused multiply-add, within rounding of the divided
+// quotient and exactly 1 when num == den (the residual num - q den is then
+// exact); double: the division.
+template <typename R> __device__ __forceinline__ R geom_quot(R num, R den);
+template <> __device__ __forceinline__ double geom_quot<double>(double num, double den)
+{
+    return num / den;
+}
+template <> __device__ __forceinline__ float geom_quot<float>(float num, float den)
+{
+    const float r = __builtin_amdgcn_rcpf(den);
+    const float q = num * r;
+    return __builtin_fmaf(__builtin_fmaf(-q, den, num), r, q);
+}
+
 // Half path length per cell length through the cell whose centre sits at
 // offsets (ax, ay, az) from the source vertex, da the largest of them:
 // sqrt(ax^2 + ay^2 + az^2) / (2 da), with the same operations (no
@@ -263,7 +279,7 @@ template <int TT> struct SweepShape {
 template <typename R> __device__ __forceinline__ R half_path(R ax, R ay, R az, R da)
 {
 #pragma clang fp contract(off)
-    return R(0.5) * r_sqrt(ax * ax + ay * ay + az * az) / da;
+    return geom_quot<R>(R(0.5) * r_sqrt(ax * ax + ay * ay + az * az), da);
 }
 
 // Short-characteristics geometry of a cell at octant-local coordinates L
@@ -285,8 +301,8 @@ template <typename R> __device__ __forceinline__ ScGeom<R> sc_geom(const int L[3
     o.a = (ad[2] >= ad[0] && ad[2] >= ad[1]) ? 2 : (ad[1] >= ad[0] ? 1 : 0);
     o.b = o.a == 2 ? 0 : o.a + 1;
     o.c = o.a == 0 ? 2 : o.a - 1;
-    // exact quotients: a tie of axes gives exactly 1 (zero weights stay zero)
-    const R fb = ad[o.b] / ad[o.a], fc = ad[o.c] / ad[o.a];
+    // a tie of axes gives a quotient of exactly 1 (zero weights stay zero)
+    const R fb = geom_quot<R>(ad[o.b], ad[o.a]), fc = geom_quot<R>(ad[o.c], ad[o.a]);
     const bool vb = L[o.b] >= 1, vc = L[o.c] >= 1;
     o.g00 = (R(1) - fb) * (R(1) - fc);
     o.g10 = vb ? fb * (R(1) - fc) : R(0);
