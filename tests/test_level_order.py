@@ -3,12 +3,13 @@ persistent edge (8^3): the table builder is taken from kernels.hip and
 compiled with the host compiler.  For every class, the 512 entries are a
 permutation of the tile's cells; for classes 0-5 every level lies in one group
 of 64 consecutive slots; with 128 and with 512 threads no thread owns two
-cells of one level; and on every tile of two octants (16^3 tiles, and a
-ragged 9 x 13 x 5) the class of the tile gives every cell a level above the
-level of each cell of the tile it reads (the four upstream centres one layer
-back along its major axis, ties z > y > x, Sect. 2.1's short
-characteristics).  A level order that broke one of these would let a cell read
-a column before it is formed."""
+cells of one level; every level lies in the 64 slots from its first one
+(c_level_start, from which the algorithm-1 pass takes a level's cells); and on
+every tile of two octants (16^3 tiles, and a ragged 9 x 13 x 5) the class of
+the tile gives every cell a level above the level of each cell of the tile it
+reads (the four upstream centres one layer back along its major axis, ties
+z > y > x, Sect. 2.1's short characteristics).  A level order that broke one
+of these would let a cell read a column before it is formed."""
 import os
 import shutil
 import subprocess
@@ -25,6 +26,7 @@ HARNESS = r"""
 constexpr int PERSIST_TILE = 8;
 %(builder)s
 static constexpr LevelOrder LO = make_level_order();
+static constexpr LevelStart LS = make_level_start();
 // major axis of the ray to a cell centre, ties z > y > x
 static int major(const int L[3])
 {
@@ -47,6 +49,12 @@ int main()
             group[lev] = i / 64;
         }
         for (int q = 0; q < 512; ++q) bad += seen[q] != 1;
+        // every level lies in the 64 slots from its first one (a wavefront
+        // takes a level's cells from there, lane t the slot that is t mod 64)
+        for (int i = 0; i < 512; ++i) {
+            const int lev = (int)(LO.cell[c][i] >> 15), f = LS.first[c][lev];
+            bad += f < 0 || i < f || i >= f + 64;
+        }
         for (int nt : { 128, 512 })
             for (int t = 0; t < nt; ++t) {
                 int cnt[32] = { 0 };
