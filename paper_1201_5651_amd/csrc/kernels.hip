@@ -1245,10 +1245,12 @@ k_sweep_a1(const GridDev<R>* __restrict__ grids, const int4* __restrict__ tiles,
     constexpr int HX = TT + 1, HY = TT + 1, NHALO = HX * HY * (TT + 1);
     __shared__ R s_tc[NHALO];
     __shared__ R s_kap[NHALO];
+    __shared__ DevTable<R> s_tab;
 
     const int4 tl = tiles[first + blockIdx.x];
     const GridDev<R>& G = grids[tl.x >> 3];
-    const Params<R> p = G.p;
+    // the rate table in LDS: every rate evaluation of the integrations reads it
+    const Params<R> p = table_to_lds(G.p, s_tab);
     const R* __restrict__ kbar_in = G.x[1];
     const R* __restrict__ tavg_in = G.tau[1];
     const int oct = tl.x & 7;
@@ -1284,13 +1286,54 @@ k_sweep_a1(const GridDev<R>* __restrict__ grids, const int4* __restrict__ tiles,
     Work w{};
     __syncthreads();
 
-    for (int s = 0; s < nlev; ++s) {
+    // the lane's cell at level s (the level's slot that is the lane modulo
+    // 64), if the level has one there inside the grid
+    struct LaneCell {
+        int cl, gi, gj, gk;
+        int64_t q;
+        bool on;
+    };
+    auto lane_cell = [&](int s) {
+        LaneCell c{ -1, 0, 0, 0, 0, false };
         const int w0 = c_level_start.first[cls][s];
         const int slot = w0 + (((int)threadIdx.x - w0) & 63);
-        const int cl = slot < NC ? (int)c_level_order.cell[cls][slot] : -1;
-        const int lx = cl & 31, ly = (cl >> 5) & 31, lz = (cl >> 10) & 31;
-        const int L[3] = { X0 + lx, Y0 + ly, Z0 + lz };
-        if (cl >= 0 && (cl >> 15) == s && L[0] < ex && L[1] < ey && L[2] < ez) {
+        c.cl = slot < NC ? (int)c_level_order.cell[cls][slot] : -1;
+        if (c.cl >= 0 && (c.cl >> 15) == s) {
+            const int Lx = X0 + (c.cl & 31), Ly = Y0 + ((c.cl >> 5) & 31);
+            const int Lz = Z0 + ((c.cl >> 10) & 31);
+            if (Lx < ex && Ly < ey && Lz < ez) {
+                c.gi = px ? p.sx + Lx : p.sx - 1 - Lx;
+                c.gj = py ? p.sy + Ly : p.sy - 1 - Ly;
+                c.gk = pz ? p.sz + Lz : p.sz - 1 - Lz;
+                c.q = c.gi + (int64_t)p.nx * (c.gj + (int64_t)p.ny * c.gk);
+                c.on = true;
+            }
+        }
+        return c;
+    };
+    // a level's inputs are loaded while the level before it integrates (no
+    // cell of a level is written before its own level)
+    LaneCell cur = lane_cell(0);
+    R n = R(1), x = R(1), E = R(0);
+    if (cur.on) {
+        n = G.nH[cur.q];
+        x = G.x[0][cur.q];
+        E = G.E[0] ? G.E[0][cur.q] : R(0);
+    }
+    for (int s = 0; s < nlev; ++s) {
+        LaneCell nxt{ -1, 0, 0, 0, 0, false };
+        R n1 = R(1), x1 = R(1), E1 = R(0);
+        if (s + 1 < nlev) {
+            nxt = lane_cell(s + 1);
+            if (nxt.on) {
+                n1 = G.nH[nxt.q];
+                x1 = G.x[0][nxt.q];
+                E1 = G.E[0] ? G.E[0][nxt.q] : R(0);
+            }
+        }
+        if (cur.on) {
+            const int lx = cur.cl & 31, ly = (cur.cl >> 5) & 31, lz = (cur.cl >> 10) & 31;
+            const int L[3] = { X0 + lx, Y0 + ly, Z0 + lz };
             const ScGeom<R> sg = sc_geom<R>(L);
             const int st[3] = { 1, HX, HX * HY };
             const int self = (lz + 1) * HX * HY + (ly + 1) * HX + (lx + 1);
@@ -1304,13 +1347,8 @@ k_sweep_a1(const GridDev<R>* __restrict__ grids, const int4* __restrict__ tiles,
                 const R T11 = upstream_T(s_tc[n11], sg.hds, s_kap[n11]);
                 tin = sc_average<R>(mellema, sg.g00, sg.g10, sg.g01, sg.g11, T00, T10, T01, T11);
             }
-            const int gi = px ? p.sx + L[0] : p.sx - 1 - L[0];
-            const int gj = py ? p.sy + L[1] : p.sy - 1 - L[1];
-            const int gk = pz ? p.sz + L[2] : p.sz - 1 - L[2];
-            const int64_t q = gi + (int64_t)p.nx * (gj + (int64_t)p.ny * gk);
-            const R n = G.nH[q], x = G.x[0][q];
-            const R E = G.E[0] ? G.E[0][q] : R(0);
-            const CellGeom<R> cg = cell_geom(p, gi, gj, gk);
+            const int64_t q = cur.q;
+            const CellGeom<R> cg = cell_geom(p, cur.gi, cur.gj, cur.gk);
             R xo = x, Eo = E, tb;
             if (!(isfinite(n) && isfinite(x) && isfinite(E) && isfinite(tin))) {
                 xo = Eo = tb = R(__builtin_nan(""));
@@ -1334,7 +1372,8 @@ k_sweep_a1(const GridDev<R>* __restrict__ grids, const int4* __restrict__ tiles,
                     if (front || (mixed && wc.close > 0)) {
                         // precision-sensitive: the same cell in double, from the same inputs
                         double xd = (double)x, Ed = (double)E, tbd;
-                        a1_cell_double(G, gi, gj, gk, (double)n, (double)tin, hd, xd, Ed, tbd, wc);
+                        a1_cell_double(G, cur.gi, cur.gj, cur.gk, (double)n, (double)tin, hd, xd,
+                                       Ed, tbd, wc);
                         xo = R(xd);
                         Eo = R(Ed);
                         tb = R(tbd);
@@ -1356,6 +1395,10 @@ k_sweep_a1(const GridDev<R>* __restrict__ grids, const int4* __restrict__ tiles,
             G.x[1][q] = kbar;
         }
         __syncthreads();
+        cur = nxt;
+        n = n1;
+        x = x1;
+        E = E1;
     }
     add_work(ctr, w);
 }
