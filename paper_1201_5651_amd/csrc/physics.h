@@ -352,16 +352,41 @@ template <typename R, int MS> struct EnvM {
     Env<R> s[MS];
 };
 
+// Source q's environment, picked by selects over the sources (no indexed
+// access, which would place the array in scratch memory).
+template <typename R, int MS>
+PI_HD __forceinline__ Env<R> env_of(const EnvM<R, MS>& e, int q)
+{
+    Env<R> r = e.s[0];
+#pragma unroll
+    for (int k = 1; k < MS; ++k) {
+        const bool on = q == k;
+        r.n = on ? e.s[k].n : r.n;
+        r.inv_n = on ? e.s[k].inv_n : r.inv_n;
+        r.c3 = on ? e.s[k].c3 : r.c3;
+        r.Qg = on ? e.s[k].Qg : r.Qg;
+        r.k = on ? e.s[k].k : r.k;
+        r.tau = on ? e.s[k].tau : r.tau;
+        r.att = on ? e.s[k].att : r.att;
+        r.Pin = on ? e.s[k].Pin : r.Pin;
+        r.Hin = on ? e.s[k].Hin : r.Hin;
+        r.lin = on ? e.s[k].lin : r.lin;
+    }
+    return r;
+}
+
+// The sources' rates one after another (a loop, not unrolled: the lookups of
+// all sources at once spill the integrator's registers).
 template <typename R, int MS>
 PI_HD __forceinline__ void photo(const Params<R>& p, const EnvM<R, MS>& e, R x, R& A, R& dA,
                                  R& G, R& dG)
 {
     photo(p, e.s[0], x, A, dA, G, dG);
-#pragma unroll
+#pragma unroll 1
     for (int q = 1; q < MS; ++q) {
         if (q < e.ns) {
             R a, da, g, dg;
-            photo(p, e.s[q], x, a, da, g, dg);
+            photo(p, env_of(e, q), x, a, da, g, dg);
             A += a;
             dA += da;
             G += g;
@@ -707,6 +732,23 @@ PI_HD __forceinline__ int substeps(const Params<R>& p, const EV& e, R x0, R E0, 
     return ns;
 }
 
+// A stage solve at its call in sdirk_step: inlined for float cells lit by
+// several sources (out of line, its environment would be passed on the stack
+// and read from scratch memory in every rate evaluation); the compiler's
+// choice otherwise.
+template <typename R, typename EV> struct SeveralFloat { static constexpr bool value = false; };
+template <int MS> struct SeveralFloat<float, EnvM<float, MS>> { static constexpr bool value = true; };
+template <typename R, typename EV>
+PI_HD __forceinline__ void stage_solve_at(const Params<R>& p, const EV& e, R xb, R Eb, R hg, R& x,
+                                          R& E, Work& w)
+{
+    if constexpr (SeveralFloat<R, EV>::value) {
+        [[clang::always_inline]] stage_solve(p, e, xb, Eb, hg, x, E, w);
+    } else {
+        stage_solve(p, e, xb, Eb, hg, x, E, w);
+    }
+}
+
 // Starting guess of a stage solve: the stage's base advanced by hg times an
 // estimate of the rate, unless that takes x out of [0, 1] or changes E by more
 // than PRED_MAX of itself (a stiff component, for which the explicit estimate
@@ -737,12 +779,12 @@ PI_HD __forceinline__ void sdirk_step(const Params<R>& p, const EV& e, R hs, R& 
     const R hg = gam * hs;
     R X1, F1;
     stage_guess(x, E, hg, fx, fE, X1, F1);
-    stage_solve(p, e, x, E, hg, X1, F1, w);
+    stage_solve_at(p, e, x, E, hg, X1, F1, w);
     const R xb = x + cst * (X1 - x);
     const R Eb = E + cst * (F1 - E);
     R X2, F2;
     stage_guess(xb, Eb, R(1), X1 - x, F1 - E, X2, F2);   // hg f(Y1) = Y1 - y
-    stage_solve(p, e, xb, Eb, hg, X2, F2, w);
+    stage_solve_at(p, e, xb, Eb, hg, X2, F2, w);
     const R ihg = r_rcp(hg);
     fx = (X2 - xb) * ihg;
     fE = (F2 - Eb) * ihg;
@@ -828,7 +870,12 @@ PI_HD void micro_t(const Params<R>& p, const EV& e, R h, R& x, R& E, Work& w, R*
 template <typename R, typename EV>
 PI_HD __forceinline__ void micro(const Params<R>& p, const EV& e, R h, R& x, R& E, Work& w)
 {
-    micro_t<R, false>(p, e, h, x, E, w, nullptr);
+    if constexpr (SeveralFloat<R, EV>::value) {
+        // inline, as stage_solve_at: its environment then stays in registers
+        [[clang::always_inline]] micro_t<R, false>(p, e, h, x, E, w, nullptr);
+    } else {
+        micro_t<R, false>(p, e, h, x, E, w, nullptr);
+    }
 }
 
 // Per-cell limit of eq. (4) at (x, E) with the entering column of t_n:
