@@ -1471,8 +1471,12 @@ k_dtdiag(const GridDev<R>* __restrict__ grids, BatchDev bd)
     // formed (uniform over the grid)
     const bool energy = p.K[1] < R(1e30) && p.thermal == 1;
     double v[NPART] = { __builtin_huge_val(), 0.0, 0.0, 0.0, 0.0, 0.0 };
-    for (int q = lb * DT_BLOCK + threadIdx.x; q < p.ncell; q += nb * DT_BLOCK) {
-        const int i = q % p.nx, j = (q / p.nx) % p.ny, k = q / (p.nx * p.ny);
+    // (i, j, k) of the thread's first cell and of the stride, divided once;
+    // each step adds them with carries
+    const int q0 = lb * DT_BLOCK + threadIdx.x, stride = nb * DT_BLOCK;
+    int i = q0 % p.nx, j = (q0 / p.nx) % p.ny, k = q0 / (p.nx * p.ny);
+    const int si = stride % p.nx, sj = (stride / p.nx) % p.ny, sk = stride / (p.nx * p.ny);
+    for (int q = q0; q < p.ncell; q += stride) {
         const CellGeom<R> cg = cell_geom(p, i, j, k);
         const R n = nH[q], xq = x[q], tq = tau[q];
         const R Eq = E ? E[q] : R(0);
@@ -1495,6 +1499,13 @@ k_dtdiag(const GridDev<R>* __restrict__ grids, BatchDev bd)
         const bool bad = !isfinite((double)xq) || !isfinite((double)tq) || !ok ||
                          (E && !isfinite((double)Eq));
         v[5] += bad ? 1.0 : 0.0;
+        i += si;
+        const int ci = i >= p.nx;
+        i -= ci ? p.nx : 0;
+        j += sj + ci;
+        const int cj = j >= p.ny;
+        j -= cj ? p.ny : 0;
+        k += sk + cj;
     }
     __shared__ double sm[NPART][DT_BLOCK / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;

@@ -116,11 +116,13 @@ template <typename R> struct Params {
 #define PI_FLOG(v) (__builtin_amdgcn_logf(v) * 0.693147181f)
 #define PI_FPOW(a, b) __powf(a, b)
 #define PI_FSQRT(v) __builtin_amdgcn_sqrtf(v)
+#define PI_FPOW01(v) __builtin_amdgcn_exp2f(0.1f * __builtin_amdgcn_logf(v))
 #else   // host-side unit harnesses
 #define PI_FEXP(v) expf(v)
 #define PI_FLOG(v) logf(v)
 #define PI_FPOW(a, b) powf(a, b)
 #define PI_FSQRT(v) sqrtf(v)
+#define PI_FPOW01(v) powf(v, 0.1f)
 #endif
 template <typename R> PI_HD __forceinline__ R r_exp(R v);
 template <> PI_HD __forceinline__ double r_exp<double>(double v) { return exp(v); }
@@ -137,6 +139,10 @@ template <> PI_HD __forceinline__ float r_sqrt<float>(float v) { return PI_FSQRT
 template <typename R> PI_HD __forceinline__ R r_pow(R a, R b);
 template <> PI_HD __forceinline__ double r_pow<double>(double a, double b) { return pow(a, b); }
 template <> PI_HD __forceinline__ float r_pow<float>(float a, float b) { return PI_FPOW(a, b); }
+// T^(1/10), from which the power laws of T are formed by products.
+template <typename R> PI_HD __forceinline__ R r_pow01(R v);
+template <> PI_HD __forceinline__ double r_pow01<double>(double v) { return exp(0.1 * log(v)); }
+template <> PI_HD __forceinline__ float r_pow01<float>(float v) { return PI_FPOW01(v); }
 // Reciprocal: correctly rounded in double, the hardware reciprocal (1 ulp) in
 // float device code.
 template <typename R> PI_HD __forceinline__ R r_rcp(R v);
@@ -408,10 +414,11 @@ template <typename R> struct Coef {
     R cin, dcin;
 };
 
-// The power laws share one logarithm: with l = ln T,
-//   (T/1e4)^-0.7          = exp(-0.7 l + 0.7 ln 1e4)
-//   (T/1e6)^0.7           = exp( 0.7 l - 0.7 ln 1e6)
-//   T^1/2 (T/1e3)^-0.2    = 10^0.6 exp(0.3 l)
+// The power laws are products of one power u = T^(1/10):
+//   T^1/2                 = u^5
+//   (T/1e4)^-0.7          = 1e4^0.7 u^3 / T
+//   (T/1e6)^0.7           = 1e6^-0.7 u^7
+//   T^1/2 (T/1e3)^-0.2    = 10^0.6 u^3
 // Without Cool the cooling coefficients are left at zero (for a caller that
 // needs no dE/dt).
 template <typename R, bool Cool = true>
@@ -421,15 +428,15 @@ PI_HD __forceinline__ Coef<R> coefs(const Params<R>& p, R T)
     const R invT = r_rcp(T);
     c.invT = invT;
     const bool pw = p.recomb != 0, cool = Cool && p.thermal == 1 && p.cooling != 0;
-    const R lT = (pw || cool) ? r_log(T) : R(0);
+    const R u = r_pow01(T), u2 = u * u, u3 = u2 * u;
     if (!pw) {
         c.alpha = p.alpha_B;
         c.dla = R(0);
     } else {
-        c.alpha = p.alpha_B * r_exp(R(-0.7) * lT + R(6.4472382603833282));   // 0.7 ln 1e4
+        c.alpha = p.alpha_B * R(630.95734448019324) * u3 * invT;   // 1e4^0.7
         c.dla = R(-0.7) * invT;
     }
-    const R sT = r_sqrt(T);
+    const R sT = u3 * u2;
     const R s5 = sT * R(0.0031622776601683794);   // sqrt(T/1e5)
     const R invq = r_rcp(R(1) + s5);
     const R dlq = R(0.5) * s5 * invT * invq;       // d ln q / dT, q = 1 + sqrt(T/1e5)
@@ -443,9 +450,9 @@ PI_HD __forceinline__ Coef<R> coefs(const Params<R>& p, R T)
     }
     c.cii = c.dcii = c.cin = c.dcin = R(0);
     if (cool) {
-        const R t6 = r_exp(R(0.7) * lT - R(9.6708573905749923));           // 0.7 ln 1e6
+        const R t6 = R(6.3095734448019325e-05) * (sT * u2);                 // 1e6^-0.7
         const R i16 = r_rcp(R(1) + t6);
-        const R crec = R(8.70e-27 * 3.9810717055349722) * r_exp(R(0.3) * lT) * i16;
+        const R crec = R(8.70e-27 * 3.9810717055349722) * u3 * i16;
         const R dlrec = (R(0.3) - R(0.7) * t6 * i16) * invT;
         const R cff = R(1.42e-27 * 1.3) * sT;
         const R cce = R(7.50e-19) * invq * r_exp(R(-118348.0) * invT);
