@@ -256,6 +256,40 @@ PI_HD __forceinline__ void table_pair(const DevTable<R>* __restrict__ T, R tau, 
     }
 }
 
+// d/dtau of the normalised P and H alone (the thin-cell quadrature needs no
+// values): between nodes V'(tau) = V0 exp(L - ln tau) dL, which needs no
+// reciprocal of tau.
+template <typename R>
+PI_HD __forceinline__ void table_dpair(const DevTable<R>* __restrict__ T, R tau, R& dP, R& dH)
+{
+    if (tau < T->tau1) {
+        dP = -T->p1_0;
+        dH = -T->h1_0;
+        return;
+    }
+    if (tau >= T->tau_last) {
+        dP = dH = R(0);
+        return;
+    }
+    const R s = r_log(tau);
+    const R f = (s - T->s1) * T->inv_delta;
+    int j = (int)f;                     // f >= 0 here
+    j = j < 0 ? 0 : (j > NTAB - 3 ? NTAB - 3 : j);
+    const R t = f - R(j);
+    {
+        const R* c = T->cp[j];
+        const R L = r_fma(r_fma(r_fma(c[3], t, c[2]), t, c[1]), t, c[0]);
+        const R dL = r_fma(r_fma(c[6], t, c[5]), t, c[4]);
+        dP = T->p0 * dL * r_exp(L - s);
+    }
+    {
+        const R* c = T->ch[j];
+        const R L = r_fma(r_fma(r_fma(c[3], t, c[2]), t, c[1]), t, c[0]);
+        const R dL = r_fma(r_fma(c[6], t, c[5]), t, c[4]);
+        dH = T->h0 * dL * r_exp(L - s);
+    }
+}
+
 // ------------------------------------------------------ rates of one cell
 // Environment of one cell for a micro-integration: density, geometry and the
 // entering column, fixed over the interval.
@@ -323,9 +357,9 @@ PI_HD __forceinline__ void photo(const Params<R>& p, const Env<R>& e, R x, R& A,
         // (no cancellation); the x-derivative keeps only the leading term
         // k * mean(-dP/dtau)
         const R c2 = R(0.28867513459481288225);   // 1 / (2 sqrt 3)
-        R P1, dP1, H1, dH1, P2, dP2, H2, dH2;
-        table_pair(p.tab, e.tau + (R(0.5) - c2) * u, P1, dP1, H1, dH1);
-        table_pair(p.tab, e.tau + (R(0.5) + c2) * u, P2, dP2, H2, dH2);
+        R dP1, dH1, dP2, dH2;
+        table_dpair(p.tab, e.tau + (R(0.5) - c2) * u, dP1, dH1);
+        table_dpair(p.tab, e.tau + (R(0.5) + c2) * u, dP2, dH2);
         const R mP = R(-0.5) * (dP1 + dP2), mH = R(-0.5) * (dH1 + dH2);
         A = e.Qg * mP * u;
         dA = e.Qg * mP * e.k;
@@ -739,17 +773,18 @@ PI_HD __forceinline__ int substeps(const Params<R>& p, const EV& e, R x0, R E0, 
     return ns;
 }
 
-// A stage solve at its call in sdirk_step: inlined for float cells lit by
-// several sources (out of line, its environment would be passed on the stack
-// and read from scratch memory in every rate evaluation); the compiler's
-// choice otherwise.
-template <typename R, typename EV> struct SeveralFloat { static constexpr bool value = false; };
-template <int MS> struct SeveralFloat<float, EnvM<float, MS>> { static constexpr bool value = true; };
+// A stage solve at its call in sdirk_step, and a float micro-integration at
+// its call: inlined for float cells (out of line, the environment would be
+// passed on the stack and read from scratch memory in every rate evaluation,
+// and the compiler's inlining budget does not always take them whole); the
+// compiler's choice for double.
+template <typename R, typename EV> struct InlineFloat { static constexpr bool value = false; };
+template <typename EV> struct InlineFloat<float, EV> { static constexpr bool value = true; };
 template <typename R, typename EV>
 PI_HD __forceinline__ void stage_solve_at(const Params<R>& p, const EV& e, R xb, R Eb, R hg, R& x,
                                           R& E, Work& w)
 {
-    if constexpr (SeveralFloat<R, EV>::value) {
+    if constexpr (InlineFloat<R, EV>::value) {
         [[clang::always_inline]] stage_solve(p, e, xb, Eb, hg, x, E, w);
     } else {
         stage_solve(p, e, xb, Eb, hg, x, E, w);
@@ -877,7 +912,7 @@ PI_HD void micro_t(const Params<R>& p, const EV& e, R h, R& x, R& E, Work& w, R*
 template <typename R, typename EV>
 PI_HD __forceinline__ void micro(const Params<R>& p, const EV& e, R h, R& x, R& E, Work& w)
 {
-    if constexpr (SeveralFloat<R, EV>::value) {
+    if constexpr (InlineFloat<R, EV>::value) {
         // inline, as stage_solve_at: its environment then stays in registers
         [[clang::always_inline]] micro_t<R, false>(p, e, h, x, E, w, nullptr);
     } else {
