@@ -448,6 +448,52 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
         }
     }
 
+    // the halo entries of the coherent kinds: every halo entry of the thread
+    // comes from the slot of its owner -- the upstream tile across every face
+    // the entry lies on -- at the owner's local coordinates and on the owner's
+    // face that holds it; all loads in flight together.  Tagged entries tell a
+    // current value from a stale one themselves, so after a tile's own
+    // micro-physics (whose upstream tiles have mostly finished by then) their
+    // loads are issued before the geometry below and arrive while it is
+    // formed; a bare sweep, which mostly finds its upstream tiles still
+    // running, and untagged entries (read only after wait() has seen the
+    // owners' done-flags) load them after it.
+    constexpr int NFACE = FaceList<TT>::N, KF = (NFACE + NT - 1) / NT;
+    constexpr bool early = Kind == TILE_FUSED && FaceWord<R>::tagged;
+    int qf[KF];
+    const face_t<R>* pk[KF];
+    const face_t<R>* pc[KF];
+    face_t<R> wk[KF], wc[KF];
+    auto face_loads = [&]() {
+#pragma unroll
+        for (int k = 0; k < KF; ++k) {
+            const int f = threadIdx.x + k * NT;
+            qf[k] = -1;
+            pk[k] = pc[k] = nullptr;
+            wk[k] = wc[k] = face_t<R>(0);
+            if (f < NFACE) {
+                const int q = face_entry<TT>(f);
+                qf[k] = q;
+                const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
+                const int Lx = X0 + hx - 1, Ly = Y0 + hy - 1, Lz = Z0 + hz - 1;
+                if (Lx >= 0 && Ly >= 0 && Lz >= 0 && Lx < ex && Ly < ey && Lz < ez) {
+                    const int ux = hx == 0, uy = hy == 0, uz = hz == 0;
+                    const int owner = idx - ux - uy * oc.y - uz * oc.y * oc.z;
+                    const int ox = ux ? TT - 1 : hx - 1, oy = uy ? TT - 1 : hy - 1;
+                    const int oz = uz ? TT - 1 : hz - 1;
+                    const int face = ux ? 0 : (uy ? 1 : 2);
+                    const int i = face == 0 ? oy : ox, j = face == 2 ? oy : oz;
+                    const face_t<R>* slot = fbuf + (int64_t)owner * FaceSlot<TT>::WORDS;
+                    pk[k] = &slot[FaceSlot<TT>::kap(face, i, j)];
+                    pc[k] = &slot[FaceSlot<TT>::col(face, i, j)];
+                    wk[k] = __hip_atomic_load(pk[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    wc[k] = __hip_atomic_load(pc[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+    };
+    if constexpr (early) face_loads();
+
     // geometry of the thread's cells (cell k: index threadIdx.x + k NT of the
     // tile's level order, or of the diagonal-plane order for other edges)
     const bool mellema = p.weights == 1;
@@ -485,13 +531,19 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
         nat[k] = lx + TX * (ly + TY * lz);
         tin[k] = R(0);
     }
+    if constexpr (early) {
+        // the geometry is formed here, while the halo loads are in flight (the
+        // compiler would otherwise defer it past the halo's arrival)
+#pragma unroll
+        for (int k = 0; k < CPT; ++k)
+            asm volatile("" ::"v"(g00[k]), "v"(g10[k]), "v"(g01[k]), "v"(g11[k]), "v"(hds[k]));
+    }
 
     wait();
     __syncthreads();
     // the upstream halo (the faces at local index -1): centre columns and,
     // for the coherent kinds, sigma0 n_H x dx; the tile's own entries of s_tc
     // are written by their cells before any cell reads them
-    constexpr int NFACE = FaceList<TT>::N, KF = (NFACE + NT - 1) / NT;
     if constexpr (Kind == TILE_STAGED) {
 #pragma unroll
         for (int k = 0; k < KF; ++k) {
@@ -512,40 +564,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev<R>* __restrict__ grids,
             s_tc[q] = tc;
         }
     } else {
-        // every halo entry of the thread from the slot of its owner -- the
-        // upstream tile across every face the entry lies on -- at the owner's
-        // local coordinates and on the owner's face that holds it; all loads
-        // in flight together
-        int qf[KF];
-        const face_t<R>* pk[KF];
-        const face_t<R>* pc[KF];
-        face_t<R> wk[KF], wc[KF];
-#pragma unroll
-        for (int k = 0; k < KF; ++k) {
-            const int f = threadIdx.x + k * NT;
-            qf[k] = -1;
-            pk[k] = pc[k] = nullptr;
-            wk[k] = wc[k] = face_t<R>(0);
-            if (f < NFACE) {
-                const int q = face_entry<TT>(f);
-                qf[k] = q;
-                const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
-                const int Lx = X0 + hx - 1, Ly = Y0 + hy - 1, Lz = Z0 + hz - 1;
-                if (Lx >= 0 && Ly >= 0 && Lz >= 0 && Lx < ex && Ly < ey && Lz < ez) {
-                    const int ux = hx == 0, uy = hy == 0, uz = hz == 0;
-                    const int owner = idx - ux - uy * oc.y - uz * oc.y * oc.z;
-                    const int ox = ux ? TT - 1 : hx - 1, oy = uy ? TT - 1 : hy - 1;
-                    const int oz = uz ? TT - 1 : hz - 1;
-                    const int face = ux ? 0 : (uy ? 1 : 2);
-                    const int i = face == 0 ? oy : ox, j = face == 2 ? oy : oz;
-                    const face_t<R>* slot = fbuf + (int64_t)owner * FaceSlot<TT>::WORDS;
-                    pk[k] = &slot[FaceSlot<TT>::kap(face, i, j)];
-                    pc[k] = &slot[FaceSlot<TT>::col(face, i, j)];
-                    wk[k] = __hip_atomic_load(pk[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    wc[k] = __hip_atomic_load(pc[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-            }
-        }
+        if constexpr (!early) face_loads();
         if constexpr (FaceWord<R>::tagged) {
             // an entry still of an earlier launch is polled until its owner
             // writes it (each lane for its own entries; the owners are held by
