@@ -18,6 +18,10 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are disabled for every HIP translation unit
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # every device atomic here is issued by one lane already; without the
+    # wave-combining rewrite a returning atomic is waited for only where its
+    # value is used (the persistent kernels claim their next tile early)
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wno-unused-command-line-argument",
 ]
 

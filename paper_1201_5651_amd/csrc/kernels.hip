@@ -778,7 +778,6 @@ k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     __shared__ R s_kap[NHALO];
     __shared__ int s_ticket;
     const bool lead = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) == 0;
-    const unsigned add = (threadIdx.x & 63) == 0 ? 1u : 0u;
     const unsigned done =
         __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) + 1u;
@@ -792,14 +791,14 @@ k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     // the tile list of this workgroup's XCD
     const int list = lists.n > 1 ? (int)(blockIdx.x % NXCD) : 0;
     const int lfirst = lists.first[list], lcount = lists.first[list + 1] - lfirst;
+    // thread 0 claims the tickets: the first here, each later one before the
+    // sweep of the tile before it, so that it arrives while that tile sweeps
+    unsigned claim = 0u;
+    if (threadIdx.x == 0)
+        claim = __hip_atomic_fetch_add(&ctl->lticket[list], 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
-        if (lead) {
-            // lane 0 takes the ticket (the others add 0); every lane of wave 0
-            // writes lane 0's value
-            const unsigned c = __hip_atomic_fetch_add(&ctl->lticket[list], add, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-            s_ticket = (int)__builtin_amdgcn_readfirstlane(c);
-        }
+        if (threadIdx.x == 0) s_ticket = (int)claim;
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(s_ticket);
         __syncthreads();   // (s_ticket is rewritten by the next claim)
@@ -807,6 +806,9 @@ k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
         const int4 tl = tiles[lfirst + t];
         const int4 oc = octs[tl.x];                         // flag base, tiles per axis
         const int idx = oc.x + (tl.w * oc.z + tl.z) * oc.y + tl.y;
+        if (threadIdx.x == 0)
+            claim = __hip_atomic_fetch_add(&ctl->lticket[list], 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
         sweep_tile<R, TT, SweepShape<TT>::THREADS, TILE_COHERENT>(
             grids, state, tau_buf, tl, s_tc, s_kap, [&] {
             if constexpr (!FaceWord<R>::tagged)
@@ -822,9 +824,9 @@ k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
         // (tagged entries need no flag; the claim's barrier keeps the next
         // tile's LDS writes behind this tile's last reads)
     }
-    if (lead) {
-        const unsigned left = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(
-            &ctl->exited, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (threadIdx.x == 0) {
+        const unsigned left = __hip_atomic_fetch_add(&ctl->exited, 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
         if (left == gridDim.x - 1) {
             // every workgroup read the condition before it left
             if (cond) __hip_atomic_store(cond, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1123,9 +1125,7 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
     __shared__ R s_kap[NHALO];
     __shared__ int s_ticket;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const bool lead = wave == 0;
     const int lane = threadIdx.x & 63;
-    const unsigned add = lane == 0 ? 1u : 0u;
     const unsigned done =
         __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) + 1u;
@@ -1134,12 +1134,14 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
     const int list = lists.n > 1 ? (int)(blockIdx.x % NXCD) : 0;
     const int lfirst = lists.first[list], lcount = lists.first[list + 1] - lfirst;
     Work w{};
+    // thread 0 claims the tickets: the first here, each later one before the
+    // sweep of the tile before it, so that it arrives while that tile sweeps
+    unsigned claim = 0u;
+    if (threadIdx.x == 0)
+        claim = __hip_atomic_fetch_add(&ctl->lticket[list], 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
-        if (lead) {
-            const unsigned c = __hip_atomic_fetch_add(&ctl->lticket[list], add, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-            s_ticket = (int)__builtin_amdgcn_readfirstlane(c);
-        }
+        if (threadIdx.x == 0) s_ticket = (int)claim;
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(s_ticket);
         __syncthreads();   // (s_ticket is rewritten by the next claim)
@@ -1203,6 +1205,9 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
                 }
             }
         }
+        if (threadIdx.x == 0)
+            claim = __hip_atomic_fetch_add(&ctl->lticket[list], 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
         // the sweep is on the launch's critical path (later tiles wait for it):
         // its instructions go before those of the integrating wavefronts of
         // the compute unit
@@ -1211,9 +1216,9 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
                                           idx, oc, done, spin_ticks, ctl);
         __builtin_amdgcn_s_setprio(0);
     }
-    if (lead) {
-        const unsigned left = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(
-            &ctl->exited, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (threadIdx.x == 0) {
+        const unsigned left = __hip_atomic_fetch_add(&ctl->exited, 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
         if (left == gridDim.x - 1) {
             for (int l = 0; l < NXCD; ++l)
                 __hip_atomic_store(&ctl->lticket[l], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
