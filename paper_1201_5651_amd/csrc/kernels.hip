@@ -938,6 +938,21 @@ __device__ __forceinline__ bool other_kind(const BatchDev& bd, const GridDev<R>&
 // input stays non-finite (the bound projections of the solver would otherwise
 // turn it into a valid-looking state), so the grid's diagnostics report it.
 // (i, j, k) are the cell's coordinates, q = i + nx (j + ny k).
+// Micro-integration of a cell lit by one point source from its loaded
+// values: (x, E) at t_n in, at t_n + hd out (NaN for a non-finite input).
+template <typename C>
+__device__ __forceinline__ void chem_cell_at(const Params<C>& p, C n, C tq, int i, int j, int k,
+                                             double hd, C& x, C& E, Work& w)
+{
+    if (!(isfinite(x) && isfinite(E) && isfinite(n) && isfinite(tq))) {
+        x = E = C(__builtin_nan(""));
+        return;
+    }
+    const CellGeom<C> cg = cell_geom(p, i, j, k);
+    const Env<C> e = make_env(p, n, cg, tq);
+    micro(p, e, C(hd), x, E, w);
+}
+
 template <typename C, typename S, int MS>
 __device__ __forceinline__ void chem_cell(const Params<C>& p, const Sources<C>& src, int q, int i,
                                           int j, int k, const S* __restrict__ nH, const S* x0,
@@ -947,15 +962,13 @@ __device__ __forceinline__ void chem_cell(const Params<C>& p, const Sources<C>& 
     x = C(x0[q]);
     E = E0 ? C(E0[q]) : C(0);
     const C n = C(nH[q]), tq = C(tau[q]);
-    if (!(isfinite(x) && isfinite(E) && isfinite(n) && isfinite(tq))) {
-        x = E = C(__builtin_nan(""));
-        return;
-    }
     if constexpr (MS == 1) {
-        const CellGeom<C> cg = cell_geom(p, i, j, k);
-        const Env<C> e = make_env(p, n, cg, tq);
-        micro(p, e, C(hd), x, E, w);
+        chem_cell_at(p, n, tq, i, j, k, hd, x, E, w);
     } else {
+        if (!(isfinite(x) && isfinite(E) && isfinite(n) && isfinite(tq))) {
+            x = E = C(__builtin_nan(""));
+            return;
+        }
         bool ok = true;
         const EnvM<C, MS> e = multi_env<MS>(p, src, n, tau, q, i, j, k, tq, ok);
         if (!ok) {
@@ -1123,6 +1136,9 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
     __shared__ DevTable<R> s_tab;
     __shared__ R s_tc[NHALO];
     __shared__ R s_kap[NHALO];
+    // inputs of the tile's cells: x, E, n_H and the column at t_n, and n_H
+    // of the state swept (each thread's own slots)
+    __shared__ R s_in[5][BRICKS * 64];
     __shared__ int s_ticket;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -1164,6 +1180,35 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
         const int ez = pz ? pl.nz - pl.sz : pl.sz;
         const double hd = dev_dt ? hscale * G.st->dt : hscale;
         const R* __restrict__ nHs = G.nHr[to];
+        // the inputs of the thread's cells of the tile, every load in flight
+        // at once, parked in LDS until their brick is integrated (one wait for
+        // memory per tile instead of one per brick)
+#pragma unroll
+        for (int b = 0; b < BPW; ++b) {
+            const int brick = wave * BPW + b;
+            const int lx = 4 * (brick % (TT / 4)) + (lane & 3);
+            const int ly = 4 * ((brick / (TT / 4)) % (TT / 4)) + ((lane >> 2) & 3);
+            const int lz = 4 * (brick / ((TT / 4) * (TT / 4))) + (lane >> 4);
+            const int Lx = tl.y * TT + lx, Ly = tl.z * TT + ly, Lz = tl.w * TT + lz;
+            R vx = R(0), vE = R(0), vn = R(0), vt = R(0), vs = R(0);
+            if (Lx < ex && Ly < ey && Lz < ez) {
+                const int gi = px ? pl.sx + Lx : pl.sx - 1 - Lx;
+                const int gj = py ? pl.sy + Ly : pl.sy - 1 - Ly;
+                const int gk = pz ? pl.sz + Lz : pl.sz - 1 - Lz;
+                const int q = gi + pl.nx * (gj + pl.ny * gk);
+                vx = G.x[from][q];
+                vE = G.E[from] ? G.E[from][q] : R(0);
+                vn = G.nH[q];
+                vt = G.tau[tau_chem][q];
+                vs = nHs[q];
+            }
+            const int slot = b * NT + threadIdx.x;
+            s_in[0][slot] = vx;
+            s_in[1][slot] = vE;
+            s_in[2][slot] = vn;
+            s_in[3][slot] = vt;
+            s_in[4][slot] = vs;
+        }
         // micro-physics of the tile's cells; sigma0 n_H x dx of each into LDS
         for (int b = 0; b < BPW; ++b) {
             const int brick = wave * BPW + b;
@@ -1179,16 +1224,16 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
                 const int gj = py ? pl.sy + Ly : pl.sy - 1 - Ly;
                 const int gk = pz ? pl.sz + Lz : pl.sz - 1 - Lz;
                 q = gi + pl.nx * (gj + pl.ny * gk);
-                R x, E;
+                const int slot = b * NT + threadIdx.x;
+                R x = s_in[0][slot], E = s_in[1][slot];
                 const int close0 = w.close;
-                chem_cell<R, R, 1>(pl, G.src, q, gi, gj, gk, G.nH, G.x[from], G.E[from],
-                                   G.tau[tau_chem], hd, x, E, w);
+                chem_cell_at<R>(pl, s_in[2][slot], s_in[3][slot], gi, gj, gk, hd, x, E, w);
                 flag = Mixed && w.close > close0;
                 if (!flag) {
                     G.x[to][q] = x;
                     if (G.E[to]) G.E[to][q] = E;
                 }
-                kap = pl.sdx * nHs[q] * x;
+                kap = pl.sdx * s_in[4][slot] * x;
             }
             s_kap[(lz + 1) * HX * HY + (ly + 1) * HX + (lx + 1)] = kap;
             if (Mixed) {
