@@ -793,6 +793,9 @@ k_sweep_persist(const GridDev<R>* __restrict__ grids, int state, int tau_buf,
     const int lfirst = lists.first[list], lcount = lists.first[list + 1] - lfirst;
     // thread 0 claims the tickets: the first here, each later one before the
     // sweep of the tile before it, so that it arrives while that tile sweeps
+    // (a held tile waits for the tile its workgroup sweeps, which is earlier
+    // in schedule order, as every upstream tile is: a chain of waits always
+    // ends at a tile that runs)
     unsigned claim = 0u;
     if (threadIdx.x == 0)
         claim = __hip_atomic_fetch_add(&ctl->lticket[list], 1u, __ATOMIC_RELAXED,
@@ -1152,6 +1155,9 @@ k_chem_sweep(const GridDev<R>* __restrict__ grids, BatchDev bd, int from, int to
     Work w{};
     // thread 0 claims the tickets: the first here, each later one before the
     // sweep of the tile before it, so that it arrives while that tile sweeps
+    // (a held tile waits for the tile its workgroup sweeps, which is earlier
+    // in schedule order, as every upstream tile is: a chain of waits always
+    // ends at a tile that runs)
     unsigned claim = 0u;
     if (threadIdx.x == 0)
         claim = __hip_atomic_fetch_add(&ctl->lticket[list], 1u, __ATOMIC_RELAXED,
