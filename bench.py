@@ -593,7 +593,7 @@ def main() -> int:
     ap.add_argument("--batch-grids", type=int, default=64)
     ap.add_argument("--batch-fp64-sample", type=int, default=8)
     # the served stream: config 5's sizes and run length (n 48..256, each to
-    # 2 t_rec) at an arrival rate the GPU sustains (4 /s; config 5 names
+    # 2 t_rec) at an arrival rate the GPU sustains (2 /s; config 5 names
     # 20 /s, above this GPU's throughput for such requests), without the 1%
     # of 512^3 outliers unless --serve-outliers says otherwise
     ap.add_argument("--serve-requests", type=int, default=120)
